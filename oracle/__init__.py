@@ -1,0 +1,217 @@
+"""Plain FP64 CPU oracle of the foap4 block-AMR Euler step.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the package smoke check and
+by the benchmark's CPU-baseline leg, never by the HIP library or its Python
+binding.  It shares no code with paper_2605_07612_amd/.
+
+Topology (leaf order, neighbour search, ghost pattern, balance, regrid map)
+lives in oracle/mesh.py; the cell and face arithmetic lives in
+oracle/foap4_oracle.c, which this module builds with gcc on first use and
+calls through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from .mesh import Forest
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "foap4_oracle.c")
+_LIB = os.path.join(_HERE, "libfoap4_oracle.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle (gcc, FP64, no FMA contraction, OpenMP over
+    independent blocks and records)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-std=c11", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        _lib.om_ghost_fill.argtypes = [P, P]
+        _lib.om_stage.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_double]
+        _lib.om_flux_fix.argtypes = [P, P, P, ctypes.c_double]
+        _lib.om_dt.argtypes = [P, P]
+        _lib.om_dt.restype = ctypes.c_double
+        _lib.om_step.argtypes = [P, P, P]
+        _lib.om_step.restype = ctypes.c_double
+        _lib.om_run.argtypes = [P, P, P, ctypes.c_int32, P]
+        _lib.om_run.restype = ctypes.c_int32
+        _lib.om_totals.argtypes = [P, P, P]
+        _lib.om_count_unphysical.argtypes = [P, P]
+        _lib.om_count_unphysical.restype = ctypes.c_int64
+        _lib.om_lohner_flags.argtypes = [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, P]
+        _lib.om_remap.argtypes = [P, P, P, P, P, P, P]
+    return _lib
+
+
+class _MeshC(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("N", ctypes.c_int32), ("g", ctypes.c_int32),
+                ("nvar", ctypes.c_int32), ("nb", ctypes.c_int64), ("level", ctypes.c_void_p),
+                ("dx0", ctypes.c_double), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("srl", ctypes.c_void_p), ("srl_off", ctypes.c_void_p),
+                ("f2c", ctypes.c_void_p), ("f2c_off", ctypes.c_void_p),
+                ("c2f", ctypes.c_void_p), ("c2f_off", ctypes.c_void_p)]
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# Lohner criterion constants of the paper's AMR runs (Sec. 5.4)
+LOHNER = dict(c_ref=5e-2, c_deref=6.25e-3, eps=1e-2, eps_abs=1e-10)
+
+
+class OracleMesh:
+    """A forest plus its FP64 state arrays [nb][nvar][P^ndim], P = N + 2g."""
+
+    def __init__(self, ndim, trees, N, g=2, tree_size=1.0, level=0, gamma=1.4, cfl=0.5,
+                 periodic=(True, True, True), origin=(0.0, 0.0, 0.0)):
+        if N % 2 or N < 2 * g or g < 2:
+            raise ValueError("need even N >= 2g and g >= 2")
+        self.ndim, self.N, self.g = ndim, N, g
+        self.nvar = 2 + ndim
+        self.tree_size, self.gamma, self.cfl = float(tree_size), float(gamma), float(cfl)
+        self.origin = origin
+        self.forest = Forest(ndim, trees, periodic, level)
+        self._refresh()
+        self.u = self.alloc()
+        self.t = 0.0
+
+    # --------------------------------------------------------------- helpers
+    @property
+    def P(self):
+        return self.N + 2 * self.g
+
+    @property
+    def nb(self):
+        return self.forest.nb
+
+    def alloc(self):
+        return np.zeros((self.nb, self.nvar) + (self.P,) * self.ndim)
+
+    def _refresh(self):
+        self.pat = self.forest.pattern()
+        self.level = self.forest.levels()
+        self._c = _MeshC()
+        c = self._c
+        c.ndim, c.N, c.g, c.nvar, c.nb = self.ndim, self.N, self.g, self.nvar, self.nb
+        c.level = _ptr(self.level)
+        c.dx0 = self.tree_size / self.N
+        c.gamma, c.cfl = self.gamma, self.cfl
+        keep = []
+        for name in ("srl", "srl_off", "f2c", "f2c_off", "c2f", "c2f_off"):
+            arr = np.ascontiguousarray(self.pat[name], dtype=np.int32)
+            if arr.size == 0:
+                arr = np.zeros(1, np.int32)
+            keep.append(arr)
+            setattr(c, name, _ptr(arr))
+        self._keep = keep
+
+    def cref(self):
+        return ctypes.byref(self._c)
+
+    def interior(self, u=None):
+        u = self.u if u is None else u
+        g, N = self.g, self.N
+        sl = (slice(None), slice(None)) + (slice(g, g + N),) * self.ndim
+        return u[sl]
+
+    def set_interior_from_field(self, field):
+        """Evaluate field(x, y[, z]) at the cell centres and store it."""
+        xc = self.forest.cell_centres(self.N, self.tree_size, self.origin)
+        vals = field(*[xc[:, d] for d in range(self.ndim)])  # [nvar][nb][N..]
+        self.interior()[...] = np.moveaxis(vals, 0, 1)
+
+    def set_interior_from_grid(self, grid):
+        """grid: [nvar][nz][ny][nx] (or [nvar][ny][nx]) on the uniform level of the mesh."""
+        N = self.N
+        for n, (l, G) in enumerate(self.forest.leaves):
+            if self.ndim == 3:
+                self.u[n][:, self.g:self.g + N, self.g:self.g + N, self.g:self.g + N] = \
+                    grid[:, G[2] * N:(G[2] + 1) * N, G[1] * N:(G[1] + 1) * N, G[0] * N:(G[0] + 1) * N]
+            else:
+                self.u[n][:, self.g:self.g + N, self.g:self.g + N] = \
+                    grid[:, G[1] * N:(G[1] + 1) * N, G[0] * N:(G[0] + 1) * N]
+
+    # -------------------------------------------------------------- numerics
+    def ghost_fill(self, u=None):
+        u = self.u if u is None else u
+        lib().om_ghost_fill(self.cref(), _ptr(u))
+        return u
+
+    def dt(self, u=None):
+        return lib().om_dt(self.cref(), _ptr(self.u if u is None else u))
+
+    def stage(self, ud, up, uo, stage, dt):
+        lib().om_stage(self.cref(), _ptr(ud), _ptr(up) if up is not None else None, _ptr(uo),
+                       stage, dt)
+
+    def flux_fix(self, ud, uo, dt_s):
+        lib().om_flux_fix(self.cref(), _ptr(ud), _ptr(uo), dt_s)
+
+    def step(self, n=1):
+        """n Heun steps; returns the list of dts."""
+        u1 = self.alloc()
+        dts = np.zeros(max(n, 1))
+        bad = lib().om_run(self.cref(), _ptr(self.u), _ptr(u1), n, _ptr(dts))
+        if bad:
+            raise FloatingPointError(f"oracle: unphysical state after step {bad}")
+        self.t += float(np.sum(dts[:n]))
+        return dts[:n]
+
+    def totals(self, u=None):
+        out = np.zeros(self.nvar)
+        lib().om_totals(self.cref(), _ptr(self.u if u is None else u), _ptr(out))
+        return out
+
+    def count_unphysical(self, u=None):
+        return lib().om_count_unphysical(self.cref(), _ptr(self.u if u is None else u))
+
+    def lohner_flags(self, u=None, **kw):
+        c = dict(LOHNER)
+        c.update(kw)
+        flags = np.zeros(self.nb, np.int8)
+        lib().om_lohner_flags(self.cref(), _ptr(self.u if u is None else u), c["c_ref"],
+                              c["c_deref"], c["eps"], c["eps_abs"], _ptr(flags))
+        return flags
+
+    def regrid(self, flags, lmin, lmax):
+        """Adapt the mesh and remap the state (old ghosts are filled first).
+        Returns the (op, src, arg) map, or None when the mesh is unchanged."""
+        self.ghost_fill()
+        old_c, old_keep, old_level, old_u = self._c, self._keep, self.level, self.u
+        res = self.forest.regrid(flags, lmin, lmax)
+        if res is None:
+            return None
+        op, src, arg = res
+        self._refresh()
+        self.u = self.alloc()
+        lib().om_remap(ctypes.byref(old_c), _ptr(old_u), self.cref(), _ptr(self.u),
+                       _ptr(op), _ptr(src), _ptr(arg))
+        del old_keep, old_level
+        return res
+
+
+def rel_l1(a, b, vol=None):
+    """sum |a - b| dV / sum |b| dV over all variables together (a, b: [nb][nvar][...])."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    w = 1.0 if vol is None else vol.reshape((-1,) + (1,) * (a.ndim - 1))
+    return float(np.sum(np.abs(a - b) * w) / np.sum(np.abs(b) * w))
