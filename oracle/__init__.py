@@ -44,6 +44,7 @@ def lib():
         _lib = ctypes.CDLL(build())
         P = ctypes.c_void_p
         _lib.om_ghost_fill.argtypes = [P, P]
+        _lib.om_ghost_round.argtypes = [P, P, ctypes.c_int]
         _lib.om_stage.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_double]
         _lib.om_flux_fix.argtypes = [P, P, P, ctypes.c_double]
         _lib.om_dt.argtypes = [P, P]
@@ -154,6 +155,12 @@ class OracleMesh:
     def ghost_fill(self, u=None):
         u = self.u if u is None else u
         lib().om_ghost_fill(self.cref(), _ptr(u))
+        return u
+
+    def ghost_round(self, rnd, u=None):
+        """Round 1 (SRL, F2C) or round 2 (C2F) of the ghost fill alone."""
+        u = self.u if u is None else u
+        lib().om_ghost_round(self.cref(), _ptr(u), rnd)
         return u
 
     def dt(self, u=None):

@@ -210,9 +210,18 @@ static void fill_c2f(const om_mesh *m, double *u, int f, int32_t q, int32_t cb, 
         }
 }
 
-/* Round R1 (SRL copies, F2C restriction), then round R2 (C2F prolongation). */
-void om_ghost_fill(const om_mesh *m, double *u) {
+/* One round of ghost filling: round 1 = SRL copies and F2C restriction,
+ * round 2 = C2F prolongation (which reads round 1's ghosts). */
+void om_ghost_round(const om_mesh *m, double *u, int round) {
   int nf = 2 * m->ndim;
+  if (round == 2) {
+    for (int f = 0; f < nf; f++) {
+#pragma omp parallel for schedule(static)
+      for (int32_t r = m->c2f_off[f]; r < m->c2f_off[f + 1]; r++)
+        fill_c2f(m, u, f, m->c2f[3 * r], m->c2f[3 * r + 1], m->c2f[3 * r + 2]);
+    }
+    return;
+  }
   for (int f = 0; f < nf; f++) {
     int ax = f / 2;
 #pragma omp parallel for schedule(static)
@@ -224,11 +233,12 @@ void om_ghost_fill(const om_mesh *m, double *u) {
     for (int32_t r = m->f2c_off[f]; r < m->f2c_off[f + 1]; r++)
       fill_f2c(m, u, f, m->f2c[4 * r], m->f2c[4 * r + 1], m->f2c[4 * r + 2]);
   }
-  for (int f = 0; f < nf; f++) {
-#pragma omp parallel for schedule(static)
-    for (int32_t r = m->c2f_off[f]; r < m->c2f_off[f + 1]; r++)
-      fill_c2f(m, u, f, m->c2f[3 * r], m->c2f[3 * r + 1], m->c2f[3 * r + 2]);
-  }
+}
+
+/* Round R1 (SRL copies, F2C restriction), then round R2 (C2F prolongation). */
+void om_ghost_fill(const om_mesh *m, double *u) {
+  om_ghost_round(m, u, 1);
+  om_ghost_round(m, u, 2);
 }
 
 /* ------------------------------------------------------------ Euler physics */
