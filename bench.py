@@ -1,0 +1,173 @@
+"""Benchmark of the foap4 hot path on one MI355X.
+
+Workload: 3D Euler on a static uniform periodic mesh of 256^3 cells in 16^3
+blocks of 16^3 cells (4096 blocks, 2 ghost layers), smoothed seeded noise
+density, sinusoidal shear, p = 2.5 (synthetic; the paper's tests use analytic
+initial conditions).  A step is one Heun (SSP-RK2) step: per stage ghost fill
+R1 (+R2), fused stage kernel, flux fix, plus the FP64 dt reduction.
+
+Reported: cell updates per second (each Heun step updates every cell twice,
+as in the paper's GCUPS) of the FP32 batched form (persistent launches,
+HIP-graph replay, autotuned work decomposition), the FP64 plain form beside
+it, the roofline of the dominant kernel (the stage kernel) from HIP-event
+timings taken on the batch's stream, and the FP64 CPU oracle on a bounded
+sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "cell-updates/s per GPU + % HBM roofline, 16^3 blocks, FP32 batched vs FP64 plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_bytes_per_cell(S):
+    """Algorithmic HBM bytes per cell of one stage-kernel launch, averaged
+    over the two Heun stages: stage 1 reads the interior and face ghosts of
+    u^n (1.75 S for 16^3 blocks, g = 2) and writes u1 (1 S); stage 2 reads u1
+    with ghosts (1.75 S) and u^n (1 S) and writes u^{n+1} (1 S)."""
+    return (2.75 + 3.75) / 2.0 * S
+
+
+def step_bytes_per_update(S):
+    """Whole step per cell update: 4.75 S (ghost fill reads and writes
+    0.75 S per stage, stages as above), counted per cell update."""
+    return 4.75 * S
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_steps(run, steps, sync):
+    import torch
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sync()
+    t0 = time.perf_counter()
+    start.record()
+    run(steps)
+    end.record()
+    sync()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(end) / 1e3, wall
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=256, help="cells per axis")
+    ap.add_argument("--block", type=int, default=16)
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--tune-cache", default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus must be 1 (the multi-GPU sharding is a design "
+              "note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2605_07612_amd as f4
+    from paper_2605_07612_amd import layout
+
+    torch.cuda.set_device(0)
+    w = synth.uniform_noise_shear(block=args.block, n=args.n, seed=0)
+    cells = args.n ** 3
+    log(f"workload {w['name']}: {cells} cells, {np.prod(w['trees'])} blocks")
+    grid = w["grid_field"]()
+
+    def make(prec):
+        m = f4.Mesh(3, w["trees"], w["N"], w["g"], w["tree_size"], prec=prec, gamma=w["gamma"], cfl=w["cfl"])
+        layout.set_from_grid(m, grid)
+        return m
+
+    # ---------------- FP32 batched: persistent + graph + autotuned
+    m32 = make(f4.F32)
+    batch = f4.Batch([m32])
+    ks, wg = batch.autotune(args.tune_cache)
+    log(f"autotune: kslabs={ks} wg_per_cu={wg}")
+    batch.step(args.warmup)
+    secs, wall = timed_steps(batch.step, args.steps, torch.cuda.synchronize)
+    t32, dt32 = m32.time()
+    gcups32 = cells * 2 * args.steps / secs / 1e9
+    log(f"FP32 batched: {secs / args.steps * 1e3:.3f} ms/step, {gcups32:.2f} Gcell-updates/s (wall {wall:.3f}s)")
+    phases = batch.phase_times(5)
+    log("phases (ms):", json.dumps({k: round(v, 4) for k, v in phases.items()}))
+    S32 = 5 * 4
+    stage_bytes = cells * stage_bytes_per_cell(S32)
+    achieved = stage_bytes / (phases["stage"] * 1e-3) / 1e9
+    step_gbs = gcups32 * step_bytes_per_update(S32)
+
+    result = {
+        "metric": METRIC,
+        "value": round(gcups32, 4),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(secs / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "cells": cells, "blocks": int(np.prod(w["trees"])),
+                   "block": args.block, "ghost": 2, "form": "batched: persistent stage launch, hipGraph, autotuned",
+                   "kslabs": ks, "wg_per_cu": wg, "reductions": "f64"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "stage_kernel<float,3>", "bytes_per_launch": int(stage_bytes),
+                     "avg_launch_ms": round(phases["stage"], 5)},
+        "step_hbm": {"bytes_per_update": step_bytes_per_update(S32), "achieved_gbs": round(step_gbs, 1),
+                     "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
+        "phases_ms": {k: round(v, 5) for k, v in phases.items()},
+    }
+    del batch, m32
+    torch.cuda.empty_cache()
+
+    # ---------------- FP64 plain: one workgroup per block, one launch per kernel
+    if not args.skip_fp64:
+        m64 = make(f4.F64)
+        m64.step(args.warmup)
+        secs64, _ = timed_steps(lambda n: m64.step(n), args.steps, torch.cuda.synchronize)
+        gcups64 = cells * 2 * args.steps / secs64 / 1e9
+        log(f"FP64 plain: {secs64 / args.steps * 1e3:.3f} ms/step, {gcups64:.2f} Gcell-updates/s")
+        result["fp64_plain"] = {"value": round(gcups64, 4), "unit": "Gcell-updates/s",
+                                "ms_per_step": round(secs64 / args.steps * 1e3, 4),
+                                "step_hbm_frac": round(gcups64 * step_bytes_per_update(40) / HBM_PEAK_GBS, 4),
+                                "batched_fp32_over_plain_fp64": round(gcups32 / gcups64, 3)}
+        del m64
+        torch.cuda.empty_cache()
+
+    # ---------------- CPU baseline: the FP64 oracle on a bounded sample
+    if not args.skip_cpu:
+        from oracle import OracleMesh
+        om = OracleMesh(3, w["trees"], w["N"], w["g"], w["tree_size"], gamma=w["gamma"], cfl=w["cfl"])
+        om.set_interior_from_grid(grid)
+        t0 = time.perf_counter()
+        om.step(args.cpu_steps)
+        el = time.perf_counter() - t0
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        result["cpu_baseline"] = {"value": round(cells * 2 * args.cpu_steps / el / 1e9, 5),
+                                  "unit": "Gcell-updates/s", "cores": threads, "kind": "oracle",
+                                  "sample": f"{args.cpu_steps} Heun steps of the same {args.n}^3 workload "
+                                            f"({el:.1f} s, FP64, OpenMP over blocks)"}
+        log(f"CPU oracle: {result['cpu_baseline']['value']} Gcell-updates/s on {threads} threads")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * foap4 on MI355X: C ABI of the block-structured quadtree/octree AMR Euler
+ * hot path (Teunissen et al., "foap4: adaptive mesh refinement with OpenACC,
+ * MPI, and p4est", arXiv 2605.07612).
+ *
+ * One library call = one of the paper's public operations (Sec. 2.1, the
+ * f4_ routines of the architecture figure): create a mesh, build the ghost
+ * pattern (Sec. 2.6), fill ghost cells (Sec. 2.6), advance in time (Sec. 3.1),
+ * adapt the mesh (Sec. 2.2), plus the batched multi-problem form.
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns foap4_status; no C++ exception crosses this ABI.
+ *    On an error the mesh is left unchanged and foap4_last_error() holds a
+ *    message.
+ *  - Device pointers are HIP device addresses on the current device; host
+ *    pointers are ordinary CPU memory.  Sizes are in elements unless noted.
+ *  - The two state buffers are owned by the caller and passed at creation.
+ *    Each is laid out [max_blocks][nvar][P]^ndim with P = N + 2g and i
+ *    fastest (the paper's uu(i,j,k,ivar,iblock), eq. array-structure), where
+ *    nvar = ndim + 2 and the variables are (rho, m_x, m_y[, m_z], E).
+ *    Cell (i,j,k) with -g <= i,j,k < N + g sits at padded index (i+g, j+g, k+g).
+ *  - Everything else (pattern, flux buffers, time step, scratch) is owned by
+ *    the library and freed by foap4_mesh_destroy().
+ *  - A mesh is not thread-safe; all its work runs on the HIP stream given at
+ *    creation, in stream order.  Calls that return host data synchronize
+ *    that stream; the others only enqueue work.
+ */
+#ifndef FOAP4_H
+#define FOAP4_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct foap4_mesh foap4_mesh;   /* opaque, library-owned */
+typedef struct foap4_batch foap4_batch; /* opaque, library-owned */
+
+typedef enum {
+  FOAP4_OK = 0,
+  FOAP4_E_INVALID = -1,    /* bad argument or descriptor                         */
+  FOAP4_E_CAPACITY = -2,   /* more blocks than max_blocks                         */
+  FOAP4_E_HIP = -3,        /* a HIP runtime call failed                           */
+  FOAP4_E_ORDER = -4,      /* call sequence misuse (e.g. step before a pattern)   */
+  FOAP4_E_UNPHYSICAL = -5  /* rho <= 0, p <= 0 or a non-finite value was produced */
+} foap4_status;
+
+typedef enum { FOAP4_F32 = 0, FOAP4_F64 = 1 } foap4_prec;
+typedef enum { FOAP4_IND_LOHNER = 0, FOAP4_IND_MLP = 1 } foap4_indicator;
+
+/* Mesh descriptor.  A brick of n_trees[0] x n_trees[1] (x n_trees[2]) trees
+ * (the paper's p4est brick, Sec. 2.2), all periodic; cubic cells with
+ * dx_l = tree_size / (N * 2^l) at refinement level l. */
+typedef struct {
+  int32_t ndim;        /* 2 or 3                                                     */
+  int32_t n_trees[3];  /* trees per axis (n_trees[2] ignored in 2D); product < 65536 */
+  int32_t periodic[3]; /* must be 1 for every used axis                               */
+  double origin[3];    /* coordinates of the brick's low corner                      */
+  double tree_size;    /* edge length of one tree                                    */
+  int32_t block_n;     /* N, cells per block edge: 8, 16 or 32                        */
+  int32_t n_ghost;     /* g, ghost layers: 2 .. 4 with N >= 2g                         */
+  int32_t init_level;  /* uniform level of the initial mesh                          */
+  int32_t min_level;   /* coarsest level regrid may produce                          */
+  int32_t max_level;   /* finest level regrid may produce (<= 14)                     */
+  int64_t max_blocks;  /* capacity of each state buffer, in blocks (Sec. 2.3)        */
+  foap4_prec prec;     /* element type of the state buffers                          */
+  double gamma;        /* ratio of specific heats (Sec. 3.5)                          */
+  double cfl;          /* CFL number of the time step                                 */
+} foap4_mesh_desc;
+
+/* Creates a mesh at the uniform level desc->init_level (Sec. 2.2) and its
+ * leaf table in Morton order per tree (block n = leaf n).  state0/state1 are
+ * caller-owned device buffers of state_bytes_each bytes each (>= max_blocks *
+ * nvar * P^ndim * element size); the caller writes the initial condition into
+ * the interior cells of state0.  hip_stream is a hipStream_t (NULL: default
+ * stream).  Builds the ghost pattern.  Errors: FOAP4_E_INVALID (descriptor),
+ * FOAP4_E_CAPACITY (initial blocks > max_blocks), FOAP4_E_HIP. */
+foap4_status foap4_mesh_create(const foap4_mesh_desc *desc, void *state0, void *state1,
+                               size_t state_bytes_each, void *hip_stream, foap4_mesh **out);
+foap4_status foap4_mesh_destroy(foap4_mesh *mesh);
+
+/* Number of blocks, mesh revision (changes only when regrid changes the
+ * mesh, Sec. 2.2) and which state buffer (0 or 1) holds the current solution. */
+foap4_status foap4_mesh_info(const foap4_mesh *mesh, int64_t *n_blocks, int64_t *revision,
+                             int32_t *cur_state);
+
+/* Host copies of the leaf table: level[n_blocks], tree[n_blocks] (tree id
+ * t_x + n_x (t_y + n_y t_z)) and anchor[n_blocks][3] (integer position of the
+ * block inside its tree at its level).  Any pointer may be NULL. */
+foap4_status foap4_mesh_export(const foap4_mesh *mesh, int32_t *level, int32_t *tree, int32_t *anchor);
+
+/* Builds the ghost pattern on the device (Sec. 2.6): for every block face a
+ * binary search in the sorted leaf keys classifies the neighbour as same
+ * level (SRL), finer (this block receives F2C restriction), coarser (this
+ * block receives C2F prolongation) or boundary; records are grouped by face
+ * direction (-x,+x,-y,+y,-z,+z) and sorted by receiving block and hanging
+ * offset with a stable count/scan/scatter.  Called by create and regrid;
+ * callable again at any time (idempotent). */
+foap4_status foap4_ghost_pattern_build(foap4_mesh *mesh);
+
+/* Record counts: counts[t * 6 + f] for type t (0 SRL, 1 F2C, 2 C2F, 3 BC)
+ * and face f.  SRL records are stored once per face pair under the + face. */
+foap4_status foap4_ghost_pattern_counts(const foap4_mesh *mesh, int32_t counts[24]);
+
+/* Host copies of the pattern records, each array sized by the counts above
+ * and ordered by face, then receiving block, then hanging offset:
+ *   srl[n][2] (a, b)           b is the + neighbour of a
+ *   f2c[n][4] (c, q, h, k)     coarse c receives restricted data from fine q
+ *                              at hanging offset h; k indexes q's C2F record
+ *   c2f[n][3] (q, c, h)        fine q receives prolonged data from coarse c
+ *   bc[n]     (b)              physical boundary face of b (always empty:
+ *                              only periodic meshes are accepted)
+ * Any pointer may be NULL. */
+foap4_status foap4_ghost_pattern_export(const foap4_mesh *mesh, int32_t *srl, int32_t *f2c,
+                                        int32_t *c2f, int32_t *bc);
+
+/* Executes the stored pattern on state buffer `state` (0 or 1): round R1
+ * (SRL copies and F2C restriction), then round R2 (C2F limited
+ * prolongation, which reads R1's ghosts) (Sec. 2.6).  Only face ghosts are
+ * written; corner and edge ghosts are never touched (Sec. 2.1). */
+foap4_status foap4_ghost_fill(foap4_mesh *mesh, int32_t state);
+
+/* Computes the CFL time step of the current state on the device:
+ * dt = cfl * min over interior cells of 1 / sum_d (|v_d| + c) / dx_l, in
+ * FP64.  Done automatically by the first foap4_step after create/regrid. */
+foap4_status foap4_compute_dt(foap4_mesh *mesh);
+
+/* Advances n_steps Heun (SSP-RK2) steps (eq. heun) on the current state:
+ * per stage ghost fill, fused flux/update stage, flux fix at refinement
+ * boundaries (Sec. 2.7); the next dt comes from the new state (FP64
+ * reduction on the device).  Enqueues only; if t_out/dt_out are non-NULL
+ * the stream is synchronized and the simulation time / the dt of the next
+ * step are returned, and FOAP4_E_UNPHYSICAL is reported if the state went
+ * bad.  This is the plain form: one kernel launch per operation and one
+ * workgroup per block tile. */
+foap4_status foap4_step(foap4_mesh *mesh, int32_t n_steps, double *t_out, double *dt_out);
+
+/* Reads back the simulation time and the dt of the next step (synchronizes). */
+foap4_status foap4_time(foap4_mesh *mesh, double *t_out, double *dt_out);
+
+/* Conserved totals sum over leaves and cells of U_v dx_l^d in FP64
+ * (out[nvar], host).  Synchronizes. */
+foap4_status foap4_conserved_totals(foap4_mesh *mesh, double *out);
+
+/* Per-block refinement flags (+1 refine, 0 keep, -1 derefine; Sec. 2.2) of
+ * the current state, written to flags_host[n_blocks].  FOAP4_IND_LOHNER is
+ * the paper's criterion (Sec. 3.3, eq. lohner-simple, constants of Sec. 5.4)
+ * on the density, in FP64; it fills ghosts first. */
+foap4_status foap4_refine_flags(foap4_mesh *mesh, foap4_indicator ind, int8_t *flags_host);
+
+/* Adapts the mesh (Sec. 2.2): refine every +1 block below max_level, then
+ * restore 2:1 balance across faces, edges and corners, then coarsen every
+ * complete family of old blocks that are all -1, lie above min_level and
+ * whose parent stays within one level of its neighbours.  The state is
+ * remapped on the device (copy, limited prolongation, restriction) into the
+ * other buffer, which becomes current; the pattern is rebuilt.  flags_host
+ * may be NULL (then the Lohner flags are computed).  *changed (may be NULL)
+ * is 1 if the mesh changed.  FOAP4_E_CAPACITY (mesh unchanged) if the new
+ * mesh would exceed max_blocks. */
+foap4_status foap4_regrid(foap4_mesh *mesh, const int8_t *flags_host, int32_t *changed);
+
+/* ------------------------------------------------------------------ batch
+ * Many independent meshes of one precision advanced together: one
+ * persistent launch per stage over the concatenated (mesh, block tile,
+ * k-slab) work items of all meshes, one launch per ghost round, steps
+ * captured once in a HIP graph and replayed.  Each mesh keeps its own dt. */
+foap4_status foap4_batch_create(foap4_mesh *const *meshes, int32_t n_meshes, foap4_batch **out);
+foap4_status foap4_batch_destroy(foap4_batch *batch);
+
+/* Work decomposition of the batched stage kernel: kslabs = 1, 2 or 4 k-slabs
+ * per block tile (the LDS tile depth is N / kslabs planes), wg_per_cu =
+ * resident workgroups per compute unit for the persistent grid (0: one
+ * workgroup per work item, no persistence). */
+foap4_status foap4_batch_set_config(foap4_batch *batch, int32_t kslabs, int32_t wg_per_cu);
+
+/* Times the candidate configurations on the batch itself and keeps the
+ * fastest; results are cached in the JSON file cache_path (may be NULL) keyed
+ * by GPU architecture, precision and the batch's block-size mix.  The
+ * meshes' states are restored afterwards.  Writes the chosen kslabs and
+ * wg_per_cu (may be NULL). */
+foap4_status foap4_batch_autotune(foap4_batch *batch, const char *cache_path, int32_t *kslabs,
+                                  int32_t *wg_per_cu);
+
+/* Advances every mesh of the batch by n_steps Heun steps (enqueue only). */
+foap4_status foap4_batch_step(foap4_batch *batch, int32_t n_steps);
+
+/* Runs n_steps steps of the batch with the same launches as the captured
+ * graph but launched one by one, with HIP events recorded on the batch's
+ * stream around every launch, and writes average durations in ms to
+ * out_ms[8]: [0] ghost round R1 per launch, [1] ghost round R2 per launch,
+ * [2] stage kernel per launch (both stages), [3] flux fixing per step,
+ * [4] dt finalisation per step, [5] whole step, [6] stage 1, [7] stage 2.
+ * Synchronizes.  Advances the meshes like foap4_batch_step. */
+foap4_status foap4_batch_phase_times(foap4_batch *batch, int32_t n_steps, double *out_ms);
+
+/* Last error message of a mesh (NULL: of the most recent failing call). */
+const char *foap4_last_error(const foap4_mesh *mesh);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FOAP4_H */

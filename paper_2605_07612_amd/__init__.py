@@ -1,0 +1,286 @@
+"""Python binding of libfoap4.so, the MI355X (gfx950) foap4 hot path.
+
+Argument marshalling only: every operation runs in the library's HIP
+kernels.  PyTorch provides the device memory of the two state buffers and
+the stream.  The binding refuses to run without the built library (there is
+no CPU fallback).  The C ABI is documented in include/foap4.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfoap4.so")
+
+F32, F64 = 0, 1
+IND_LOHNER, IND_MLP = 0, 1
+_STATUS = {0: "OK", -1: "E_INVALID", -2: "E_CAPACITY", -3: "E_HIP", -4: "E_ORDER", -5: "E_UNPHYSICAL"}
+
+
+class Foap4Error(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("n_trees", ctypes.c_int32 * 3), ("periodic", ctypes.c_int32 * 3),
+                ("origin", ctypes.c_double * 3), ("tree_size", ctypes.c_double), ("block_n", ctypes.c_int32),
+                ("n_ghost", ctypes.c_int32), ("init_level", ctypes.c_int32), ("min_level", ctypes.c_int32),
+                ("max_level", ctypes.c_int32), ("max_blocks", ctypes.c_int64), ("prec", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("cfl", ctypes.c_double)]
+
+
+_lib = None
+P = ctypes.c_void_p
+I32, I64, DBL = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+EXPORTS = {
+    # name: (restype, argtypes)
+    "foap4_mesh_create": (I32, [ctypes.POINTER(MeshDesc), P, P, ctypes.c_size_t, P, ctypes.POINTER(P)]),
+    "foap4_mesh_destroy": (I32, [P]),
+    "foap4_mesh_info": (I32, [P, P, P, P]),
+    "foap4_mesh_export": (I32, [P, P, P, P]),
+    "foap4_ghost_pattern_build": (I32, [P]),
+    "foap4_ghost_pattern_counts": (I32, [P, P]),
+    "foap4_ghost_pattern_export": (I32, [P, P, P, P, P]),
+    "foap4_ghost_fill": (I32, [P, I32]),
+    "foap4_compute_dt": (I32, [P]),
+    "foap4_step": (I32, [P, I32, P, P]),
+    "foap4_time": (I32, [P, P, P]),
+    "foap4_conserved_totals": (I32, [P, P]),
+    "foap4_refine_flags": (I32, [P, I32, P]),
+    "foap4_regrid": (I32, [P, P, P]),
+    "foap4_batch_create": (I32, [P, I32, ctypes.POINTER(P)]),
+    "foap4_batch_destroy": (I32, [P]),
+    "foap4_batch_set_config": (I32, [P, I32, I32]),
+    "foap4_batch_autotune": (I32, [P, ctypes.c_char_p, P, P]),
+    "foap4_batch_step": (I32, [P, I32]),
+    "foap4_batch_phase_times": (I32, [P, I32, P]),
+    "foap4_last_error": (ctypes.c_char_p, [P]),
+}
+
+
+def lib():
+    """Load libfoap4.so (built by __graft_entry__.build()); fails loudly if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _check(st, handle=None):
+    if st != 0:
+        msg = lib().foap4_last_error(handle)
+        raise Foap4Error(st, msg.decode() if msg else "")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Mesh:
+    """A mesh, its two caller-owned state buffers (torch tensors on the GPU)
+    and the library handle."""
+
+    def __init__(self, ndim, trees, N, g=2, tree_size=1.0, level=0, min_level=0, max_level=None,
+                 max_blocks=None, prec=F64, gamma=1.4, cfl=0.5, origin=(0.0, 0.0, 0.0), device="cuda",
+                 stream=None):
+        torch = _torch()
+        self.ndim, self.N, self.g = ndim, N, g
+        self.nvar = ndim + 2
+        self.P = N + 2 * g
+        self.prec = prec
+        self.dtype = torch.float64 if prec == F64 else torch.float32
+        nt = list(trees[:ndim]) + [1] * (3 - ndim)
+        base = int(np.prod(nt[:ndim]))
+        if max_level is None:
+            max_level = level
+        if max_blocks is None:
+            max_blocks = base * (1 << (ndim * max_level))
+        self.max_blocks = int(max_blocks)
+        d = MeshDesc()
+        d.ndim = ndim
+        d.n_trees[:] = nt
+        d.periodic[:] = [1, 1, 1]
+        d.origin[:] = list(origin)
+        d.tree_size = tree_size
+        d.block_n = N
+        d.n_ghost = g
+        d.init_level = level
+        d.min_level = min_level
+        d.max_level = max_level
+        d.max_blocks = self.max_blocks
+        d.prec = prec
+        d.gamma = gamma
+        d.cfl = cfl
+        self.desc = d
+        shape = (self.max_blocks, self.nvar) + (self.P,) * ndim
+        self.state = [torch.zeros(shape, dtype=self.dtype, device=device),
+                      torch.zeros(shape, dtype=self.dtype, device=device)]
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        nbytes = self.state[0].numel() * self.state[0].element_size()
+        h = ctypes.c_void_p()
+        st = lib().foap4_mesh_create(ctypes.byref(d), P(self.state[0].data_ptr()), P(self.state[1].data_ptr()),
+                                     nbytes, P(self.stream.cuda_stream), ctypes.byref(h))
+        _check(st)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().foap4_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- queries
+    def info(self):
+        nb, rev, cur = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(lib().foap4_mesh_info(self.h, ctypes.byref(nb), ctypes.byref(rev), ctypes.byref(cur)), self.h)
+        return nb.value, rev.value, cur.value
+
+    @property
+    def nb(self):
+        return self.info()[0]
+
+    @property
+    def cur(self):
+        return self.info()[2]
+
+    def export(self):
+        nb = self.nb
+        lev = np.zeros(nb, np.int32)
+        tree = np.zeros(nb, np.int32)
+        anc = np.zeros((nb, 3), np.int32)
+        _check(lib().foap4_mesh_export(self.h, _ptr(lev), _ptr(tree), _ptr(anc)), self.h)
+        return lev, tree, anc
+
+    def pattern_counts(self):
+        c = np.zeros(24, np.int32)
+        _check(lib().foap4_ghost_pattern_counts(self.h, _ptr(c)), self.h)
+        return c.reshape(4, 6)
+
+    def pattern_export(self):
+        c = self.pattern_counts()
+        n = c.sum(axis=1)
+        srl = np.zeros((n[0], 2), np.int32)
+        f2c = np.zeros((n[1], 4), np.int32)
+        c2f = np.zeros((n[2], 3), np.int32)
+        bc = np.zeros((n[3],), np.int32)
+        _check(lib().foap4_ghost_pattern_export(self.h, _ptr(srl), _ptr(f2c), _ptr(c2f), _ptr(bc)), self.h)
+        nf = 2 * self.ndim
+        offs = [np.concatenate([[0], np.cumsum(c[t, :nf])]).astype(np.int32) for t in range(4)]
+        return dict(srl=srl, srl_off=offs[0], f2c=f2c, f2c_off=offs[1], c2f=c2f, c2f_off=offs[2], bc=bc,
+                    bc_off=offs[3])
+
+    # ---------------------------------------------------------- operations
+    def pattern_build(self):
+        _check(lib().foap4_ghost_pattern_build(self.h), self.h)
+
+    def ghost_fill(self, state=None):
+        _check(lib().foap4_ghost_fill(self.h, self.cur if state is None else state), self.h)
+
+    def compute_dt(self):
+        _check(lib().foap4_compute_dt(self.h), self.h)
+
+    def step(self, n=1, sync=False):
+        if sync:
+            t, dt = ctypes.c_double(), ctypes.c_double()
+            _check(lib().foap4_step(self.h, n, ctypes.byref(t), ctypes.byref(dt)), self.h)
+            return t.value, dt.value
+        _check(lib().foap4_step(self.h, n, None, None), self.h)
+        return None
+
+    def time(self):
+        t, dt = ctypes.c_double(), ctypes.c_double()
+        _check(lib().foap4_time(self.h, ctypes.byref(t), ctypes.byref(dt)), self.h)
+        return t.value, dt.value
+
+    def totals(self):
+        out = np.zeros(self.nvar)
+        _check(lib().foap4_conserved_totals(self.h, _ptr(out)), self.h)
+        return out
+
+    def refine_flags(self, indicator=IND_LOHNER):
+        f = np.zeros(self.nb, np.int8)
+        _check(lib().foap4_refine_flags(self.h, indicator, _ptr(f)), self.h)
+        return f
+
+    def regrid(self, flags=None):
+        ch = ctypes.c_int32()
+        fl = None if flags is None else np.ascontiguousarray(flags, dtype=np.int8)
+        _check(lib().foap4_regrid(self.h, _ptr(fl), ctypes.byref(ch)), self.h)
+        return bool(ch.value)
+
+    # ------------------------------------------------------------- states
+    def current(self):
+        """The current state tensor restricted to the leaf blocks."""
+        return self.state[self.cur][: self.nb]
+
+    def interior(self, state=None):
+        u = self.state[self.cur if state is None else state][: self.nb]
+        g, N = self.g, self.N
+        sl = (slice(None), slice(None)) + (slice(g, g + N),) * self.ndim
+        return u[sl]
+
+
+class Batch:
+    """Several meshes of one precision advanced by one persistent launch per
+    stage, with steps replayed from a HIP graph."""
+
+    def __init__(self, meshes):
+        self.meshes = list(meshes)
+        arr = (ctypes.c_void_p * len(self.meshes))(*[m.h.value for m in self.meshes])
+        h = ctypes.c_void_p()
+        _check(lib().foap4_batch_create(arr, len(self.meshes), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().foap4_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_config(self, kslabs=1, wg_per_cu=0):
+        _check(lib().foap4_batch_set_config(self.h, kslabs, wg_per_cu))
+
+    def autotune(self, cache_path=None):
+        ks, wg = ctypes.c_int32(), ctypes.c_int32()
+        cp = cache_path.encode() if cache_path else None
+        _check(lib().foap4_batch_autotune(self.h, cp, ctypes.byref(ks), ctypes.byref(wg)))
+        return ks.value, wg.value
+
+    def step(self, n=1):
+        _check(lib().foap4_batch_step(self.h, n))
+
+    PHASES = ("ghost_r1", "ghost_r2", "stage", "fluxfix", "finalize", "step", "stage1", "stage2")
+
+    def phase_times(self, n=3):
+        """Average ms per launch/step of each phase (advances the meshes n steps)."""
+        out = np.zeros(8)
+        _check(lib().foap4_batch_phase_times(self.h, n, _ptr(out)))
+        return dict(zip(self.PHASES, out.tolist()))

@@ -1,0 +1,738 @@
+// extern "C" entry points of include/foap4.h and the host-side drivers:
+// the plain per-kernel step, the batched persistent step captured in a HIP
+// graph, regrid, and the work-decomposition autotuner.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+
+#include "foap4_internal.h"
+
+namespace {
+thread_local std::string g_last_err;
+}
+
+namespace f4 {
+
+foap4_status fail(foap4_mesh *m, foap4_status s, const std::string &msg) {
+  g_last_err = msg;
+  if (m) m->err = msg;
+  return s;
+}
+
+MeshDev make_dev(const foap4_mesh *m, int ks) {
+  MeshDev d{};
+  d.s[0] = m->state[0];
+  d.s[1] = m->state[1];
+  d.level = m->d_level;
+  d.face_info = m->pat.face_info;
+  d.srl = m->pat.srl;
+  d.f2c = m->pat.f2c;
+  d.c2f = m->pat.c2f;
+  d.fix_list = m->pat.fix_list;
+  d.bflux_f = m->pat.bflux_f;
+  d.bflux_c = m->pat.bflux_c;
+  d.scal = m->d_scal;
+  d.nb = (int64_t)m->topo.leaves.size();
+  d.item_begin = 0;
+  d.r1_begin = 0;
+  d.r2_begin = 0;
+  d.dx0 = m->d.tree_size / m->d.block_n;
+  d.gamma = m->d.gamma;
+  d.cfl = m->d.cfl;
+  for (int t = 0; t < kTypes; t++) {
+    d.pn[t] = m->pat.n[t];
+    for (int f = 0; f < 7; f++) d.poff[t][f] = m->pat.off[t][f];
+  }
+  d.n_fix = m->pat.n_fix;
+  d.cur = m->cur;
+  d.N = m->d.block_n;
+  d.g = m->d.n_ghost;
+  d.ks = std::max(1, std::min(ks, m->d.block_n / 8));
+  return d;
+}
+
+foap4_status upload_dev(foap4_mesh *m) {
+  MeshDev d = make_dev(m, 1);
+  F4_HIP(m, hipMemcpyAsync(m->d_dev, &d, sizeof(d), hipMemcpyHostToDevice, m->stream));
+  F4_HIP(m, hipStreamSynchronize(m->stream));
+  return FOAP4_OK;
+}
+
+static foap4_status upload_leaves(foap4_mesh *m) {
+  const size_t nb = m->topo.leaves.size();
+  std::vector<int32_t> lev(nb), gc(3 * nb);
+  std::vector<uint64_t> keys(nb);
+  for (size_t i = 0; i < nb; i++) {
+    const Leaf &L = m->topo.leaves[i];
+    lev[i] = L.level;
+    for (int d = 0; d < 3; d++) gc[3 * i + d] = L.g[d];
+    keys[i] = m->topo.key(L);
+  }
+  if (nb) {
+    F4_HIP(m, hipMemcpyAsync(m->d_level, lev.data(), nb * 4, hipMemcpyHostToDevice, m->stream));
+    F4_HIP(m, hipMemcpyAsync(m->d_gc, gc.data(), nb * 12, hipMemcpyHostToDevice, m->stream));
+    F4_HIP(m, hipMemcpyAsync(m->d_keys, keys.data(), nb * 8, hipMemcpyHostToDevice, m->stream));
+  }
+  F4_HIP(m, hipStreamSynchronize(m->stream));
+  return FOAP4_OK;
+}
+
+static foap4_status check_bad(foap4_mesh *m) {
+  double bad = 0.0;
+  F4_HIP(m, hipMemcpyAsync(&bad, m->d_scal + kBad, 8, hipMemcpyDeviceToHost, m->stream));
+  F4_HIP(m, hipStreamSynchronize(m->stream));
+  if (bad != 0.0) return fail(m, FOAP4_E_UNPHYSICAL, "unphysical state (rho <= 0, p <= 0 or non-finite)");
+  return FOAP4_OK;
+}
+
+static foap4_status fill(foap4_mesh *m, const MeshDev *dd, int which) {
+  const bool f64 = m->d.prec == FOAP4_F64;
+  const int64_t r1 = m->pat.n[kSRL] + m->pat.n[kF2C], r2 = m->pat.n[kC2F];
+  F4_HIP(m, launch_ghost(dd, 1, r1, 1, which, m->d.ndim, f64, 0, m->stream));
+  if (r2) F4_HIP(m, launch_ghost(dd, 1, r2, 2, which, m->d.ndim, f64, 0, m->stream));
+  return FOAP4_OK;
+}
+
+static foap4_status ensure_dt(foap4_mesh *m) {
+  if (m->dt_valid) return FOAP4_OK;
+  F4_HIP(m, launch_dt_full(m, m->stream));
+  F4_HIP(m, launch_finalize(m->d_dev, 1, 0, m->stream));
+  m->dt_valid = true;
+  return FOAP4_OK;
+}
+
+}  // namespace f4
+
+using namespace f4;
+
+// ------------------------------------------------------------------ batch type
+struct foap4_batch {
+  std::vector<foap4_mesh *> meshes;
+  std::vector<int64_t> revs;
+  int ndim = 3;
+  bool f64 = false;
+  int ks = 1, wg_per_cu = 0;
+  MeshDev *d_devs = nullptr;
+  int64_t total_items = 0, r1_total = 0, r2_total = 0;
+  hipStream_t stream = nullptr, cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool graph_valid = false;
+  int n_cu = 256;
+  std::string err;
+};
+
+extern "C" {
+
+const char *foap4_last_error(const foap4_mesh *mesh) {
+  return mesh ? mesh->err.c_str() : g_last_err.c_str();
+}
+
+foap4_status foap4_mesh_create(const foap4_mesh_desc *desc, void *state0, void *state1, size_t state_bytes_each,
+                               void *hip_stream, foap4_mesh **out) {
+  if (!desc || !out) return fail(nullptr, FOAP4_E_INVALID, "null descriptor or output pointer");
+  *out = nullptr;
+  const foap4_mesh_desc &d = *desc;
+  if (d.ndim != 2 && d.ndim != 3) return fail(nullptr, FOAP4_E_INVALID, "ndim must be 2 or 3");
+  if (d.block_n != 8 && d.block_n != 16 && d.block_n != 32)
+    return fail(nullptr, FOAP4_E_INVALID, "block_n must be 8, 16 or 32");
+  if (d.n_ghost < 2 || d.n_ghost > 4 || d.block_n < 2 * d.n_ghost)
+    return fail(nullptr, FOAP4_E_INVALID, "n_ghost must be in 2..4 with block_n >= 2 n_ghost");
+  int64_t ntrees = 1;
+  for (int a = 0; a < d.ndim; a++) {
+    if (d.n_trees[a] < 1) return fail(nullptr, FOAP4_E_INVALID, "n_trees must be >= 1");
+    if (!d.periodic[a]) return fail(nullptr, FOAP4_E_INVALID, "only periodic domains are supported");
+    ntrees *= d.n_trees[a];
+  }
+  if (ntrees >= 65536) return fail(nullptr, FOAP4_E_INVALID, "at most 65535 trees");
+  if (d.init_level < 0 || d.min_level < 0 || d.max_level > kMaxLevel || d.min_level > d.max_level ||
+      d.init_level > d.max_level)
+    return fail(nullptr, FOAP4_E_INVALID, "levels must satisfy 0 <= min <= max <= 14, init <= max");
+  if (!(d.tree_size > 0) || !(d.gamma > 1) || !(d.cfl > 0)) return fail(nullptr, FOAP4_E_INVALID, "tree_size, gamma, cfl");
+  if (d.prec != FOAP4_F32 && d.prec != FOAP4_F64) return fail(nullptr, FOAP4_E_INVALID, "prec");
+  if (!state0 || !state1 || state0 == state1) return fail(nullptr, FOAP4_E_INVALID, "two distinct state buffers needed");
+  foap4_mesh *m = new foap4_mesh();
+  m->d = d;
+  m->nvar = d.ndim + 2;
+  m->P = d.block_n + 2 * d.n_ghost;
+  m->nf = 2 * d.ndim;
+  m->elem = d.prec == FOAP4_F64 ? 8 : 4;
+  m->block_elems = (int64_t)m->nvar * m->P * m->P * (d.ndim == 3 ? m->P : 1);
+  m->state[0] = state0;
+  m->state[1] = state1;
+  m->state_bytes = state_bytes_each;
+  m->stream = (hipStream_t)hip_stream;
+  if ((size_t)d.max_blocks * m->block_elems * m->elem > state_bytes_each || d.max_blocks < 1) {
+    delete m;
+    return fail(nullptr, FOAP4_E_INVALID, "state buffers smaller than max_blocks blocks");
+  }
+  m->topo.init_uniform(d.ndim, d.n_trees, d.init_level);
+  if ((int64_t)m->topo.leaves.size() > d.max_blocks) {
+    delete m;
+    return fail(nullptr, FOAP4_E_CAPACITY, "initial mesh exceeds max_blocks");
+  }
+  auto bail = [&](foap4_status s) {
+    std::string msg = m->err;
+    foap4_mesh_destroy(m);
+    g_last_err = msg;
+    return s;
+  };
+  const size_t cap = (size_t)d.max_blocks;
+  if (hipMalloc((void **)&m->d_level, cap * 4) != hipSuccess || hipMalloc((void **)&m->d_gc, cap * 12) != hipSuccess ||
+      hipMalloc((void **)&m->d_keys, cap * 8) != hipSuccess || hipMalloc((void **)&m->d_scal, kNScal * 8) != hipSuccess ||
+      hipMalloc((void **)&m->d_dev, sizeof(MeshDev)) != hipSuccess) {
+    m->err = "device allocation failed";
+    return bail(FOAP4_E_HIP);
+  }
+  m->cap_blocks = cap;
+  if (hipMemsetAsync(m->d_scal, 0, kNScal * 8, m->stream) != hipSuccess) {
+    m->err = "memset failed";
+    return bail(FOAP4_E_HIP);
+  }
+  foap4_status st;
+  if ((st = upload_leaves(m)) != FOAP4_OK) return bail(st);
+  if ((st = build_pattern(m)) != FOAP4_OK) return bail(st);
+  if ((st = upload_dev(m)) != FOAP4_OK) return bail(st);
+  *out = m;
+  return FOAP4_OK;
+}
+
+foap4_status foap4_mesh_destroy(foap4_mesh *m) {
+  if (!m) return FOAP4_OK;
+  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  void *ptrs[] = {m->d_level, m->d_gc, m->d_keys, m->d_scal, m->d_dev, m->d_item_begin,
+                  m->pat.srl, m->pat.f2c, m->pat.c2f, m->pat.bc, m->pat.face_info, m->pat.fix_list,
+                  m->pat.cnt, m->pat.tot, m->pat.bflux_f, m->pat.bflux_c};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete m;
+  return FOAP4_OK;
+}
+
+foap4_status foap4_mesh_info(const foap4_mesh *m, int64_t *n_blocks, int64_t *revision, int32_t *cur_state) {
+  if (!m) return fail(nullptr, FOAP4_E_INVALID, "null mesh");
+  if (n_blocks) *n_blocks = (int64_t)m->topo.leaves.size();
+  if (revision) *revision = m->revision;
+  if (cur_state) *cur_state = m->cur;
+  return FOAP4_OK;
+}
+
+foap4_status foap4_mesh_export(const foap4_mesh *m, int32_t *level, int32_t *tree, int32_t *anchor) {
+  if (!m) return fail(nullptr, FOAP4_E_INVALID, "null mesh");
+  for (size_t i = 0; i < m->topo.leaves.size(); i++) {
+    const Leaf &L = m->topo.leaves[i];
+    if (level) level[i] = L.level;
+    if (tree) tree[i] = m->topo.tree_id(L);
+    if (anchor)
+      for (int d = 0; d < 3; d++) anchor[3 * i + d] = (d < m->d.ndim) ? L.g[d] - ((L.g[d] >> L.level) << L.level) : 0;
+  }
+  return FOAP4_OK;
+}
+
+foap4_status foap4_ghost_pattern_build(foap4_mesh *m) {
+  if (!m) return fail(nullptr, FOAP4_E_INVALID, "null mesh");
+  foap4_status st = build_pattern(m);
+  if (st != FOAP4_OK) return st;
+  return upload_dev(m);
+}
+
+foap4_status foap4_ghost_pattern_counts(const foap4_mesh *m, int32_t counts[24]) {
+  if (!m || !counts) return fail(nullptr, FOAP4_E_INVALID, "null argument");
+  for (int t = 0; t < 4; t++)
+    for (int f = 0; f < 6; f++) counts[t * 6 + f] = m->pat.off[t][f + 1] - m->pat.off[t][f];
+  return FOAP4_OK;
+}
+
+foap4_status foap4_ghost_pattern_export(const foap4_mesh *mc, int32_t *srl, int32_t *f2c, int32_t *c2f,
+                                        int32_t *bc) {
+  foap4_mesh *m = const_cast<foap4_mesh *>(mc);
+  if (!m) return fail(nullptr, FOAP4_E_INVALID, "null mesh");
+  const Pattern &P = m->pat;
+  if (srl && P.n[kSRL]) F4_HIP(m, hipMemcpyAsync(srl, P.srl, (size_t)P.n[kSRL] * 8, hipMemcpyDeviceToHost, m->stream));
+  if (f2c && P.n[kF2C]) F4_HIP(m, hipMemcpyAsync(f2c, P.f2c, (size_t)P.n[kF2C] * 16, hipMemcpyDeviceToHost, m->stream));
+  if (c2f && P.n[kC2F]) F4_HIP(m, hipMemcpyAsync(c2f, P.c2f, (size_t)P.n[kC2F] * 12, hipMemcpyDeviceToHost, m->stream));
+  if (bc && P.n[kBC]) F4_HIP(m, hipMemcpyAsync(bc, P.bc, (size_t)P.n[kBC] * 4, hipMemcpyDeviceToHost, m->stream));
+  F4_HIP(m, hipStreamSynchronize(m->stream));
+  return FOAP4_OK;
+}
+
+foap4_status foap4_ghost_fill(foap4_mesh *m, int32_t state) {
+  if (!m || (state != 0 && state != 1)) return fail(m, FOAP4_E_INVALID, "bad mesh or state index");
+  if (!m->pat_valid) return fail(m, FOAP4_E_ORDER, "no ghost pattern");
+  return fill(m, m->d_dev, state == m->cur ? 0 : 1);
+}
+
+foap4_status foap4_compute_dt(foap4_mesh *m) {
+  if (!m) return fail(nullptr, FOAP4_E_INVALID, "null mesh");
+  m->dt_valid = false;
+  return ensure_dt(m);
+}
+
+foap4_status foap4_step(foap4_mesh *m, int32_t n_steps, double *t_out, double *dt_out) {
+  if (!m || n_steps < 0) return fail(m, FOAP4_E_INVALID, "bad mesh or step count");
+  if (!m->pat_valid) return fail(m, FOAP4_E_ORDER, "no ghost pattern");
+  const bool f64 = m->d.prec == FOAP4_F64;
+  const int ndim = m->d.ndim;
+  const int64_t items = stage_items_for(ndim, m->d.block_n, (int64_t)m->topo.leaves.size(), 1);
+  foap4_status st;
+  if ((st = ensure_dt(m)) != FOAP4_OK) return st;
+  for (int32_t s = 0; s < n_steps; s++) {
+    if ((st = fill(m, m->d_dev, 0)) != FOAP4_OK) return st;
+    F4_HIP(m, launch_stage(m->d_dev, 1, items, 1, ndim, f64, 0, m->stream));
+    F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, 1, m->stream));
+    if ((st = fill(m, m->d_dev, 1)) != FOAP4_OK) return st;
+    F4_HIP(m, launch_stage(m->d_dev, 1, items, 2, ndim, f64, 0, m->stream));
+    F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, 2, m->stream));
+    F4_HIP(m, launch_finalize(m->d_dev, 1, 1, m->stream));
+  }
+  if (t_out || dt_out) return foap4_time(m, t_out, dt_out);
+  return FOAP4_OK;
+}
+
+foap4_status foap4_time(foap4_mesh *m, double *t_out, double *dt_out) {
+  if (!m) return fail(nullptr, FOAP4_E_INVALID, "null mesh");
+  double sc[kNScal];
+  F4_HIP(m, hipMemcpyAsync(sc, m->d_scal, sizeof(sc), hipMemcpyDeviceToHost, m->stream));
+  F4_HIP(m, hipStreamSynchronize(m->stream));
+  if (t_out) *t_out = sc[kTime];
+  if (dt_out) *dt_out = sc[kDt];
+  if (sc[kBad] != 0.0) return fail(m, FOAP4_E_UNPHYSICAL, "unphysical state (rho <= 0, p <= 0 or non-finite)");
+  return FOAP4_OK;
+}
+
+foap4_status foap4_conserved_totals(foap4_mesh *m, double *out) {
+  if (!m || !out) return fail(m, FOAP4_E_INVALID, "null argument");
+  const size_t nb = m->topo.leaves.size();
+  double *d_part = nullptr;
+  F4_HIP(m, hipMalloc((void **)&d_part, (nb * m->nvar + m->nvar) * 8));
+  hipError_t e = launch_totals(m, d_part, d_part + nb * m->nvar, m->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d_part + nb * m->nvar, m->nvar * 8, hipMemcpyDeviceToHost, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  (void)hipFree(d_part);
+  if (e != hipSuccess) return fail(m, FOAP4_E_HIP, std::string("totals: ") + hipGetErrorString(e));
+  return FOAP4_OK;
+}
+
+foap4_status foap4_refine_flags(foap4_mesh *m, foap4_indicator ind, int8_t *flags_host) {
+  if (!m || !flags_host) return fail(m, FOAP4_E_INVALID, "null argument");
+  if (ind != FOAP4_IND_LOHNER) return fail(m, FOAP4_E_INVALID, "indicator not available on this mesh");
+  const size_t nb = m->topo.leaves.size();
+  foap4_status st;
+  if ((st = fill(m, m->d_dev, 0)) != FOAP4_OK) return st;
+  int8_t *d_flags = nullptr;
+  F4_HIP(m, hipMalloc((void **)&d_flags, nb + 1));
+  hipError_t e = launch_lohner(m, d_flags, m->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(flags_host, d_flags, nb, hipMemcpyDeviceToHost, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  (void)hipFree(d_flags);
+  if (e != hipSuccess) return fail(m, FOAP4_E_HIP, std::string("lohner: ") + hipGetErrorString(e));
+  return FOAP4_OK;
+}
+
+foap4_status foap4_regrid(foap4_mesh *m, const int8_t *flags_host, int32_t *changed) {
+  if (!m) return fail(nullptr, FOAP4_E_INVALID, "null mesh");
+  if (changed) *changed = 0;
+  const size_t nb = m->topo.leaves.size();
+  std::vector<int8_t> fl(nb);
+  foap4_status st;
+  if (flags_host) {
+    std::memcpy(fl.data(), flags_host, nb);
+  } else if ((st = foap4_refine_flags(m, FOAP4_IND_LOHNER, fl.data())) != FOAP4_OK) {
+    return st;
+  }
+  std::vector<Leaf> nl;
+  std::vector<int32_t> op, src, arg;
+  if (!m->topo.regrid(fl.data(), m->d.min_level, m->d.max_level, nl, op, src, arg)) return FOAP4_OK;
+  if ((int64_t)nl.size() > m->d.max_blocks) return fail(m, FOAP4_E_CAPACITY, "regrid would exceed max_blocks");
+  // old ghosts feed the prolongation stencils
+  if ((st = fill(m, m->d_dev, 0)) != FOAP4_OK) return st;
+  std::vector<int32_t> map(3 * nl.size());
+  for (size_t i = 0; i < nl.size(); i++) {
+    map[3 * i] = op[i];
+    map[3 * i + 1] = src[i];
+    map[3 * i + 2] = arg[i];
+  }
+  int32_t *d_map = nullptr;
+  F4_HIP(m, hipMalloc((void **)&d_map, map.size() * 4 + 4));
+  hipError_t e = hipMemcpyAsync(d_map, map.data(), map.size() * 4, hipMemcpyHostToDevice, m->stream);
+  if (e == hipSuccess) e = launch_remap(m, m->state[m->cur], m->state[1 - m->cur], d_map, (int64_t)nl.size(), m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  (void)hipFree(d_map);
+  if (e != hipSuccess) return fail(m, FOAP4_E_HIP, std::string("remap: ") + hipGetErrorString(e));
+  m->cur = 1 - m->cur;
+  m->topo.leaves.swap(nl);
+  m->topo.sort_and_index();
+  m->revision++;
+  if ((st = upload_leaves(m)) != FOAP4_OK) return st;
+  if ((st = build_pattern(m)) != FOAP4_OK) return st;
+  if ((st = upload_dev(m)) != FOAP4_OK) return st;
+  m->dt_valid = false;
+  if (changed) *changed = 1;
+  return FOAP4_OK;
+}
+
+// -------------------------------------------------------------------- batch
+
+static foap4_status batch_fail(foap4_batch *b, foap4_status s, const std::string &msg) {
+  g_last_err = msg;
+  if (b) b->err = msg;
+  return s;
+}
+#define B_HIP(b, call)                                                                          \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess) return batch_fail((b), FOAP4_E_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+static void drop_graph(foap4_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_valid = false;
+}
+
+static foap4_status batch_upload(foap4_batch *b) {
+  std::vector<MeshDev> devs;
+  int64_t it = 0, r1 = 0, r2 = 0;
+  for (foap4_mesh *m : b->meshes) {
+    MeshDev d = make_dev(m, b->ks);
+    d.item_begin = it;
+    d.r1_begin = r1;
+    d.r2_begin = r2;
+    it += stage_items_for(b->ndim, m->d.block_n, d.nb, d.ks);
+    r1 += m->pat.n[kSRL] + m->pat.n[kF2C];
+    r2 += m->pat.n[kC2F];
+    devs.push_back(d);
+  }
+  b->total_items = it;
+  b->r1_total = r1;
+  b->r2_total = r2;
+  B_HIP(b, hipMemcpyAsync(b->d_devs, devs.data(), devs.size() * sizeof(MeshDev), hipMemcpyHostToDevice, b->stream));
+  B_HIP(b, hipStreamSynchronize(b->stream));
+  return FOAP4_OK;
+}
+
+// one Heun step of every mesh: 9 + 2 n_fix launches
+static hipError_t batch_enqueue_step(foap4_batch *b, hipStream_t s) {
+  const int n = (int)b->meshes.size();
+  const int grid = b->wg_per_cu > 0 ? b->wg_per_cu * b->n_cu : 0;
+  hipError_t e;
+  for (int stage = 1; stage <= 2; stage++) {
+    const int which = stage - 1;
+    if ((e = launch_ghost(b->d_devs, n, b->r1_total, 1, which, b->ndim, b->f64, 0, s)) != hipSuccess) return e;
+    if (b->r2_total && (e = launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s)) != hipSuccess)
+      return e;
+    if ((e = launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, grid, s)) != hipSuccess) return e;
+    for (int i = 0; i < n; i++)
+      if (b->meshes[i]->pat.n_fix > 0 &&
+          (e = launch_fluxfix(b->d_devs + i, b->ndim, b->f64, b->meshes[i]->pat.n_fix, stage, s)) != hipSuccess)
+        return e;
+  }
+  return launch_finalize(b->d_devs, n, 1, s);
+}
+
+static foap4_status batch_prepare(foap4_batch *b) {
+  bool stale = !b->graph_valid;
+  for (size_t i = 0; i < b->meshes.size(); i++)
+    if (b->meshes[i]->revision != b->revs[i]) stale = true;
+  for (foap4_mesh *m : b->meshes)
+    if (!m->dt_valid) {
+      foap4_status st = ensure_dt(m);
+      if (st != FOAP4_OK) return batch_fail(b, st, m->err);
+      B_HIP(b, hipStreamSynchronize(m->stream));
+    }
+  if (!stale) return FOAP4_OK;
+  drop_graph(b);
+  for (size_t i = 0; i < b->meshes.size(); i++) b->revs[i] = b->meshes[i]->revision;
+  foap4_status st = batch_upload(b);
+  if (st != FOAP4_OK) return st;
+  B_HIP(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = batch_enqueue_step(b, b->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return batch_fail(b, FOAP4_E_HIP, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  b->graph = g;
+  B_HIP(b, hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+  b->graph_valid = true;
+  return FOAP4_OK;
+}
+
+foap4_status foap4_batch_create(foap4_mesh *const *meshes, int32_t n, foap4_batch **out) {
+  if (!meshes || n < 1 || !out) return fail(nullptr, FOAP4_E_INVALID, "need at least one mesh");
+  *out = nullptr;
+  foap4_batch *b = new foap4_batch();
+  for (int i = 0; i < n; i++) {
+    if (!meshes[i]) {
+      delete b;
+      return fail(nullptr, FOAP4_E_INVALID, "null mesh in batch");
+    }
+    b->meshes.push_back(meshes[i]);
+    b->revs.push_back(-1);
+  }
+  b->ndim = meshes[0]->d.ndim;
+  b->f64 = meshes[0]->d.prec == FOAP4_F64;
+  for (foap4_mesh *m : b->meshes)
+    if (m->d.ndim != b->ndim || (m->d.prec == FOAP4_F64) != b->f64) {
+      delete b;
+      return fail(nullptr, FOAP4_E_INVALID, "batch meshes must share ndim and precision");
+    }
+  b->stream = meshes[0]->stream;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) b->n_cu = prop.multiProcessorCount;
+  if (hipMalloc((void **)&b->d_devs, sizeof(MeshDev) * n) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    foap4_batch_destroy(b);
+    return fail(nullptr, FOAP4_E_HIP, "batch allocation failed");
+  }
+  *out = b;
+  return FOAP4_OK;
+}
+
+foap4_status foap4_batch_destroy(foap4_batch *b) {
+  if (!b) return FOAP4_OK;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  if (b->d_devs) (void)hipFree(b->d_devs);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  delete b;
+  return FOAP4_OK;
+}
+
+foap4_status foap4_batch_set_config(foap4_batch *b, int32_t kslabs, int32_t wg_per_cu) {
+  if (!b || (kslabs != 1 && kslabs != 2 && kslabs != 4) || wg_per_cu < 0 || wg_per_cu > 64)
+    return batch_fail(b, FOAP4_E_INVALID, "kslabs must be 1, 2 or 4 and 0 <= wg_per_cu <= 64");
+  if (b->ks != kslabs || b->wg_per_cu != wg_per_cu) drop_graph(b);
+  b->ks = kslabs;
+  b->wg_per_cu = wg_per_cu;
+  return FOAP4_OK;
+}
+
+foap4_status foap4_batch_step(foap4_batch *b, int32_t n_steps) {
+  if (!b || n_steps < 0) return batch_fail(b, FOAP4_E_INVALID, "bad batch or step count");
+  for (foap4_mesh *m : b->meshes)
+    if (!m->pat_valid) return batch_fail(b, FOAP4_E_ORDER, "mesh without ghost pattern");
+  foap4_status st = batch_prepare(b);
+  if (st != FOAP4_OK) return st;
+  for (int32_t s = 0; s < n_steps; s++) B_HIP(b, hipGraphLaunch(b->exec, b->stream));
+  return FOAP4_OK;
+}
+
+// ------------------------------------------------------------- phase timing
+
+foap4_status foap4_batch_phase_times(foap4_batch *b, int32_t n_steps, double *out_ms) {
+  if (!b || n_steps < 1 || !out_ms) return batch_fail(b, FOAP4_E_INVALID, "bad arguments");
+  foap4_status st = batch_prepare(b);
+  if (st != FOAP4_OK) return st;
+  const int n = (int)b->meshes.size();
+  const int grid = b->wg_per_cu > 0 ? b->wg_per_cu * b->n_cu : 0;
+  hipStream_t s = b->stream;
+  // events: per step 2 x (R1, R2, stage, fix) + finalize = 9 intervals
+  const int per = 9;
+  std::vector<hipEvent_t> ev((size_t)n_steps * per + 1);
+  for (auto &e : ev) B_HIP(b, hipEventCreate(&e));
+  B_HIP(b, hipEventRecord(ev[0], s));
+  int k = 0;
+  for (int it = 0; it < n_steps; it++) {
+    for (int stage = 1; stage <= 2; stage++) {
+      const int which = stage - 1;
+      B_HIP(b, launch_ghost(b->d_devs, n, b->r1_total, 1, which, b->ndim, b->f64, 0, s));
+      B_HIP(b, hipEventRecord(ev[++k], s));
+      if (b->r2_total) B_HIP(b, launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s));
+      B_HIP(b, hipEventRecord(ev[++k], s));
+      B_HIP(b, launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, grid, s));
+      B_HIP(b, hipEventRecord(ev[++k], s));
+      for (int i = 0; i < n; i++)
+        if (b->meshes[i]->pat.n_fix > 0)
+          B_HIP(b, launch_fluxfix(b->d_devs + i, b->ndim, b->f64, b->meshes[i]->pat.n_fix, stage, s));
+      B_HIP(b, hipEventRecord(ev[++k], s));
+    }
+    B_HIP(b, launch_finalize(b->d_devs, n, 1, s));
+    B_HIP(b, hipEventRecord(ev[++k], s));
+  }
+  B_HIP(b, hipEventSynchronize(ev[k]));
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int it = 0; it < n_steps; it++) {
+    const int base = it * per;
+    float ms[9];
+    for (int j = 0; j < per; j++) B_HIP(b, hipEventElapsedTime(&ms[j], ev[base + j], ev[base + j + 1]));
+    acc[0] += ms[0] + ms[4];  // R1
+    acc[1] += ms[1] + ms[5];  // R2
+    acc[6] += ms[2];          // stage 1
+    acc[7] += ms[6];          // stage 2
+    acc[3] += ms[3] + ms[7];  // flux fix
+    acc[4] += ms[8];          // finalize
+    for (int j = 0; j < per; j++) acc[5] += ms[j];
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  out_ms[0] = acc[0] / (2.0 * n_steps);
+  out_ms[1] = acc[1] / (2.0 * n_steps);
+  out_ms[2] = (acc[6] + acc[7]) / (2.0 * n_steps);
+  out_ms[3] = acc[3] / n_steps;
+  out_ms[4] = acc[4] / n_steps;
+  out_ms[5] = acc[5] / n_steps;
+  out_ms[6] = acc[6] / n_steps;
+  out_ms[7] = acc[7] / n_steps;
+  return FOAP4_OK;
+}
+
+// ---------------------------------------------------------------- autotune
+
+static std::string batch_key(const foap4_batch *b) {
+  std::map<int, int64_t> mix;
+  int64_t total = 0;
+  for (foap4_mesh *m : b->meshes) {
+    mix[m->d.block_n] += (int64_t)m->topo.leaves.size();
+    total += (int64_t)m->topo.leaves.size();
+  }
+  char arch[64] = "gfx";
+  hipDeviceProp_t prop;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    std::snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+  for (char *c = arch; *c; c++)
+    if (*c == ':' || *c == '"') *c = '_';
+  std::ostringstream k;
+  k << arch << "|" << (b->f64 ? "f64" : "f32") << "|" << b->ndim << "d|meshes" << b->meshes.size();
+  for (auto &kv : mix) {
+    // block counts rounded to two significant digits so that nearby sizes share an entry
+    const double share = (double)kv.second / (double)std::max<int64_t>(total, 1);
+    k << "|N" << kv.first << ":" << (int)std::lround(share * 100.0);
+  }
+  const int mag = total > 0 ? (int)std::floor(std::log2((double)total)) : 0;
+  k << "|log2blocks" << mag;
+  return k.str();
+}
+
+static bool cache_lookup(const char *path, const std::string &key, int &ks, int &wg) {
+  if (!path) return false;
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t q0 = line.find('"'), q1 = line.find('"', q0 + 1);
+    if (q0 == std::string::npos || q1 == std::string::npos) continue;
+    if (line.substr(q0 + 1, q1 - q0 - 1) != key) continue;
+    int a = 0, c = 0;
+    if (std::sscanf(line.c_str() + q1 + 1, " : [%d , %d]", &a, &c) == 2 ||
+        std::sscanf(line.c_str() + q1 + 1, ": [%d, %d]", &a, &c) == 2) {
+      ks = a;
+      wg = c;
+      return true;
+    }
+  }
+  return false;
+}
+
+static void cache_store(const char *path, const std::string &key, int ks, int wg) {
+  if (!path) return;
+  std::vector<std::string> keep;
+  {
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+      const size_t q0 = line.find('"'), q1 = line.find('"', q0 + 1);
+      if (q0 == std::string::npos || q1 == std::string::npos) continue;
+      if (line.substr(q0 + 1, q1 - q0 - 1) == key) continue;
+      std::string l = line;
+      while (!l.empty() && (l.back() == ',' || l.back() == ' ')) l.pop_back();
+      keep.push_back(l);
+    }
+  }
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d]", key.c_str(), ks, wg);
+  keep.push_back(buf);
+  std::ofstream o(path);
+  o << "{\n";
+  for (size_t i = 0; i < keep.size(); i++) o << keep[i] << (i + 1 < keep.size() ? ",\n" : "\n");
+  o << "}\n";
+}
+
+foap4_status foap4_batch_autotune(foap4_batch *b, const char *cache_path, int32_t *ks_out, int32_t *wg_out) {
+  if (!b) return batch_fail(nullptr, FOAP4_E_INVALID, "null batch");
+  const std::string key = batch_key(b);
+  int ks = 1, wg = 0;
+  if (cache_lookup(cache_path, key, ks, wg)) {
+    foap4_status st = foap4_batch_set_config(b, ks, wg);
+    if (ks_out) *ks_out = ks;
+    if (wg_out) *wg_out = wg;
+    return st;
+  }
+  // save the current states and scalars; restored after timing
+  std::vector<void *> saved;
+  std::vector<std::array<double, kNScal>> scal(b->meshes.size());
+  for (size_t i = 0; i < b->meshes.size(); i++) {
+    foap4_mesh *m = b->meshes[i];
+    void *p = nullptr;
+    const size_t bytes = m->topo.leaves.size() * m->block_elems * m->elem;
+    B_HIP(b, hipMalloc(&p, bytes + 16));
+    saved.push_back(p);
+    B_HIP(b, hipMemcpyAsync(p, m->state[m->cur], bytes, hipMemcpyDeviceToDevice, b->stream));
+    B_HIP(b, hipMemcpyAsync(scal[i].data(), m->d_scal, kNScal * 8, hipMemcpyDeviceToHost, b->stream));
+  }
+  B_HIP(b, hipStreamSynchronize(b->stream));
+  auto restore = [&]() -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < b->meshes.size() && e == hipSuccess; i++) {
+      foap4_mesh *m = b->meshes[i];
+      const size_t bytes = m->topo.leaves.size() * m->block_elems * m->elem;
+      e = hipMemcpyAsync(m->state[m->cur], saved[i], bytes, hipMemcpyDeviceToDevice, b->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(m->d_scal, scal[i].data(), kNScal * 8, hipMemcpyHostToDevice, b->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    return e;
+  };
+  const int ks_cand[3] = {1, 2, 4};
+  const int wg_cand[5] = {0, 2, 4, 6, 8};
+  int max_ks = 1;
+  for (foap4_mesh *m : b->meshes) max_ks = std::max(max_ks, m->d.block_n / 8);
+  if (b->ndim == 2) max_ks = 1;
+  float best = 1e30f;
+  int best_ks = 1, best_wg = 0;
+  hipEvent_t e0, e1;
+  B_HIP(b, hipEventCreate(&e0));
+  B_HIP(b, hipEventCreate(&e1));
+  foap4_status result = FOAP4_OK;
+  for (int a = 0; a < 3 && result == FOAP4_OK; a++) {
+    if (ks_cand[a] > max_ks) continue;
+    for (int c = 0; c < 5 && result == FOAP4_OK; c++) {
+      if ((result = foap4_batch_set_config(b, ks_cand[a], wg_cand[c])) != FOAP4_OK) break;
+      if ((result = foap4_batch_step(b, 2)) != FOAP4_OK) break;  // capture + warm-up
+      if (hipEventRecord(e0, b->stream) != hipSuccess) { result = FOAP4_E_HIP; break; }
+      if ((result = foap4_batch_step(b, 4)) != FOAP4_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        result = FOAP4_E_HIP;
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        best_ks = ks_cand[a];
+        best_wg = wg_cand[c];
+      }
+      if (restore() != hipSuccess) { result = FOAP4_E_HIP; break; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const hipError_t re = restore();
+  for (void *p : saved) (void)hipFree(p);
+  if (result != FOAP4_OK) return result;
+  if (re != hipSuccess) return batch_fail(b, FOAP4_E_HIP, "autotune restore failed");
+  cache_store(cache_path, key, best_ks, best_wg);
+  if (ks_out) *ks_out = best_ks;
+  if (wg_out) *wg_out = best_wg;
+  return foap4_batch_set_config(b, best_ks, best_wg);
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Device-side physics and limiter helpers shared by the library's kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace f4 {
+
+// Generalized minmod G(a, b, theta = 1) (eq. gminmod): zero unless a and b
+// have the same strict sign, else the one of smaller magnitude.
+template <typename T>
+__device__ __forceinline__ T minmod(T a, T b) {
+  if (a > T(0) && b > T(0)) return a < b ? a : b;
+  if (a < T(0) && b < T(0)) return a > b ? a : b;
+  return T(0);
+}
+
+// Primitive state (rho, v[0..NDIM-1], p) packed as NV = NDIM + 2 values.
+// Conservative -> primitive (Sec. 3.5): v = m / rho, p = (gamma-1)(E - m.v/2).
+template <typename T, int NDIM>
+__device__ __forceinline__ void to_prim(const T *U, T gamma, T *W) {
+  const T r = U[0];
+  const T ir = T(1) / r;
+  T ke = T(0);
+  W[0] = r;
+#pragma unroll
+  for (int d = 0; d < NDIM; d++) {
+    const T v = U[1 + d] * ir;
+    W[1 + d] = v;
+    ke += U[1 + d] * v;
+  }
+  W[NDIM + 1] = (gamma - T(1)) * (U[NDIM + 1] - T(0.5) * ke);
+}
+
+// Rusanov flux (Sec. 3.2) along axis AX between reconstructed primitive
+// states WL and WR, with the largest Einfeldt wave speed (Sec. 3.5):
+// sqrt(rho)-weighted mean velocity u_bar and
+// d_bar^2 = (sL cL^2 + sR cR^2)/(sL + sR) + sL sR/(2 (sL+sR)^2) (vR - vL)^2;
+// a = max(|u_bar - d_bar|, |u_bar + d_bar|), F = (FL+FR)/2 - a (UR-UL)/2.
+template <typename T, int NDIM, int AX>
+__device__ __forceinline__ void rusanov(const T *WL, const T *WR, T gamma, T *F) {
+  constexpr int NV = NDIM + 2;
+  const T rl = WL[0], rr = WR[0];
+  const T pl = WL[NV - 1], pr = WR[NV - 1];
+  const T vl = WL[1 + AX], vr = WR[1 + AX];
+  const T igm1 = T(1) / (gamma - T(1));
+  T UL[NV], UR[NV], FL[NV], FR[NV];
+  T kel = T(0), ker = T(0);
+  UL[0] = rl;
+  UR[0] = rr;
+  FL[0] = rl * vl;
+  FR[0] = rr * vr;
+#pragma unroll
+  for (int d = 0; d < NDIM; d++) {
+    const T ml = rl * WL[1 + d], mr = rr * WR[1 + d];
+    UL[1 + d] = ml;
+    UR[1 + d] = mr;
+    FL[1 + d] = ml * vl + (d == AX ? pl : T(0));
+    FR[1 + d] = mr * vr + (d == AX ? pr : T(0));
+    kel += ml * WL[1 + d];
+    ker += mr * WR[1 + d];
+  }
+  const T El = pl * igm1 + T(0.5) * kel;
+  const T Er = pr * igm1 + T(0.5) * ker;
+  UL[NV - 1] = El;
+  UR[NV - 1] = Er;
+  FL[NV - 1] = (El + pl) * vl;
+  FR[NV - 1] = (Er + pr) * vr;
+  const T sl = sqrt(rl), sr = sqrt(rr);
+  const T is = T(1) / (sl + sr);
+  const T cl2 = gamma * pl / rl, cr2 = gamma * pr / rr;
+  const T ubar = (sl * vl + sr * vr) * is;
+  const T eta2 = T(0.5) * sl * sr * is * is;
+  const T dv = vr - vl;
+  const T d2 = (sl * cl2 + sr * cr2) * is + eta2 * dv * dv;
+  const T db = sqrt(d2);
+  const T lm = fabs(ubar - db), lp = fabs(ubar + db);
+  const T a = lm > lp ? lm : lp;
+#pragma unroll
+  for (int v = 0; v < NV; v++) F[v] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * a * (UR[v] - UL[v]);
+}
+
+// Face flux from four primitive states along the face normal: minmod-limited
+// linear reconstruction (Sec. 3.2) W_L = W1 + s1/2, W_R = W2 - s2/2.
+template <typename T, int NDIM, int AX>
+__device__ __forceinline__ void face_flux(const T *W0, const T *W1, const T *W2, const T *W3, T gamma,
+                                          T *F) {
+  constexpr int NV = NDIM + 2;
+  T L[NV], R[NV];
+#pragma unroll
+  for (int v = 0; v < NV; v++) {
+    const T s1 = minmod(W1[v] - W0[v], W2[v] - W1[v]);
+    const T s2 = minmod(W2[v] - W1[v], W3[v] - W2[v]);
+    L[v] = W1[v] + T(0.5) * s1;
+    R[v] = W2[v] - T(0.5) * s2;
+  }
+  rusanov<T, NDIM, AX>(L, R, gamma, F);
+}
+
+// Atomic max of a non-negative double through its bit pattern (IEEE order of
+// non-negative doubles equals the order of their bit patterns).
+__device__ __forceinline__ void atomic_max_pos(double *addr, double v) {
+  atomicMax(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+}  // namespace f4

@@ -1,0 +1,153 @@
+// Internal declarations of the foap4 MI355X library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "foap4.h"
+
+namespace f4 {
+
+constexpr int kMaxLevel = 14;     // finest level accepted in a descriptor
+constexpr int kKeyLevel = 16;     // Morton key resolution per tree
+constexpr int kTypes = 4;         // SRL, F2C, C2F, BC
+enum { kSRL = 0, kF2C = 1, kC2F = 2, kBC = 3 };
+
+// scal[] slots of a mesh (FP64, device)
+enum { kDt = 0, kTime = 1, kMaxInv = 2, kBad = 3, kNScal = 8 };
+
+struct Leaf {
+  int32_t level;
+  int32_t g[3];  // global integer coordinates at `level` (tree * 2^level + anchor)
+};
+
+struct LeafHash {
+  size_t operator()(const std::array<int32_t, 4> &k) const {
+    uint64_t h = 1469598103934665603ull;
+    for (int32_t v : k) { h ^= (uint32_t)v; h *= 1099511628211ull; }
+    return (size_t)h;
+  }
+};
+
+// Host-side forest of trees: leaf table, lookup, regrid (refine, 2:1 corner
+// balance, coarsen) and the old -> new remap lists.
+class Topology {
+ public:
+  int ndim = 3;
+  int nt[3] = {1, 1, 1};
+  std::vector<Leaf> leaves;
+
+  void init_uniform(int ndim_, const int32_t nt_[3], int level);
+  uint64_t key(const Leaf &l) const;
+  int32_t tree_id(const Leaf &l) const;
+  void sort_and_index();
+  int64_t find(int32_t level, const int32_t g[3]) const;
+  // Returns false (and leaves the mesh unchanged) when nothing changes.
+  // On success fills op/src/arg for every new block (0 copy, 1 prolong child
+  // arg of old src, 2 restrict old children src..src+2^d-1).
+  bool regrid(const int8_t *flags, int lmin, int lmax, std::vector<Leaf> &out,
+              std::vector<int32_t> &op, std::vector<int32_t> &src, std::vector<int32_t> &arg) const;
+
+ private:
+  std::unordered_map<std::array<int32_t, 4>, int64_t, LeafHash> index_;
+};
+
+// Device descriptor of one mesh as the kernels see it (copied to the device).
+struct MeshDev {
+  void *s[2];                 // state buffers
+  const int32_t *level;       // [nb]
+  const int32_t *face_info;   // [nb][2*ndim]: -1, or 2*slot (fine-side flux) / 2*slot+1 (coarse side)
+  const int32_t *srl, *f2c, *c2f, *fix_list;  // ghost pattern records
+  void *bflux_f;              // fine-side face fluxes [n_c2f][nvar][N^(d-1)]
+  void *bflux_c;              // coarse-side face fluxes [n_f2c/2^(d-1)][nvar][N^(d-1)]
+  double *scal;               // kDt, kTime, kMaxInv, kBad ...
+  int64_t nb;
+  int64_t item_begin;         // first stage work item of this mesh in its launch
+  int64_t r1_begin, r2_begin; // first ghost record of this mesh in R1 / R2 launches
+  double dx0;                 // cell width at level 0
+  double gamma, cfl;
+  int32_t pn[4];              // record totals per type
+  int32_t poff[4][7];         // CSR offsets per type and face
+  int32_t n_fix;
+  int32_t cur;                // current state buffer
+  int32_t N, g, ks;           // block size, ghost layers, k-slabs per tile
+};
+
+struct Pattern {
+  int32_t off[kTypes][7] = {};  // CSR offsets per face (host copy)
+  int32_t n[kTypes] = {};       // totals
+  int32_t n_fix = 0;            // coarse blocks with at least one F2C face
+  int32_t *srl = nullptr, *f2c = nullptr, *c2f = nullptr, *bc = nullptr;
+  int32_t *face_info = nullptr, *fix_list = nullptr;
+  int32_t *cnt = nullptr;       // classification and scan workspace
+  int32_t *tot = nullptr;       // row totals + error flag (device)
+  void *bflux_f = nullptr, *bflux_c = nullptr;
+  size_t cap[8] = {};           // capacities in bytes of the buffers above
+  size_t cap_bflux[2] = {};
+};
+
+}  // namespace f4
+
+struct foap4_mesh {
+  foap4_mesh_desc d{};
+  int nvar = 0, P = 0, nf = 0;
+  size_t elem = 0;             // bytes per value
+  int64_t block_elems = 0;     // nvar * P^ndim
+  void *state[2] = {nullptr, nullptr};
+  size_t state_bytes = 0;
+  hipStream_t stream = nullptr;
+  int32_t cur = 0;
+  f4::Topology topo;
+  int64_t revision = 0;
+  // device copies of the leaf table
+  int32_t *d_level = nullptr, *d_gc = nullptr;
+  uint64_t *d_keys = nullptr;
+  size_t cap_blocks = 0;
+  f4::Pattern pat;
+  bool pat_valid = false;
+  double *d_scal = nullptr;
+  bool dt_valid = false;
+  f4::MeshDev *d_dev = nullptr;  // single-mesh descriptor for the plain path
+  int64_t *d_item_begin = nullptr;
+  std::string err;
+};
+
+namespace f4 {
+
+// error helpers
+foap4_status fail(foap4_mesh *m, foap4_status s, const std::string &msg);
+#define F4_HIP(m, call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return ::f4::fail((m), FOAP4_E_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+MeshDev make_dev(const foap4_mesh *m, int ks);
+foap4_status upload_dev(foap4_mesh *m);
+
+// pattern.hip
+foap4_status build_pattern(foap4_mesh *m);
+// ghost.hip: round 1 = SRL + F2C, round 2 = C2F; which 0 = current state, 1 = other
+hipError_t launch_ghost(const MeshDev *d_meshes, int n_meshes, int64_t total, int round, int which,
+                        int ndim, bool f64, int grid, hipStream_t s);
+// stage.hip
+int64_t stage_items_for(int ndim, int N, int64_t nb, int ks);
+hipError_t launch_stage(const MeshDev *d_meshes, int n_meshes, int64_t total_items, int stage,
+                        int ndim, bool f64, int grid, hipStream_t s);
+// reduce.hip
+hipError_t launch_dt_full(const foap4_mesh *m, hipStream_t s);
+hipError_t launch_finalize(const MeshDev *d_meshes, int n_meshes, int advance, hipStream_t s);
+hipError_t launch_fluxfix(const MeshDev *d_mesh, int ndim, bool f64, int n_fix, int stage, hipStream_t s);
+hipError_t launch_totals(const foap4_mesh *m, double *d_part, double *d_out, hipStream_t s);
+// regrid.hip
+hipError_t launch_lohner(const foap4_mesh *m, int8_t *d_flags, hipStream_t s);
+hipError_t launch_remap(const foap4_mesh *m, const void *src_state, void *dst_state,
+                        const int32_t *d_map, int64_t nb_new, hipStream_t s);
+
+}  // namespace f4

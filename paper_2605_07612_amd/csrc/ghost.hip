@@ -1,0 +1,251 @@
+// Execution of the stored ghost pattern (Sec. 2.6), one workgroup per record.
+//   round R1: SRL records (copy g layers both ways across a face pair) and
+//             F2C records (coarse ghost = mean of the 2^d fine cells, FP64)
+//   round R2: C2F records (fine ghost = limited prolongation from the coarse
+//             block, FP64 slopes; reads the coarse block's R1 ghosts)
+// Work items of several meshes are concatenated (r1_begin / r2_begin).
+#include "foap4_internal.h"
+
+namespace f4 {
+
+template <int NDIM>
+struct Geo {
+  int g, P;
+  int64_t sv;  // values per variable
+  __device__ Geo(int N, int g_) : g(g_), P(N + 2 * g_), sv(NDIM == 3 ? (int64_t)(N + 2 * g_) * (N + 2 * g_) * (N + 2 * g_)
+                                                               : (int64_t)(N + 2 * g_) * (N + 2 * g_)) {}
+  __device__ __forceinline__ int64_t at(const int c[3]) const {
+    return (NDIM == 3 ? (int64_t)(c[2] + g) * P * P : 0) + (int64_t)(c[1] + g) * P + (c[0] + g);
+  }
+};
+
+__device__ __forceinline__ void tangential(int ndim, int ax, int &t1, int &t2) {
+  t1 = (ax == 0) ? 1 : 0;
+  t2 = (ndim == 3) ? ((ax == 2) ? 1 : 2) : -1;
+}
+
+__device__ __forceinline__ double mm(double a, double b) {
+  if (a > 0.0 && b > 0.0) return a < b ? a : b;
+  if (a < 0.0 && b < 0.0) return a > b ? a : b;
+  return 0.0;
+}
+
+template <typename T, int NDIM, int N>
+__device__ void srl_record(const MeshDev &M, T *u, int ax, int32_t a, int32_t b) {
+  constexpr int NV = NDIM + 2;
+  constexpr int N2 = (NDIM == 3) ? N : 1;
+  const Geo<NDIM> G(N, M.g);
+  const int g = M.g;
+  int t1, t2;
+  tangential(NDIM, ax, t1, t2);
+  const int64_t bel = G.sv * NV;
+  const int total = 2 * NV * N2 * N * g;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int l, p1, p2, v, side, r = e;
+    if (ax == 0) {  // layers are contiguous in memory: layer fastest
+      l = r % g; r /= g;
+      p1 = r % N; r /= N;
+    } else {        // rows along x are contiguous: t1 (= x) fastest
+      p1 = r % N; r /= N;
+      l = r % g; r /= g;
+    }
+    p2 = r % N2; r /= N2;
+    v = r % NV; side = r / NV;
+    int src[3] = {0, 0, 0}, dst[3] = {0, 0, 0};
+    src[t1] = dst[t1] = p1;
+    if (t2 >= 0) src[t2] = dst[t2] = p2;
+    int64_t sb, db;
+    if (side == 0) {  // b's -ax ghosts from a's last layers
+      src[ax] = N - 1 - l; dst[ax] = -1 - l; sb = a; db = b;
+    } else {          // a's +ax ghosts from b's first layers
+      src[ax] = l; dst[ax] = N + l; sb = b; db = a;
+    }
+    u[db * bel + v * G.sv + G.at(dst)] = u[sb * bel + v * G.sv + G.at(src)];
+  }
+}
+
+// mean of the 2^d fine cells base + {0,1}^d of block q, summed in pairs
+// along x, then y, then z, in FP64
+template <typename T, int NDIM>
+__device__ __forceinline__ double fine_mean(const T *uq, const Geo<NDIM> &G, const int base[3]) {
+  int c[3] = {base[0], base[1], base[2]};
+  if (NDIM == 2) {
+    const double f00 = uq[G.at(c)];
+    c[0]++; const double f10 = uq[G.at(c)];
+    c[1]++; const double f11 = uq[G.at(c)];
+    c[0]--; const double f01 = uq[G.at(c)];
+    return ((f00 + f10) + (f01 + f11)) * 0.25;
+  } else {
+    double f[2][2][2];
+#pragma unroll
+    for (int oz = 0; oz < 2; oz++)
+#pragma unroll
+      for (int oy = 0; oy < 2; oy++)
+#pragma unroll
+        for (int ox = 0; ox < 2; ox++) {
+          const int cc[3] = {base[0] + ox, base[1] + oy, base[2] + oz};
+          f[oz][oy][ox] = uq[G.at(cc)];
+        }
+    const double a0 = f[0][0][0] + f[0][0][1], a1 = f[0][1][0] + f[0][1][1];
+    const double a2 = f[1][0][0] + f[1][0][1], a3 = f[1][1][0] + f[1][1][1];
+    return ((a0 + a1) + (a2 + a3)) * 0.125;
+  }
+}
+
+template <typename T, int NDIM, int N>
+__device__ void f2c_record(const MeshDev &M, T *u, int f, int32_t cb, int32_t q, int32_t h) {
+  constexpr int NV = NDIM + 2;
+  constexpr int H = N / 2;
+  constexpr int H2 = (NDIM == 3) ? H : 1;
+  const Geo<NDIM> G(N, M.g);
+  const int g = M.g, ax = f / 2, side = f % 2;
+  int t1, t2;
+  tangential(NDIM, ax, t1, t2);
+  const int bt1 = h & 1, bt2 = (h >> 1) & 1;
+  const int64_t bel = G.sv * NV;
+  const int total = NV * H2 * H * g;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int l, p1, p2, v, r = e;
+    if (ax == 0) {
+      l = r % g; r /= g;
+      p1 = r % H; r /= H;
+    } else {
+      p1 = r % H; r /= H;
+      l = r % g; r /= g;
+    }
+    p2 = r % H2; v = r / H2;
+    const int L = l + 1;
+    int cc[3] = {0, 0, 0}, base[3] = {0, 0, 0};
+    cc[ax] = side ? N - 1 + L : -L;
+    base[ax] = side ? 2 * (L - 1) : N - 2 * L;
+    cc[t1] = bt1 * H + p1;
+    base[t1] = 2 * p1;
+    if (t2 >= 0) {
+      cc[t2] = bt2 * H + p2;
+      base[t2] = 2 * p2;
+    }
+    const double mean = fine_mean<T, NDIM>(u + (int64_t)q * bel + v * G.sv, G, base);
+    u[(int64_t)cb * bel + v * G.sv + G.at(cc)] = (T)mean;
+  }
+}
+
+// limited prolongation (Sec. 2.2) of coarse cell P of block data uc for the
+// child whose position is sig (+-1 per axis); slopes and sum in FP64, axes
+// summed in order x, y, z
+template <typename T, int NDIM>
+__device__ __forceinline__ double prolong(const T *uc, const Geo<NDIM> &G, const int P[3], const int sig[3]) {
+  const double up = uc[G.at(P)];
+  double corr = 0.0;
+#pragma unroll
+  for (int d = 0; d < NDIM; d++) {
+    int lo[3] = {P[0], P[1], P[2]}, hi[3] = {P[0], P[1], P[2]};
+    lo[d] -= 1;
+    hi[d] += 1;
+    const double delta = mm(up - (double)uc[G.at(lo)], (double)uc[G.at(hi)] - up);
+    const double term = sig[d] > 0 ? delta : -delta;
+    corr = (d == 0) ? term : corr + term;
+  }
+  return up + 0.25 * corr;
+}
+
+template <typename T, int NDIM, int N>
+__device__ void c2f_record(const MeshDev &M, T *u, int f, int32_t q, int32_t cb, int32_t h) {
+  constexpr int NV = NDIM + 2;
+  constexpr int N2 = (NDIM == 3) ? N : 1;
+  constexpr int H = N / 2;
+  const Geo<NDIM> G(N, M.g);
+  const int g = M.g, ax = f / 2, side = f % 2;
+  int t1, t2;
+  tangential(NDIM, ax, t1, t2);
+  const int bt1 = h & 1, bt2 = (h >> 1) & 1;
+  const int64_t bel = G.sv * NV;
+  const int total = NV * N2 * N * g;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int l, p1, p2, v, r = e;
+    if (ax == 0) {
+      l = r % g; r /= g;
+      p1 = r % N; r /= N;
+    } else {
+      p1 = r % N; r /= N;
+      l = r % g; r /= g;
+    }
+    p2 = r % N2; v = r / N2;
+    const int L = l + 1;
+    int fc[3] = {0, 0, 0}, P[3] = {0, 0, 0}, sig[3] = {0, 0, 0};
+    fc[ax] = side ? N - 1 + L : -L;
+    const int fn = side ? (L - 1) : (2 * N - L);
+    P[ax] = fn >> 1;
+    sig[ax] = (fn & 1) ? 1 : -1;
+    fc[t1] = p1;
+    P[t1] = bt1 * H + (p1 >> 1);
+    sig[t1] = (p1 & 1) ? 1 : -1;
+    if (t2 >= 0) {
+      fc[t2] = p2;
+      P[t2] = bt2 * H + (p2 >> 1);
+      sig[t2] = (p2 & 1) ? 1 : -1;
+    }
+    const double val = prolong<T, NDIM>(u + (int64_t)cb * bel + v * G.sv, G, P, sig);
+    u[(int64_t)q * bel + v * G.sv + G.at(fc)] = (T)val;
+  }
+}
+
+template <typename T, int NDIM, int N>
+__device__ void ghost_item(const MeshDev &M, int round, int64_t r, int which) {
+  T *u = (T *)M.s[which == 0 ? M.cur : 1 - M.cur];
+  if (round == 1) {
+    if (r < M.pn[kSRL]) {
+      int f = 1;
+      while (r >= M.poff[kSRL][f + 1]) f += 2;
+      srl_record<T, NDIM, N>(M, u, f / 2, M.srl[2 * r], M.srl[2 * r + 1]);
+    } else {
+      r -= M.pn[kSRL];
+      int f = 0;
+      while (r >= M.poff[kF2C][f + 1]) f++;
+      f2c_record<T, NDIM, N>(M, u, f, M.f2c[4 * r], M.f2c[4 * r + 1], M.f2c[4 * r + 2]);
+    }
+  } else {
+    int f = 0;
+    while (r >= M.poff[kC2F][f + 1]) f++;
+    c2f_record<T, NDIM, N>(M, u, f, M.c2f[3 * r], M.c2f[3 * r + 1], M.c2f[3 * r + 2]);
+  }
+}
+
+template <typename T, int NDIM>
+__global__ __launch_bounds__(256) void ghost_kernel(const MeshDev *__restrict__ meshes, int n_meshes,
+                                                    int64_t total, int round, int which) {
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    int lo = 0, hi = n_meshes - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      const int64_t b = round == 1 ? meshes[mid].r1_begin : meshes[mid].r2_begin;
+      if (b <= item) lo = mid; else hi = mid - 1;
+    }
+    const MeshDev &M = meshes[lo];
+    const int64_t r = item - (round == 1 ? M.r1_begin : M.r2_begin);
+    switch (M.N) {
+      case 8: ghost_item<T, NDIM, 8>(M, round, r, which); break;
+      case 16: ghost_item<T, NDIM, 16>(M, round, r, which); break;
+      default: ghost_item<T, NDIM, 32>(M, round, r, which); break;
+    }
+  }
+}
+
+hipError_t launch_ghost(const MeshDev *d_meshes, int n_meshes, int64_t total, int round, int which,
+                        int ndim, bool f64, int grid, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  const unsigned nblk = (unsigned)((grid > 0 && grid < total) ? grid : total);
+  if (f64) {
+    if (ndim == 3)
+      ghost_kernel<double, 3><<<nblk, 256, 0, s>>>(d_meshes, n_meshes, total, round, which);
+    else
+      ghost_kernel<double, 2><<<nblk, 256, 0, s>>>(d_meshes, n_meshes, total, round, which);
+  } else {
+    if (ndim == 3)
+      ghost_kernel<float, 3><<<nblk, 256, 0, s>>>(d_meshes, n_meshes, total, round, which);
+    else
+      ghost_kernel<float, 2><<<nblk, 256, 0, s>>>(d_meshes, n_meshes, total, round, which);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace f4

@@ -1,0 +1,251 @@
+// FP64 reductions and flux fixing: CFL time step, step finalisation,
+// conserved totals, and the flux correction at refinement boundaries
+// (Sec. 2.7).
+#include "device_common.h"
+#include "foap4_internal.h"
+
+namespace f4 {
+
+// sum_d (|v_d| + c) / dx of one cell in FP64, operation order of the
+// definition, no contraction (bit-identical to a plain evaluation).
+template <int NDIM>
+__device__ __forceinline__ double inv_dt_cell(const double *U, double gamma, double dx, bool &bad) {
+#pragma clang fp contract(off)
+  const double r = U[0];
+  double ke = 0.0, v[3];
+#pragma unroll
+  for (int d = 0; d < NDIM; d++) {
+    v[d] = U[1 + d] / r;
+    ke += U[1 + d] * v[d];
+  }
+  const double p = (gamma - 1.0) * (U[NDIM + 1] - 0.5 * ke);
+  const double cs = sqrt(gamma * p / r);
+  double s = 0.0;
+#pragma unroll
+  for (int d = 0; d < NDIM; d++) s += (fabs(v[d]) + cs) / dx;
+  bad |= !(r > 0.0) || !(p > 0.0) || !isfinite(s);
+  return s;
+}
+
+__device__ __forceinline__ void wave_flush(double *scal, double vmax, bool bad) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
+  const bool anybad = __ballot(bad) != 0;
+  if ((threadIdx.x & 63) == 0) {
+    if (vmax > 0.0) atomic_max_pos(&scal[kMaxInv], vmax);
+    if (anybad) atomic_max_pos(&scal[kBad], 1.0);
+  }
+}
+
+// CFL limit of every interior cell of the current state (one workgroup per block)
+template <typename T, int NDIM>
+__global__ __launch_bounds__(256) void dt_full_kernel(const MeshDev *__restrict__ Mp) {
+  const MeshDev &M = *Mp;
+  constexpr int NV = NDIM + 2;
+  const int64_t b = blockIdx.x;
+  const int N = M.N, g = M.g, P = N + 2 * g;
+  const int64_t sv = (NDIM == 3) ? (int64_t)P * P * P : (int64_t)P * P;
+  const T *u = (const T *)M.s[M.cur] + b * sv * NV;
+  const double dx = ldexp(M.dx0, -M.level[b]);
+  const int cells = (NDIM == 3) ? N * N * N : N * N;
+  double vmax = 0.0;
+  bool bad = false;
+  for (int c = threadIdx.x; c < cells; c += blockDim.x) {
+    const int i = c % N, j = (c / N) % N, k = (NDIM == 3) ? c / (N * N) : 0;
+    const int64_t o = (NDIM == 3 ? (int64_t)(k + g) * P * P : 0) + (int64_t)(j + g) * P + (i + g);
+    double U[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) U[v] = (double)u[v * sv + o];
+    vmax = fmax(vmax, inv_dt_cell<NDIM>(U, M.gamma, dx, bad));
+  }
+  wave_flush(M.scal, vmax, bad);
+}
+
+// dt_next = cfl / max_cells(inv dt); advance: t += dt (of the finished step)
+__global__ void finalize_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int advance) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_meshes) return;
+  double *sc = meshes[m].scal;
+  const double mx = sc[kMaxInv];
+  const double next = mx > 0.0 ? meshes[m].cfl * (1.0 / mx) : 0.0;
+  if (advance) sc[kTime] += sc[kDt];
+  sc[kDt] = next;
+  sc[kMaxInv] = 0.0;
+}
+
+// Flux fixing (Sec. 2.7): one workgroup per coarse block with F2C faces.
+// Faces are applied in face order; each coarse face cell is corrected by
+// dt_s (F_c - <F_f>) / dx on a + face, dt_s (<F_f> - F_c) / dx on a - face,
+// with <F_f> the FP64 pairwise mean of the 2^(d-1) fine fluxes.  In stage 2
+// the CFL limit of the corrected cells is then added to the reduction.
+template <typename T, int NDIM>
+__global__ __launch_bounds__(256) void fluxfix_kernel(const MeshDev *__restrict__ Mp, int stage) {
+  const MeshDev &M = *Mp;
+  constexpr int NV = NDIM + 2;
+  constexpr int NF = 2 * NDIM;
+  constexpr int PER = 1 << (NDIM - 1);
+  const int32_t cb = M.fix_list[blockIdx.x];
+  const int N = M.N, H = N / 2, g = M.g, P = N + 2 * g;
+  const int64_t sv = (NDIM == 3) ? (int64_t)P * P * P : (int64_t)P * P;
+  T *uo = (T *)M.s[stage == 1 ? 1 - M.cur : M.cur] + (int64_t)cb * sv * NV;
+  const double dx = ldexp(M.dx0, -M.level[cb]);
+  const double dts = stage == 1 ? M.scal[kDt] : 0.5 * M.scal[kDt];
+  const int N2 = (NDIM == 3) ? N : 1;
+  const int64_t fv = (int64_t)N * N2;  // face values per variable
+  const T *bf = (const T *)M.bflux_f;
+  const T *bc = (const T *)M.bflux_c;
+  for (int f = 0; f < NF; f++) {
+    const int info = M.face_info[(int64_t)cb * NF + f];
+    if (info < 0 || !(info & 1)) continue;
+    const int ax = f / 2, side = f % 2;
+    const int t1 = (ax == 0) ? 1 : 0, t2 = (NDIM == 3) ? ((ax == 2) ? 1 : 2) : -1;
+    const int64_t grp = info >> 1;
+    for (int e = threadIdx.x; e < NV * fv; e += blockDim.x) {
+      const int p1 = e % N, p2 = (e / N) % N2, v = e / (int)fv;
+      const int bt1 = p1 >= H, bt2 = (NDIM == 3) ? (p2 >= H) : 0;
+      const int h = bt1 + 2 * bt2;
+      const int32_t kf = M.f2c[4 * (grp * PER + h) + 3];
+      const double Fc = (double)bc[(grp * NV + v) * fv + (int64_t)p2 * N + p1];
+      const int q1 = 2 * (p1 - bt1 * H), q2 = (NDIM == 3) ? 2 * (p2 - bt2 * H) : 0;
+      const T *ff = bf + ((int64_t)kf * NV + v) * fv;
+      double mean;
+      if (NDIM == 3) {
+        const double s0 = (double)ff[(int64_t)q2 * N + q1] + (double)ff[(int64_t)q2 * N + q1 + 1];
+        const double s1 = (double)ff[(int64_t)(q2 + 1) * N + q1] + (double)ff[(int64_t)(q2 + 1) * N + q1 + 1];
+        mean = (s0 + s1) * 0.25;
+      } else {
+        mean = ((double)ff[q1] + (double)ff[q1 + 1]) * 0.5;
+      }
+      int c[3] = {0, 0, 0};
+      c[ax] = side ? N - 1 : 0;
+      c[t1] = p1;
+      if (t2 >= 0) c[t2] = p2;
+      const int64_t o = (int64_t)v * sv + (NDIM == 3 ? (int64_t)(c[2] + g) * P * P : 0) +
+                        (int64_t)(c[1] + g) * P + (c[0] + g);
+      const double corr = side ? dts * (Fc - mean) / dx : dts * (mean - Fc) / dx;
+      uo[o] = (T)((double)uo[o] + corr);
+    }
+    __syncthreads();
+  }
+  if (stage != 2) return;
+  double vmax = 0.0;
+  bool bad = false;
+  for (int f = 0; f < NF; f++) {
+    const int info = M.face_info[(int64_t)cb * NF + f];
+    if (info < 0 || !(info & 1)) continue;
+    const int ax = f / 2, side = f % 2;
+    const int t1 = (ax == 0) ? 1 : 0, t2 = (NDIM == 3) ? ((ax == 2) ? 1 : 2) : -1;
+    for (int e = threadIdx.x; e < (int)fv; e += blockDim.x) {
+      const int p1 = e % N, p2 = e / N;
+      int c[3] = {0, 0, 0};
+      c[ax] = side ? N - 1 : 0;
+      c[t1] = p1;
+      if (t2 >= 0) c[t2] = p2;
+      const int64_t o = (NDIM == 3 ? (int64_t)(c[2] + g) * P * P : 0) + (int64_t)(c[1] + g) * P + (c[0] + g);
+      double U[NV];
+#pragma unroll
+      for (int v = 0; v < NV; v++) U[v] = (double)uo[v * sv + o];
+      vmax = fmax(vmax, inv_dt_cell<NDIM>(U, M.gamma, dx, bad));
+    }
+  }
+  wave_flush(M.scal, vmax, bad);
+}
+
+// per-block interior sums of every variable in FP64 times the cell volume
+template <typename T, int NDIM>
+__global__ __launch_bounds__(256) void totals_kernel(const MeshDev *__restrict__ Mp, double *part) {
+  const MeshDev &M = *Mp;
+  constexpr int NV = NDIM + 2;
+  __shared__ double red[4][NV];
+  const int64_t b = blockIdx.x;
+  const int N = M.N, g = M.g, P = N + 2 * g;
+  const int64_t sv = (NDIM == 3) ? (int64_t)P * P * P : (int64_t)P * P;
+  const T *u = (const T *)M.s[M.cur] + b * sv * NV;
+  const int cells = (NDIM == 3) ? N * N * N : N * N;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; v++) acc[v] = 0.0;
+  for (int c = threadIdx.x; c < cells; c += blockDim.x) {
+    const int i = c % N, j = (c / N) % N, k = (NDIM == 3) ? c / (N * N) : 0;
+    const int64_t o = (NDIM == 3 ? (int64_t)(k + g) * P * P : 0) + (int64_t)(j + g) * P + (i + g);
+#pragma unroll
+    for (int v = 0; v < NV; v++) acc[v] += (double)u[v * sv + o];
+  }
+#pragma unroll
+  for (int v = 0; v < NV; v++)
+    for (int o = 32; o > 0; o >>= 1) acc[v] += __shfl_xor(acc[v], o);
+  if ((threadIdx.x & 63) == 0)
+    for (int v = 0; v < NV; v++) red[threadIdx.x >> 6][v] = acc[v];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const double dx = ldexp(M.dx0, -M.level[b]);
+    const double vol = (NDIM == 3) ? dx * dx * dx : dx * dx;
+    const int v = threadIdx.x;
+    part[b * NV + v] = (((red[0][v] + red[1][v]) + red[2][v]) + red[3][v]) * vol;
+  }
+}
+
+// fixed-order sum over blocks (one workgroup, deterministic)
+__global__ __launch_bounds__(256) void totals_sum_kernel(const double *part, int64_t nb, int nv, double *out) {
+  __shared__ double red[256];
+  for (int v = 0; v < nv; v++) {
+    double s = 0.0;
+    for (int64_t b = threadIdx.x; b < nb; b += 256) s += part[b * nv + v];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[v] = red[0];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_dt_full(const foap4_mesh *m, hipStream_t s) {
+  if (m->topo.leaves.empty()) return hipSuccess;
+  const unsigned nb = (unsigned)m->topo.leaves.size();
+  const bool f64 = m->d.prec == FOAP4_F64;
+  if (m->d.ndim == 3) {
+    if (f64) dt_full_kernel<double, 3><<<nb, 256, 0, s>>>(m->d_dev);
+    else dt_full_kernel<float, 3><<<nb, 256, 0, s>>>(m->d_dev);
+  } else {
+    if (f64) dt_full_kernel<double, 2><<<nb, 256, 0, s>>>(m->d_dev);
+    else dt_full_kernel<float, 2><<<nb, 256, 0, s>>>(m->d_dev);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const MeshDev *d_meshes, int n_meshes, int advance, hipStream_t s) {
+  finalize_kernel<<<(n_meshes + 63) / 64, 64, 0, s>>>(d_meshes, n_meshes, advance);
+  return hipGetLastError();
+}
+
+hipError_t launch_fluxfix(const MeshDev *d_mesh, int ndim, bool f64, int n_fix, int stage, hipStream_t s) {
+  if (n_fix <= 0) return hipSuccess;
+  if (ndim == 3) {
+    if (f64) fluxfix_kernel<double, 3><<<n_fix, 256, 0, s>>>(d_mesh, stage);
+    else fluxfix_kernel<float, 3><<<n_fix, 256, 0, s>>>(d_mesh, stage);
+  } else {
+    if (f64) fluxfix_kernel<double, 2><<<n_fix, 256, 0, s>>>(d_mesh, stage);
+    else fluxfix_kernel<float, 2><<<n_fix, 256, 0, s>>>(d_mesh, stage);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_totals(const foap4_mesh *m, double *d_part, double *d_out, hipStream_t s) {
+  const int64_t nb = (int64_t)m->topo.leaves.size();
+  if (nb == 0) return hipSuccess;
+  const bool f64 = m->d.prec == FOAP4_F64;
+  if (m->d.ndim == 3) {
+    if (f64) totals_kernel<double, 3><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, d_part);
+    else totals_kernel<float, 3><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, d_part);
+  } else {
+    if (f64) totals_kernel<double, 2><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, d_part);
+    else totals_kernel<float, 2><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, d_part);
+  }
+  totals_sum_kernel<<<1, 256, 0, s>>>(d_part, nb, m->nvar, d_out);
+  return hipGetLastError();
+}
+
+}  // namespace f4

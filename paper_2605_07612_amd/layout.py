@@ -1,0 +1,64 @@
+"""Caller-side helpers for writing initial conditions into a mesh's state
+tensor and reading results back (host numpy work, not part of the hot path).
+
+Block n of the state tensor is leaf n of the mesh; its cell (i, j, k) is at
+padded index (i+g, j+g, k+g) (include/foap4.h)."""
+from __future__ import annotations
+
+import numpy as np
+
+
+def global_coords(mesh):
+    """(level[nb], G[nb][3]): global integer block coordinates at each block's level."""
+    lev, tree, anc = mesh.export()
+    nt = list(mesh.desc.n_trees)
+    t = np.stack([tree % nt[0], (tree // nt[0]) % nt[1], tree // (nt[0] * nt[1])], axis=1)
+    G = (t.astype(np.int64) << lev[:, None].astype(np.int64)) + anc
+    return lev, G
+
+
+def cell_centres(mesh):
+    """Cell-centre coordinates [nb][ndim][N]*ndim (index order k, j, i)."""
+    lev, G = global_coords(mesh)
+    N, ndim = mesh.N, mesh.ndim
+    ts = mesh.desc.tree_size
+    org = list(mesh.desc.origin)
+    dx = ts / (N * (2.0 ** lev))
+    idx = np.arange(N) + 0.5
+    out = np.empty((len(lev), ndim) + (N,) * ndim)
+    for d in range(ndim):
+        c = org[d] + (G[:, d, None] * N + idx[None, :]) * dx[:, None]  # [nb][N]
+        shape = [len(lev)] + [1] * ndim
+        shape[ndim - d] = N
+        out[:, d] = np.broadcast_to(c.reshape(shape), (len(lev),) + (N,) * ndim)
+    return out
+
+
+def set_interior(mesh, values):
+    """values: [nb][nvar][N]*ndim (numpy) written into the current state."""
+    torch = __import__("torch")
+    t = torch.from_numpy(np.ascontiguousarray(values)).to(mesh.dtype).to(mesh.state[0].device)
+    mesh.interior().copy_(t)
+
+
+def set_from_field(mesh, field):
+    """Evaluate field(x, y[, z]) -> [nvar][nb][N..] at the cell centres."""
+    xc = cell_centres(mesh)
+    vals = field(*[xc[:, d] for d in range(mesh.ndim)])
+    set_interior(mesh, np.moveaxis(vals, 0, 1))
+
+
+def set_from_grid(mesh, grid):
+    """grid: [nvar][nz][ny][nx] (or [nvar][ny][nx]) on a uniform-level mesh."""
+    lev, G = global_coords(mesh)
+    N, ndim = mesh.N, mesh.ndim
+    nv = grid.shape[0]
+    if ndim == 3:
+        nz, ny, nx = grid.shape[1:]
+        blk = grid.reshape(nv, nz // N, N, ny // N, N, nx // N, N).transpose(1, 3, 5, 0, 2, 4, 6)
+        vals = blk[G[:, 2], G[:, 1], G[:, 0]]
+    else:
+        ny, nx = grid.shape[1:]
+        blk = grid.reshape(nv, ny // N, N, nx // N, N).transpose(1, 3, 0, 2, 4)
+        vals = blk[G[:, 1], G[:, 0]]
+    set_interior(mesh, vals)
