@@ -97,8 +97,8 @@ def main():
     # ---------------- FP32 batched: persistent + graph + autotuned
     m32 = make(f4.F32)
     batch = f4.Batch([m32])
-    ks, wg = batch.autotune(args.tune_cache)
-    log(f"autotune: kslabs={ks} wg_per_cu={wg}")
+    ks, wg, xcd = batch.autotune(args.tune_cache)
+    log(f"autotune: kslabs={ks} wg_per_cu={wg} xcd_order={xcd}")
     batch.step(args.warmup)
     secs, wall = timed_steps(batch.step, args.steps, torch.cuda.synchronize)
     t32, dt32 = m32.time()
@@ -126,7 +126,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "cells": cells, "blocks": int(np.prod(w["trees"])),
                    "block": args.block, "ghost": 2, "form": "batched: persistent stage launch, hipGraph, autotuned",
-                   "kslabs": ks, "wg_per_cu": wg, "reductions": "f64"},
+                   "kslabs": ks, "wg_per_cu": wg, "xcd_order": xcd, "gather_halos": 1, "reductions": "f64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "stage_kernel<float,3>", "bytes_per_launch": int(stage_bytes),

@@ -172,16 +172,22 @@ foap4_status foap4_batch_destroy(foap4_batch *batch);
 /* Work decomposition of the batched stage kernel: kslabs = 1, 2 or 4 k-slabs
  * per block tile (the LDS tile depth is N / kslabs planes), wg_per_cu =
  * resident workgroups per compute unit for the persistent grid (0: one
- * workgroup per work item, no persistence). */
-foap4_status foap4_batch_set_config(foap4_batch *batch, int32_t kslabs, int32_t wg_per_cu);
+ * workgroup per work item, no persistence), xcd_order = 1 to give each of
+ * the 8 XCDs a contiguous range of work items (Morton neighbours share an
+ * L2), gather_halos = 1 to read same-level halo cells straight from the
+ * neighbouring blocks instead of copying them into ghost cells first (the
+ * results are identical; the SRL copies are then skipped except where the
+ * coarse-to-fine prolongation reads them).  Defaults: 1, 0, 1, 1. */
+foap4_status foap4_batch_set_config(foap4_batch *batch, int32_t kslabs, int32_t wg_per_cu,
+                                    int32_t xcd_order, int32_t gather_halos);
 
-/* Times the candidate configurations on the batch itself and keeps the
- * fastest; results are cached in the JSON file cache_path (may be NULL) keyed
- * by GPU architecture, precision and the batch's block-size mix.  The
- * meshes' states are restored afterwards.  Writes the chosen kslabs and
- * wg_per_cu (may be NULL). */
-foap4_status foap4_batch_autotune(foap4_batch *batch, const char *cache_path, int32_t *kslabs,
-                                  int32_t *wg_per_cu);
+/* Times the candidate configurations (kslabs x wg_per_cu x xcd_order) on the
+ * batch itself and keeps the fastest; results are cached in the JSON file
+ * cache_path (may be NULL) keyed by GPU architecture, precision and the
+ * batch's block-size mix.  The meshes' states are restored afterwards.
+ * Writes the chosen {kslabs, wg_per_cu, xcd_order} to cfg_out[3] (may be
+ * NULL). */
+foap4_status foap4_batch_autotune(foap4_batch *batch, const char *cache_path, int32_t *cfg_out);
 
 /* Advances every mesh of the batch by n_steps Heun steps (enqueue only). */
 foap4_status foap4_batch_step(foap4_batch *batch, int32_t n_steps);

@@ -56,8 +56,8 @@ EXPORTS = {
     "foap4_regrid": (I32, [P, P, P]),
     "foap4_batch_create": (I32, [P, I32, ctypes.POINTER(P)]),
     "foap4_batch_destroy": (I32, [P]),
-    "foap4_batch_set_config": (I32, [P, I32, I32]),
-    "foap4_batch_autotune": (I32, [P, ctypes.c_char_p, P, P]),
+    "foap4_batch_set_config": (I32, [P, I32, I32, I32, I32]),
+    "foap4_batch_autotune": (I32, [P, ctypes.c_char_p, P]),
     "foap4_batch_step": (I32, [P, I32]),
     "foap4_batch_phase_times": (I32, [P, I32, P]),
     "foap4_last_error": (ctypes.c_char_p, [P]),
@@ -265,14 +265,15 @@ class Batch:
         except Exception:
             pass
 
-    def set_config(self, kslabs=1, wg_per_cu=0):
-        _check(lib().foap4_batch_set_config(self.h, kslabs, wg_per_cu))
+    def set_config(self, kslabs=1, wg_per_cu=0, xcd_order=1, gather_halos=1):
+        _check(lib().foap4_batch_set_config(self.h, kslabs, wg_per_cu, xcd_order, gather_halos))
 
     def autotune(self, cache_path=None):
-        ks, wg = ctypes.c_int32(), ctypes.c_int32()
+        """Returns the chosen (kslabs, wg_per_cu, xcd_order)."""
+        cfg = np.zeros(3, np.int32)
         cp = cache_path.encode() if cache_path else None
-        _check(lib().foap4_batch_autotune(self.h, cp, ctypes.byref(ks), ctypes.byref(wg)))
-        return ks.value, wg.value
+        _check(lib().foap4_batch_autotune(self.h, cp, _ptr(cfg)))
+        return tuple(int(x) for x in cfg)
 
     def step(self, n=1):
         _check(lib().foap4_batch_step(self.h, n))

@@ -24,7 +24,7 @@ foap4_status fail(foap4_mesh *m, foap4_status s, const std::string &msg) {
   return s;
 }
 
-MeshDev make_dev(const foap4_mesh *m, int ks) {
+MeshDev make_dev(const foap4_mesh *m, int ks, int gather) {
   MeshDev d{};
   d.s[0] = m->state[0];
   d.s[1] = m->state[1];
@@ -53,11 +53,15 @@ MeshDev make_dev(const foap4_mesh *m, int ks) {
   d.N = m->d.block_n;
   d.g = m->d.n_ghost;
   d.ks = std::max(1, std::min(ks, m->d.block_n / 8));
+  d.gather = gather;
+  // with gathered halos the SRL ghosts are needed only as input of the C2F
+  // prolongation stencils, i.e. on meshes with refinement boundaries
+  d.r1_srl = (gather && m->pat.n[kC2F] == 0) ? 0 : m->pat.n[kSRL];
   return d;
 }
 
 foap4_status upload_dev(foap4_mesh *m) {
-  MeshDev d = make_dev(m, 1);
+  MeshDev d = make_dev(m, 1, 0);
   F4_HIP(m, hipMemcpyAsync(m->d_dev, &d, sizeof(d), hipMemcpyHostToDevice, m->stream));
   F4_HIP(m, hipStreamSynchronize(m->stream));
   return FOAP4_OK;
@@ -116,9 +120,10 @@ struct foap4_batch {
   std::vector<int64_t> revs;
   int ndim = 3;
   bool f64 = false;
-  int ks = 1, wg_per_cu = 0;
+  int ks = 1, wg_per_cu = 0, gather = 1, xcd = 1;
   MeshDev *d_devs = nullptr;
   int64_t total_items = 0, r1_total = 0, r2_total = 0;
+  int nmask = 0;
   hipStream_t stream = nullptr, cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -283,10 +288,10 @@ foap4_status foap4_step(foap4_mesh *m, int32_t n_steps, double *t_out, double *d
   if ((st = ensure_dt(m)) != FOAP4_OK) return st;
   for (int32_t s = 0; s < n_steps; s++) {
     if ((st = fill(m, m->d_dev, 0)) != FOAP4_OK) return st;
-    F4_HIP(m, launch_stage(m->d_dev, 1, items, 1, ndim, f64, 0, m->stream));
+    F4_HIP(m, launch_stage(m->d_dev, 1, items, 1, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n)));
     F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, 1, m->stream));
     if ((st = fill(m, m->d_dev, 1)) != FOAP4_OK) return st;
-    F4_HIP(m, launch_stage(m->d_dev, 1, items, 2, ndim, f64, 0, m->stream));
+    F4_HIP(m, launch_stage(m->d_dev, 1, items, 2, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n)));
     F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, 2, m->stream));
     F4_HIP(m, launch_finalize(m->d_dev, 1, 1, m->stream));
   }
@@ -401,16 +406,18 @@ static foap4_status batch_upload(foap4_batch *b) {
   std::vector<MeshDev> devs;
   int64_t it = 0, r1 = 0, r2 = 0;
   for (foap4_mesh *m : b->meshes) {
-    MeshDev d = make_dev(m, b->ks);
+    MeshDev d = make_dev(m, b->ks, b->gather);
     d.item_begin = it;
     d.r1_begin = r1;
     d.r2_begin = r2;
     it += stage_items_for(b->ndim, m->d.block_n, d.nb, d.ks);
-    r1 += m->pat.n[kSRL] + m->pat.n[kF2C];
+    r1 += d.r1_srl + m->pat.n[kF2C];
     r2 += m->pat.n[kC2F];
     devs.push_back(d);
   }
   b->total_items = it;
+  b->nmask = 0;
+  for (foap4_mesh *m : b->meshes) b->nmask |= nmask_of(m->d.block_n);
   b->r1_total = r1;
   b->r2_total = r2;
   B_HIP(b, hipMemcpyAsync(b->d_devs, devs.data(), devs.size() * sizeof(MeshDev), hipMemcpyHostToDevice, b->stream));
@@ -428,7 +435,7 @@ static hipError_t batch_enqueue_step(foap4_batch *b, hipStream_t s) {
     if ((e = launch_ghost(b->d_devs, n, b->r1_total, 1, which, b->ndim, b->f64, 0, s)) != hipSuccess) return e;
     if (b->r2_total && (e = launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s)) != hipSuccess)
       return e;
-    if ((e = launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, grid, s)) != hipSuccess) return e;
+    if ((e = launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, grid, s, b->xcd, b->nmask)) != hipSuccess) return e;
     for (int i = 0; i < n; i++)
       if (b->meshes[i]->pat.n_fix > 0 &&
           (e = launch_fluxfix(b->d_devs + i, b->ndim, b->f64, b->meshes[i]->pat.n_fix, stage, s)) != hipSuccess)
@@ -508,12 +515,18 @@ foap4_status foap4_batch_destroy(foap4_batch *b) {
   return FOAP4_OK;
 }
 
-foap4_status foap4_batch_set_config(foap4_batch *b, int32_t kslabs, int32_t wg_per_cu) {
-  if (!b || (kslabs != 1 && kslabs != 2 && kslabs != 4) || wg_per_cu < 0 || wg_per_cu > 64)
-    return batch_fail(b, FOAP4_E_INVALID, "kslabs must be 1, 2 or 4 and 0 <= wg_per_cu <= 64");
-  if (b->ks != kslabs || b->wg_per_cu != wg_per_cu) drop_graph(b);
+foap4_status foap4_batch_set_config(foap4_batch *b, int32_t kslabs, int32_t wg_per_cu, int32_t xcd_order,
+                                    int32_t gather_halos) {
+  if (!b || (kslabs != 1 && kslabs != 2 && kslabs != 4) || wg_per_cu < 0 || wg_per_cu > 64 ||
+      (xcd_order != 0 && xcd_order != 1) || (gather_halos != 0 && gather_halos != 1))
+    return batch_fail(b, FOAP4_E_INVALID,
+                      "kslabs must be 1, 2 or 4, 0 <= wg_per_cu <= 64, xcd_order and gather_halos 0 or 1");
+  if (b->ks != kslabs || b->wg_per_cu != wg_per_cu || b->xcd != xcd_order || b->gather != gather_halos)
+    drop_graph(b);
   b->ks = kslabs;
   b->wg_per_cu = wg_per_cu;
+  b->xcd = xcd_order;
+  b->gather = gather_halos;
   return FOAP4_OK;
 }
 
@@ -549,7 +562,7 @@ foap4_status foap4_batch_phase_times(foap4_batch *b, int32_t n_steps, double *ou
       B_HIP(b, hipEventRecord(ev[++k], s));
       if (b->r2_total) B_HIP(b, launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s));
       B_HIP(b, hipEventRecord(ev[++k], s));
-      B_HIP(b, launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, grid, s));
+      B_HIP(b, launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, grid, s, b->xcd, b->nmask));
       B_HIP(b, hipEventRecord(ev[++k], s));
       for (int i = 0; i < n; i++)
         if (b->meshes[i]->pat.n_fix > 0)
@@ -613,7 +626,8 @@ static std::string batch_key(const foap4_batch *b) {
   return k.str();
 }
 
-static bool cache_lookup(const char *path, const std::string &key, int &ks, int &wg) {
+// cache entries: "key": [kslabs, wg_per_cu, xcd_order]
+static bool cache_lookup(const char *path, const std::string &key, int cfg[3]) {
   if (!path) return false;
   std::ifstream f(path);
   if (!f) return false;
@@ -622,18 +636,18 @@ static bool cache_lookup(const char *path, const std::string &key, int &ks, int 
     const size_t q0 = line.find('"'), q1 = line.find('"', q0 + 1);
     if (q0 == std::string::npos || q1 == std::string::npos) continue;
     if (line.substr(q0 + 1, q1 - q0 - 1) != key) continue;
-    int a = 0, c = 0;
-    if (std::sscanf(line.c_str() + q1 + 1, " : [%d , %d]", &a, &c) == 2 ||
-        std::sscanf(line.c_str() + q1 + 1, ": [%d, %d]", &a, &c) == 2) {
-      ks = a;
-      wg = c;
+    int a = 0, c = 0, x = 0;
+    if (std::sscanf(line.c_str() + q1 + 1, " : [%d , %d , %d]", &a, &c, &x) == 3) {
+      cfg[0] = a;
+      cfg[1] = c;
+      cfg[2] = x;
       return true;
     }
   }
   return false;
 }
 
-static void cache_store(const char *path, const std::string &key, int ks, int wg) {
+static void cache_store(const char *path, const std::string &key, const int cfg[3]) {
   if (!path) return;
   std::vector<std::string> keep;
   {
@@ -649,7 +663,7 @@ static void cache_store(const char *path, const std::string &key, int ks, int wg
     }
   }
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d]", key.c_str(), ks, wg);
+  std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d]", key.c_str(), cfg[0], cfg[1], cfg[2]);
   keep.push_back(buf);
   std::ofstream o(path);
   o << "{\n";
@@ -657,14 +671,14 @@ static void cache_store(const char *path, const std::string &key, int ks, int wg
   o << "}\n";
 }
 
-foap4_status foap4_batch_autotune(foap4_batch *b, const char *cache_path, int32_t *ks_out, int32_t *wg_out) {
+foap4_status foap4_batch_autotune(foap4_batch *b, const char *cache_path, int32_t *cfg_out) {
   if (!b) return batch_fail(nullptr, FOAP4_E_INVALID, "null batch");
   const std::string key = batch_key(b);
-  int ks = 1, wg = 0;
-  if (cache_lookup(cache_path, key, ks, wg)) {
-    foap4_status st = foap4_batch_set_config(b, ks, wg);
-    if (ks_out) *ks_out = ks;
-    if (wg_out) *wg_out = wg;
+  int cached[3] = {1, 0, 1};
+  if (cache_lookup(cache_path, key, cached)) {
+    foap4_status st = foap4_batch_set_config(b, cached[0], cached[1], cached[2], b->gather);
+    if (cfg_out)
+      for (int i = 0; i < 3; i++) cfg_out[i] = cached[i];
     return st;
   }
   // save the current states and scalars; restored after timing
@@ -697,31 +711,33 @@ foap4_status foap4_batch_autotune(foap4_batch *b, const char *cache_path, int32_
   for (foap4_mesh *m : b->meshes) max_ks = std::max(max_ks, m->d.block_n / 8);
   if (b->ndim == 2) max_ks = 1;
   float best = 1e30f;
-  int best_ks = 1, best_wg = 0;
+  int best_cfg[3] = {1, 0, 1};
   hipEvent_t e0, e1;
   B_HIP(b, hipEventCreate(&e0));
   B_HIP(b, hipEventCreate(&e1));
   foap4_status result = FOAP4_OK;
   for (int a = 0; a < 3 && result == FOAP4_OK; a++) {
     if (ks_cand[a] > max_ks) continue;
-    for (int c = 0; c < 5 && result == FOAP4_OK; c++) {
-      if ((result = foap4_batch_set_config(b, ks_cand[a], wg_cand[c])) != FOAP4_OK) break;
-      if ((result = foap4_batch_step(b, 2)) != FOAP4_OK) break;  // capture + warm-up
-      if (hipEventRecord(e0, b->stream) != hipSuccess) { result = FOAP4_E_HIP; break; }
-      if ((result = foap4_batch_step(b, 4)) != FOAP4_OK) break;
-      float ms = 0.f;
-      if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        result = FOAP4_E_HIP;
-        break;
+    for (int c = 0; c < 5 && result == FOAP4_OK; c++)
+      for (int x = 0; x < 2 && result == FOAP4_OK; x++) {
+        if ((result = foap4_batch_set_config(b, ks_cand[a], wg_cand[c], x, b->gather)) != FOAP4_OK) break;
+        if ((result = foap4_batch_step(b, 2)) != FOAP4_OK) break;  // capture + warm-up
+        if (hipEventRecord(e0, b->stream) != hipSuccess) { result = FOAP4_E_HIP; break; }
+        if ((result = foap4_batch_step(b, 4)) != FOAP4_OK) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          result = FOAP4_E_HIP;
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          best_cfg[0] = ks_cand[a];
+          best_cfg[1] = wg_cand[c];
+          best_cfg[2] = x;
+        }
+        if (restore() != hipSuccess) { result = FOAP4_E_HIP; break; }
       }
-      if (ms < best) {
-        best = ms;
-        best_ks = ks_cand[a];
-        best_wg = wg_cand[c];
-      }
-      if (restore() != hipSuccess) { result = FOAP4_E_HIP; break; }
-    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -729,10 +745,10 @@ foap4_status foap4_batch_autotune(foap4_batch *b, const char *cache_path, int32_
   for (void *p : saved) (void)hipFree(p);
   if (result != FOAP4_OK) return result;
   if (re != hipSuccess) return batch_fail(b, FOAP4_E_HIP, "autotune restore failed");
-  cache_store(cache_path, key, best_ks, best_wg);
-  if (ks_out) *ks_out = best_ks;
-  if (wg_out) *wg_out = best_wg;
-  return foap4_batch_set_config(b, best_ks, best_wg);
+  cache_store(cache_path, key, best_cfg);
+  if (cfg_out)
+    for (int i = 0; i < 3; i++) cfg_out[i] = best_cfg[i];
+  return foap4_batch_set_config(b, best_cfg[0], best_cfg[1], best_cfg[2], b->gather);
 }
 
 }  // extern "C"

@@ -8,20 +8,33 @@
 namespace f4 {
 
 // Generalized minmod G(a, b, theta = 1) (eq. gminmod): zero unless a and b
-// have the same strict sign, else the one of smaller magnitude.
-template <typename T>
-__device__ __forceinline__ T minmod(T a, T b) {
-  if (a > T(0) && b > T(0)) return a < b ? a : b;
-  if (a < T(0) && b < T(0)) return a > b ? a : b;
-  return T(0);
+// have the same strict sign, else the one of smaller magnitude.  Branch-free:
+// equal sign bits select copysign(min(|a|, |b|), a), which is +-0 when either
+// argument is zero; different sign bits give 0.
+__device__ __forceinline__ float minmod(float a, float b) {
+  const float m = copysignf(fminf(fabsf(a), fabsf(b)), a);
+  return ((__float_as_uint(a) ^ __float_as_uint(b)) >> 31) ? 0.0f : m;
 }
+__device__ __forceinline__ double minmod(double a, double b) {
+  const double m = copysign(fmin(fabs(a), fabs(b)), a);
+  return ((__double_as_longlong(a) ^ __double_as_longlong(b)) < 0) ? 0.0 : m;
+}
+
+// Reciprocal and square root: the hardware approximations (about 1 ulp) for
+// FP32 states, IEEE division and square root for FP64 states.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
 
 // Primitive state (rho, v[0..NDIM-1], p) packed as NV = NDIM + 2 values.
 // Conservative -> primitive (Sec. 3.5): v = m / rho, p = (gamma-1)(E - m.v/2).
 template <typename T, int NDIM>
 __device__ __forceinline__ void to_prim(const T *U, T gamma, T *W) {
   const T r = U[0];
-  const T ir = T(1) / r;
+  const T ir = frcp(r);
   T ke = T(0);
   W[0] = r;
 #pragma unroll
@@ -44,41 +57,34 @@ __device__ __forceinline__ void rusanov(const T *WL, const T *WR, T gamma, T *F)
   const T rl = WL[0], rr = WR[0];
   const T pl = WL[NV - 1], pr = WR[NV - 1];
   const T vl = WL[1 + AX], vr = WR[1 + AX];
-  const T igm1 = T(1) / (gamma - T(1));
-  T UL[NV], UR[NV], FL[NV], FR[NV];
-  T kel = T(0), ker = T(0);
-  UL[0] = rl;
-  UR[0] = rr;
-  FL[0] = rl * vl;
-  FR[0] = rr * vr;
-#pragma unroll
-  for (int d = 0; d < NDIM; d++) {
-    const T ml = rl * WL[1 + d], mr = rr * WR[1 + d];
-    UL[1 + d] = ml;
-    UR[1 + d] = mr;
-    FL[1 + d] = ml * vl + (d == AX ? pl : T(0));
-    FR[1 + d] = mr * vr + (d == AX ? pr : T(0));
-    kel += ml * WL[1 + d];
-    ker += mr * WR[1 + d];
-  }
-  const T El = pl * igm1 + T(0.5) * kel;
-  const T Er = pr * igm1 + T(0.5) * ker;
-  UL[NV - 1] = El;
-  UR[NV - 1] = Er;
-  FL[NV - 1] = (El + pl) * vl;
-  FR[NV - 1] = (Er + pr) * vr;
-  const T sl = sqrt(rl), sr = sqrt(rr);
-  const T is = T(1) / (sl + sr);
-  const T cl2 = gamma * pl / rl, cr2 = gamma * pr / rr;
+  // wave speed first, so the per-component flux needs few live registers
+  const T sl = fsqrt(rl), sr = fsqrt(rr);
+  const T is = frcp(sl + sr);
+  const T cl2 = fdiv(gamma * pl, rl), cr2 = fdiv(gamma * pr, rr);
   const T ubar = (sl * vl + sr * vr) * is;
   const T eta2 = T(0.5) * sl * sr * is * is;
   const T dv = vr - vl;
   const T d2 = (sl * cl2 + sr * cr2) * is + eta2 * dv * dv;
-  const T db = sqrt(d2);
+  const T db = fsqrt(d2);
   const T lm = fabs(ubar - db), lp = fabs(ubar + db);
-  const T a = lm > lp ? lm : lp;
+  const T ha = T(0.5) * (lm > lp ? lm : lp);
+  // mass
+  F[0] = T(0.5) * (rl * vl + rr * vr) - ha * (rr - rl);
+  // momentum and energy
+  T kel = T(0), ker = T(0);
 #pragma unroll
-  for (int v = 0; v < NV; v++) F[v] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * a * (UR[v] - UL[v]);
+  for (int d = 0; d < NDIM; d++) {
+    const T ml = rl * WL[1 + d], mr = rr * WR[1 + d];
+    const T fl = ml * vl + (d == AX ? pl : T(0));
+    const T fr = mr * vr + (d == AX ? pr : T(0));
+    F[1 + d] = T(0.5) * (fl + fr) - ha * (mr - ml);
+    kel += ml * WL[1 + d];
+    ker += mr * WR[1 + d];
+  }
+  const T igm1 = frcp(gamma - T(1));
+  const T El = pl * igm1 + T(0.5) * kel;
+  const T Er = pr * igm1 + T(0.5) * ker;
+  F[NV - 1] = T(0.5) * ((El + pl) * vl + (Er + pr) * vr) - ha * (Er - El);
 }
 
 // Face flux from four primitive states along the face normal: minmod-limited

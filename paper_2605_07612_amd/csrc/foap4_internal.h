@@ -61,7 +61,9 @@ class Topology {
 struct MeshDev {
   void *s[2];                 // state buffers
   const int32_t *level;       // [nb]
-  const int32_t *face_info;   // [nb][2*ndim]: -1, or 2*slot (fine-side flux) / 2*slot+1 (coarse side)
+  // [nb][2*ndim]: -2 - n for a same-level neighbour n, -1 for a boundary,
+  // 2*slot for a C2F face (fine-side flux slot), 2*slot+1 for an F2C face
+  const int32_t *face_info;
   const int32_t *srl, *f2c, *c2f, *fix_list;  // ghost pattern records
   void *bflux_f;              // fine-side face fluxes [n_c2f][nvar][N^(d-1)]
   void *bflux_c;              // coarse-side face fluxes [n_f2c/2^(d-1)][nvar][N^(d-1)]
@@ -76,6 +78,8 @@ struct MeshDev {
   int32_t n_fix;
   int32_t cur;                // current state buffer
   int32_t N, g, ks;           // block size, ghost layers, k-slabs per tile
+  int32_t gather;             // stage reads same-level halos from the neighbours
+  int32_t r1_srl;             // SRL records executed in round R1 (0 or pn[kSRL])
 };
 
 struct Pattern {
@@ -128,7 +132,9 @@ foap4_status fail(foap4_mesh *m, foap4_status s, const std::string &msg);
       return ::f4::fail((m), FOAP4_E_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
   } while (0)
 
-MeshDev make_dev(const foap4_mesh *m, int ks);
+// ks: k-slabs per tile; gather: same-level halos read from the neighbours,
+// so round R1 runs its SRL copies only where R2's prolongation needs them
+MeshDev make_dev(const foap4_mesh *m, int ks, int gather);
 foap4_status upload_dev(foap4_mesh *m);
 
 // pattern.hip
@@ -138,8 +144,10 @@ hipError_t launch_ghost(const MeshDev *d_meshes, int n_meshes, int64_t total, in
                         int ndim, bool f64, int grid, hipStream_t s);
 // stage.hip
 int64_t stage_items_for(int ndim, int N, int64_t nb, int ks);
+// nmask: block sizes present in the launch (1: N = 8, 2: N = 16, 4: N = 32)
 hipError_t launch_stage(const MeshDev *d_meshes, int n_meshes, int64_t total_items, int stage,
-                        int ndim, bool f64, int grid, hipStream_t s);
+                        int ndim, bool f64, int grid, hipStream_t s, int xcd, int nmask);
+inline int nmask_of(int N) { return N == 8 ? 1 : (N == 16 ? 2 : 4); }
 // reduce.hip
 hipError_t launch_dt_full(const foap4_mesh *m, hipStream_t s);
 hipError_t launch_finalize(const MeshDev *d_meshes, int n_meshes, int advance, hipStream_t s);

@@ -40,27 +40,40 @@ __device__ void srl_record(const MeshDev &M, T *u, int ax, int32_t a, int32_t b)
   tangential(NDIM, ax, t1, t2);
   const int64_t bel = G.sv * NV;
   const int total = 2 * NV * N2 * N * g;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    int l, p1, p2, v, side, r = e;
-    if (ax == 0) {  // layers are contiguous in memory: layer fastest
-      l = r % g; r /= g;
-      p1 = r % N; r /= N;
-    } else {        // rows along x are contiguous: t1 (= x) fastest
-      p1 = r % N; r /= N;
-      l = r % g; r /= g;
+  constexpr int B = 8;  // elements in flight per thread: loads first, then stores
+  for (int e0 = threadIdx.x; e0 < total; e0 += B * blockDim.x) {
+    T val[B];
+    int64_t dsto[B];
+#pragma unroll
+    for (int q = 0; q < B; q++) {
+      const int e = e0 + q * blockDim.x;
+      dsto[q] = -1;
+      if (e >= total) continue;
+      int l, p1, p2, v, side, r = e;
+      if (ax == 0) {  // layers are contiguous in memory: layer fastest
+        l = r % g; r /= g;
+        p1 = r % N; r /= N;
+      } else {        // rows along x are contiguous: t1 (= x) fastest
+        p1 = r % N; r /= N;
+        l = r % g; r /= g;
+      }
+      p2 = r % N2; r /= N2;
+      v = r % NV; side = r / NV;
+      int src[3] = {0, 0, 0}, dst[3] = {0, 0, 0};
+      src[t1] = dst[t1] = p1;
+      if (t2 >= 0) src[t2] = dst[t2] = p2;
+      int64_t sb, db;
+      if (side == 0) {  // b's -ax ghosts from a's last layers
+        src[ax] = N - 1 - l; dst[ax] = -1 - l; sb = a; db = b;
+      } else {          // a's +ax ghosts from b's first layers
+        src[ax] = l; dst[ax] = N + l; sb = b; db = a;
+      }
+      val[q] = u[sb * bel + v * G.sv + G.at(src)];
+      dsto[q] = db * bel + v * G.sv + G.at(dst);
     }
-    p2 = r % N2; r /= N2;
-    v = r % NV; side = r / NV;
-    int src[3] = {0, 0, 0}, dst[3] = {0, 0, 0};
-    src[t1] = dst[t1] = p1;
-    if (t2 >= 0) src[t2] = dst[t2] = p2;
-    int64_t sb, db;
-    if (side == 0) {  // b's -ax ghosts from a's last layers
-      src[ax] = N - 1 - l; dst[ax] = -1 - l; sb = a; db = b;
-    } else {          // a's +ax ghosts from b's first layers
-      src[ax] = l; dst[ax] = N + l; sb = b; db = a;
-    }
-    u[db * bel + v * G.sv + G.at(dst)] = u[sb * bel + v * G.sv + G.at(src)];
+#pragma unroll
+    for (int q = 0; q < B; q++)
+      if (dsto[q] >= 0) u[dsto[q]] = val[q];
   }
 }
 
@@ -193,12 +206,12 @@ template <typename T, int NDIM, int N>
 __device__ void ghost_item(const MeshDev &M, int round, int64_t r, int which) {
   T *u = (T *)M.s[which == 0 ? M.cur : 1 - M.cur];
   if (round == 1) {
-    if (r < M.pn[kSRL]) {
+    if (r < M.r1_srl) {
       int f = 1;
       while (r >= M.poff[kSRL][f + 1]) f += 2;
       srl_record<T, NDIM, N>(M, u, f / 2, M.srl[2 * r], M.srl[2 * r + 1]);
     } else {
-      r -= M.pn[kSRL];
+      r -= M.r1_srl;
       int f = 0;
       while (r >= M.poff[kF2C][f + 1]) f++;
       f2c_record<T, NDIM, N>(M, u, f, M.f2c[4 * r], M.f2c[4 * r + 1], M.f2c[4 * r + 2]);

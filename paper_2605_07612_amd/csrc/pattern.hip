@@ -174,6 +174,7 @@ __global__ void scatter_kernel(ScatterArgs A) {
   const int32_t *nb4 = A.nbr + id * 4;
   int32_t info = -1;
   if (k == kKindSRL) {
+    info = -2 - nb4[0];  // same-level neighbour, read directly by the gathering stage kernel
     if (f & 1) {
       const int64_t pos = A.off[kSRL][f] + A.cnt[(int64_t)(kSRL * nf + f) * A.nb + b];
       A.srl[2 * pos] = (int32_t)b;

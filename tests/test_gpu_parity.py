@@ -256,7 +256,7 @@ def test_batch_equals_plain_bitwise(f4):
     for m in plain:
         m.step(4)
     b = f4.Batch(batched)
-    b.set_config(kslabs=2, wg_per_cu=2)
+    b.set_config(kslabs=2, wg_per_cu=2, xcd_order=1)
     b.step(4)
     for w, p, q in zip(ws, plain, batched):
         a, c = interior(gpu_state(p), 2, w["N"], 3), interior(gpu_state(q), 2, w["N"], 3)
