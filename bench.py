@@ -38,10 +38,12 @@ def stage_bytes_per_cell(S):
     return (2.75 + 3.75) / 2.0 * S
 
 
-def step_bytes_per_update(S):
-    """Whole step per cell update: 4.75 S (ghost fill reads and writes
-    0.75 S per stage, stages as above), counted per cell update."""
-    return 4.75 * S
+def step_bytes_per_update(S, gather):
+    """Whole step per cell update.  Stored ghosts (the paper's design, the
+    plain form): 4.75 S (ghost fill reads and writes 0.75 S per stage, stages
+    as above).  Gathered halos on a mesh without refinement boundaries (the
+    batched form): no ghost fill, 3.25 S."""
+    return (3.25 if gather else 4.75) * S
 
 
 def log(*a):
@@ -61,6 +63,22 @@ def timed_steps(run, steps, sync):
     return start.elapsed_time(end) / 1e3, wall
 
 
+def traffic_from_counters(path, stage_launch_bytes):
+    """HBM bytes per stage launch from a rocprofv3 --pmc counter summary
+    (profiles/*.json written from two counter passes, FETCH_SIZE and
+    WRITE_SIZE in KiB per dispatch), each scaled by the factor that makes the
+    same counter read the known size of a plain 1 GiB device copy."""
+    try:
+        d = json.load(open(path))
+        fetch = d["stage_fetch_kib"] * d["fetch_scale"]
+        write = d["stage_write_kib"] * d["write_scale"]
+        return {"bytes_per_launch": int((fetch + write) * 1024), "fetch_kib": round(fetch, 1),
+                "write_kib": round(write, 1), "algorithmic_bytes_per_launch": int(stage_launch_bytes),
+                "source": os.path.relpath(path, ROOT)}
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +90,11 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--profile-run", action="store_true",
+                    help="short run for hardware-counter passes: a 1 GiB device copy (counter calibration) "
+                         "then 3 batched FP32 steps in the tuned configuration")
+    ap.add_argument("--config", default="1,3,0", help="kslabs,wg_per_cu,xcd_order of --profile-run")
+    ap.add_argument("--counters", default=os.path.join(ROOT, "profiles", "stage_traffic_noise_shear_256cubed_b16.json"))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 (the multi-GPU sharding is a design "
@@ -94,6 +117,25 @@ def main():
         layout.set_from_grid(m, grid)
         return m
 
+    if args.profile_run:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        bb = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        bb.copy_(a)  # calibration: reads and writes exactly 1 GiB
+        torch.cuda.synchronize()
+        del a, bb
+        m32 = make(f4.F32)
+        batch = f4.Batch([m32])
+        ks, wg, xcd = (int(x) for x in args.config.split(","))
+        batch.set_config(ks, wg, xcd, 1)
+        batch.step(3)
+        torch.cuda.synchronize()
+        log("profile run done")
+        return
+
+    S32, S64 = 5 * 4, 5 * 8
+
     # ---------------- FP32 batched: persistent + graph + autotuned
     m32 = make(f4.F32)
     batch = f4.Batch([m32])
@@ -101,15 +143,13 @@ def main():
     log(f"autotune: kslabs={ks} wg_per_cu={wg} xcd_order={xcd}")
     batch.step(args.warmup)
     secs, wall = timed_steps(batch.step, args.steps, torch.cuda.synchronize)
-    t32, dt32 = m32.time()
     gcups32 = cells * 2 * args.steps / secs / 1e9
     log(f"FP32 batched: {secs / args.steps * 1e3:.3f} ms/step, {gcups32:.2f} Gcell-updates/s (wall {wall:.3f}s)")
     phases = batch.phase_times(5)
     log("phases (ms):", json.dumps({k: round(v, 4) for k, v in phases.items()}))
-    S32 = 5 * 4
     stage_bytes = cells * stage_bytes_per_cell(S32)
     achieved = stage_bytes / (phases["stage"] * 1e-3) / 1e9
-    step_gbs = gcups32 * step_bytes_per_update(S32)
+    step_gbs = gcups32 * step_bytes_per_update(S32, True)
 
     result = {
         "metric": METRIC,
@@ -128,18 +168,19 @@ def main():
                    "block": args.block, "ghost": 2, "form": "batched: persistent stage launch, hipGraph, autotuned",
                    "kslabs": ks, "wg_per_cu": wg, "xcd_order": xcd, "gather_halos": 1, "reductions": "f64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "stage_kernel<float,3>", "bytes_per_launch": int(stage_bytes),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_counters(args.counters, stage_bytes),
+                     "kernel": "stage_kernel<float,3,N=16>", "bytes_per_launch": int(stage_bytes),
                      "avg_launch_ms": round(phases["stage"], 5)},
-        "step_hbm": {"bytes_per_update": step_bytes_per_update(S32), "achieved_gbs": round(step_gbs, 1),
+        "step_hbm": {"bytes_per_update": step_bytes_per_update(S32, True), "achieved_gbs": round(step_gbs, 1),
                      "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
         "phases_ms": {k: round(v, 5) for k, v in phases.items()},
     }
     del batch, m32
     torch.cuda.empty_cache()
 
-    # ---------------- FP64 plain: one workgroup per block, one launch per kernel
     if not args.skip_fp64:
+        # ---------------- FP64 plain: one workgroup per block, stored ghosts, one launch per kernel
         m64 = make(f4.F64)
         m64.step(args.warmup)
         secs64, _ = timed_steps(lambda n: m64.step(n), args.steps, torch.cuda.synchronize)
@@ -147,9 +188,22 @@ def main():
         log(f"FP64 plain: {secs64 / args.steps * 1e3:.3f} ms/step, {gcups64:.2f} Gcell-updates/s")
         result["fp64_plain"] = {"value": round(gcups64, 4), "unit": "Gcell-updates/s",
                                 "ms_per_step": round(secs64 / args.steps * 1e3, 4),
-                                "step_hbm_frac": round(gcups64 * step_bytes_per_update(40) / HBM_PEAK_GBS, 4),
+                                "step_hbm_frac": round(gcups64 * step_bytes_per_update(S64, False) / HBM_PEAK_GBS, 4),
                                 "batched_fp32_over_plain_fp64": round(gcups32 / gcups64, 3)}
         del m64
+        torch.cuda.empty_cache()
+        # ---------------- FP64 batched, for reference
+        m64 = make(f4.F64)
+        b64 = f4.Batch([m64])
+        cfg64 = b64.autotune(args.tune_cache)
+        b64.step(args.warmup)
+        secs64b, _ = timed_steps(b64.step, args.steps, torch.cuda.synchronize)
+        gcups64b = cells * 2 * args.steps / secs64b / 1e9
+        log(f"FP64 batched: {secs64b / args.steps * 1e3:.3f} ms/step, {gcups64b:.2f} Gcell-updates/s")
+        result["fp64_batched"] = {"value": round(gcups64b, 4), "unit": "Gcell-updates/s",
+                                  "ms_per_step": round(secs64b / args.steps * 1e3, 4), "config": list(cfg64),
+                                  "step_hbm_frac": round(gcups64b * step_bytes_per_update(S64, True) / HBM_PEAK_GBS, 4)}
+        del b64, m64
         torch.cuda.empty_cache()
 
     # ---------------- CPU baseline: the FP64 oracle on a bounded sample

@@ -8,16 +8,24 @@
 namespace f4 {
 
 // Generalized minmod G(a, b, theta = 1) (eq. gminmod): zero unless a and b
-// have the same strict sign, else the one of smaller magnitude.  Branch-free:
-// equal sign bits select copysign(min(|a|, |b|), a), which is +-0 when either
-// argument is zero; different sign bits give 0.
-__device__ __forceinline__ float minmod(float a, float b) {
-  const float m = copysignf(fminf(fabsf(a), fabsf(b)), a);
-  return ((__float_as_uint(a) ^ __float_as_uint(b)) >> 31) ? 0.0f : m;
-}
+// have the same strict sign, else the one of smaller magnitude.  That value is
+// the median of {0, a, b}: for equal signs the argument closer to zero, for
+// opposite signs zero.  FP32: one v_med3_f32; FP64: min/max of the median.
+__device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(0.0f, a, b); }
 __device__ __forceinline__ double minmod(double a, double b) {
-  const double m = copysign(fmin(fabs(a), fabs(b)), a);
-  return ((__double_as_longlong(a) ^ __double_as_longlong(b)) < 0) ? 0.0 : m;
+  return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
+}
+
+// sqrt(r) and 1/r of a positive density from one reciprocal square root
+// (FP32), or IEEE square root and division (FP64).
+__device__ __forceinline__ void sqrt_and_rcp(float r, float &s, float &ir) {
+  const float q = __builtin_amdgcn_rsqf(r);
+  s = r * q;
+  ir = q * q;
+}
+__device__ __forceinline__ void sqrt_and_rcp(double r, double &s, double &ir) {
+  s = sqrt(r);
+  ir = 1.0 / r;
 }
 
 // Reciprocal and square root: the hardware approximations (about 1 ulp) for
@@ -58,9 +66,11 @@ __device__ __forceinline__ void rusanov(const T *WL, const T *WR, T gamma, T *F)
   const T pl = WL[NV - 1], pr = WR[NV - 1];
   const T vl = WL[1 + AX], vr = WR[1 + AX];
   // wave speed first, so the per-component flux needs few live registers
-  const T sl = fsqrt(rl), sr = fsqrt(rr);
+  T sl, sr, irl, irr;
+  sqrt_and_rcp(rl, sl, irl);
+  sqrt_and_rcp(rr, sr, irr);
   const T is = frcp(sl + sr);
-  const T cl2 = fdiv(gamma * pl, rl), cr2 = fdiv(gamma * pr, rr);
+  const T cl2 = gamma * pl * irl, cr2 = gamma * pr * irr;
   const T ubar = (sl * vl + sr * vr) * is;
   const T eta2 = T(0.5) * sl * sr * is * is;
   const T dv = vr - vl;

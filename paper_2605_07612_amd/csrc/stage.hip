@@ -246,45 +246,47 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       if (k == N - 1) store_bflux(5, I, J, Fz1);
     }
 
-    // x and y faces of the plane, flattened over the sub-tile's threads
-#pragma unroll 1
-    for (int e = lt; e < 2 * NFX; e += TT) {
-      T F[NV];
-      if (e < NFX) {
-        const int fi = e % (TILE + 1), fj = e / (TILE + 1);
-        T A0[NV], A1[NV], A2[NV], A3[NV];
-        const int base = (fj + 2) * LP + fi;  // cell fi - 2
+    // x and y faces of the plane: every thread computes the -x and the -y
+    // face of its cell; the TILE extra +x faces of the last column go to the
+    // first TILE lanes and the TILE extra +y faces of the last row to the
+    // lanes of the next wave (TILE 16), so that no wave mixes x and y faces.
+    auto xface = [&](int fi, int fj) {
+      T A0[NV], A1[NV], A2[NV], A3[NV], F[NV];
+      const int base = (fj + 2) * LP + fi;  // cell fi - 2
 #pragma unroll
-        for (int v = 0; v < NV; v++) {
-          A0[v] = Wp[v * PLANE + base];
-          A1[v] = Wp[v * PLANE + base + 1];
-          A2[v] = Wp[v * PLANE + base + 2];
-          A3[v] = Wp[v * PLANE + base + 3];
-        }
-        face_flux<T, NDIM, 0>(A0, A1, A2, A3, gamma, F);
-#pragma unroll
-        for (int v = 0; v < NV; v++) FX[(v * TILE + fj) * (TILE + 1) + fi] = F[v];
-        if (fi == 0 && i0 == 0) store_bflux(0, j0 + fj, k, F);
-        if (fi == TILE && i0 + TILE == N) store_bflux(1, j0 + fj, k, F);
-      } else {
-        const int e2 = e - NFX;
-        const int fi = e2 % TILE, fj = e2 / TILE;
-        T A0[NV], A1[NV], A2[NV], A3[NV];
-        const int base = fj * LP + fi + 2;  // cell fj - 2
-#pragma unroll
-        for (int v = 0; v < NV; v++) {
-          A0[v] = Wp[v * PLANE + base];
-          A1[v] = Wp[v * PLANE + base + LP];
-          A2[v] = Wp[v * PLANE + base + 2 * LP];
-          A3[v] = Wp[v * PLANE + base + 3 * LP];
-        }
-        face_flux<T, NDIM, 1>(A0, A1, A2, A3, gamma, F);
-#pragma unroll
-        for (int v = 0; v < NV; v++) FY[(v * (TILE + 1) + fj) * TILE + fi] = F[v];
-        if (fj == 0 && j0 == 0) store_bflux(2, i0 + fi, k, F);
-        if (fj == TILE && j0 + TILE == N) store_bflux(3, i0 + fi, k, F);
+      for (int v = 0; v < NV; v++) {
+        A0[v] = Wp[v * PLANE + base];
+        A1[v] = Wp[v * PLANE + base + 1];
+        A2[v] = Wp[v * PLANE + base + 2];
+        A3[v] = Wp[v * PLANE + base + 3];
       }
-    }
+      face_flux<T, NDIM, 0>(A0, A1, A2, A3, gamma, F);
+#pragma unroll
+      for (int v = 0; v < NV; v++) FX[(v * TILE + fj) * (TILE + 1) + fi] = F[v];
+      if (fi == 0 && i0 == 0) store_bflux(0, j0 + fj, k, F);
+      if (fi == TILE && i0 + TILE == N) store_bflux(1, j0 + fj, k, F);
+    };
+    auto yface = [&](int fi, int fj) {
+      T A0[NV], A1[NV], A2[NV], A3[NV], F[NV];
+      const int base = fj * LP + fi + 2;  // cell fj - 2
+#pragma unroll
+      for (int v = 0; v < NV; v++) {
+        A0[v] = Wp[v * PLANE + base];
+        A1[v] = Wp[v * PLANE + base + LP];
+        A2[v] = Wp[v * PLANE + base + 2 * LP];
+        A3[v] = Wp[v * PLANE + base + 3 * LP];
+      }
+      face_flux<T, NDIM, 1>(A0, A1, A2, A3, gamma, F);
+#pragma unroll
+      for (int v = 0; v < NV; v++) FY[(v * (TILE + 1) + fj) * TILE + fi] = F[v];
+      if (fj == 0 && j0 == 0) store_bflux(2, i0 + fi, k, F);
+      if (fj == TILE && j0 + TILE == N) store_bflux(3, i0 + fi, k, F);
+    };
+    xface(ti, tj);
+    yface(ti, tj);
+    constexpr int YX = (TT >= 64 + TILE && TILE == 16) ? 64 : TILE;  // first lane of the extra y faces
+    if (lt < TILE) xface(TILE, lt);
+    else if (lt >= YX && lt < YX + TILE) yface(lt - YX, TILE);
     __syncthreads();
 
     // conservative update of the own cell (eq. feuler with Heun weights)
@@ -356,10 +358,15 @@ __device__ __forceinline__ int64_t item_of(int64_t w, int64_t it, int64_t grid, 
   return j < per_xcd ? (w & 7) * per_xcd + j : total;
 }
 
+// Target waves per SIMD: 3 for single-size FP32 kernels (167 VGPRs, no
+// spills); the mixed-size and FP64 kernels keep what their registers allow.
+template <typename T, int NM>
+constexpr int stage_waves() { return (sizeof(T) == 4 && NM != 7) ? 3 : 1; }
+
 // NM: bit mask of the block sizes present (1: N = 8, 2: N = 16, 4: N = 32)
 template <typename T, int NDIM, int NM>
-__global__ __launch_bounds__(256) void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes,
-                                                    int64_t total, int stage, int xcd) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM>())))
+void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t total, int stage, int xcd) {
   __shared__ T smem[smem_cells<NDIM>()];
   double vmax = 0.0;
   bool bad = false;
