@@ -70,6 +70,11 @@ def traffic_from_counters(path, stage_launch_bytes):
     same counter read the known size of a plain 1 GiB device copy."""
     try:
         d = json.load(open(path))
+        import hashlib
+        csrc = os.path.join(ROOT, "paper_2605_07612_amd", "csrc")
+        src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("stage.hip", "device_common.h"))
+        if hashlib.sha256(src).hexdigest() != d["source_sha256"]:
+            return None  # the kernel changed since the counters were taken
         fetch = d["stage_fetch_kib"] * d["fetch_scale"]
         write = d["stage_write_kib"] * d["write_scale"]
         return {"bytes_per_launch": int((fetch + write) * 1024), "fetch_kib": round(fetch, 1),
@@ -88,12 +93,14 @@ def main():
     ap.add_argument("--block", type=int, default=16)
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-batch64", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for hardware-counter passes: a 1 GiB device copy (counter calibration) "
                          "then 3 batched FP32 steps in the tuned configuration")
-    ap.add_argument("--config", default="1,3,0", help="kslabs,wg_per_cu,xcd_order of --profile-run")
+    ap.add_argument("--config", default=None,
+                    help="kslabs,wg_per_cu,xcd_order instead of autotuning (--profile-run default: 1,3,0)")
     ap.add_argument("--counters", default=os.path.join(ROOT, "profiles", "stage_traffic_noise_shear_256cubed_b16.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -127,7 +134,7 @@ def main():
         del a, bb
         m32 = make(f4.F32)
         batch = f4.Batch([m32])
-        ks, wg, xcd = (int(x) for x in args.config.split(","))
+        ks, wg, xcd = (int(x) for x in (args.config or "1,3,0").split(","))
         batch.set_config(ks, wg, xcd, 1)
         batch.step(3)
         torch.cuda.synchronize()
@@ -139,7 +146,11 @@ def main():
     # ---------------- FP32 batched: persistent + graph + autotuned
     m32 = make(f4.F32)
     batch = f4.Batch([m32])
-    ks, wg, xcd = batch.autotune(args.tune_cache)
+    if args.config:
+        ks, wg, xcd = (int(x) for x in args.config.split(","))
+        batch.set_config(ks, wg, xcd, 1)
+    else:
+        ks, wg, xcd = batch.autotune(args.tune_cache)
     log(f"autotune: kslabs={ks} wg_per_cu={wg} xcd_order={xcd}")
     batch.step(args.warmup)
     secs, wall = timed_steps(batch.step, args.steps, torch.cuda.synchronize)
@@ -204,6 +215,31 @@ def main():
                                   "ms_per_step": round(secs64b / args.steps * 1e3, 4), "config": list(cfg64),
                                   "step_hbm_frac": round(gcups64b * step_bytes_per_update(S64, True) / HBM_PEAK_GBS, 4)}
         del b64, m64
+        torch.cuda.empty_cache()
+
+    # ---------------- the 64-problem batch (mixed 8^3/16^3/32^3 blocks), FP32
+    if not args.skip_batch64:
+        ws = [synth.batch_problem(p) for p in range(64)]
+        ms = []
+        for wp in ws:
+            m = f4.Mesh(3, wp["trees"], wp["N"], wp["g"], wp["tree_size"], prec=f4.F32, gamma=wp["gamma"],
+                        cfl=wp["cfl"])
+            layout.set_from_field_device(m, wp["field"])
+            ms.append(m)
+        cells64 = sum(int(np.prod(wp["trees"])) * wp["N"] ** 3 for wp in ws)
+        b64 = f4.Batch(ms)
+        cfg = b64.autotune(args.tune_cache)
+        b64.step(args.warmup)
+        s64, _ = timed_steps(b64.step, args.steps, torch.cuda.synchronize)
+        g64 = cells64 * 2 * args.steps / s64 / 1e9
+        ph64 = b64.phase_times(3)
+        log(f"batch of 64: {s64 / args.steps * 1e3:.3f} ms/step, {g64:.2f} Gcell-updates/s, config {cfg}")
+        result["batch64"] = {"value": round(g64, 4), "unit": "Gcell-updates/s", "problems": 64,
+                             "blocks": int(sum(m.nb for m in ms)), "cells": int(cells64),
+                             "ms_per_step": round(s64 / args.steps * 1e3, 4), "config": list(cfg),
+                             "stage_ms": round(ph64["stage"], 4),
+                             "step_hbm_frac": round(g64 * step_bytes_per_update(S32, True) / HBM_PEAK_GBS, 4)}
+        del b64, ms
         torch.cuda.empty_cache()
 
     # ---------------- CPU baseline: the FP64 oracle on a bounded sample

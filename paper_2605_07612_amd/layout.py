@@ -48,6 +48,29 @@ def set_from_field(mesh, field):
     set_interior(mesh, np.moveaxis(vals, 0, 1))
 
 
+def set_from_field_device(mesh, field):
+    """Evaluate field(x, y[, z], xp=torch) at the cell centres on the device
+    (float64 torch tensors) and store it: for initial data too large to
+    build on the host."""
+    torch = __import__("torch")
+    dev = mesh.state[0].device
+    lev, G = global_coords(mesh)
+    N, ndim, nb = mesh.N, mesh.ndim, len(lev)
+    ts = mesh.desc.tree_size
+    org = list(mesh.desc.origin)
+    dx = torch.tensor(ts / (N * (2.0 ** lev)), dtype=torch.float64, device=dev)
+    Gt = torch.tensor(G, dtype=torch.float64, device=dev)
+    idx = torch.arange(N, dtype=torch.float64, device=dev) + 0.5
+    coords = []
+    for d in range(ndim):
+        c = org[d] + (Gt[:, d, None] * N + idx[None, :]) * dx[:, None]  # [nb][N]
+        shape = [nb] + [1] * ndim
+        shape[ndim - d] = N
+        coords.append(c.reshape(shape).expand((nb,) + (N,) * ndim))
+    vals = field(*coords, xp=torch)  # [nvar][nb][N..]
+    mesh.interior().copy_(vals.movedim(0, 1).to(mesh.dtype))
+
+
 def set_from_grid(mesh, grid):
     """grid: [nvar][nz][ny][nx] (or [nvar][ny][nx]) on a uniform-level mesh."""
     lev, G = global_coords(mesh)

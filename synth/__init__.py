@@ -47,13 +47,18 @@ def uniform01(seed: int, n: int, start: int = 0) -> np.ndarray:
     return (x >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
 
 
-def conserved_from_primitive(rho, vel, p, gamma):
-    """Stack (rho, rho*v_d..., E) for the given primitive fields."""
-    rho = np.asarray(rho, dtype=np.float64)
-    mom = [rho * np.asarray(v, dtype=np.float64) for v in vel]
-    ke = 0.5 * sum(m * np.asarray(v, dtype=np.float64) for m, v in zip(mom, vel))
-    E = np.asarray(p, dtype=np.float64) / (gamma - 1.0) + ke
-    return np.stack([rho * np.ones_like(E)] + [m * np.ones_like(E) for m in mom] + [E])
+def conserved_from_primitive(rho, vel, p, gamma, xp=np):
+    """Stack (rho, rho*v_d..., E) for the given primitive fields (xp: numpy
+    or torch, for inputs that live on the host or on the device)."""
+    if xp is np:
+        rho = np.asarray(rho, dtype=np.float64)
+        vel = [np.asarray(v, dtype=np.float64) for v in vel]
+        p = np.asarray(p, dtype=np.float64)
+    mom = [rho * v for v in vel]
+    ke = 0.5 * sum(m * v for m, v in zip(mom, vel))
+    E = p / (gamma - 1.0) + ke
+    one = xp.ones_like(E)
+    return xp.stack([rho * one] + [m * one for m in mom] + [E])
 
 
 # --------------------------------------------------------------------------
@@ -177,22 +182,23 @@ def batch_problem(p: int):
     mr = modes(2)
     mp = modes(22)
 
-    def smooth(x, y, z, mo):
+    def smooth(x, y, z, mo, xp):
         ks, amps, phis = mo
-        s = np.zeros_like(x)
+        s = xp.zeros_like(x)
         for k, a, ph in zip(ks, amps, phis):
-            s = s + a * np.sin(2 * np.pi * (k[0] * x / L[0] + k[1] * y / L[1] + k[2] * z / L[2]) + ph)
+            s = s + a * xp.sin(2 * np.pi * (k[0] * x / L[0] + k[1] * y / L[1] + k[2] * z / L[2]) + ph)
         return s
 
-    def field(x, y, z):
-        sr = smooth(x, y, z, mr)
-        sp = smooth(x, y, z, mp)
-        mr_ = np.max(np.abs(sr))
-        mp_ = np.max(np.abs(sp))
+    def field(x, y, z, xp=np):
+        """xp = numpy (host) or torch (device tensors)."""
+        sr = smooth(x, y, z, mr, xp)
+        sp = smooth(x, y, z, mp, xp)
+        mr_ = float(xp.max(xp.abs(sr)))
+        mp_ = float(xp.max(xp.abs(sp)))
         rho = 1.25 + 0.75 * (sr / mr_ if mr_ > 0 else 0.0 * sr)
         pr = 1.25 + 0.75 * (sp / mp_ if mp_ > 0 else 0.0 * sp)
-        zero = np.zeros_like(x)
-        return conserved_from_primitive(rho, [zero, zero, zero], pr, gamma)
+        zero = xp.zeros_like(x)
+        return conserved_from_primitive(rho, [zero, zero, zero], pr, gamma, xp)
 
     return dict(name=f"batch_p{p}", ndim=3, trees=(nx, ny, nz), N=N, g=2, tree_size=ts,
                 level=0, gamma=gamma, cfl=0.5, field=field, steps=20)
