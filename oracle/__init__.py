@@ -59,6 +59,7 @@ def lib():
         _lib.om_lohner_flags.argtypes = [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, P]
         _lib.om_remap.argtypes = [P, P, P, P, P, P, P]
+        _lib.om_block_raw_features.argtypes = [P, P, P]
     return _lib
 
 
@@ -198,6 +199,12 @@ class OracleMesh:
         lib().om_lohner_flags(self.cref(), _ptr(self.u if u is None else u), c["c_ref"],
                               c["c_deref"], c["eps"], c["eps_abs"], _ptr(flags))
         return flags
+
+    def raw_features(self, u=None):
+        """[nb][2]: max |grad rho|/rho and max |grad p|/p per block (face ghosts needed)."""
+        r = np.zeros((self.nb, 2))
+        lib().om_block_raw_features(self.cref(), _ptr(self.u if u is None else u), _ptr(r))
+        return r
 
     def regrid(self, flags, lmin, lmax):
         """Adapt the mesh and remap the state (old ghosts are filled first).

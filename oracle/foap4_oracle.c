@@ -553,6 +553,40 @@ void om_lohner_flags(const om_mesh *m, const double *u, double c_ref, double c_d
   }
 }
 
+/* --------------------------------------------- learned-indicator features */
+
+/* Per-block raw inputs of the learned refinement indicator: r[2b] = max over
+ * interior cells of |grad_c rho| / rho and r[2b+1] = max of |grad_c p| / p,
+ * with grad_c the undivided central difference (u_+ - u_-)/2 along each axis
+ * (norm over the axes, summed in axis order).  Needs the face ghosts. */
+void om_block_raw_features(const om_mesh *m, const double *u, double *r) {
+  int N = m->N, nk = (m->ndim == 3) ? N : 1;
+  for (int64_t b = 0; b < m->nb; b++) {
+    double best_r = 0.0, best_p = 0.0;
+    for (int k = 0; k < nk; k++)
+      for (int j = 0; j < N; j++)
+        for (int i = 0; i < N; i++) {
+          int c[3] = {i, j, k};
+          prim_t w = to_primitive(m, u, b, c);
+          double sr = 0.0, sp = 0.0;
+          for (int d = 0; d < m->ndim; d++) {
+            int lo[3] = {i, j, k}, hi[3] = {i, j, k};
+            lo[d] -= 1;
+            hi[d] += 1;
+            prim_t wl = to_primitive(m, u, b, lo), wh = to_primitive(m, u, b, hi);
+            double dr = 0.5 * (wh.rho - wl.rho), dp = 0.5 * (wh.p - wl.p);
+            sr = (d == 0) ? dr * dr : sr + dr * dr;
+            sp = (d == 0) ? dp * dp : sp + dp * dp;
+          }
+          double gr = sqrt(sr) / w.rho, gp = sqrt(sp) / w.p;
+          if (gr > best_r) best_r = gr;
+          if (gp > best_p) best_p = gp;
+        }
+    r[2 * b] = best_r;
+    r[2 * b + 1] = best_p;
+  }
+}
+
 /* ------------------------------------------------------------ regrid remap */
 
 /* Data transfer after a mesh change (Sec. 2.2): for each new block n,
