@@ -37,6 +37,7 @@ extern "C" {
 
 typedef struct foap4_mesh foap4_mesh;   /* opaque, library-owned */
 typedef struct foap4_batch foap4_batch; /* opaque, library-owned */
+typedef struct foap4_mlp foap4_mlp;     /* opaque, library-owned */
 
 typedef enum {
   FOAP4_OK = 0,
@@ -145,9 +146,14 @@ foap4_status foap4_time(foap4_mesh *mesh, double *t_out, double *dt_out);
 foap4_status foap4_conserved_totals(foap4_mesh *mesh, double *out);
 
 /* Per-block refinement flags (+1 refine, 0 keep, -1 derefine; Sec. 2.2) of
- * the current state, written to flags_host[n_blocks].  FOAP4_IND_LOHNER is
- * the paper's criterion (Sec. 3.3, eq. lohner-simple, constants of Sec. 5.4)
- * on the density, in FP64; it fills ghosts first. */
+ * the current state, written to flags_host[n_blocks].  Both indicators fill
+ * ghosts first.  FOAP4_IND_LOHNER is the paper's criterion (Sec. 3.3, eq.
+ * lohner-simple, constants of Sec. 5.4) on the density, in FP64.
+ * FOAP4_IND_MLP needs an MLP attached with foap4_mesh_set_indicator and
+ * holding weights (else FOAP4_E_ORDER): features (foap4_block_features), the
+ * network, flag = argmax class - 1 where the largest class probability is
+ * at least the MLP's threshold, and the Lohner flag elsewhere (computed only
+ * for those blocks). */
 foap4_status foap4_refine_flags(foap4_mesh *mesh, foap4_indicator ind, int8_t *flags_host);
 
 /* Adapts the mesh (Sec. 2.2): refine every +1 block below max_level, then
@@ -156,10 +162,90 @@ foap4_status foap4_refine_flags(foap4_mesh *mesh, foap4_indicator ind, int8_t *f
  * whose parent stays within one level of its neighbours.  The state is
  * remapped on the device (copy, limited prolongation, restriction) into the
  * other buffer, which becomes current; the pattern is rebuilt.  flags_host
- * may be NULL (then the Lohner flags are computed).  *changed (may be NULL)
+ * may be NULL (then the indicator chosen with foap4_mesh_set_indicator,
+ * Lohner by default, computes them).  *changed (may be NULL)
  * is 1 if the mesh changed.  FOAP4_E_CAPACITY (mesh unchanged) if the new
  * mesh would exceed max_blocks. */
 foap4_status foap4_regrid(foap4_mesh *mesh, const int8_t *flags_host, int32_t *changed);
+
+/* ----------------------------------------------- learned refinement indicator
+ * Not part of the paper's method: a small network that predicts the flags of
+ * its gradient criterion (Sec. 3.3) from per-block features, with that
+ * criterion kept as fallback.  Features, 16 per block, all computed on the
+ * device from the current state with ghosts filled, with r0 = max over the
+ * block's interior cells of |(rho(x+e_d) - rho(x-e_d)) / 2|_2 / rho(x) (norm
+ * over the axes d, undivided central differences) and r1 the same for the
+ * pressure p:
+ *   f0 = log(1 + r0), f1 = log(1 + r1), f2 = level / max(max_level, 1),
+ *   f(3+2k), f(4+2k) = f0, f1 of the neighbour across face k (order -x, +x,
+ *   -y, +y, -z, +z; maximum over the finer blocks of a refined face; 0 in 2D
+ *   for k >= 4), f15 = 0.
+ * Network: 16 -> 64 (ReLU) -> 64 (ReLU) -> 3 logits of the classes -1, 0, +1.
+ * Parameters, FP32, flat in this order (row-major matrices, input index
+ * first): W1[16][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3].  The
+ * three products run on the matrix cores with BF16 operands (weights,
+ * inputs, activations and back-propagated errors rounded to nearest even)
+ * and FP32 accumulation; biases stay FP32. */
+#define FOAP4_MLP_NIN 16
+#define FOAP4_MLP_NHID 64
+#define FOAP4_MLP_NOUT 3
+#define FOAP4_MLP_NPARAM 5443
+
+/* Features of the current state: fills ghosts, then writes feat_dev
+ * [n_blocks][16] FP32 and, if raw_dev is non-NULL, raw_dev[n_blocks][2] =
+ * (r0, r1) in FP64 (evaluated in FP64 in the operation order of the
+ * definition above, with v = m / rho and p = (gamma - 1)(E - m.v / 2)).
+ * Device buffers owned by the caller; feat_dev 16-byte aligned.  Enqueue only. */
+foap4_status foap4_block_features(foap4_mesh *mesh, float *feat_dev, double *raw_dev);
+
+/* Chooses the indicator foap4_regrid uses when flags_host is NULL, and
+ * attaches net (may be NULL for FOAP4_IND_LOHNER) for FOAP4_IND_MLP.  The
+ * network is referenced, not copied: it must outlive the attachment, and its
+ * work must be ordered with the mesh's stream by the caller. */
+foap4_status foap4_mesh_set_indicator(foap4_mesh *mesh, foap4_indicator ind, const foap4_mlp *net);
+
+/* Number of blocks of the last FOAP4_IND_MLP flag computation that fell back
+ * to the Lohner flag. */
+foap4_status foap4_indicator_fallbacks(const foap4_mesh *mesh, int64_t *n_fallback);
+
+/* A network with no weights yet, working on hip_stream (a hipStream_t, NULL:
+ * default stream).  Holds the FP32 master weights, FP64 Adam moments and the
+ * training workspace in device memory. */
+foap4_status foap4_mlp_create(void *hip_stream, foap4_mlp **out);
+foap4_status foap4_mlp_destroy(foap4_mlp *net);
+
+/* Copies n = FOAP4_MLP_NPARAM FP32 parameters from w_host (layout above),
+ * resets the Adam moments and step count.  Synchronizes. */
+foap4_status foap4_mlp_set_params(foap4_mlp *net, const float *w_host, int64_t n);
+
+/* Copies the current FP32 parameters to w_host[n], n = FOAP4_MLP_NPARAM.
+ * Synchronizes. */
+foap4_status foap4_mlp_get_params(foap4_mlp *net, float *w_host, int64_t n);
+
+/* Smallest largest-class probability at which the network's flag is used
+ * (default 0.5; 0 never falls back). */
+foap4_status foap4_mlp_set_threshold(foap4_mlp *net, float threshold);
+
+/* Logits of n feature rows: feat_dev[n][16] -> logits_dev[n][3] (FP32,
+ * device, caller-owned, feat_dev 16-byte aligned).  Enqueue only. */
+foap4_status foap4_mlp_forward(foap4_mlp *net, const float *feat_dev, int64_t n, float *logits_dev);
+
+/* Class-weighted cross-entropy sum_s w(c_s) CE_s / sum_s w(c_s) of n rows
+ * with labels label_dev[n] in {-1, 0, +1} (class = label + 1, weights
+ * class_w[3] on the host, each >= 0 with a positive total) and its gradient
+ * with respect to the parameters, written to loss_host and grad_host
+ * [FOAP4_MLP_NPARAM] (either may be NULL).  The sum over rows is
+ * deterministic: per-workgroup partials reduced in a fixed order in FP64.
+ * FOAP4_E_INVALID for a label outside {-1, 0, +1}.  Synchronizes. */
+foap4_status foap4_mlp_loss_grad(foap4_mlp *net, const float *feat_dev, const int8_t *label_dev, int64_t n,
+                                 const float *class_w, double *loss_host, float *grad_host);
+
+/* iters full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning
+ * rate lr) on the loss above, all on the device; loss_host[iters] (may be
+ * NULL) receives the loss before each step.  Synchronizes once at the start
+ * (label check) and once at the end. */
+foap4_status foap4_mlp_train(foap4_mlp *net, const float *feat_dev, const int8_t *label_dev, int64_t n,
+                             const float *class_w, int32_t iters, float lr, double *loss_host);
 
 /* ------------------------------------------------------------------ batch
  * Many independent meshes of one precision advanced together: one

@@ -60,8 +60,21 @@ EXPORTS = {
     "foap4_batch_autotune": (I32, [P, ctypes.c_char_p, P]),
     "foap4_batch_step": (I32, [P, I32]),
     "foap4_batch_phase_times": (I32, [P, I32, P]),
+    "foap4_block_features": (I32, [P, P, P]),
+    "foap4_mesh_set_indicator": (I32, [P, I32, P]),
+    "foap4_indicator_fallbacks": (I32, [P, P]),
+    "foap4_mlp_create": (I32, [P, ctypes.POINTER(P)]),
+    "foap4_mlp_destroy": (I32, [P]),
+    "foap4_mlp_set_params": (I32, [P, P, I64]),
+    "foap4_mlp_get_params": (I32, [P, P, I64]),
+    "foap4_mlp_set_threshold": (I32, [P, ctypes.c_float]),
+    "foap4_mlp_forward": (I32, [P, P, I64, P]),
+    "foap4_mlp_loss_grad": (I32, [P, P, P, I64, P, P, P]),
+    "foap4_mlp_train": (I32, [P, P, P, I64, P, I32, ctypes.c_float, P]),
     "foap4_last_error": (ctypes.c_char_p, [P]),
 }
+
+MLP_NIN, MLP_NHID, MLP_NOUT, MLP_NPARAM = 16, 64, 3, 5443
 
 
 def lib():
@@ -225,6 +238,26 @@ class Mesh:
         _check(lib().foap4_refine_flags(self.h, indicator, _ptr(f)), self.h)
         return f
 
+    def block_features(self, raw=False):
+        """Per-block features [nb][16] (FP32, device); with raw=True also the
+        FP64 raw maxima [nb][2]."""
+        torch = _torch()
+        nb = self.nb
+        feat = torch.empty((max(nb, 1), 16), dtype=torch.float32, device=self.state[0].device)
+        r = torch.empty((max(nb, 1), 2), dtype=torch.float64, device=self.state[0].device) if raw else None
+        _check(lib().foap4_block_features(self.h, P(feat.data_ptr()), P(r.data_ptr()) if raw else None), self.h)
+        return (feat[:nb], r[:nb]) if raw else feat[:nb]
+
+    def set_indicator(self, indicator, mlp=None):
+        """Indicator used by regrid() without flags; mlp is kept referenced."""
+        _check(lib().foap4_mesh_set_indicator(self.h, indicator, mlp.h if mlp is not None else None), self.h)
+        self._mlp = mlp
+
+    def fallbacks(self):
+        n = ctypes.c_int64()
+        _check(lib().foap4_indicator_fallbacks(self.h, ctypes.byref(n)), self.h)
+        return n.value
+
     def regrid(self, flags=None):
         ch = ctypes.c_int32()
         fl = None if flags is None else np.ascontiguousarray(flags, dtype=np.int8)
@@ -285,3 +318,83 @@ class Batch:
         out = np.zeros(8)
         _check(lib().foap4_batch_phase_times(self.h, n, _ptr(out)))
         return dict(zip(self.PHASES, out.tolist()))
+
+
+class Mlp:
+    """The learned refinement indicator's network: FP32 master weights and
+    training state in device memory, BF16 matrix-core kernels."""
+
+    def __init__(self, weights=None, stream=None):
+        torch = _torch()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(lib().foap4_mlp_create(P(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        if weights is not None:
+            self.set_params(weights)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().foap4_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(lib().foap4_mlp_set_params(self.h, _ptr(w), w.size))
+
+    def get_params(self):
+        w = np.zeros(MLP_NPARAM, np.float32)
+        _check(lib().foap4_mlp_get_params(self.h, _ptr(w), w.size))
+        return w
+
+    def set_threshold(self, thr):
+        _check(lib().foap4_mlp_set_threshold(self.h, float(thr)))
+
+    @staticmethod
+    def _rows(x):
+        torch = _torch()
+        if x.dtype != torch.float32 or x.dim() != 2 or x.shape[1] != 16 or not x.is_cuda:
+            raise ValueError("features must be a float32 CUDA tensor [n][16]")
+        return x.contiguous()
+
+    @staticmethod
+    def _labels(y, n):
+        torch = _torch()
+        if y.dtype != torch.int8 or y.numel() != n or not y.is_cuda:
+            raise ValueError("labels must be an int8 CUDA tensor of n entries")
+        return y.contiguous()
+
+    def forward(self, x):
+        """Logits [n][3] of feature rows x [n][16] (device tensors)."""
+        torch = _torch()
+        x = self._rows(x)
+        out = torch.empty((max(x.shape[0], 1), 3), dtype=torch.float32, device=x.device)
+        _check(lib().foap4_mlp_forward(self.h, P(x.data_ptr()), x.shape[0], P(out.data_ptr())))
+        return out[: x.shape[0]]
+
+    def loss_grad(self, x, y, class_w=(1.0, 1.0, 1.0)):
+        """(loss, gradient[NPARAM]) of the class-weighted cross-entropy."""
+        x = self._rows(x)
+        y = self._labels(y, x.shape[0])
+        cw = np.ascontiguousarray(class_w, dtype=np.float32)
+        loss = ctypes.c_double()
+        g = np.zeros(MLP_NPARAM, np.float32)
+        _check(lib().foap4_mlp_loss_grad(self.h, P(x.data_ptr()), P(y.data_ptr()), x.shape[0], _ptr(cw),
+                                         ctypes.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def train(self, x, y, iters, lr=1e-3, class_w=(1.0, 1.0, 1.0)):
+        """iters full-batch Adam steps; returns the loss before each step."""
+        x = self._rows(x)
+        y = self._labels(y, x.shape[0])
+        cw = np.ascontiguousarray(class_w, dtype=np.float32)
+        losses = np.zeros(max(iters, 1))
+        _check(lib().foap4_mlp_train(self.h, P(x.data_ptr()), P(y.data_ptr()), x.shape[0], _ptr(cw), iters,
+                                     float(lr), _ptr(losses)))
+        return losses[:iters]

@@ -212,7 +212,7 @@ foap4_status foap4_mesh_destroy(foap4_mesh *m) {
   if (m->stream) (void)hipStreamSynchronize(m->stream);
   void *ptrs[] = {m->d_level, m->d_gc, m->d_keys, m->d_scal, m->d_dev, m->d_item_begin,
                   m->pat.srl, m->pat.f2c, m->pat.c2f, m->pat.bc, m->pat.face_info, m->pat.fix_list,
-                  m->pat.cnt, m->pat.tot, m->pat.bflux_f, m->pat.bflux_c};
+                  m->pat.cnt, m->pat.tot, m->pat.bflux_f, m->pat.bflux_c, m->d_ind};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -323,19 +323,85 @@ foap4_status foap4_conserved_totals(foap4_mesh *m, double *out) {
   return FOAP4_OK;
 }
 
+// indicator scratch of nb blocks: raw [nb][2] FP64, features [nb][16] FP32,
+// flags [nb], decisions [nb]
+struct IndScratch {
+  double *raw;
+  float *feat;
+  int8_t *flags, *decided;
+};
+
+static foap4_status ind_scratch(foap4_mesh *m, IndScratch &S) {
+  const size_t nb = std::max<size_t>(1, m->topo.leaves.size());
+  const size_t a = (nb * 16 + 255) & ~(size_t)255, b = (nb * 64 + 255) & ~(size_t)255, c = (nb + 255) & ~(size_t)255;
+  const size_t bytes = a + b + 2 * c;
+  if (m->cap_ind < bytes) {
+    if (m->d_ind) F4_HIP(m, hipFree(m->d_ind));
+    m->d_ind = nullptr;
+    m->cap_ind = 0;
+    F4_HIP(m, hipMalloc(&m->d_ind, bytes));
+    m->cap_ind = bytes;
+  }
+  char *p = (char *)m->d_ind;
+  S.raw = (double *)p;
+  S.feat = (float *)(p + a);
+  S.flags = (int8_t *)(p + a + b);
+  S.decided = (int8_t *)(p + a + b + c);
+  return FOAP4_OK;
+}
+
+foap4_status foap4_block_features(foap4_mesh *m, float *feat_dev, double *raw_dev) {
+  if (!m || !feat_dev) return fail(m, FOAP4_E_INVALID, "null argument");
+  if (((uintptr_t)feat_dev & 15u) != 0) return fail(m, FOAP4_E_INVALID, "features must be 16-byte aligned");
+  foap4_status st;
+  IndScratch S;
+  if (!raw_dev && (st = ind_scratch(m, S)) != FOAP4_OK) return st;
+  if ((st = fill(m, m->d_dev, 0)) != FOAP4_OK) return st;
+  F4_HIP(m, launch_block_features(m, raw_dev ? raw_dev : S.raw, feat_dev, m->stream));
+  return FOAP4_OK;
+}
+
+foap4_status foap4_mesh_set_indicator(foap4_mesh *m, foap4_indicator ind, const foap4_mlp *net) {
+  if (!m) return fail(nullptr, FOAP4_E_INVALID, "null mesh");
+  if (ind != FOAP4_IND_LOHNER && ind != FOAP4_IND_MLP) return fail(m, FOAP4_E_INVALID, "unknown indicator");
+  if (ind == FOAP4_IND_MLP && !net) return fail(m, FOAP4_E_INVALID, "the MLP indicator needs a network");
+  m->ind = ind;
+  m->mlp = net;
+  return FOAP4_OK;
+}
+
+foap4_status foap4_indicator_fallbacks(const foap4_mesh *m, int64_t *n_fallback) {
+  if (!m || !n_fallback) return fail(nullptr, FOAP4_E_INVALID, "null argument");
+  *n_fallback = m->n_fallback;
+  return FOAP4_OK;
+}
+
 foap4_status foap4_refine_flags(foap4_mesh *m, foap4_indicator ind, int8_t *flags_host) {
   if (!m || !flags_host) return fail(m, FOAP4_E_INVALID, "null argument");
-  if (ind != FOAP4_IND_LOHNER) return fail(m, FOAP4_E_INVALID, "indicator not available on this mesh");
+  if (ind != FOAP4_IND_LOHNER && ind != FOAP4_IND_MLP) return fail(m, FOAP4_E_INVALID, "unknown indicator");
+  if (ind == FOAP4_IND_MLP && (!m->mlp || !m->mlp->has_weights))
+    return fail(m, FOAP4_E_ORDER, "no MLP with weights attached to this mesh");
   const size_t nb = m->topo.leaves.size();
+  if (nb == 0) return FOAP4_OK;
   foap4_status st;
+  IndScratch S;
+  if ((st = ind_scratch(m, S)) != FOAP4_OK) return st;
   if ((st = fill(m, m->d_dev, 0)) != FOAP4_OK) return st;
-  int8_t *d_flags = nullptr;
-  F4_HIP(m, hipMalloc((void **)&d_flags, nb + 1));
-  hipError_t e = launch_lohner(m, d_flags, m->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(flags_host, d_flags, nb, hipMemcpyDeviceToHost, m->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
-  (void)hipFree(d_flags);
-  if (e != hipSuccess) return fail(m, FOAP4_E_HIP, std::string("lohner: ") + hipGetErrorString(e));
+  if (ind == FOAP4_IND_MLP) {
+    F4_HIP(m, launch_block_features(m, S.raw, S.feat, m->stream));
+    F4_HIP(m, launch_mlp_decide(m->mlp, S.feat, (int64_t)nb, S.flags, S.decided, m->stream));
+    F4_HIP(m, launch_lohner(m, S.flags, S.decided, m->stream));
+  } else {
+    F4_HIP(m, launch_lohner(m, S.flags, nullptr, m->stream));
+  }
+  F4_HIP(m, hipMemcpyAsync(flags_host, S.flags, nb, hipMemcpyDeviceToHost, m->stream));
+  std::vector<int8_t> dec;
+  if (ind == FOAP4_IND_MLP) {
+    dec.resize(nb);
+    F4_HIP(m, hipMemcpyAsync(dec.data(), S.decided, nb, hipMemcpyDeviceToHost, m->stream));
+  }
+  F4_HIP(m, hipStreamSynchronize(m->stream));
+  if (ind == FOAP4_IND_MLP) m->n_fallback = (int64_t)std::count(dec.begin(), dec.end(), (int8_t)0);
   return FOAP4_OK;
 }
 
@@ -347,7 +413,7 @@ foap4_status foap4_regrid(foap4_mesh *m, const int8_t *flags_host, int32_t *chan
   foap4_status st;
   if (flags_host) {
     std::memcpy(fl.data(), flags_host, nb);
-  } else if ((st = foap4_refine_flags(m, FOAP4_IND_LOHNER, fl.data())) != FOAP4_OK) {
+  } else if ((st = foap4_refine_flags(m, m->ind, fl.data())) != FOAP4_OK) {
     return st;
   }
   std::vector<Leaf> nl;

@@ -18,6 +18,13 @@ constexpr int kKeyLevel = 16;     // Morton key resolution per tree
 constexpr int kTypes = 4;         // SRL, F2C, C2F, BC
 enum { kSRL = 0, kF2C = 1, kC2F = 2, kBC = 3 };
 
+// learned indicator: 16 features -> 64 -> 64 -> 3 classes
+constexpr int kMlpIn = 16, kMlpHid = 64, kMlpOut = 3;
+constexpr int kOffW1 = 0, kOffB1 = 1024, kOffW2 = 1088, kOffB2 = 5184, kOffW3 = 5248, kOffB3 = 5440;
+constexpr int kMlpParams = 5443;
+constexpr int kMlpPartStride = 5448;  // partial gradient row: parameters, loss, padding
+constexpr int kMlpFrags = 26;         // 16x32 / 32x16 BF16 weight operand tiles
+
 // scal[] slots of a mesh (FP64, device)
 enum { kDt = 0, kTime = 1, kMaxInv = 2, kBad = 3, kNScal = 8 };
 
@@ -118,6 +125,32 @@ struct foap4_mesh {
   bool dt_valid = false;
   f4::MeshDev *d_dev = nullptr;  // single-mesh descriptor for the plain path
   int64_t *d_item_begin = nullptr;
+  // refinement indicator: default for regrid, attached MLP, scratch
+  foap4_indicator ind = FOAP4_IND_LOHNER;
+  const foap4_mlp *mlp = nullptr;
+  void *d_ind = nullptr;       // raw features, features, flags, decisions
+  size_t cap_ind = 0;
+  int64_t n_fallback = 0;      // blocks of the last MLP flag call that took the Lohner flag
+  std::string err;
+};
+
+// Learned refinement indicator: FP32 master weights, FP64 Adam moments,
+// BF16 MFMA operand fragments and the gradient workspace, all on the device.
+struct foap4_mlp {
+  hipStream_t stream = nullptr;
+  float *d_w = nullptr;        // [kMlpParams] flat W1 b1 W2 b2 W3 b3
+  double *d_mv = nullptr;      // [2][kMlpParams] Adam first and second moments
+  float *d_grad = nullptr;     // [kMlpParams] last gradient
+  void *d_frag = nullptr;      // [kMlpFrags][64] 16-byte operand fragments
+  float *d_cls = nullptr;      // [4] per-class sample weight of the loss
+  unsigned long long *d_cnt = nullptr;  // [4] label counts (classes, invalid)
+  float *d_part = nullptr;     // [groups][kMlpPartStride] per-workgroup partial gradients
+  size_t cap_part = 0;         // in workgroups
+  double *d_loss = nullptr;    // [cap_loss] loss per iteration
+  size_t cap_loss = 0;
+  int64_t t = 0;               // Adam steps taken since the last set_params
+  bool has_weights = false;
+  float threshold = 0.5f;
   std::string err;
 };
 
@@ -154,8 +187,15 @@ hipError_t launch_finalize(const MeshDev *d_meshes, int n_meshes, int advance, h
 hipError_t launch_fluxfix(const MeshDev *d_mesh, int ndim, bool f64, int n_fix, int stage, hipStream_t s);
 hipError_t launch_totals(const foap4_mesh *m, double *d_part, double *d_out, hipStream_t s);
 // regrid.hip
-hipError_t launch_lohner(const foap4_mesh *m, int8_t *d_flags, hipStream_t s);
+// skip (may be null): blocks whose flag is already set are left alone
+hipError_t launch_lohner(const foap4_mesh *m, int8_t *d_flags, const int8_t *skip, hipStream_t s);
 hipError_t launch_remap(const foap4_mesh *m, const void *src_state, void *dst_state,
                         const int32_t *d_map, int64_t nb_new, hipStream_t s);
+// mlp.hip: features of the current state (ghosts filled), raw [nb][2] FP64 and
+// feat [nb][16] FP32; MLP decisions: flags[b] = argmax - 1 and decided[b] = 1
+// where the largest class probability reaches the threshold, else decided 0
+hipError_t launch_block_features(const foap4_mesh *m, double *d_raw, float *d_feat, hipStream_t s);
+hipError_t launch_mlp_decide(const foap4_mlp *net, const float *d_feat, int64_t n, int8_t *d_flags,
+                             int8_t *d_decided, hipStream_t s);
 
 }  // namespace f4

@@ -8,11 +8,13 @@ namespace f4 {
 // flags equal a plain evaluation bit for bit.  One workgroup per block.
 template <typename T, int NDIM>
 __global__ __launch_bounds__(256) void lohner_kernel(const MeshDev *__restrict__ Mp, double cr2, double cd2,
-                                                     double eps, double eps_abs, int8_t *flags) {
+                                                     double eps, double eps_abs, int8_t *flags,
+                                                     const int8_t *skip) {
 #pragma clang fp contract(off)
   const MeshDev &M = *Mp;
   constexpr int NV = NDIM + 2;
   const int64_t b = blockIdx.x;
+  if (skip && skip[b]) return;
   const int N = M.N, g = M.g, P = N + 2 * g;
   const int64_t sv = (NDIM == 3) ? (int64_t)P * P * P : (int64_t)P * P;
   const T *u = (const T *)M.s[M.cur] + b * sv * NV;  // variable 0 = density
@@ -118,18 +120,18 @@ __global__ __launch_bounds__(256) void remap_kernel(const T *__restrict__ uold, 
   }
 }
 
-hipError_t launch_lohner(const foap4_mesh *m, int8_t *d_flags, hipStream_t s) {
+hipError_t launch_lohner(const foap4_mesh *m, int8_t *d_flags, const int8_t *skip, hipStream_t s) {
   const int64_t nb = (int64_t)m->topo.leaves.size();
   if (nb == 0) return hipSuccess;
   const double cr = 5e-2, cd = 6.25e-3;  // c_refine, c_derefine of the AMR runs (Sec. 5.4)
   const double cr2 = cr * cr, cd2 = cd * cd, eps = 1e-2, eps_abs = 1e-10;
   const bool f64 = m->d.prec == FOAP4_F64;
   if (m->d.ndim == 3) {
-    if (f64) lohner_kernel<double, 3><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, cr2, cd2, eps, eps_abs, d_flags);
-    else lohner_kernel<float, 3><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, cr2, cd2, eps, eps_abs, d_flags);
+    if (f64) lohner_kernel<double, 3><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, cr2, cd2, eps, eps_abs, d_flags, skip);
+    else lohner_kernel<float, 3><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, cr2, cd2, eps, eps_abs, d_flags, skip);
   } else {
-    if (f64) lohner_kernel<double, 2><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, cr2, cd2, eps, eps_abs, d_flags);
-    else lohner_kernel<float, 2><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, cr2, cd2, eps, eps_abs, d_flags);
+    if (f64) lohner_kernel<double, 2><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, cr2, cd2, eps, eps_abs, d_flags, skip);
+    else lohner_kernel<float, 2><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, cr2, cd2, eps, eps_abs, d_flags, skip);
   }
   return hipGetLastError();
 }
