@@ -258,9 +258,11 @@ foap4_status foap4_batch_destroy(foap4_batch *batch);
 /* Work decomposition of the batched stage kernel: kslabs = 1, 2 or 4 k-slabs
  * per block tile (the LDS tile depth is N / kslabs planes), wg_per_cu =
  * resident workgroups per compute unit for the persistent grid (0: one
- * workgroup per work item, no persistence), xcd_order = 1 to give each of
- * the 8 XCDs a contiguous range of work items (Morton neighbours share an
- * L2), gather_halos = 1 to read same-level halo cells straight from the
+ * workgroup per work item, no persistence), xcd_order = 0 for plain
+ * striding of the work items over the workgroups, 1 to give each of the 8
+ * XCDs a contiguous range of work items (Morton neighbours share an L2), 2 to
+ * give each workgroup a contiguous chunk (a block and its Morton neighbours
+ * run back to back on one CU), gather_halos = 1 to read same-level halo cells straight from the
  * neighbouring blocks instead of copying them into ghost cells first (the
  * results are identical; the SRL copies are then skipped except where the
  * coarse-to-fine prolongation reads them).  Defaults: 1, 0, 1, 1. */

@@ -584,9 +584,9 @@ foap4_status foap4_batch_destroy(foap4_batch *b) {
 foap4_status foap4_batch_set_config(foap4_batch *b, int32_t kslabs, int32_t wg_per_cu, int32_t xcd_order,
                                     int32_t gather_halos) {
   if (!b || (kslabs != 1 && kslabs != 2 && kslabs != 4) || wg_per_cu < 0 || wg_per_cu > 64 ||
-      (xcd_order != 0 && xcd_order != 1) || (gather_halos != 0 && gather_halos != 1))
+      xcd_order < 0 || xcd_order > 2 || (gather_halos != 0 && gather_halos != 1))
     return batch_fail(b, FOAP4_E_INVALID,
-                      "kslabs must be 1, 2 or 4, 0 <= wg_per_cu <= 64, xcd_order and gather_halos 0 or 1");
+                      "kslabs must be 1, 2 or 4, 0 <= wg_per_cu <= 64, xcd_order 0, 1 or 2, gather_halos 0 or 1");
   if (b->ks != kslabs || b->wg_per_cu != wg_per_cu || b->xcd != xcd_order || b->gather != gather_halos)
     drop_graph(b);
   b->ks = kslabs;
@@ -785,7 +785,7 @@ foap4_status foap4_batch_autotune(foap4_batch *b, const char *cache_path, int32_
   for (int a = 0; a < 3 && result == FOAP4_OK; a++) {
     if (ks_cand[a] > max_ks) continue;
     for (int c = 0; c < 5 && result == FOAP4_OK; c++)
-      for (int x = 0; x < 2 && result == FOAP4_OK; x++) {
+      for (int x = 0; x < 3 && result == FOAP4_OK; x++) {
         if ((result = foap4_batch_set_config(b, ks_cand[a], wg_cand[c], x, b->gather)) != FOAP4_OK) break;
         if ((result = foap4_batch_step(b, 2)) != FOAP4_OK) break;  // capture + warm-up
         if (hipEventRecord(e0, b->stream) != hipSuccess) { result = FOAP4_E_HIP; break; }

@@ -78,23 +78,23 @@ __device__ __forceinline__ void rusanov(const T *WL, const T *WR, T gamma, T *F)
   const T db = fsqrt(d2);
   const T lm = fabs(ubar - db), lp = fabs(ubar + db);
   const T ha = T(0.5) * (lm > lp ? lm : lp);
-  // mass
-  F[0] = T(0.5) * (rl * vl + rr * vr) - ha * (rr - rl);
-  // momentum and energy
+  // (F_L + F_R)/2 - ha (U_R - U_L) with F = U v_n + pressure terms, grouped
+  // per side: al U_L + ar U_R + pressure terms, al = vl/2 + ha, ar = vr/2 - ha
+  const T al = T(0.5) * vl + ha, ar = T(0.5) * vr - ha;
+  F[0] = al * rl + ar * rr;
   T kel = T(0), ker = T(0);
 #pragma unroll
   for (int d = 0; d < NDIM; d++) {
     const T ml = rl * WL[1 + d], mr = rr * WR[1 + d];
-    const T fl = ml * vl + (d == AX ? pl : T(0));
-    const T fr = mr * vr + (d == AX ? pr : T(0));
-    F[1 + d] = T(0.5) * (fl + fr) - ha * (mr - ml);
+    F[1 + d] = al * ml + ar * mr;
+    if (d == AX) F[1 + d] += T(0.5) * (pl + pr);
     kel += ml * WL[1 + d];
     ker += mr * WR[1 + d];
   }
   const T igm1 = frcp(gamma - T(1));
   const T El = pl * igm1 + T(0.5) * kel;
   const T Er = pr * igm1 + T(0.5) * ker;
-  F[NV - 1] = T(0.5) * ((El + pl) * vl + (Er + pr) * vr) - ha * (Er - El);
+  F[NV - 1] = al * El + ar * Er + T(0.5) * (pl * vl + pr * vr);
 }
 
 // Face flux from four primitive states along the face normal: minmod-limited

@@ -3,10 +3,11 @@
 // Work decomposition (gfx950, wave64): a workgroup of 256 threads processes
 // one work item.  An item is a TILE x TILE column of cells of one block
 // (TILE = 16 for N = 16, 32; for N = 8 four 8 x 8 blocks share the workgroup,
-// one per wave) that marches along k over a slab of N / ks planes.  Per
-// plane the primitive variables of the tile and of its +-2 ring are staged in
-// LDS for the x/y stencils, while each thread keeps its own column's k-2..k+2
-// window in registers for the z stencil; global loads run ahead of use.
+// one per wave) that marches along k over a slab of N / ks planes.  The
+// primitive variables of the tile and of its +-2 ring are staged in LDS, in a
+// ring of three planes (k, k+1, k+2) that serves both the x/y stencils of
+// plane k and the z stencil of each thread's own column; global loads run a
+// plane ahead of use.
 // Every face flux is computed once.  Halo cells across a same-level face are
 // read straight from the neighbouring block ("gather"); across refinement
 // faces they come from the ghost cells that the ghost rounds filled.  Fluxes
@@ -28,10 +29,26 @@ struct TileCfg {
   static constexpr int TPB = (N / TILE) * (N / TILE);   // tiles per block plane
 };
 
-// LDS elements per workgroup: SUB * (plane + x faces + y faces) * NV, maximum
-// over the block sizes (TILE 16: 400 + 272 + 272; TILE 8: 4 * (144 + 72 + 72)).
+// Primitive planes held in LDS: k, k+1, k+2 in a ring of three slots (3D).
 template <int NDIM>
-constexpr int smem_cells() { return 1152 * (NDIM + 2); }
+constexpr int lds_planes() { return NDIM == 3 ? 3 : 1; }
+
+// LDS elements of one work item: SUB * (planes + x faces + y faces) * NV.
+template <int NDIM, int N>
+constexpr int item_cells() {
+  using C = TileCfg<N>;
+  return C::SUB * (lds_planes<NDIM>() * (C::TILE + 4) * (C::TILE + 4) + 2 * (C::TILE + 1) * C::TILE) * (NDIM + 2);
+}
+
+// LDS elements per workgroup: the maximum over the block sizes in NM.
+template <int NDIM, int NM>
+constexpr int smem_cells() {
+  int c = 0;
+  if (NM & 1) c = item_cells<NDIM, 8>() > c ? item_cells<NDIM, 8>() : c;
+  if (NM & 2) c = item_cells<NDIM, 16>() > c ? item_cells<NDIM, 16>() : c;
+  if (NM & 4) c = item_cells<NDIM, 32>() > c ? item_cells<NDIM, 32>() : c;
+  return c;
+}
 
 // CFL inverse time step sum_d (|v_d| + c) / dx of one cell.  FP64 states use
 // the operation order of the definition without contraction (equal to a plain
@@ -80,6 +97,32 @@ __device__ __forceinline__ void copyv(T *dst, const T *src) {
   for (int v = 0; v < NV; v++) dst[v] = src[v];
 }
 
+// Variable slot of v when the velocity components x and y are exchanged
+// (sw): a y face is evaluated as the x face of the exchanged state, so x and
+// y faces run the same instructions and the flux components are exchanged
+// back on store.
+__device__ __forceinline__ int xy_slot(int v, bool sw) { return (sw && (v == 1 || v == 2)) ? 3 - v : v; }
+
+// Flux of one x or y face of the LDS plane Wp ([v][PLANE]) from the four cells
+// base + m * step (m = 0..3) along the face normal; F is in natural variable
+// order.  sw may differ between lanes.
+template <typename T, int NDIM, int PLANE>
+__device__ __forceinline__ void plane_face(const T *Wp, int base, int step, bool sw, T gamma, T *F) {
+  constexpr int NV = NDIM + 2;
+  T A0[NV], A1[NV], A2[NV], A3[NV], G[NV];
+#pragma unroll
+  for (int v = 0; v < NV; v++) {
+    const T *p = Wp + xy_slot(v, sw) * PLANE + base;
+    A0[v] = p[0];
+    A1[v] = p[step];
+    A2[v] = p[2 * step];
+    A3[v] = p[3 * step];
+  }
+  face_flux<T, NDIM, 0>(A0, A1, A2, A3, gamma, G);
+#pragma unroll
+  for (int v = 0; v < NV; v++) F[v] = (v == 1) ? (sw ? G[2] : G[1]) : (v == 2) ? (sw ? G[1] : G[2]) : G[v];
+}
+
 template <typename T, int NDIM, int N>
 __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t local, T *smem,
                                            double &vmax, bool &bad) {
@@ -88,7 +131,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   constexpr int NV = NDIM + 2;
   constexpr int LP = TILE + 4;
   constexpr int PLANE = LP * LP;
-  constexpr int NFX = (TILE + 1) * TILE;
+  constexpr int NFX = (TILE + 1) * TILE;  // x (and y) face fluxes per variable
   constexpr int TT = TILE * TILE;
   constexpr int NF = 2 * NDIM;
 
@@ -124,9 +167,11 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   for (int f = 0; f < NF; f++) finfo[f] = M.face_info[b * NF + f];
   auto nbr_of = [&](int f) -> int64_t { return (M.gather && finfo[f] <= -2) ? (int64_t)(-2 - finfo[f]) : -1; };
 
-  T *Wp = smem + sub * (PLANE + 2 * NFX) * NV;  // [v][PLANE]
-  T *FX = Wp + PLANE * NV;                      // [v][TILE][TILE + 1]
-  T *FY = FX + NFX * NV;                        // [v][TILE + 1][TILE]
+  constexpr int NS = lds_planes<NDIM>();
+  T *Wring = smem + sub * (NS * PLANE + 2 * NFX) * NV;  // [slot][v][PLANE]
+  T *FX = Wring + NS * PLANE * NV;                      // [v][TILE][TILE + 1]
+  T *FY = FX + NFX * NV;                                // [v][TILE + 1][TILE]
+  auto slot = [&](int kk) -> T * { return NS == 1 ? Wring : Wring + (kk % NS) * (PLANE * NV); };
 
   auto off = [&](int ii, int jj, int kk) -> int {
     return (NDIM == 3 ? (kk + g) * sk : 0) + (jj + g) * sj + (ii + g);
@@ -200,110 +245,149 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
                        (is_f2c(3) && J == N - 1);
   const bool f2c_zlo = NDIM == 3 && is_f2c(4), f2c_zhi = NDIM == 3 && is_f2c(5);
 
-  T U0[NV], U1[NV], U2[NV], Q1[NV], R0[NV];
-  T Wm1[NV], W0[NV], W1[NV], W2[NV], Fz[NV];
+  // Primitive planes live in a ring of LDS slots (plane kk in slot kk % 3):
+  // at iteration k the slots hold planes k, k+1, k+2; the own column's z
+  // stencil reads them there, so no register window has to rotate.  The
+  // conserved state of the own cell is reloaded for the update (it was read
+  // two planes earlier and is still cached).
+  T Q[NV], R[NV], Sk[NV], Fz[NV];  // prefetch (own, ring), z slope of cell k, flux of face k - 1/2
+  auto put = [&](T *S, int at, const T *U) {
+    T W[NV];
+    to_prim<T, NDIM>(U, gamma, W);
+#pragma unroll
+    for (int v = 0; v < NV; v++) S[v * PLANE + at] = W[v];
+  };
 
   if constexpr (NDIM == 3) {
-    T tmp[NV], Wm2[NV];
+    T tmp[NV], Wm2[NV], Wm1[NV], W0[NV], W1[NV];
     load(col(k0 - 2), tmp);
     to_prim<T, NDIM>(tmp, gamma, Wm2);
     load(col(k0 - 1), tmp);
     to_prim<T, NDIM>(tmp, gamma, Wm1);
-    load(col(k0), U0);
-    load(col(k0 + 1), U1);
-    load(col(k0 + 2), U2);
-    if (ring) load(ring_p + k0 * sk, R0);
-    if (k0 + 3 <= k1 + 1) load(col(k0 + 3), Q1);
-    to_prim<T, NDIM>(U0, gamma, W0);
-    to_prim<T, NDIM>(U1, gamma, W1);
-    to_prim<T, NDIM>(U2, gamma, W2);
-    face_flux<T, NDIM, 2>(Wm2, Wm1, W0, W1, gamma, Fz);
+    load(col(k0), tmp);
+    to_prim<T, NDIM>(tmp, gamma, W0);
+    load(col(k0 + 1), tmp);
+    to_prim<T, NDIM>(tmp, gamma, W1);
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+      slot(k0)[v * PLANE + own_lds] = W0[v];
+      slot(k0 + 1)[v * PLANE + own_lds] = W1[v];
+    }
+    if (ring) {
+      load(ring_p + k0 * sk, tmp);
+      put(slot(k0), ring_lds, tmp);
+      load(ring_p + (k0 + 1) * sk, tmp);
+      put(slot(k0 + 1), ring_lds, tmp);
+    }
+    // face k0 - 1/2; the slope of cell k0 is carried into the plane loop
+    T L[NV], Rt[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+      const T s1 = minmod(Wm1[v] - Wm2[v], W0[v] - Wm1[v]);
+      Sk[v] = minmod(W0[v] - Wm1[v], W1[v] - W0[v]);
+      L[v] = Wm1[v] + T(0.5) * s1;
+      Rt[v] = W0[v] - T(0.5) * Sk[v];
+    }
+    rusanov<T, NDIM, 2>(L, Rt, gamma, Fz);
     if (k0 == 0) store_bflux(4, I, J, Fz);
+    load(col(k0 + 2), Q);
+    if (ring) load(ring_p + (k0 + 2) * sk, R);
   } else {
-    load(own_p, U0);
-    if (ring) load(ring_p, R0);
-    to_prim<T, NDIM>(U0, gamma, W0);
+    T tmp[NV];
+    load(own_p, tmp);
+    put(slot(0), own_lds, tmp);
+    if (ring) {
+      load(ring_p, tmp);
+      put(slot(0), ring_lds, tmp);
+    }
   }
-  T Up[NV];
-  if (stage == 2) load(up + off(I, J, k0), Up);
+
+  T U0n[NV], Upn[NV];
+  load(col(k0), U0n);
+  if (stage == 2) load(up + off(I, J, k0), Upn);
 
   for (int k = k0; k < k1; k++) {
-    // stage the primitive plane k (own cell + ring) in LDS
-#pragma unroll
-    for (int v = 0; v < NV; v++) Wp[v * PLANE + own_lds] = W0[v];
-    if (ring) {
-      T Wr[NV];
-      to_prim<T, NDIM>(R0, gamma, Wr);
-#pragma unroll
-      for (int v = 0; v < NV; v++) Wp[v * PLANE + ring_lds] = Wr[v];
-      if (k + 1 < k1) load(ring_p + (k + 1) * sk, R0);
+    if constexpr (NDIM == 3) {
+      // plane k + 2 into the slot plane k - 1 used; prefetch plane k + 3
+      put(slot(k + 2), own_lds, Q);
+      if (ring && k + 2 < k1) put(slot(k + 2), ring_lds, R);
+      if (k + 3 <= k1 + 1) load(col(k + 3), Q);
+      if (ring && k + 3 < k1) load(ring_p + (k + 3) * sk, R);
     }
+    // conserved state of the own cell for the update: loaded one plane ahead
+    T U0[NV], Up[NV];
+    copyv<T, NV>(U0, U0n);
+    if (stage == 2) copyv<T, NV>(Up, Upn);
+    if (k + 1 < k1) {
+      load(col(k + 1), U0n);
+      if (stage == 2) load(up + off(I, J, k + 1), Upn);
+    }
+    const T *Wp = slot(k);
     __syncthreads();
 
     T Fz1[NV];
     if constexpr (NDIM == 3) {
-      face_flux<T, NDIM, 2>(Wm1, W0, W1, W2, gamma, Fz1);
+      // face k + 1/2 with the carried slope of cell k
+      const T *A = Wp + own_lds, *B = slot(k + 1) + own_lds, *Cc = slot(k + 2) + own_lds;
+      T L[NV], Rt[NV];
+#pragma unroll
+      for (int v = 0; v < NV; v++) {
+        const T w0 = A[v * PLANE], w1 = B[v * PLANE], w2 = Cc[v * PLANE];
+        const T sn = minmod(w1 - w0, w2 - w1);
+        L[v] = w0 + T(0.5) * Sk[v];
+        Rt[v] = w1 - T(0.5) * sn;
+        Sk[v] = sn;
+      }
+      rusanov<T, NDIM, 2>(L, Rt, gamma, Fz1);
       if (k == N - 1) store_bflux(5, I, J, Fz1);
     }
 
     // x and y faces of the plane: every thread computes the -x and the -y
-    // face of its cell; the TILE extra +x faces of the last column go to the
-    // first TILE lanes and the TILE extra +y faces of the last row to the
-    // lanes of the next wave (TILE 16), so that no wave mixes x and y faces.
-    auto xface = [&](int fi, int fj) {
-      T A0[NV], A1[NV], A2[NV], A3[NV], F[NV];
-      const int base = (fj + 2) * LP + fi;  // cell fi - 2
+    // face of its cell (FX[v][fj][fi], FY[v][fj][fi], both NFX per variable).
+    // The TILE extra +x faces of the last column and the TILE extra +y faces
+    // of the last row run together in 2 TILE lanes of one wave (the y ones
+    // on exchanged velocities); with 4 waves per tile the wave rotates with
+    // the plane so that every SIMD gets its share.
+    {
+      T F[NV];
+      plane_face<T, NDIM, PLANE>(Wp, (tj + 2) * LP + ti, 1, false, gamma, F);  // cells ti-2 .. ti+1
 #pragma unroll
-      for (int v = 0; v < NV; v++) {
-        A0[v] = Wp[v * PLANE + base];
-        A1[v] = Wp[v * PLANE + base + 1];
-        A2[v] = Wp[v * PLANE + base + 2];
-        A3[v] = Wp[v * PLANE + base + 3];
+      for (int v = 0; v < NV; v++) FX[v * NFX + tj * (TILE + 1) + ti] = F[v];
+      if (ti == 0 && i0 == 0) store_bflux(0, j0 + tj, k, F);
+      plane_face<T, NDIM, PLANE>(Wp, tj * LP + ti + 2, LP, true, gamma, F);  // cells tj-2 .. tj+1
+#pragma unroll
+      for (int v = 0; v < NV; v++) FY[v * NFX + tj * TILE + ti] = F[v];
+      if (tj == 0 && j0 == 0) store_bflux(2, i0 + ti, k, F);
+    }
+    {
+      const int e = (TT == 256) ? lt - 64 * ((k + (int)local) & 3) : lt;
+      if (e >= 0 && e < 2 * TILE) {
+        const bool sw = e >= TILE;
+        const int m = sw ? e - TILE : e;
+        T F[NV];
+        plane_face<T, NDIM, PLANE>(Wp, sw ? TILE * LP + m + 2 : (m + 2) * LP + TILE, sw ? LP : 1, sw, gamma, F);
+        T *out = sw ? FY + TILE * TILE + m : FX + m * (TILE + 1) + TILE;
+#pragma unroll
+        for (int v = 0; v < NV; v++) out[v * NFX] = F[v];
+        if (!sw && i0 + TILE == N) store_bflux(1, j0 + m, k, F);
+        if (sw && j0 + TILE == N) store_bflux(3, i0 + m, k, F);
       }
-      face_flux<T, NDIM, 0>(A0, A1, A2, A3, gamma, F);
-#pragma unroll
-      for (int v = 0; v < NV; v++) FX[(v * TILE + fj) * (TILE + 1) + fi] = F[v];
-      if (fi == 0 && i0 == 0) store_bflux(0, j0 + fj, k, F);
-      if (fi == TILE && i0 + TILE == N) store_bflux(1, j0 + fj, k, F);
-    };
-    auto yface = [&](int fi, int fj) {
-      T A0[NV], A1[NV], A2[NV], A3[NV], F[NV];
-      const int base = fj * LP + fi + 2;  // cell fj - 2
-#pragma unroll
-      for (int v = 0; v < NV; v++) {
-        A0[v] = Wp[v * PLANE + base];
-        A1[v] = Wp[v * PLANE + base + LP];
-        A2[v] = Wp[v * PLANE + base + 2 * LP];
-        A3[v] = Wp[v * PLANE + base + 3 * LP];
-      }
-      face_flux<T, NDIM, 1>(A0, A1, A2, A3, gamma, F);
-#pragma unroll
-      for (int v = 0; v < NV; v++) FY[(v * (TILE + 1) + fj) * TILE + fi] = F[v];
-      if (fj == 0 && j0 == 0) store_bflux(2, i0 + fi, k, F);
-      if (fj == TILE && j0 + TILE == N) store_bflux(3, i0 + fi, k, F);
-    };
-    xface(ti, tj);
-    yface(ti, tj);
-    constexpr int YX = (TT >= 64 + TILE && TILE == 16) ? 64 : TILE;  // first lane of the extra y faces
-    if (lt < TILE) xface(TILE, lt);
-    else if (lt >= YX && lt < YX + TILE) yface(lt - YX, TILE);
+    }
     __syncthreads();
 
-    // conservative update of the own cell (eq. feuler with Heun weights)
+    // conservative update of the own cell (eq. feuler with Heun weights):
+    // U_out = base - (dt_s / dx) sum_d (F_d(+) - F_d(-))
     T Uout[NV];
+    const T cdt = dts * idx;
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-      const T dfx = FX[(v * TILE + tj) * (TILE + 1) + ti + 1] - FX[(v * TILE + tj) * (TILE + 1) + ti];
-      const T dfy = FY[(v * (TILE + 1) + tj + 1) * TILE + ti] - FY[(v * (TILE + 1) + tj) * TILE + ti];
-      T rhs = -(dfx * idx);
-      rhs -= dfy * idx;
-      if constexpr (NDIM == 3) rhs -= (Fz1[v] - Fz[v]) * idx;
-      if (stage == 1)
-        Uout[v] = dts * rhs + U0[v];
-      else
-        Uout[v] = dts * rhs + T(0.5) * (Up[v] + U0[v]);
+      const T dfx = FX[v * NFX + tj * (TILE + 1) + ti + 1] - FX[v * NFX + tj * (TILE + 1) + ti];
+      const T dfy = FY[v * NFX + (tj + 1) * TILE + ti] - FY[v * NFX + tj * TILE + ti];
+      T div = dfx + dfy;
+      if constexpr (NDIM == 3) div += Fz1[v] - Fz[v];
+      const T base = (stage == 1) ? U0[v] : T(0.5) * (Up[v] + U0[v]);
+      Uout[v] = base - cdt * div;
     }
-    if (stage == 2 && k + 1 < k1) load(up + off(I, J, k + 1), Up);
     const int o = off(I, J, k);
     if (valid) {
 #pragma unroll
@@ -322,16 +406,6 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
 
     if constexpr (NDIM == 3) {
       copyv<T, NV>(Fz, Fz1);
-      copyv<T, NV>(Wm1, W0);
-      copyv<T, NV>(W0, W1);
-      copyv<T, NV>(W1, W2);
-      copyv<T, NV>(U0, U1);
-      copyv<T, NV>(U1, U2);
-      if (k + 3 <= k1 + 1) {
-        copyv<T, NV>(U2, Q1);
-        to_prim<T, NDIM>(U2, gamma, W2);
-        if (k + 4 <= k1 + 1) load(col(k + 4), Q1);
-      }
     }
   }
 }
@@ -348,10 +422,14 @@ __device__ __forceinline__ void flush_dt(const MeshDev &M, double &vmax, bool &b
   bad = false;
 }
 
-// Item visited by iteration `it` of workgroup w: with xcd != 0, XCD x = w mod 8
-// walks the x-th eighth of the item range; else plain striding.
+// Item visited by iteration `it` of workgroup w.  order 0: plain striding;
+// 1: XCD x = w mod 8 walks the x-th eighth of the item range; 2: workgroup w
+// takes the w-th contiguous chunk, so a block and its Morton neighbours (the
+// x neighbour first) run back to back on one CU and the neighbour rows that a
+// halo read pulls into the cache are used again by the next item.
 __device__ __forceinline__ int64_t item_of(int64_t w, int64_t it, int64_t grid, int64_t total, int xcd) {
   if (!xcd) return w + it * grid;
+  if (xcd == 2) return w * ((total + grid - 1) / grid) + it;
   const int64_t per_xcd = (total + 7) / 8;
   const int64_t lanes = (grid + 7 - (w & 7)) / 8;  // workgroups on this XCD
   const int64_t j = (w >> 3) + it * lanes;         // position inside the XCD's range
@@ -367,13 +445,13 @@ constexpr int stage_waves() { return (sizeof(T) == 4 && NM != 7) ? 3 : 1; }
 template <typename T, int NDIM, int NM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM>())))
 void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t total, int stage, int xcd) {
-  __shared__ T smem[smem_cells<NDIM>()];
+  __shared__ T smem[smem_cells<NDIM, NM>()];
   double vmax = 0.0;
   bool bad = false;
   int mprev = -1;
   const int64_t grid = gridDim.x;
   const int64_t lanes = grid / 8 > 0 ? grid / 8 : 1;
-  const int64_t iters = xcd ? ((total + 7) / 8 + lanes - 1) / lanes : (total + grid - 1) / grid;
+  const int64_t iters = xcd == 1 ? ((total + 7) / 8 + lanes - 1) / lanes : (total + grid - 1) / grid;
   for (int64_t it = 0; it < iters; it++) {
     const int64_t item = item_of(blockIdx.x, it, grid, total, xcd);
     if (item >= total) break;
@@ -427,7 +505,7 @@ hipError_t launch_stage(const MeshDev *d_meshes, int n_meshes, int64_t total_ite
                         int ndim, bool f64, int grid, hipStream_t s, int xcd, int nmask) {
   if (total_items <= 0) return hipSuccess;
   int64_t nblk = (grid > 0 && grid < total_items) ? grid : total_items;
-  if (xcd) nblk = (nblk + 7) / 8 * 8;  // every XCD gets the same number of workgroups
+  if (xcd == 1) nblk = (nblk + 7) / 8 * 8;  // every XCD gets the same number of workgroups
   if (f64) {
     if (ndim == 3) launch_t<double, 3>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);
     else launch_t<double, 2>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);

@@ -112,12 +112,12 @@ def uniform_noise_shear(block: int = 16, n: int = 256, seed: int = 0):
 
 
 def blast_field(gamma=1.4, p_in=100.0, p_out=1e-3, r0=0.05, centre=(0.5, 0.5, 0.5)):
-    def field(x, y, z):
-        r = np.sqrt((x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2)
-        rho = np.ones_like(r)
-        p = np.where(r < r0, p_in, p_out)
-        zero = np.zeros_like(r)
-        return conserved_from_primitive(rho, [zero, zero, zero], p, gamma)
+    def field(x, y, z, xp=np):
+        r = xp.sqrt((x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2)
+        rho = xp.ones_like(r)
+        p = xp.where(r < r0, xp.full_like(r, p_in), xp.full_like(r, p_out))
+        zero = xp.zeros_like(r)
+        return conserved_from_primitive(rho, [zero, zero, zero], p, gamma, xp=xp)
     return field
 
 
@@ -221,3 +221,35 @@ def mirrored_sod(nx_cells: int, block: int = 16, ndim: int = 2):
 
     return dict(name=f"sod_{nx_cells}", ndim=ndim, trees=(nt, 1, 1), N=block, g=2,
                 tree_size=1.0 / nt, level=0, gamma=gamma, cfl=0.5, field=field)
+
+
+def adaptive_blast(centre=(0.5, 0.5, 0.5), p_in=100.0, trees=4, block=16, max_level=3, steps=400,
+                   regrid_every=10, r0=0.05):
+    """3D adaptive blast: trees^3 periodic trees of block^3 cells, levels
+    0..max_level, blast p = p_in inside r < r0 around centre, p = 1e-3
+    outside, rho = 1, v = 0.  Initial refinement is geometric: blocks that
+    meet the ball of radius 2 r0 are refined, max_level times (the density
+    criterion sees nothing in a uniform density).  The run regrids every
+    regrid_every steps."""
+    gamma = 1.4
+    ts = 1.0 / trees
+
+    def init_flags(level, G):
+        size = ts / (2.0 ** np.asarray(level, dtype=np.float64))
+        G = np.asarray(G, dtype=np.float64)
+        lo = [G[:, a] * size for a in range(3)]
+        hi = [(G[:, a] + 1) * size for a in range(3)]
+        return np.where(box_intersects_ball(lo, hi, centre, 2 * r0), 1, 0).astype(np.int8)
+
+    return dict(name=f"adaptive_blast_{trees * block}^3_L{max_level}_b{block}", ndim=3, trees=(trees,) * 3,
+                N=block, g=2, tree_size=ts, level=0, max_level=max_level, gamma=gamma, cfl=0.5,
+                field=blast_field(gamma, p_in, 1e-3, r0, centre), init_flags=init_flags, steps=steps,
+                regrid_every=regrid_every, centre=tuple(centre), p_in=p_in)
+
+
+def blast_training_runs(n_centres=4, seed=500):
+    """(centre, p_in) of the indicator's training runs: centres drawn
+    uniformly within +-0.05 of the domain centre, p_in in {30, 300} (the
+    evaluation run uses the domain centre and p_in = 100)."""
+    u = uniform_pm1(seed, 3 * n_centres).reshape(n_centres, 3) * 0.05
+    return [(tuple(0.5 + u[c]), p) for p in (30.0, 300.0) for c in range(n_centres)]
