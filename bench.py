@@ -98,9 +98,9 @@ def main():
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for hardware-counter passes: a 1 GiB device copy (counter calibration) "
-                         "then 3 batched FP32 steps in the tuned configuration")
+                         "then 3 batched FP32 steps in the given configuration")
     ap.add_argument("--config", default=None,
-                    help="kslabs,wg_per_cu,xcd_order instead of autotuning (--profile-run default: 1,3,0)")
+                    help="kslabs,wg_per_cu,xcd_order instead of autotuning (--profile-run default: 1,3,1)")
     ap.add_argument("--counters", default=os.path.join(ROOT, "profiles", "stage_traffic_noise_shear_256cubed_b16.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -134,7 +134,7 @@ def main():
         del a, bb
         m32 = make(f4.F32)
         batch = f4.Batch([m32])
-        ks, wg, xcd = (int(x) for x in (args.config or "1,3,0").split(","))
+        ks, wg, xcd = (int(x) for x in (args.config or "1,3,1").split(","))
         batch.set_config(ks, wg, xcd, 1)
         batch.step(3)
         torch.cuda.synchronize()

@@ -7,6 +7,19 @@
 
 namespace f4 {
 
+// Global-memory access through address-space-1 pointers.  Pointers read out
+// of a descriptor are generic, and the compiler would use FLAT instructions,
+// which count against the LDS wait counter too: every wait for an LDS result
+// would then also wait for all outstanding prefetch loads.
+template <typename T>
+__device__ __forceinline__ T gload(const T *p) {
+  return *(const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T *p, T v) {
+  *(__attribute__((address_space(1))) T *)p = v;
+}
+
 // Generalized minmod G(a, b, theta = 1) (eq. gminmod): zero unless a and b
 // have the same strict sign, else the one of smaller magnitude.  That value is
 // the median of {0, a, b}: for equal signs the argument closer to zero, for
@@ -117,7 +130,8 @@ __device__ __forceinline__ void face_flux(const T *W0, const T *W1, const T *W2,
 // Atomic max of a non-negative double through its bit pattern (IEEE order of
 // non-negative doubles equals the order of their bit patterns).
 __device__ __forceinline__ void atomic_max_pos(double *addr, double v) {
-  atomicMax(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
+  __hip_atomic_fetch_max((__attribute__((address_space(1))) unsigned long long *)addr,
+                         (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace f4

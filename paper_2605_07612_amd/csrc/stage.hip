@@ -156,15 +156,15 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   T *uo = (T *)M.s[stage == 1 ? 1 - cur : cur] + b * bel;
   const T *up = (const T *)M.s[cur] + b * bel;
   const T gamma = (T)M.gamma;
-  const double dx = ldexp(M.dx0, -M.level[b]);
+  const double dx = ldexp(M.dx0, -gload(M.level + b));
   const T idx = (T)(1.0 / dx);
-  const double dt = M.scal[kDt];
+  const double dt = gload(M.scal + kDt);
   const T dts = (T)(stage == 1 ? dt : 0.5 * dt);
 
   // per face: refinement-face flux slot (>= 0), same-level neighbour (-2 - n) or -1
   int finfo[NF];
 #pragma unroll
-  for (int f = 0; f < NF; f++) finfo[f] = M.face_info[b * NF + f];
+  for (int f = 0; f < NF; f++) finfo[f] = gload(M.face_info + b * NF + f);
   auto nbr_of = [&](int f) -> int64_t { return (M.gather && finfo[f] <= -2) ? (int64_t)(-2 - finfo[f]) : -1; };
 
   constexpr int NS = lds_planes<NDIM>();
@@ -178,7 +178,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   };
   auto load = [&](const T *p, T *U) {
 #pragma unroll
-    for (int v = 0; v < NV; v++) U[v] = p[v * sv];
+    for (int v = 0; v < NV; v++) U[v] = gload(p + v * sv);
   };
   auto store_bflux = [&](int f, int t1, int t2, const T *F) {
     const int info = finfo[f];
@@ -188,7 +188,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
 #pragma unroll
     for (int v = 0; v < NV; v++) {
       const int64_t o = (NDIM == 3) ? ((slot * NV + v) * N + t2) * N + t1 : (slot * NV + v) * N + t1;
-      buf[o] = F[v];
+      gstore(buf + o, F[v]);
     }
   };
 
@@ -247,10 +247,10 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
 
   // Primitive planes live in a ring of LDS slots (plane kk in slot kk % 3):
   // at iteration k the slots hold planes k, k+1, k+2; the own column's z
-  // stencil reads them there, so no register window has to rotate.  The
-  // conserved state of the own cell is reloaded for the update (it was read
-  // two planes earlier and is still cached).
+  // stencil reads them there, so only the conserved state of the own column
+  // (cells k, k+1, k+2, needed by the update) is kept in registers.
   T Q[NV], R[NV], Sk[NV], Fz[NV];  // prefetch (own, ring), z slope of cell k, flux of face k - 1/2
+  T Ua[NV], Ub[NV];                // conserved state of own cells k, k+1
   auto put = [&](T *S, int at, const T *U) {
     T W[NV];
     to_prim<T, NDIM>(U, gamma, W);
@@ -264,10 +264,10 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     to_prim<T, NDIM>(tmp, gamma, Wm2);
     load(col(k0 - 1), tmp);
     to_prim<T, NDIM>(tmp, gamma, Wm1);
-    load(col(k0), tmp);
-    to_prim<T, NDIM>(tmp, gamma, W0);
-    load(col(k0 + 1), tmp);
-    to_prim<T, NDIM>(tmp, gamma, W1);
+    load(col(k0), Ua);
+    to_prim<T, NDIM>(Ua, gamma, W0);
+    load(col(k0 + 1), Ub);
+    to_prim<T, NDIM>(Ub, gamma, W1);
 #pragma unroll
     for (int v = 0; v < NV; v++) {
       slot(k0)[v * PLANE + own_lds] = W0[v];
@@ -294,33 +294,33 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     if (ring) load(ring_p + (k0 + 2) * sk, R);
   } else {
     T tmp[NV];
-    load(own_p, tmp);
-    put(slot(0), own_lds, tmp);
+    load(own_p, Ua);
+    put(slot(0), own_lds, Ua);
     if (ring) {
       load(ring_p, tmp);
       put(slot(0), ring_lds, tmp);
     }
   }
 
-  T U0n[NV], Upn[NV];
-  load(col(k0), U0n);
+  T Upn[NV];
   if (stage == 2) load(up + off(I, J, k0), Upn);
 
+  T Uc[NV];  // conserved state of own cell k + 2
   for (int k = k0; k < k1; k++) {
     if constexpr (NDIM == 3) {
       // plane k + 2 into the slot plane k - 1 used; prefetch plane k + 3
       put(slot(k + 2), own_lds, Q);
+      copyv<T, NV>(Uc, Q);
       if (ring && k + 2 < k1) put(slot(k + 2), ring_lds, R);
       if (k + 3 <= k1 + 1) load(col(k + 3), Q);
       if (ring && k + 3 < k1) load(ring_p + (k + 3) * sk, R);
     }
-    // conserved state of the own cell for the update: loaded one plane ahead
-    T U0[NV], Up[NV];
-    copyv<T, NV>(U0, U0n);
-    if (stage == 2) copyv<T, NV>(Up, Upn);
-    if (k + 1 < k1) {
-      load(col(k + 1), U0n);
-      if (stage == 2) load(up + off(I, J, k + 1), Upn);
+    // U^n of the own cell (stage 2): loaded one plane ahead
+    T Up[NV];
+    const T *U0 = Ua;
+    if (stage == 2) {
+      copyv<T, NV>(Up, Upn);
+      if (k + 1 < k1) load(up + off(I, J, k + 1), Upn);
     }
     const T *Wp = slot(k);
     __syncthreads();
@@ -391,7 +391,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     const int o = off(I, J, k);
     if (valid) {
 #pragma unroll
-      for (int v = 0; v < NV; v++) uo[v * sv + o] = Uout[v];
+      for (int v = 0; v < NV; v++) gstore(uo + v * sv + o, Uout[v]);
     }
     if (stage == 2 && valid) {
       const bool skip = f2c_adj || (f2c_zlo && k == 0) || (f2c_zhi && k == N - 1);
@@ -406,6 +406,8 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
 
     if constexpr (NDIM == 3) {
       copyv<T, NV>(Fz, Fz1);
+      copyv<T, NV>(Ua, Ub);
+      copyv<T, NV>(Ub, Uc);
     }
   }
 }
