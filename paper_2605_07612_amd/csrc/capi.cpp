@@ -324,7 +324,7 @@ foap4_status foap4_conserved_totals(foap4_mesh *m, double *out) {
 }
 
 // indicator scratch of nb blocks: raw [nb][2] FP64, features [nb][16] FP32,
-// flags [nb], decisions [nb]
+// flags [nb] directly followed by decisions [nb] (one copy to the host)
 struct IndScratch {
   double *raw;
   float *feat;
@@ -333,7 +333,7 @@ struct IndScratch {
 
 static foap4_status ind_scratch(foap4_mesh *m, IndScratch &S) {
   const size_t nb = std::max<size_t>(1, m->topo.leaves.size());
-  const size_t a = (nb * 16 + 255) & ~(size_t)255, b = (nb * 64 + 255) & ~(size_t)255, c = (nb + 255) & ~(size_t)255;
+  const size_t a = (nb * 16 + 255) & ~(size_t)255, b = (nb * 64 + 255) & ~(size_t)255, c = nb;
   const size_t bytes = a + b + 2 * c;
   if (m->cap_ind < bytes) {
     if (m->d_ind) F4_HIP(m, hipFree(m->d_ind));
@@ -394,14 +394,16 @@ foap4_status foap4_refine_flags(foap4_mesh *m, foap4_indicator ind, int8_t *flag
   } else {
     F4_HIP(m, launch_lohner(m, S.flags, nullptr, m->stream));
   }
-  F4_HIP(m, hipMemcpyAsync(flags_host, S.flags, nb, hipMemcpyDeviceToHost, m->stream));
-  std::vector<int8_t> dec;
   if (ind == FOAP4_IND_MLP) {
-    dec.resize(nb);
-    F4_HIP(m, hipMemcpyAsync(dec.data(), S.decided, nb, hipMemcpyDeviceToHost, m->stream));
+    std::vector<int8_t> both(2 * nb);
+    F4_HIP(m, hipMemcpyAsync(both.data(), S.flags, 2 * nb, hipMemcpyDeviceToHost, m->stream));
+    F4_HIP(m, hipStreamSynchronize(m->stream));
+    std::memcpy(flags_host, both.data(), nb);
+    m->n_fallback = (int64_t)std::count(both.begin() + nb, both.end(), (int8_t)0);
+  } else {
+    F4_HIP(m, hipMemcpyAsync(flags_host, S.flags, nb, hipMemcpyDeviceToHost, m->stream));
+    F4_HIP(m, hipStreamSynchronize(m->stream));
   }
-  F4_HIP(m, hipStreamSynchronize(m->stream));
-  if (ind == FOAP4_IND_MLP) m->n_fallback = (int64_t)std::count(dec.begin(), dec.end(), (int8_t)0);
   return FOAP4_OK;
 }
 

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "device_common.h"
 #include "foap4_internal.h"
 
 namespace f4 {
@@ -52,53 +53,141 @@ __device__ inline u32x4 gather8(const uint16_t *p, int st) {
 
 // ------------------------------------------------------------------ features
 
-// r0, r1 of every block in FP64 with the operation order of the definition
-// and no contraction.  One workgroup per block.
+// Density and pressure of one cell: FP64 states in the operation order of the
+// definition (v = m / rho, ke = sum m v, p = (gamma-1)(E - ke/2), no
+// contraction), FP32 states in FP32 with the hardware reciprocal.
+template <typename T, int NDIM>
+__device__ __forceinline__ void rho_p(const T *u, int64_t sv, int64_t o, double gm1, T &rho, T &p) {
+#pragma clang fp contract(off)
+  constexpr int NV = NDIM + 2;
+  rho = gload(u + o);
+  T ke = T(0);
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int d = 0; d < NDIM; d++) {
+      const T md = gload(u + (1 + d) * sv + o);
+      const T v = md / rho;
+      ke = ke + md * v;
+    }
+    p = (T)gm1 * (gload(u + (NV - 1) * sv + o) - T(0.5) * ke);
+  } else {
+    const T ir = __builtin_amdgcn_rcpf(rho);
+#pragma unroll
+    for (int d = 0; d < NDIM; d++) {
+      const T md = gload(u + (1 + d) * sv + o);
+      ke = ke + md * (md * ir);
+    }
+    p = (T)gm1 * (gload(u + (NV - 1) * sv + o) - T(0.5) * ke);
+  }
+}
+
+// r0, r1 of every block: one workgroup per block marches over the planes;
+// density and pressure of plane k (interior and the one-cell face ring from
+// the ghost cells) go to LDS for the x/y differences, each thread keeps its
+// own cells' planes k-1, k, k+1 in registers for the z differences, so every
+// cell is converted once.  Differences, squares (summed x, y, z) and the
+// maxima follow the definition; FP64 states give the plain evaluation's
+// values bit for bit.
 template <typename T, int NDIM>
 __global__ __launch_bounds__(256) void raw_features_kernel(const MeshDev *__restrict__ Mp, double *raw) {
 #pragma clang fp contract(off)
   const MeshDev &M = *Mp;
   constexpr int NV = NDIM + 2;
+  constexpr int CPT = 4;      // own cells per thread (N <= 32)
+  constexpr int LW = 34;      // LDS row: N + 2 <= 34
+  __shared__ T pl[2][2][LW * LW];  // [buffer][rho, p][cell]
+  __shared__ double red[2][256];
   const int64_t b = blockIdx.x;
-  const int N = M.N, g = M.g, P = N + 2 * g;
+  const int N = M.N, g = M.g, P = N + 2 * g, L = N + 2;
   const int64_t sv = (NDIM == 3) ? (int64_t)P * P * P : (int64_t)P * P;
   const T *u = (const T *)M.s[M.cur] + b * sv * NV;
-  const int64_t st[3] = {1, P, (int64_t)P * P};
   const double gm1 = M.gamma - 1.0;
-  auto prim = [&](int64_t o, double &rho, double &p) {
-    rho = (double)u[o];
-    double ke = 0.0;
-#pragma unroll
-    for (int d = 0; d < NDIM; d++) {
-      const double md = (double)u[(1 + d) * sv + o];
-      const double v = md / rho;
-      ke = ke + md * v;
-    }
-    const double E = (double)u[(NV - 1) * sv + o];
-    p = gm1 * (E - 0.5 * ke);
+  const int nk = (NDIM == 3) ? N : 1;
+  auto at = [&](int i, int j, int k) -> int64_t {
+    return (NDIM == 3 ? (int64_t)(k + g) * P * P : 0) + (int64_t)(j + g) * P + (i + g);
   };
-  const int cells = (NDIM == 3) ? N * N * N : N * N;
-  double best_r = 0.0, best_p = 0.0;
-  for (int c = threadIdx.x; c < cells; c += blockDim.x) {
-    const int i = c % N, j = (c / N) % N, k = (NDIM == 3) ? c / (N * N) : 0;
-    const int64_t o = (NDIM == 3 ? (int64_t)(k + g) * P * P : 0) + (int64_t)(j + g) * P + (i + g);
-    double rc, pc;
-    prim(o, rc, pc);
-    double sr = 0.0, sp = 0.0;
+  const int ncell = N * N;
+  // own cells c = tid + 256 m, m < CPT, c < N*N
+  T r0[CPT], p0[CPT], r1[CPT], p1[CPT], r2[CPT], p2[CPT];  // planes k-1, k, k+1
 #pragma unroll
-    for (int d = 0; d < NDIM; d++) {
-      double rl, pl, rh, ph;
-      prim(o - st[d], rl, pl);
-      prim(o + st[d], rh, ph);
-      const double dr = 0.5 * (rh - rl), dp = 0.5 * (ph - pl);
-      sr = (d == 0) ? dr * dr : sr + dr * dr;
-      sp = (d == 0) ? dp * dp : sp + dp * dp;
+  for (int m = 0; m < CPT; m++) {
+    const int c = threadIdx.x + 256 * m;
+    r0[m] = p0[m] = r1[m] = p1[m] = T(1);
+    if (c < ncell) {
+      if (NDIM == 3) rho_p<T, NDIM>(u, sv, at(c % N, c / N, -1), gm1, r0[m], p0[m]);
+      rho_p<T, NDIM>(u, sv, at(c % N, c / N, 0), gm1, r1[m], p1[m]);
     }
-    const double gr = sqrt(sr) / rc, gp = sqrt(sp) / pc;
-    if (gr > best_r) best_r = gr;
-    if (gp > best_p) best_p = gp;
   }
-  __shared__ double red[2][256];
+  double best_r = 0.0, best_p = 0.0;
+  for (int k = 0; k < nk; k++) {
+    T *R = pl[k & 1][0], *Pp = pl[k & 1][1];
+    // plane k into LDS: own cells, then the face ring (ghost cells)
+#pragma unroll
+    for (int m = 0; m < CPT; m++) {
+      const int c = threadIdx.x + 256 * m;
+      if (c < ncell) {
+        const int o = (c / N + 1) * L + (c % N + 1);
+        R[o] = r1[m];
+        Pp[o] = p1[m];
+      }
+    }
+    if ((int)threadIdx.x < 4 * N) {
+      const int side = threadIdx.x / N, t = threadIdx.x % N;
+      const int i = side == 0 ? -1 : side == 1 ? N : t, j = side < 2 ? t : (side == 2 ? -1 : N);
+      T rr, pp;
+      rho_p<T, NDIM>(u, sv, at(i, j, k), gm1, rr, pp);
+      R[(j + 1) * L + (i + 1)] = rr;
+      Pp[(j + 1) * L + (i + 1)] = pp;
+    }
+    // own cells of plane k + 1 for the z differences
+    if constexpr (NDIM == 3) {
+#pragma unroll
+      for (int m = 0; m < CPT; m++) {
+        const int c = threadIdx.x + 256 * m;
+        r2[m] = p2[m] = T(1);
+        if (c < ncell) rho_p<T, NDIM>(u, sv, at(c % N, c / N, k + 1), gm1, r2[m], p2[m]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < CPT; m++) {
+      const int c = threadIdx.x + 256 * m;
+      if (c < ncell) {
+        const int o = (c / N + 1) * L + (c % N + 1);
+        const T hf = T(0.5);
+        const T drx = hf * (R[o + 1] - R[o - 1]), dpx = hf * (Pp[o + 1] - Pp[o - 1]);
+        const T dry = hf * (R[o + L] - R[o - L]), dpy = hf * (Pp[o + L] - Pp[o - L]);
+        T sr = drx * drx, sp = dpx * dpx;
+        sr = sr + dry * dry;
+        sp = sp + dpy * dpy;
+        if constexpr (NDIM == 3) {
+          const T drz = hf * (r2[m] - r0[m]), dpz = hf * (p2[m] - p0[m]);
+          sr = sr + drz * drz;
+          sp = sp + dpz * dpz;
+        }
+        double gr, gp;
+        if constexpr (sizeof(T) == 8) {
+          gr = sqrt(sr) / r1[m];
+          gp = sqrt(sp) / p1[m];
+        } else {
+          gr = (double)(__builtin_amdgcn_sqrtf(sr) * __builtin_amdgcn_rcpf(r1[m]));
+          gp = (double)(__builtin_amdgcn_sqrtf(sp) * __builtin_amdgcn_rcpf(p1[m]));
+        }
+        if (gr > best_r) best_r = gr;
+        if (gp > best_p) best_p = gp;
+      }
+    }
+    if constexpr (NDIM == 3) {
+#pragma unroll
+      for (int m = 0; m < CPT; m++) {
+        r0[m] = r1[m];
+        p0[m] = p1[m];
+        r1[m] = r2[m];
+        p1[m] = p2[m];
+      }
+    }
+    // the other LDS buffer is written next; this one is reused two planes on
+  }
   red[0][threadIdx.x] = best_r;
   red[1][threadIdx.x] = best_p;
   __syncthreads();
