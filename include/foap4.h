@@ -198,6 +198,22 @@ foap4_status foap4_regrid(foap4_mesh *mesh, const int8_t *flags_host, int32_t *c
  * Device buffers owned by the caller; feat_dev 16-byte aligned.  Enqueue only. */
 foap4_status foap4_block_features(foap4_mesh *mesh, float *feat_dev, double *raw_dev);
 
+/* on != 0: every later foap4_step call also evaluates r0, r1 of the state at
+ * the start of its last step, inside that step's first stage (the primitive
+ * planes the stage stages in LDS give the central differences; FP32 states
+ * in FP32), so that no separate pass over the state is needed at a regrid.
+ * The captured values stay valid until the next step or regrid. */
+foap4_status foap4_mesh_capture_features(foap4_mesh *mesh, int32_t on);
+
+/* The 16 features (layout as foap4_block_features) assembled from the values
+ * captured by the last foap4_step call, and (raw_dev non-NULL) the captured
+ * r0, r1 [n_blocks][2].  They describe the state one step before the current
+ * one.  FOAP4_E_ORDER if that call did not capture (capture off, or a step
+ * or regrid came after it).  Enqueue only.  FOAP4_IND_MLP flags use them
+ * whenever they are valid; then ghosts are filled and the criterion runs
+ * only if some block falls back to it. */
+foap4_status foap4_captured_features(foap4_mesh *mesh, float *feat_dev, double *raw_dev);
+
 /* Chooses the indicator foap4_regrid uses when flags_host is NULL, and
  * attaches net (may be NULL for FOAP4_IND_LOHNER) for FOAP4_IND_MLP.  The
  * network is referenced, not copied: it must outlive the attachment, and its

@@ -62,6 +62,8 @@ EXPORTS = {
     "foap4_batch_phase_times": (I32, [P, I32, P]),
     "foap4_block_features": (I32, [P, P, P]),
     "foap4_mesh_set_indicator": (I32, [P, I32, P]),
+    "foap4_mesh_capture_features": (I32, [P, I32]),
+    "foap4_captured_features": (I32, [P, P, P]),
     "foap4_indicator_fallbacks": (I32, [P, P]),
     "foap4_mlp_create": (I32, [P, ctypes.POINTER(P)]),
     "foap4_mlp_destroy": (I32, [P]),
@@ -246,6 +248,20 @@ class Mesh:
         feat = torch.empty((max(nb, 1), 16), dtype=torch.float32, device=self.state[0].device)
         r = torch.empty((max(nb, 1), 2), dtype=torch.float64, device=self.state[0].device) if raw else None
         _check(lib().foap4_block_features(self.h, P(feat.data_ptr()), P(r.data_ptr()) if raw else None), self.h)
+        return (feat[:nb], r[:nb]) if raw else feat[:nb]
+
+    def capture_features(self, on=True):
+        """Let every later step() capture the features of the state at the
+        start of its last step, inside that step's first stage."""
+        _check(lib().foap4_mesh_capture_features(self.h, 1 if on else 0), self.h)
+
+    def captured_features(self, raw=False):
+        """Features [nb][16] (and raw [nb][2]) captured by the last step()."""
+        torch = _torch()
+        nb = self.nb
+        feat = torch.empty((max(nb, 1), 16), dtype=torch.float32, device=self.state[0].device)
+        r = torch.empty((max(nb, 1), 2), dtype=torch.float64, device=self.state[0].device) if raw else None
+        _check(lib().foap4_captured_features(self.h, P(feat.data_ptr()), P(r.data_ptr()) if raw else None), self.h)
         return (feat[:nb], r[:nb]) if raw else feat[:nb]
 
     def set_indicator(self, indicator, mlp=None):

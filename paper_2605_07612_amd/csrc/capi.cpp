@@ -212,7 +212,7 @@ foap4_status foap4_mesh_destroy(foap4_mesh *m) {
   if (m->stream) (void)hipStreamSynchronize(m->stream);
   void *ptrs[] = {m->d_level, m->d_gc, m->d_keys, m->d_scal, m->d_dev, m->d_item_begin,
                   m->pat.srl, m->pat.f2c, m->pat.c2f, m->pat.bc, m->pat.face_info, m->pat.fix_list,
-                  m->pat.cnt, m->pat.tot, m->pat.bflux_f, m->pat.bflux_c, m->d_ind};
+                  m->pat.cnt, m->pat.tot, m->pat.bflux_f, m->pat.bflux_c, m->d_ind, m->d_featcap};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -286,16 +286,56 @@ foap4_status foap4_step(foap4_mesh *m, int32_t n_steps, double *t_out, double *d
   const int64_t items = stage_items_for(ndim, m->d.block_n, (int64_t)m->topo.leaves.size(), 1);
   foap4_status st;
   if ((st = ensure_dt(m)) != FOAP4_OK) return st;
+  const size_t nb = m->topo.leaves.size();
+  const bool capture = m->capture && n_steps > 0 && nb > 0;
+  if (capture && m->cap_featcap < nb) {
+    if (m->d_featcap) F4_HIP(m, hipFree(m->d_featcap));
+    m->d_featcap = nullptr;
+    m->cap_featcap = 0;
+    F4_HIP(m, hipMalloc((void **)&m->d_featcap, nb * 16));
+    m->cap_featcap = nb;
+  }
   for (int32_t s = 0; s < n_steps; s++) {
     if ((st = fill(m, m->d_dev, 0)) != FOAP4_OK) return st;
-    F4_HIP(m, launch_stage(m->d_dev, 1, items, 1, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n)));
+    if (capture && s == n_steps - 1) {
+      // last step: stage 1 also reduces the features of its input state
+      F4_HIP(m, hipMemsetAsync(m->d_featcap, 0, nb * 16, m->stream));
+      F4_HIP(m, launch_stage1_features(m->d_dev, items, ndim, f64, nmask_of(m->d.block_n), m->d_featcap, m->stream));
+    } else {
+      F4_HIP(m, launch_stage(m->d_dev, 1, items, 1, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n)));
+    }
     F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, 1, m->stream));
     if ((st = fill(m, m->d_dev, 1)) != FOAP4_OK) return st;
     F4_HIP(m, launch_stage(m->d_dev, 1, items, 2, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n)));
     F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, 2, m->stream));
     F4_HIP(m, launch_finalize(m->d_dev, 1, 1, m->stream));
   }
+  m->steps_done += n_steps;
+  if (capture) {
+    m->cap_at = m->steps_done;
+    m->cap_rev = m->revision;
+  }
   if (t_out || dt_out) return foap4_time(m, t_out, dt_out);
+  return FOAP4_OK;
+}
+
+foap4_status foap4_mesh_capture_features(foap4_mesh *m, int32_t on) {
+  if (!m) return fail(nullptr, FOAP4_E_INVALID, "null mesh");
+  m->capture = on != 0;
+  return FOAP4_OK;
+}
+
+static bool capture_fresh(const foap4_mesh *m) {
+  return m->cap_at >= 0 && m->cap_at == m->steps_done && m->cap_rev == m->revision;
+}
+
+foap4_status foap4_captured_features(foap4_mesh *m, float *feat_dev, double *raw_dev) {
+  if (!m || !feat_dev) return fail(m, FOAP4_E_INVALID, "null argument");
+  if (((uintptr_t)feat_dev & 15u) != 0) return fail(m, FOAP4_E_INVALID, "features must be 16-byte aligned");
+  if (!capture_fresh(m)) return fail(m, FOAP4_E_ORDER, "no features captured by the last step of this mesh");
+  const size_t nb = m->topo.leaves.size();
+  F4_HIP(m, launch_assemble_features(m, m->d_featcap, feat_dev, m->stream));
+  if (raw_dev) F4_HIP(m, hipMemcpyAsync(raw_dev, m->d_featcap, nb * 16, hipMemcpyDeviceToDevice, m->stream));
   return FOAP4_OK;
 }
 
@@ -386,6 +426,24 @@ foap4_status foap4_refine_flags(foap4_mesh *m, foap4_indicator ind, int8_t *flag
   foap4_status st;
   IndScratch S;
   if ((st = ind_scratch(m, S)) != FOAP4_OK) return st;
+  if (ind == FOAP4_IND_MLP && capture_fresh(m)) {
+    // features captured by the last step: the network first; ghosts and the
+    // criterion only if some block falls back to it
+    F4_HIP(m, launch_assemble_features(m, m->d_featcap, S.feat, m->stream));
+    F4_HIP(m, launch_mlp_decide(m->mlp, S.feat, (int64_t)nb, S.flags, S.decided, m->stream));
+    std::vector<int8_t> both(2 * nb);
+    F4_HIP(m, hipMemcpyAsync(both.data(), S.flags, 2 * nb, hipMemcpyDeviceToHost, m->stream));
+    F4_HIP(m, hipStreamSynchronize(m->stream));
+    m->n_fallback = (int64_t)std::count(both.begin() + nb, both.end(), (int8_t)0);
+    if (m->n_fallback > 0) {
+      if ((st = fill(m, m->d_dev, 0)) != FOAP4_OK) return st;
+      F4_HIP(m, launch_lohner(m, S.flags, S.decided, m->stream));
+      F4_HIP(m, hipMemcpyAsync(both.data(), S.flags, nb, hipMemcpyDeviceToHost, m->stream));
+      F4_HIP(m, hipStreamSynchronize(m->stream));
+    }
+    std::memcpy(flags_host, both.data(), nb);
+    return FOAP4_OK;
+  }
   if ((st = fill(m, m->d_dev, 0)) != FOAP4_OK) return st;
   if (ind == FOAP4_IND_MLP) {
     F4_HIP(m, launch_block_features(m, S.raw, S.feat, m->stream));

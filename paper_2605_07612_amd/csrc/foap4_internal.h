@@ -131,6 +131,12 @@ struct foap4_mesh {
   void *d_ind = nullptr;       // raw features, features, flags, decisions
   size_t cap_ind = 0;
   int64_t n_fallback = 0;      // blocks of the last MLP flag call that took the Lohner flag
+  // features captured by the stage-1 pass of the last step of a foap4_step call
+  bool capture = false;
+  double *d_featcap = nullptr; // [nb][2] raw maxima of the state at the start of that step
+  size_t cap_featcap = 0;      // in blocks
+  int64_t steps_done = 0;      // steps taken by foap4_step since creation
+  int64_t cap_at = -1, cap_rev = -1;  // steps_done and revision when captured
   std::string err;
 };
 
@@ -180,6 +186,10 @@ int64_t stage_items_for(int ndim, int N, int64_t nb, int ks);
 // nmask: block sizes present in the launch (1: N = 8, 2: N = 16, 4: N = 32)
 hipError_t launch_stage(const MeshDev *d_meshes, int n_meshes, int64_t total_items, int stage,
                         int ndim, bool f64, int grid, hipStream_t s, int xcd, int nmask);
+// stage 1 of one mesh that also reduces the raw features of its input state
+// (feat_raw [nb][2], zeroed by the caller) by atomic maxima
+hipError_t launch_stage1_features(const MeshDev *d_mesh, int64_t total_items, int ndim, bool f64, int nmask,
+                                  double *feat_raw, hipStream_t s);
 inline int nmask_of(int N) { return N == 8 ? 1 : (N == 16 ? 2 : 4); }
 // reduce.hip
 hipError_t launch_dt_full(const foap4_mesh *m, hipStream_t s);
@@ -195,6 +205,7 @@ hipError_t launch_remap(const foap4_mesh *m, const void *src_state, void *dst_st
 // feat [nb][16] FP32; MLP decisions: flags[b] = argmax - 1 and decided[b] = 1
 // where the largest class probability reaches the threshold, else decided 0
 hipError_t launch_block_features(const foap4_mesh *m, double *d_raw, float *d_feat, hipStream_t s);
+hipError_t launch_assemble_features(const foap4_mesh *m, const double *d_raw, float *d_feat, hipStream_t s);
 hipError_t launch_mlp_decide(const foap4_mlp *net, const float *d_feat, int64_t n, int8_t *d_flags,
                              int8_t *d_decided, hipStream_t s);
 

@@ -656,6 +656,13 @@ hipError_t launch_block_features(const foap4_mesh *m, double *d_raw, float *d_fe
     if (f64) raw_features_kernel<double, 2><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, d_raw);
     else raw_features_kernel<float, 2><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, d_raw);
   }
+  const hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch_assemble_features(m, d_raw, d_feat, s);
+}
+
+hipError_t launch_assemble_features(const foap4_mesh *m, const double *d_raw, float *d_feat, hipStream_t s) {
+  const int64_t nb = (int64_t)m->topo.leaves.size();
+  if (nb == 0) return hipSuccess;
   const double lmax = (double)(m->d.max_level > 1 ? m->d.max_level : 1);
   assemble_features_kernel<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(m->d_dev, m->d.ndim, lmax, d_raw, d_feat);
   return hipGetLastError();

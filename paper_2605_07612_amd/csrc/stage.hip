@@ -123,9 +123,13 @@ __device__ __forceinline__ void plane_face(const T *Wp, int base, int step, bool
   for (int v = 0; v < NV; v++) F[v] = (v == 1) ? (sw ? G[2] : G[1]) : (v == 2) ? (sw ? G[1] : G[2]) : G[v];
 }
 
-template <typename T, int NDIM, int N>
+// FEAT (stage 1 only): also reduce, per block, r0 = max |grad rho| / rho and
+// r1 = max |grad p| / p over the interior cells of the stage's input state
+// (undivided central differences, squares summed x, y, z) into feat_raw[b][2]
+// by an atomic maximum; the primitive planes are already in LDS.
+template <typename T, int NDIM, int N, bool FEAT = false>
 __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t local, T *smem,
-                                           double &vmax, bool &bad) {
+                                           double &vmax, bool &bad, double *feat_raw = nullptr) {
   using C = TileCfg<N>;
   constexpr int TILE = C::TILE, SUB = C::SUB, TPB = C::TPB;
   constexpr int NV = NDIM + 2;
@@ -258,6 +262,27 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     for (int v = 0; v < NV; v++) S[v * PLANE + at] = W[v];
   };
 
+  [[maybe_unused]] T fr = T(0), fp = T(0);  // this thread's feature maxima
+  [[maybe_unused]] T zr = T(1), zp = T(1);  // rho, p of own cell k0 - 1
+  // features of plane q of the own column; planes q-1 / q+1 from lo / hi
+  [[maybe_unused]] auto feat_cell = [&](const T *Sq, T rlo, T plo, T rhi, T phi) {
+    const T *c = Sq + own_lds, *cp = Sq + (NV - 1) * PLANE + own_lds;
+    const T hf = T(0.5);
+    const T drx = hf * (c[1] - c[-1]), dpx = hf * (cp[1] - cp[-1]);
+    const T dry = hf * (c[LP] - c[-LP]), dpy = hf * (cp[LP] - cp[-LP]);
+    T sr = drx * drx, sp = dpx * dpx;
+    sr = sr + dry * dry;
+    sp = sp + dpy * dpy;
+    if constexpr (NDIM == 3) {
+      const T drz = hf * (rhi - rlo), dpz = hf * (phi - plo);
+      sr = sr + drz * drz;
+      sp = sp + dpz * dpz;
+    }
+    const T gr = fsqrt(sr) * frcp(c[0]), gp = fsqrt(sp) * frcp(cp[0]);
+    fr = gr > fr ? gr : fr;
+    fp = gp > fp ? gp : fp;
+  };
+
   if constexpr (NDIM == 3) {
     T tmp[NV], Wm2[NV], Wm1[NV], W0[NV], W1[NV];
     load(col(k0 - 2), tmp);
@@ -290,6 +315,10 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     }
     rusanov<T, NDIM, 2>(L, Rt, gamma, Fz);
     if (k0 == 0) store_bflux(4, I, J, Fz);
+    if constexpr (FEAT) {
+      zr = Wm1[0];
+      zp = Wm1[NV - 1];
+    }
     load(col(k0 + 2), Q);
     if (ring) load(ring_p + (k0 + 2) * sk, R);
   } else {
@@ -324,6 +353,19 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     }
     const T *Wp = slot(k);
     __syncthreads();
+
+    if constexpr (FEAT) {
+      if (valid) {
+        if constexpr (NDIM == 3) {
+          const T *S1 = slot(k + 1), *S2 = slot(k + 2);
+          constexpr int PV = (NV - 1) * PLANE;
+          if (k == k0) feat_cell(Wp, zr, zp, S1[own_lds], S1[PV + own_lds]);
+          if (k + 1 < k1) feat_cell(S1, Wp[own_lds], Wp[PV + own_lds], S2[own_lds], S2[PV + own_lds]);
+        } else {
+          feat_cell(Wp, T(0), T(0), T(0), T(0));
+        }
+      }
+    }
 
     T Fz1[NV];
     if constexpr (NDIM == 3) {
@@ -408,6 +450,18 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       copyv<T, NV>(Fz, Fz1);
       copyv<T, NV>(Ua, Ub);
       copyv<T, NV>(Ub, Uc);
+    }
+  }
+  if constexpr (FEAT) {
+    double dr = (double)fr, dp = (double)fp;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      dr = fmax(dr, __shfl_xor(dr, o));
+      dp = fmax(dp, __shfl_xor(dp, o));
+    }
+    if ((threadIdx.x & 63) == 0 && valid) {
+      atomic_max_pos(feat_raw + 2 * b, dr);
+      atomic_max_pos(feat_raw + 2 * b + 1, dp);
     }
   }
 }
@@ -514,6 +568,43 @@ hipError_t launch_stage(const MeshDev *d_meshes, int n_meshes, int64_t total_ite
   } else {
     if (ndim == 3) launch_t<float, 3>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);
     else launch_t<float, 2>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);
+  }
+  return hipGetLastError();
+}
+
+// Stage 1 of one mesh (one workgroup per work item) that also reduces the
+// per-block features of its input state into feat_raw (zeroed by the caller).
+template <typename T, int NDIM, int NM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM>())))
+void stage1_feat_kernel(const MeshDev *__restrict__ Mp, int64_t total, double *feat_raw) {
+  __shared__ T smem[smem_cells<NDIM, NM>()];
+  constexpr int N = (NM == 1) ? 8 : (NM == 2) ? 16 : 32;
+  double vmax = 0.0;
+  bool bad = false;
+  if ((int64_t)blockIdx.x >= total) return;
+  stage_item<T, NDIM, N, true>(*Mp, 1, blockIdx.x, smem, vmax, bad, feat_raw);
+}
+
+template <typename T, int NDIM>
+static void launch_feat_t(unsigned nblk, int nmask, const MeshDev *d, int64_t total, double *fr, hipStream_t s) {
+  switch (nmask) {
+    case 1: stage1_feat_kernel<T, NDIM, 1><<<nblk, 256, 0, s>>>(d, total, fr); break;
+    case 2: stage1_feat_kernel<T, NDIM, 2><<<nblk, 256, 0, s>>>(d, total, fr); break;
+    default: stage1_feat_kernel<T, NDIM, 4><<<nblk, 256, 0, s>>>(d, total, fr); break;
+  }
+}
+
+hipError_t launch_stage1_features(const MeshDev *d_mesh, int64_t total_items, int ndim, bool f64, int nmask,
+                                  double *feat_raw, hipStream_t s) {
+  if (total_items <= 0) return hipSuccess;
+  if (nmask != 1 && nmask != 2 && nmask != 4) return hipErrorInvalidValue;
+  const unsigned nblk = (unsigned)total_items;
+  if (f64) {
+    if (ndim == 3) launch_feat_t<double, 3>(nblk, nmask, d_mesh, total_items, feat_raw, s);
+    else launch_feat_t<double, 2>(nblk, nmask, d_mesh, total_items, feat_raw, s);
+  } else {
+    if (ndim == 3) launch_feat_t<float, 3>(nblk, nmask, d_mesh, total_items, feat_raw, s);
+    else launch_feat_t<float, 2>(nblk, nmask, d_mesh, total_items, feat_raw, s);
   }
   return hipGetLastError();
 }

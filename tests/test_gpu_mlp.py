@@ -255,3 +255,77 @@ def test_regrid_uses_attached_indicator(f4):
     l1, l2 = g1.export(), g2.export()
     assert all(np.array_equal(a, b) for a, b in zip(l1, l2))
     assert np.array_equal(g1.current().cpu().numpy(), g2.current().cpu().numpy())
+
+
+@pytest.mark.parametrize("wname,prec", [("noise3d_refined", 1), ("noise3d_refined", 0), ("wave2d_refined", 1),
+                                        ("blast_small", 1)])
+def test_captured_features_match_oracle(f4, wname, prec):
+    """Features captured inside the first stage of a step describe the state
+    at the start of that step: compare with the oracle's features of that
+    state (FP64: to rounding of the reciprocal-multiply; FP32: to FP32
+    rounding of the log features)."""
+    w = WORKLOADS[wname]()
+    say("case", wname, prec)
+    gm, om = build_pair(w, prec)
+    if prec == 0:
+        om.interior()[...] = om.interior().astype(np.float32).astype(np.float64)
+    raw_o, F_o = oracle_features(om, lmax=1)
+    with pytest.raises(f4.Foap4Error, match="E_ORDER"):
+        gm.captured_features()
+    gm.capture_features(True)
+    gm.step(1)
+    feat, raw = gm.captured_features(raw=True)
+    raw_g, F_g = raw.cpu().numpy(), feat.cpu().numpy().astype(np.float64)
+    if prec == 1:
+        # r is a ratio of O(1) state values: rounding differences are ~1e-16
+        # absolute (a uniform pressure gives r1 ~ 1e-16 of pure rounding)
+        assert np.allclose(raw_g, raw_o, rtol=1e-12, atol=1e-13), np.max(np.abs(raw_g - raw_o))
+        assert np.all(np.abs(F_g - F_o) <= 1.2e-7 * np.abs(F_o) + 1e-13)
+    else:
+        assert np.max(np.abs(F_g - F_o)) <= 2e-5 * max(1.0, np.max(np.abs(F_o)))
+    # the values are those of one step: a later step without capture retires them
+    gm.capture_features(False)
+    gm.step(1)
+    with pytest.raises(f4.Foap4Error, match="E_ORDER"):
+        gm.captured_features()
+
+
+def test_mlp_flags_from_captured_features(f4):
+    """With captured features the MLP flags equal the network on those
+    features (the fallback taking the criterion's flag of the current state)."""
+    w = noise3d_refined()
+    gm, om = build_pair(w, 1)
+    wt = scaled_weights(12, 8.0)
+    net = f4.Mlp(wt)
+    gm.set_indicator(f4.IND_MLP, net)
+    raw_o, F_o = oracle_features(om, lmax=1)
+    gm.capture_features(True)
+    gm.step(1)
+    net.set_threshold(0.0)
+    fg = gm.refine_flags(f4.IND_MLP)
+    z = omlp.forward(wt.astype(np.float64), F_o, emulate=True)["z3"]
+    zs = np.sort(z, axis=1)
+    safe = (zs[:, 2] - zs[:, 1]) > 1e-3
+    fo, _ = omlp.predict_flags(wt.astype(np.float64), F_o, lohner=None)
+    assert np.array_equal(fg[safe], fo[safe])
+    assert gm.fallbacks() == 0
+    # with the fallback: undecided blocks get the criterion's flag of the
+    # current state; the oracle follows the same two steps
+    net.set_threshold(0.5)
+    om.step(1)
+    _, F_o1 = oracle_features(om, lmax=1)   # the state the second step starts from
+    gm.step(1)
+    om.step(1)
+    om.ghost_fill()
+    fl_o = om.lohner_flags()
+    fm = gm.refine_flags(f4.IND_MLP)
+    P = omlp.softmax(omlp.forward(wt.astype(np.float64), F_o1, emulate=True)["z3"])
+    pm = P.max(axis=1)
+    low, ok = pm < 0.5, np.abs(pm - 0.5) > 1e-3
+    say("fallbacks", gm.fallbacks(), "oracle low", int(low.sum()))
+    assert np.array_equal(fm[low & ok], fl_o[low & ok])
+    fo1, _ = omlp.predict_flags(wt.astype(np.float64), F_o1, lohner=fl_o, threshold=0.5)
+    zs = np.sort(omlp.forward(wt.astype(np.float64), F_o1, emulate=True)["z3"], axis=1)
+    safe = ok & ((zs[:, 2] - zs[:, 1]) > 1e-3)
+    assert np.array_equal(fm[safe], fo1[safe])
+    assert abs(gm.fallbacks() - int(low.sum())) <= int((~ok).sum())
