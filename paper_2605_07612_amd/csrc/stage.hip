@@ -492,15 +492,19 @@ __device__ __forceinline__ int64_t item_of(int64_t w, int64_t it, int64_t grid, 
   return j < per_xcd ? (w & 7) * per_xcd + j : total;
 }
 
-// Target waves per SIMD: 3 for single-size FP32 kernels (167 VGPRs, no
-// spills); the mixed-size and FP64 kernels keep what their registers allow.
-template <typename T, int NM>
-constexpr int stage_waves() { return (sizeof(T) == 4 && NM != 7) ? 3 : 1; }
+// Target waves per SIMD: single-size FP32 kernels 4 in stage 1 (no stage-2
+// state) and 3 in stage 2; the mixed-size and FP64 kernels keep what their
+// registers allow.
+template <typename T, int NM, int STG = 2>
+constexpr int stage_waves() { return (sizeof(T) == 4 && NM != 7) ? (STG == 1 ? 4 : 3) : 1; }
 
 // NM: bit mask of the block sizes present (1: N = 8, 2: N = 16, 4: N = 32)
-template <typename T, int NDIM, int NM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM>())))
-void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t total, int stage, int xcd) {
+// STG: the Heun stage (compiled separately: stage 1 needs no U^n stream and
+// no dt epilogue, so it runs with fewer registers)
+template <typename T, int NDIM, int NM, int STG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM, STG>())))
+void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t total, int xcd) {
+  constexpr int stage = STG;
   __shared__ T smem[smem_cells<NDIM, NM>()];
   double vmax = 0.0;
   bool bad = false;
@@ -550,10 +554,22 @@ template <typename T, int NDIM>
 static void launch_t(unsigned nblk, int nmask, const MeshDev *d, int n, int64_t total, int stage, int xcd,
                      hipStream_t s) {
   switch (nmask) {
-    case 1: stage_kernel<T, NDIM, 1><<<nblk, 256, 0, s>>>(d, n, total, stage, xcd); break;
-    case 2: stage_kernel<T, NDIM, 2><<<nblk, 256, 0, s>>>(d, n, total, stage, xcd); break;
-    case 4: stage_kernel<T, NDIM, 4><<<nblk, 256, 0, s>>>(d, n, total, stage, xcd); break;
-    default: stage_kernel<T, NDIM, 7><<<nblk, 256, 0, s>>>(d, n, total, stage, xcd); break;
+    case 1:
+      if (stage == 1) stage_kernel<T, NDIM, 1, 1><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      else stage_kernel<T, NDIM, 1, 2><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      break;
+    case 2:
+      if (stage == 1) stage_kernel<T, NDIM, 2, 1><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      else stage_kernel<T, NDIM, 2, 2><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      break;
+    case 4:
+      if (stage == 1) stage_kernel<T, NDIM, 4, 1><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      else stage_kernel<T, NDIM, 4, 2><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      break;
+    default:
+      if (stage == 1) stage_kernel<T, NDIM, 7, 1><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      else stage_kernel<T, NDIM, 7, 2><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      break;
   }
 }
 
@@ -575,7 +591,7 @@ hipError_t launch_stage(const MeshDev *d_meshes, int n_meshes, int64_t total_ite
 // Stage 1 of one mesh (one workgroup per work item) that also reduces the
 // per-block features of its input state into feat_raw (zeroed by the caller).
 template <typename T, int NDIM, int NM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM>())))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM, 1>())))
 void stage1_feat_kernel(const MeshDev *__restrict__ Mp, int64_t total, double *feat_raw) {
   __shared__ T smem[smem_cells<NDIM, NM>()];
   constexpr int N = (NM == 1) ? 8 : (NM == 2) ? 16 : 32;
