@@ -135,7 +135,9 @@ foap4_status foap4_compute_dt(foap4_mesh *mesh);
  * the stream is synchronized and the simulation time / the dt of the next
  * step are returned, and FOAP4_E_UNPHYSICAL is reported if the state went
  * bad.  This is the plain form: one kernel launch per operation and one
- * workgroup per block tile. */
+ * workgroup per block tile.  Ghost cells of both state buffers are
+ * unspecified after a step (the stages may overwrite them); every call that
+ * reads ghosts fills them first. */
 foap4_status foap4_step(foap4_mesh *mesh, int32_t n_steps, double *t_out, double *dt_out);
 
 /* Reads back the simulation time and the dt of the next step (synchronizes). */

@@ -243,6 +243,39 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     return own_p + kk * sk;
   };
 
+  // Ghost positions of this tile's share of an output plane: the x ghosts of
+  // its rows and, where it touches a y face of the block, the full-width
+  // ghost rows (corners included), enumerated u = 0 .. n_gh - 1 as plane
+  // offsets.  In stage 1 every tile stores zeros there, so the tiles of a
+  // block write each output plane whole: the block's written region of each
+  // variable (planes g .. g + N - 1) is then one contiguous range, and no
+  // cache line of it reaches HBM partly written (the stage-1 output buffer
+  // is not read by the launch, so a partly written line would cost a
+  // read-modify-write at the memory).  Stage 2 writes over U^n, whose lines
+  // it has just read, and stores the interior only.  Ghost cells of a
+  // stage's output are never read before a ghost fill (or a gather)
+  // rewrites them.
+  const int gl = (i0 == 0) ? g : 0, gr = (i0 + TILE == N) ? g : 0;
+  const int gb = (j0 == 0) ? g : 0, gt = (j0 + TILE == N) ? g : 0;
+  const int gw = TILE + gl + gr;
+  const int n_gh = (gb + gt) * gw + TILE * (gl + gr);
+  auto ghost_at = [&](int u) -> int {
+    int x, y;
+    if (u < gb * gw) {
+      y = j0 - gb + u / gw;
+      x = i0 - gl + u % gw;
+    } else if ((u -= gb * gw) < gt * gw) {
+      y = j0 + TILE + u / gw;
+      x = i0 - gl + u % gw;
+    } else {
+      u -= gt * gw;
+      const int w = gl + gr, c = u % w;
+      y = j0 + u / w;
+      x = c < gl ? i0 - gl + c : i0 + TILE + (c - gl);
+    }
+    return (y + g) * sj + (x + g);
+  };
+
   // cells next to F2C faces are finished (and their dt taken) by the flux fix
   auto is_f2c = [&](int f) { return f < NF && finfo[f] >= 0 && (finfo[f] & 1); };
   const bool f2c_adj = (is_f2c(0) && I == 0) || (is_f2c(1) && I == N - 1) || (is_f2c(2) && J == 0) ||
@@ -434,6 +467,12 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     if (valid) {
 #pragma unroll
       for (int v = 0; v < NV; v++) gstore(uo + v * sv + o, Uout[v]);
+      const int pk = (NDIM == 3) ? (k + g) * sk : 0;
+      for (int u = lt; stage == 1 && u < n_gh; u += TT) {
+        const int q = pk + ghost_at(u);
+#pragma unroll
+        for (int v = 0; v < NV; v++) gstore(uo + v * sv + q, T(0));
+      }
     }
     if (stage == 2 && valid) {
       const bool skip = f2c_adj || (f2c_zlo && k == 0) || (f2c_zhi && k == N - 1);
@@ -493,10 +532,11 @@ __device__ __forceinline__ int64_t item_of(int64_t w, int64_t it, int64_t grid, 
 }
 
 // Target waves per SIMD: single-size FP32 kernels 4 in stage 1 (no stage-2
-// state) and 3 in stage 2; the mixed-size and FP64 kernels keep what their
+// state; 3 for N = 32, whose tiles do not fit 128 registers without spills)
+// and 3 in stage 2; the mixed-size and FP64 kernels keep what their
 // registers allow.
 template <typename T, int NM, int STG = 2>
-constexpr int stage_waves() { return (sizeof(T) == 4 && NM != 7) ? (STG == 1 ? 4 : 3) : 1; }
+constexpr int stage_waves() { return (sizeof(T) == 4 && NM != 7) ? ((STG == 1 && NM != 4) ? 4 : 3) : 1; }
 
 // NM: bit mask of the block sizes present (1: N = 8, 2: N = 16, 4: N = 32)
 // STG: the Heun stage (compiled separately: stage 1 needs no U^n stream and
