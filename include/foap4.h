@@ -74,7 +74,9 @@ typedef struct {
 /* Creates a mesh at the uniform level desc->init_level (Sec. 2.2) and its
  * leaf table in Morton order per tree (block n = leaf n).  state0/state1 are
  * caller-owned device buffers of state_bytes_each bytes each (>= max_blocks *
- * nvar * P^ndim * element size); the caller writes the initial condition into
+ * nvar * P^ndim * element size), 16-byte aligned (256-byte alignment, as
+ * torch gives, keeps every block's rows on whole cache lines where the
+ * layout allows); the caller writes the initial condition into
  * the interior cells of state0.  hip_stream is a hipStream_t (NULL: default
  * stream).  Builds the ghost pattern.  Errors: FOAP4_E_INVALID (descriptor),
  * FOAP4_E_CAPACITY (initial blocks > max_blocks), FOAP4_E_HIP. */

@@ -161,6 +161,8 @@ foap4_status foap4_mesh_create(const foap4_mesh_desc *desc, void *state0, void *
   if (!(d.tree_size > 0) || !(d.gamma > 1) || !(d.cfl > 0)) return fail(nullptr, FOAP4_E_INVALID, "tree_size, gamma, cfl");
   if (d.prec != FOAP4_F32 && d.prec != FOAP4_F64) return fail(nullptr, FOAP4_E_INVALID, "prec");
   if (!state0 || !state1 || state0 == state1) return fail(nullptr, FOAP4_E_INVALID, "two distinct state buffers needed");
+  if ((((uintptr_t)state0) | ((uintptr_t)state1)) & 15u)
+    return fail(nullptr, FOAP4_E_INVALID, "state buffers must be 16-byte aligned");
   foap4_mesh *m = new foap4_mesh();
   m->d = d;
   m->nvar = d.ndim + 2;

@@ -50,6 +50,17 @@ constexpr int smem_cells() {
   return c;
 }
 
+// Stage-1 output planes of FP32 3D kernels for N = 16 leave through an LDS
+// staging plane as whole 16-byte vectors.  The stage-1 output buffer is not
+// read by the launch, so any partly written cache line would cost the memory
+// a read-modify-write; stage 2 writes over U^n, whose lines it has just read,
+// and gains nothing from staging (measured), so it stores cell by cell.
+template <typename T, int NDIM, int NM, int STG>
+constexpr bool stage_sout() {
+  return sizeof(T) == 4 && NDIM == 3 && NM == 2 && STG == 1;
+}
+constexpr int kSoutPlane = 20 * 20;  // padded 16^3-block plane with g = 2
+
 // CFL inverse time step sum_d (|v_d| + c) / dx of one cell.  FP64 states use
 // the operation order of the definition without contraction (equal to a plain
 // evaluation); FP32 states evaluate it in FP32 with the hardware reciprocal
@@ -127,7 +138,7 @@ __device__ __forceinline__ void plane_face(const T *Wp, int base, int step, bool
 // r1 = max |grad p| / p over the interior cells of the stage's input state
 // (undivided central differences, squares summed x, y, z) into feat_raw[b][2]
 // by an atomic maximum; the primitive planes are already in LDS.
-template <typename T, int NDIM, int N, bool FEAT = false>
+template <typename T, int NDIM, int N, bool FEAT = false, bool SOUT = false>
 __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t local, T *smem,
                                            double &vmax, bool &bad, double *feat_raw = nullptr) {
   using C = TileCfg<N>;
@@ -276,6 +287,28 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     return (y + g) * sj + (x + g);
   };
 
+  // Staged output (SOUT, g = 2): the update of plane k writes the interior
+  // of the LDS plane SO ([v][20 x 20], ghost positions kept at zero by the
+  // kernel), and plane k leaves as 16-byte vectors of the whole padded plane
+  // right after the first barrier of iteration k + 1 (the last plane after
+  // the loop), so it needs no barrier of its own.
+  static_assert(!SOUT || (N == 16 && NDIM == 3 && sizeof(T) == 4), "staged output: FP32 3D N = 16 only");
+  const bool staged = SOUT && g == 2;
+  T *SO = smem + item_cells<NDIM, N>();
+  auto copy_out = [&](int kk) {
+    if constexpr (SOUT) {
+      if (!valid) return;
+      T *dp = uo + (kk + 2) * sk;
+      constexpr int NCH = kSoutPlane / 4;
+      for (int x = lt; x < NV * NCH; x += TT) {
+        const int v = x / NCH, c = x - v * NCH;
+        using V4 = float __attribute__((ext_vector_type(4)));
+        const V4 val = *(const V4 *)(SO + v * kSoutPlane + 4 * c);
+        *(__attribute__((address_space(1))) V4 *)(dp + v * sv + 4 * c) = val;
+      }
+    }
+  };
+
   // cells next to F2C faces are finished (and their dt taken) by the flux fix
   auto is_f2c = [&](int f) { return f < NF && finfo[f] >= 0 && (finfo[f] & 1); };
   const bool f2c_adj = (is_f2c(0) && I == 0) || (is_f2c(1) && I == N - 1) || (is_f2c(2) && J == 0) ||
@@ -386,6 +419,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     }
     const T *Wp = slot(k);
     __syncthreads();
+    if (staged && k > k0) copy_out(k - 1);
 
     if constexpr (FEAT) {
       if (valid) {
@@ -464,7 +498,10 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       Uout[v] = base - cdt * div;
     }
     const int o = off(I, J, k);
-    if (valid) {
+    if (staged) {
+#pragma unroll
+      for (int v = 0; v < NV; v++) SO[v * kSoutPlane + (tj + 2) * 20 + ti + 2] = Uout[v];
+    } else if (valid) {
 #pragma unroll
       for (int v = 0; v < NV; v++) gstore(uo + v * sv + o, Uout[v]);
       const int pk = (NDIM == 3) ? (k + g) * sk : 0;
@@ -490,6 +527,10 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       copyv<T, NV>(Ua, Ub);
       copyv<T, NV>(Ub, Uc);
     }
+  }
+  if (staged) {
+    __syncthreads();
+    copy_out(k1 - 1);
   }
   if constexpr (FEAT) {
     double dr = (double)fr, dp = (double)fp;
@@ -545,7 +586,11 @@ template <typename T, int NDIM, int NM, int STG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM, STG>())))
 void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t total, int xcd) {
   constexpr int stage = STG;
-  __shared__ T smem[smem_cells<NDIM, NM>()];
+  constexpr bool SOUT = stage_sout<T, NDIM, NM, STG>();
+  __shared__ T smem[smem_cells<NDIM, NM>() + (SOUT ? (NDIM + 2) * kSoutPlane : 0)];
+  if constexpr (SOUT) {
+    for (int x = threadIdx.x; x < (NDIM + 2) * kSoutPlane; x += 256) smem[smem_cells<NDIM, NM>() + x] = T(0);
+  }
   double vmax = 0.0;
   bool bad = false;
   int mprev = -1;
@@ -567,7 +612,7 @@ void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t tota
     if constexpr (NM == 1) {
       stage_item<T, NDIM, 8>(M, stage, local, smem, vmax, bad);
     } else if constexpr (NM == 2) {
-      stage_item<T, NDIM, 16>(M, stage, local, smem, vmax, bad);
+      stage_item<T, NDIM, 16, false, SOUT>(M, stage, local, smem, vmax, bad);
     } else if constexpr (NM == 4) {
       stage_item<T, NDIM, 32>(M, stage, local, smem, vmax, bad);
     } else {
@@ -633,12 +678,16 @@ hipError_t launch_stage(const MeshDev *d_meshes, int n_meshes, int64_t total_ite
 template <typename T, int NDIM, int NM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM, 1>())))
 void stage1_feat_kernel(const MeshDev *__restrict__ Mp, int64_t total, double *feat_raw) {
-  __shared__ T smem[smem_cells<NDIM, NM>()];
+  constexpr bool SOUT = stage_sout<T, NDIM, NM, 1>();
+  __shared__ T smem[smem_cells<NDIM, NM>() + (SOUT ? (NDIM + 2) * kSoutPlane : 0)];
+  if constexpr (SOUT) {
+    for (int x = threadIdx.x; x < (NDIM + 2) * kSoutPlane; x += 256) smem[smem_cells<NDIM, NM>() + x] = T(0);
+  }
   constexpr int N = (NM == 1) ? 8 : (NM == 2) ? 16 : 32;
   double vmax = 0.0;
   bool bad = false;
   if ((int64_t)blockIdx.x >= total) return;
-  stage_item<T, NDIM, N, true>(*Mp, 1, blockIdx.x, smem, vmax, bad, feat_raw);
+  stage_item<T, NDIM, N, true, SOUT>(*Mp, 1, blockIdx.x, smem, vmax, bad, feat_raw);
 }
 
 template <typename T, int NDIM>

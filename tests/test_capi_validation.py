@@ -36,10 +36,11 @@ def desc(f4, **kw):
     return d
 
 
-def create(f4, d, nbytes=None, same=False):
-    buf = np.zeros(16, np.uint8)
-    p0 = ctypes.c_void_p(buf.ctypes.data)
-    p1 = p0 if same else ctypes.c_void_p(buf.ctypes.data + 8)
+def create(f4, d, nbytes=None, same=False, misalign=0):
+    buf = np.zeros(128, np.uint8)
+    a = (buf.ctypes.data + 15) // 16 * 16  # 16-byte aligned host dummies, never touched
+    p0 = ctypes.c_void_p(a)
+    p1 = p0 if same else ctypes.c_void_p(a + 32 + misalign)
     if nbytes is None:
         P = d.block_n + 2 * d.n_ghost
         nbytes = d.max_blocks * (d.ndim + 2) * P ** d.ndim * (8 if d.prec == 1 else 4)
@@ -84,6 +85,11 @@ def test_state_buffers_must_be_distinct_and_large_enough(f4):
     P = 12
     st, h, msg = create(f4, d, nbytes=8 * 5 * P ** 3 * 4 - 1)
     assert st == E_INVALID and not h and "smaller" in msg
+
+
+def test_state_buffers_must_be_16_byte_aligned(f4):
+    st, h, msg = create(f4, desc(f4), misalign=8)
+    assert st == E_INVALID and not h and "aligned" in msg
 
 
 def test_initial_mesh_beyond_capacity(f4):
