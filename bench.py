@@ -30,20 +30,27 @@ METRIC = "cell-updates/s per GPU + % HBM roofline, 16^3 blocks, FP32 batched vs 
 HBM_PEAK_GBS = 8000.0
 
 
-def stage_bytes_per_cell(S):
+def halo_share(N, g=2, ndim=3):
+    """Face-ghost (halo) cells per interior cell of an N^ndim block: 2 ndim g / N."""
+    return 2.0 * ndim * g / N
+
+
+def stage_bytes_per_cell(S, N=16):
     """Algorithmic HBM bytes per cell of one stage-kernel launch, averaged
-    over the two Heun stages: stage 1 reads the interior and face ghosts of
-    u^n (1.75 S for 16^3 blocks, g = 2) and writes u1 (1 S); stage 2 reads u1
-    with ghosts (1.75 S) and u^n (1 S) and writes u^{n+1} (1 S)."""
-    return (2.75 + 3.75) / 2.0 * S
+    over the two Heun stages, with h = halo_share(N) (0.75 for 16^3 blocks,
+    g = 2): stage 1 reads the interior and halo of u^n ((1 + h) S) and writes
+    u1 (1 S); stage 2 reads u1 with its halo ((1 + h) S) and u^n (1 S) and
+    writes u^{n+1} (1 S).  (2.5 + h) S: 3.25 S at N = 16."""
+    return (2.5 + halo_share(N)) * S
 
 
-def step_bytes_per_update(S, gather):
-    """Whole step per cell update.  Stored ghosts (the paper's design, the
-    plain form): 4.75 S (ghost fill reads and writes 0.75 S per stage, stages
-    as above).  Gathered halos on a mesh without refinement boundaries (the
-    batched form): no ghost fill, 3.25 S."""
-    return (3.25 if gather else 4.75) * S
+def step_bytes_per_update(S, gather, N=16):
+    """Whole step per cell update.  Gathered halos on a mesh without
+    refinement boundaries (the batched form): no ghost fill, (2.5 + h) S.
+    Stored ghosts (the paper's design, the plain form): each stage's ghost
+    fill also reads and writes h S, (2.5 + 3 h) S (4.75 S at N = 16)."""
+    h = halo_share(N)
+    return (2.5 + h if gather else 2.5 + 3.0 * h) * S
 
 
 def log(*a):
@@ -158,9 +165,9 @@ def main():
     log(f"FP32 batched: {secs / args.steps * 1e3:.3f} ms/step, {gcups32:.2f} Gcell-updates/s (wall {wall:.3f}s)")
     phases = batch.phase_times(5)
     log("phases (ms):", json.dumps({k: round(v, 4) for k, v in phases.items()}))
-    stage_bytes = cells * stage_bytes_per_cell(S32)
+    stage_bytes = cells * stage_bytes_per_cell(S32, args.block)
     achieved = stage_bytes / (phases["stage"] * 1e-3) / 1e9
-    step_gbs = gcups32 * step_bytes_per_update(S32, True)
+    step_gbs = gcups32 * step_bytes_per_update(S32, True, args.block)
 
     result = {
         "metric": METRIC,
@@ -180,10 +187,12 @@ def main():
                    "kslabs": ks, "wg_per_cu": wg, "xcd_order": xcd, "gather_halos": 1, "reductions": "f64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_counters(args.counters, stage_bytes),
-                     "kernel": "stage_kernel<float,3,N=16>", "bytes_per_launch": int(stage_bytes),
+                     # the committed counters cover the 256^3 workload in 16^3 blocks only
+                     "traffic": (traffic_from_counters(args.counters, stage_bytes)
+                                 if (args.block, args.n) == (16, 256) else None),
+                     "kernel": f"stage_kernel<float,3,N={args.block}>", "bytes_per_launch": int(stage_bytes),
                      "avg_launch_ms": round(phases["stage"], 5)},
-        "step_hbm": {"bytes_per_update": step_bytes_per_update(S32, True), "achieved_gbs": round(step_gbs, 1),
+        "step_hbm": {"bytes_per_update": step_bytes_per_update(S32, True, args.block), "achieved_gbs": round(step_gbs, 1),
                      "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
         "phases_ms": {k: round(v, 5) for k, v in phases.items()},
     }
@@ -199,7 +208,7 @@ def main():
         log(f"FP64 plain: {secs64 / args.steps * 1e3:.3f} ms/step, {gcups64:.2f} Gcell-updates/s")
         result["fp64_plain"] = {"value": round(gcups64, 4), "unit": "Gcell-updates/s",
                                 "ms_per_step": round(secs64 / args.steps * 1e3, 4),
-                                "step_hbm_frac": round(gcups64 * step_bytes_per_update(S64, False) / HBM_PEAK_GBS, 4),
+                                "step_hbm_frac": round(gcups64 * step_bytes_per_update(S64, False, args.block) / HBM_PEAK_GBS, 4),
                                 "batched_fp32_over_plain_fp64": round(gcups32 / gcups64, 3)}
         del m64
         torch.cuda.empty_cache()
@@ -213,7 +222,7 @@ def main():
         log(f"FP64 batched: {secs64b / args.steps * 1e3:.3f} ms/step, {gcups64b:.2f} Gcell-updates/s")
         result["fp64_batched"] = {"value": round(gcups64b, 4), "unit": "Gcell-updates/s",
                                   "ms_per_step": round(secs64b / args.steps * 1e3, 4), "config": list(cfg64),
-                                  "step_hbm_frac": round(gcups64b * step_bytes_per_update(S64, True) / HBM_PEAK_GBS, 4)}
+                                  "step_hbm_frac": round(gcups64b * step_bytes_per_update(S64, True, args.block) / HBM_PEAK_GBS, 4)}
         del b64, m64
         torch.cuda.empty_cache()
 
@@ -227,6 +236,9 @@ def main():
             layout.set_from_field_device(m, wp["field"])
             ms.append(m)
         cells64 = sum(int(np.prod(wp["trees"])) * wp["N"] ** 3 for wp in ws)
+        # algorithmic bytes per update, cell-weighted over the problems' block sizes
+        bpu64 = sum(int(np.prod(wp["trees"])) * wp["N"] ** 3 * step_bytes_per_update(S32, True, wp["N"])
+                    for wp in ws) / cells64
         b64 = f4.Batch(ms)
         cfg = b64.autotune(args.tune_cache)
         b64.step(args.warmup)
@@ -238,7 +250,8 @@ def main():
                              "blocks": int(sum(m.nb for m in ms)), "cells": int(cells64),
                              "ms_per_step": round(s64 / args.steps * 1e3, 4), "config": list(cfg),
                              "stage_ms": round(ph64["stage"], 4),
-                             "step_hbm_frac": round(g64 * step_bytes_per_update(S32, True) / HBM_PEAK_GBS, 4)}
+                             "bytes_per_update": round(bpu64, 2),
+                             "step_hbm_frac": round(g64 * bpu64 / HBM_PEAK_GBS, 4)}
         del b64, ms
         torch.cuda.empty_cache()
 
