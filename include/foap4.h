@@ -15,10 +15,17 @@
  *  - Device pointers are HIP device addresses on the current device; host
  *    pointers are ordinary CPU memory.  Sizes are in elements unless noted.
  *  - The two state buffers are owned by the caller and passed at creation.
- *    Each is laid out [max_blocks][nvar][P]^ndim with P = N + 2g and i
- *    fastest (the paper's uu(i,j,k,ivar,iblock), eq. array-structure), where
- *    nvar = ndim + 2 and the variables are (rho, m_x, m_y[, m_z], E).
- *    Cell (i,j,k) with -g <= i,j,k < N + g sits at padded index (i+g, j+g, k+g).
+ *    Each holds [max_blocks][nvar] groups of P^ndim values, P = N + 2g (the
+ *    paper's uu(i,j,k,ivar,iblock) of eq. array-structure, one padded block
+ *    per group), nvar = ndim + 2, variables (rho, m_x, m_y[, m_z], E).
+ *    Inside a group the rows (j, k) = (-g .. N+g-1)^(ndim-1), k slowest,
+ *    hold the N interior x cells each (i fastest), so a plane's interior is
+ *    N^2 contiguous values; then the 2g x ghosts of every row, in the same
+ *    row order.  Cell (i,j,k), -g <= i,j,k < N + g, is at offset
+ *      row * N + i                          if 0 <= i < N,
+ *      P^(ndim-1) * N + row * 2g + c        otherwise,
+ *    with row = (k+g) P + (j+g) (2D: j+g) and c = i+g (i < 0) or
+ *    i-N+g (i >= N).
  *  - Everything else (pattern, flux buffers, time step, scratch) is owned by
  *    the library and freed by foap4_mesh_destroy().
  *  - A mesh is not thread-safe; all its work runs on the HIP stream given at

@@ -145,7 +145,7 @@ class Mesh:
         d.gamma = gamma
         d.cfl = cfl
         self.desc = d
-        shape = (self.max_blocks, self.nvar) + (self.P,) * ndim
+        shape = (self.max_blocks, self.nvar, self.P ** ndim)  # row part, then x ghosts (include/foap4.h)
         self.state = [torch.zeros(shape, dtype=self.dtype, device=device),
                       torch.zeros(shape, dtype=self.dtype, device=device)]
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -281,15 +281,21 @@ class Mesh:
         return bool(ch.value)
 
     # ------------------------------------------------------------- states
-    def current(self):
-        """The current state tensor restricted to the leaf blocks."""
-        return self.state[self.cur][: self.nb]
+    def current(self, state=None):
+        """A copy of the leaf blocks' state as padded cubes [nb][nvar][P]^ndim
+        (index order k, j, i; cell (i, j, k) at (k+g, j+g, i+g))."""
+        from . import layout
+        u = self.state[self.cur if state is None else state][: self.nb]
+        return layout.to_padded(u, self.N, self.g, self.ndim)
 
     def interior(self, state=None):
+        """Writable view [nb][nvar][N]^ndim (k, j, i) of the interior cells."""
+        from . import layout
         u = self.state[self.cur if state is None else state][: self.nb]
         g, N = self.g, self.N
-        sl = (slice(None), slice(None)) + (slice(g, g + N),) * self.ndim
-        return u[sl]
+        rows = layout.rows_view(u, N, g, self.ndim)
+        sl = (slice(None), slice(None)) + (slice(g, g + N),) * (self.ndim - 1) + (slice(None),)
+        return rows[sl]
 
 
 class Batch:

@@ -28,6 +28,22 @@ constexpr int kMlpFrags = 26;         // 16x32 / 32x16 BF16 weight operand tiles
 // scal[] slots of a mesh (FP64, device)
 enum { kDt = 0, kTime = 1, kMaxInv = 2, kBad = 3, kNScal = 8 };
 
+// Offset of cell (i, j, k), -g <= i, j, k < N + g, inside the P^d values
+// (P = N + 2g) that one variable of one block occupies.  The rows [k][j]
+// (z ghost planes and y ghost rows included) hold the N interior x cells
+// only, so the interior of a plane is N^2 contiguous values; the 2g x ghosts
+// of every row follow all rows, as [k][j][c] with c = i + g for i < 0 and
+// c = i - N + g for i >= N.  The block stride (nvar P^d) and the variable
+// stride (P^d) are those of a padded cube.
+template <int NDIM>
+__host__ __device__ __forceinline__ int cell_off(int i, int j, int k, int N, int g) {
+  const int P = N + 2 * g;
+  const int row = (NDIM == 3) ? (k + g) * P + (j + g) : (j + g);
+  if ((unsigned)i < (unsigned)N) return row * N + i;
+  const int rows = (NDIM == 3) ? P * P : P;
+  return rows * N + row * 2 * g + (i < 0 ? i + g : i - N + g);
+}
+
 struct Leaf {
   int32_t level;
   int32_t g[3];  // global integer coordinates at `level` (tree * 2^level + anchor)

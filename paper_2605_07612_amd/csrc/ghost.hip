@@ -10,13 +10,11 @@ namespace f4 {
 
 template <int NDIM>
 struct Geo {
-  int g, P;
+  int N, g, P;
   int64_t sv;  // values per variable
-  __device__ Geo(int N, int g_) : g(g_), P(N + 2 * g_), sv(NDIM == 3 ? (int64_t)(N + 2 * g_) * (N + 2 * g_) * (N + 2 * g_)
-                                                               : (int64_t)(N + 2 * g_) * (N + 2 * g_)) {}
-  __device__ __forceinline__ int64_t at(const int c[3]) const {
-    return (NDIM == 3 ? (int64_t)(c[2] + g) * P * P : 0) + (int64_t)(c[1] + g) * P + (c[0] + g);
-  }
+  __device__ Geo(int N_, int g_) : N(N_), g(g_), P(N_ + 2 * g_), sv(NDIM == 3 ? (int64_t)(N_ + 2 * g_) * (N_ + 2 * g_) * (N_ + 2 * g_)
+                                                                     : (int64_t)(N_ + 2 * g_) * (N_ + 2 * g_)) {}
+  __device__ __forceinline__ int64_t at(const int c[3]) const { return cell_off<NDIM>(c[0], c[1], c[2], N, g); }
 };
 
 __device__ __forceinline__ void tangential(int ndim, int ax, int &t1, int &t2) {
@@ -50,7 +48,7 @@ __device__ void srl_record(const MeshDev &M, T *u, int ax, int32_t a, int32_t b)
       dsto[q] = -1;
       if (e >= total) continue;
       int l, p1, p2, v, side, r = e;
-      if (ax == 0) {  // layers are contiguous in memory: layer fastest
+      if (ax == 0) {  // x ghost layers of a row are contiguous in memory: layer fastest
         l = r % g; r /= g;
         p1 = r % N; r /= N;
       } else {        // rows along x are contiguous: t1 (= x) fastest

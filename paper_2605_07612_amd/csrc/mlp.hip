@@ -103,9 +103,7 @@ __global__ __launch_bounds__(256) void raw_features_kernel(const MeshDev *__rest
   const T *u = (const T *)M.s[M.cur] + b * sv * NV;
   const double gm1 = M.gamma - 1.0;
   const int nk = (NDIM == 3) ? N : 1;
-  auto at = [&](int i, int j, int k) -> int64_t {
-    return (NDIM == 3 ? (int64_t)(k + g) * P * P : 0) + (int64_t)(j + g) * P + (i + g);
-  };
+  auto at = [&](int i, int j, int k) -> int64_t { return cell_off<NDIM>(i, j, k, N, g); };
   const int ncell = N * N;
   // own cells c = tid + 256 m, m < CPT, c < N*N
   T r0[CPT], p0[CPT], r1[CPT], p1[CPT], r2[CPT], p2[CPT];  // planes k-1, k, k+1

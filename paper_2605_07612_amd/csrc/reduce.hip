@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void dt_full_kernel(const MeshDev *__restrict_
   bool bad = false;
   for (int c = threadIdx.x; c < cells; c += blockDim.x) {
     const int i = c % N, j = (c / N) % N, k = (NDIM == 3) ? c / (N * N) : 0;
-    const int64_t o = (NDIM == 3 ? (int64_t)(k + g) * P * P : 0) + (int64_t)(j + g) * P + (i + g);
+    const int64_t o = cell_off<NDIM>(i, j, k, N, g);
     double U[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) U[v] = (double)u[v * sv + o];
@@ -120,8 +120,7 @@ __global__ __launch_bounds__(256) void fluxfix_kernel(const MeshDev *__restrict_
       c[ax] = side ? N - 1 : 0;
       c[t1] = p1;
       if (t2 >= 0) c[t2] = p2;
-      const int64_t o = (int64_t)v * sv + (NDIM == 3 ? (int64_t)(c[2] + g) * P * P : 0) +
-                        (int64_t)(c[1] + g) * P + (c[0] + g);
+      const int64_t o = (int64_t)v * sv + cell_off<NDIM>(c[0], c[1], c[2], N, g);
       const double corr = side ? dts * (Fc - mean) / dx : dts * (mean - Fc) / dx;
       uo[o] = (T)((double)uo[o] + corr);
     }
@@ -141,7 +140,7 @@ __global__ __launch_bounds__(256) void fluxfix_kernel(const MeshDev *__restrict_
       c[ax] = side ? N - 1 : 0;
       c[t1] = p1;
       if (t2 >= 0) c[t2] = p2;
-      const int64_t o = (NDIM == 3 ? (int64_t)(c[2] + g) * P * P : 0) + (int64_t)(c[1] + g) * P + (c[0] + g);
+      const int64_t o = cell_off<NDIM>(c[0], c[1], c[2], N, g);
       double U[NV];
 #pragma unroll
       for (int v = 0; v < NV; v++) U[v] = (double)uo[v * sv + o];
@@ -167,7 +166,7 @@ __global__ __launch_bounds__(256) void totals_kernel(const MeshDev *__restrict__
   for (int v = 0; v < NV; v++) acc[v] = 0.0;
   for (int c = threadIdx.x; c < cells; c += blockDim.x) {
     const int i = c % N, j = (c / N) % N, k = (NDIM == 3) ? c / (N * N) : 0;
-    const int64_t o = (NDIM == 3 ? (int64_t)(k + g) * P * P : 0) + (int64_t)(j + g) * P + (i + g);
+    const int64_t o = cell_off<NDIM>(i, j, k, N, g);
 #pragma unroll
     for (int v = 0; v < NV; v++) acc[v] += (double)u[v * sv + o];
   }

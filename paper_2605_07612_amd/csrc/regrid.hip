@@ -18,17 +18,17 @@ __global__ __launch_bounds__(256) void lohner_kernel(const MeshDev *__restrict__
   const int N = M.N, g = M.g, P = N + 2 * g;
   const int64_t sv = (NDIM == 3) ? (int64_t)P * P * P : (int64_t)P * P;
   const T *u = (const T *)M.s[M.cur] + b * sv * NV;  // variable 0 = density
-  const int64_t st[3] = {1, P, (int64_t)P * P};
   const int cells = (NDIM == 3) ? N * N * N : N * N;
   bool any_ref = false, all_deref = true;
   for (int c = threadIdx.x; c < cells; c += blockDim.x) {
     const int i = c % N, j = (c / N) % N, k = (NDIM == 3) ? c / (N * N) : 0;
-    const int64_t o = (NDIM == 3 ? (int64_t)(k + g) * P * P : 0) + (int64_t)(j + g) * P + (i + g);
-    const double uc = u[o];
+    const double uc = u[cell_off<NDIM>(i, j, k, N, g)];
     double S = 0.0;
 #pragma unroll
     for (int d = 0; d < NDIM; d++) {
-      const double um = u[o - st[d]], up = u[o + st[d]];
+      const int dm[3] = {d == 0, d == 1, d == 2};
+      const double um = u[cell_off<NDIM>(i - dm[0], j - dm[1], k - dm[2], N, g)];
+      const double up = u[cell_off<NDIM>(i + dm[0], j + dm[1], k + dm[2], N, g)];
       const double num = fabs((um - 2.0 * uc) + up);
       const double den = ((eps_abs + fabs(uc - um)) + fabs(up - uc)) + eps * ((fabs(um) + 2.0 * fabs(uc)) + fabs(up));
       const double E = num / den;
@@ -55,9 +55,7 @@ __global__ __launch_bounds__(256) void remap_kernel(const T *__restrict__ uold, 
   const int64_t bel = sv * NV;
   const int op = map[3 * n], src = map[3 * n + 1], arg = map[3 * n + 2];
   const int cells = (NDIM == 3) ? N * N * N : N * N;
-  auto at = [&](const int c[3]) -> int64_t {
-    return (NDIM == 3 ? (int64_t)(c[2] + g) * P * P : 0) + (int64_t)(c[1] + g) * P + (c[0] + g);
-  };
+  auto at = [&](const int c[3]) -> int64_t { return cell_off<NDIM>(c[0], c[1], c[2], N, g); };
   for (int e = threadIdx.x; e < NV * cells; e += blockDim.x) {
     const int v = e / cells, c0 = e % cells;
     const int c[3] = {c0 % N, (c0 / N) % N, (NDIM == 3) ? c0 / (N * N) : 0};

@@ -50,17 +50,6 @@ constexpr int smem_cells() {
   return c;
 }
 
-// Stage-1 output planes of FP32 3D kernels for N = 16 leave through an LDS
-// staging plane as whole 16-byte vectors.  The stage-1 output buffer is not
-// read by the launch, so any partly written cache line would cost the memory
-// a read-modify-write; stage 2 writes over U^n, whose lines it has just read,
-// and gains nothing from staging (measured), so it stores cell by cell.
-template <typename T, int NDIM, int NM, int STG>
-constexpr bool stage_sout() {
-  return sizeof(T) == 4 && NDIM == 3 && NM == 2 && STG == 1;
-}
-constexpr int kSoutPlane = 20 * 20;  // padded 16^3-block plane with g = 2
-
 // CFL inverse time step sum_d (|v_d| + c) / dx of one cell.  FP64 states use
 // the operation order of the definition without contraction (equal to a plain
 // evaluation); FP32 states evaluate it in FP32 with the hardware reciprocal
@@ -138,7 +127,7 @@ __device__ __forceinline__ void plane_face(const T *Wp, int base, int step, bool
 // r1 = max |grad p| / p over the interior cells of the stage's input state
 // (undivided central differences, squares summed x, y, z) into feat_raw[b][2]
 // by an atomic maximum; the primitive planes are already in LDS.
-template <typename T, int NDIM, int N, bool FEAT = false, bool SOUT = false>
+template <typename T, int NDIM, int N, bool FEAT = false>
 __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t local, T *smem,
                                            double &vmax, bool &bad, double *feat_raw = nullptr) {
   using C = TileCfg<N>;
@@ -163,8 +152,8 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   const int kd = (NDIM == 3) ? N / ks : 1;
   const int k0 = (NDIM == 3) ? kslab * kd : 0, k1 = k0 + kd;
   const int g = M.g, P = N + 2 * g;
-  const int sj = P, sk = P * P;
-  const int sv = (NDIM == 3) ? sk * P : sk;
+  const int sk = P * N;  // plane stride of a row-part column (cell_off: a plane is P rows of N)
+  const int sv = (NDIM == 3) ? P * P * P : P * P;
   const int64_t bel = (int64_t)sv * NV;
   const int cur = M.cur;
   const T *__restrict__ ud0 = (const T *)M.s[stage == 1 ? cur : 1 - cur];
@@ -188,9 +177,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   T *FY = FX + NFX * NV;                                // [v][TILE + 1][TILE]
   auto slot = [&](int kk) -> T * { return NS == 1 ? Wring : Wring + (kk % NS) * (PLANE * NV); };
 
-  auto off = [&](int ii, int jj, int kk) -> int {
-    return (NDIM == 3 ? (kk + g) * sk : 0) + (jj + g) * sj + (ii + g);
-  };
+  auto off = [&](int ii, int jj, int kk) -> int { return cell_off<NDIM>(ii, jj, kk, N, g); };
   auto load = [&](const T *p, T *U) {
 #pragma unroll
     for (int v = 0; v < NV; v++) U[v] = gload(p + v * sv);
@@ -225,8 +212,10 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
 
   // Source pointers, fixed for the whole item: the ring cell's column (its
   // block does not change with k) and the own column inside the block and
-  // across the -z / +z faces.  Plane k of a column is at + k * sk.
+  // across the -z / +z faces.  Plane k of a column is at + k * sk, of the
+  // ring column at + k * ring_sk (an own x ghost column steps by P 2g).
   const T *ring_p;
+  int ring_sk;
   {
     int RI = i0 + ri, RJ = j0 + rj;
     int64_t blk = b;
@@ -240,6 +229,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       }
     }
     ring_p = ud0 + blk * bel + off(RI, RJ, 0);
+    ring_sk = ((unsigned)RI < (unsigned)N) ? sk : P * 2 * g;
   }
   const T *own_p = ud0 + b * bel + off(I, J, 0);
   const T *zlo_p = nullptr, *zhi_p = nullptr;  // neighbour columns across -z / +z (gather)
@@ -252,61 +242,6 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     if (kk < 0 && zlo_p) return zlo_p + (kk + N) * sk;
     if (kk >= N && zhi_p) return zhi_p + (kk - N) * sk;
     return own_p + kk * sk;
-  };
-
-  // Ghost positions of this tile's share of an output plane: the x ghosts of
-  // its rows and, where it touches a y face of the block, the full-width
-  // ghost rows (corners included), enumerated u = 0 .. n_gh - 1 as plane
-  // offsets.  In stage 1 every tile stores zeros there, so the tiles of a
-  // block write each output plane whole: the block's written region of each
-  // variable (planes g .. g + N - 1) is then one contiguous range, and no
-  // cache line of it reaches HBM partly written (the stage-1 output buffer
-  // is not read by the launch, so a partly written line would cost a
-  // read-modify-write at the memory).  Stage 2 writes over U^n, whose lines
-  // it has just read, and stores the interior only.  Ghost cells of a
-  // stage's output are never read before a ghost fill (or a gather)
-  // rewrites them.
-  const int gl = (i0 == 0) ? g : 0, gr = (i0 + TILE == N) ? g : 0;
-  const int gb = (j0 == 0) ? g : 0, gt = (j0 + TILE == N) ? g : 0;
-  const int gw = TILE + gl + gr;
-  const int n_gh = (gb + gt) * gw + TILE * (gl + gr);
-  auto ghost_at = [&](int u) -> int {
-    int x, y;
-    if (u < gb * gw) {
-      y = j0 - gb + u / gw;
-      x = i0 - gl + u % gw;
-    } else if ((u -= gb * gw) < gt * gw) {
-      y = j0 + TILE + u / gw;
-      x = i0 - gl + u % gw;
-    } else {
-      u -= gt * gw;
-      const int w = gl + gr, c = u % w;
-      y = j0 + u / w;
-      x = c < gl ? i0 - gl + c : i0 + TILE + (c - gl);
-    }
-    return (y + g) * sj + (x + g);
-  };
-
-  // Staged output (SOUT, g = 2): the update of plane k writes the interior
-  // of the LDS plane SO ([v][20 x 20], ghost positions kept at zero by the
-  // kernel), and plane k leaves as 16-byte vectors of the whole padded plane
-  // right after the first barrier of iteration k + 1 (the last plane after
-  // the loop), so it needs no barrier of its own.
-  static_assert(!SOUT || (N == 16 && NDIM == 3 && sizeof(T) == 4), "staged output: FP32 3D N = 16 only");
-  const bool staged = SOUT && g == 2;
-  T *SO = smem + item_cells<NDIM, N>();
-  auto copy_out = [&](int kk) {
-    if constexpr (SOUT) {
-      if (!valid) return;
-      T *dp = uo + (kk + 2) * sk;
-      constexpr int NCH = kSoutPlane / 4;
-      for (int x = lt; x < NV * NCH; x += TT) {
-        const int v = x / NCH, c = x - v * NCH;
-        using V4 = float __attribute__((ext_vector_type(4)));
-        const V4 val = *(const V4 *)(SO + v * kSoutPlane + 4 * c);
-        *(__attribute__((address_space(1))) V4 *)(dp + v * sv + 4 * c) = val;
-      }
-    }
   };
 
   // cells next to F2C faces are finished (and their dt taken) by the flux fix
@@ -365,9 +300,9 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       slot(k0 + 1)[v * PLANE + own_lds] = W1[v];
     }
     if (ring) {
-      load(ring_p + k0 * sk, tmp);
+      load(ring_p + k0 * ring_sk, tmp);
       put(slot(k0), ring_lds, tmp);
-      load(ring_p + (k0 + 1) * sk, tmp);
+      load(ring_p + (k0 + 1) * ring_sk, tmp);
       put(slot(k0 + 1), ring_lds, tmp);
     }
     // face k0 - 1/2; the slope of cell k0 is carried into the plane loop
@@ -386,7 +321,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       zp = Wm1[NV - 1];
     }
     load(col(k0 + 2), Q);
-    if (ring) load(ring_p + (k0 + 2) * sk, R);
+    if (ring) load(ring_p + (k0 + 2) * ring_sk, R);
   } else {
     T tmp[NV];
     load(own_p, Ua);
@@ -408,7 +343,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       copyv<T, NV>(Uc, Q);
       if (ring && k + 2 < k1) put(slot(k + 2), ring_lds, R);
       if (k + 3 <= k1 + 1) load(col(k + 3), Q);
-      if (ring && k + 3 < k1) load(ring_p + (k + 3) * sk, R);
+      if (ring && k + 3 < k1) load(ring_p + (k + 3) * ring_sk, R);
     }
     // U^n of the own cell (stage 2): loaded one plane ahead
     T Up[NV];
@@ -419,7 +354,6 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     }
     const T *Wp = slot(k);
     __syncthreads();
-    if (staged && k > k0) copy_out(k - 1);
 
     if constexpr (FEAT) {
       if (valid) {
@@ -497,19 +431,12 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       const T base = (stage == 1) ? U0[v] : T(0.5) * (Up[v] + U0[v]);
       Uout[v] = base - cdt * div;
     }
+    // a tile's rows are contiguous runs of the block's row part; the tiles
+    // of a block together write each interior plane as one contiguous range
     const int o = off(I, J, k);
-    if (staged) {
-#pragma unroll
-      for (int v = 0; v < NV; v++) SO[v * kSoutPlane + (tj + 2) * 20 + ti + 2] = Uout[v];
-    } else if (valid) {
+    if (valid) {
 #pragma unroll
       for (int v = 0; v < NV; v++) gstore(uo + v * sv + o, Uout[v]);
-      const int pk = (NDIM == 3) ? (k + g) * sk : 0;
-      for (int u = lt; stage == 1 && u < n_gh; u += TT) {
-        const int q = pk + ghost_at(u);
-#pragma unroll
-        for (int v = 0; v < NV; v++) gstore(uo + v * sv + q, T(0));
-      }
     }
     if (stage == 2 && valid) {
       const bool skip = f2c_adj || (f2c_zlo && k == 0) || (f2c_zhi && k == N - 1);
@@ -527,10 +454,6 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       copyv<T, NV>(Ua, Ub);
       copyv<T, NV>(Ub, Uc);
     }
-  }
-  if (staged) {
-    __syncthreads();
-    copy_out(k1 - 1);
   }
   if constexpr (FEAT) {
     double dr = (double)fr, dp = (double)fp;
@@ -586,11 +509,7 @@ template <typename T, int NDIM, int NM, int STG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM, STG>())))
 void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t total, int xcd) {
   constexpr int stage = STG;
-  constexpr bool SOUT = stage_sout<T, NDIM, NM, STG>();
-  __shared__ T smem[smem_cells<NDIM, NM>() + (SOUT ? (NDIM + 2) * kSoutPlane : 0)];
-  if constexpr (SOUT) {
-    for (int x = threadIdx.x; x < (NDIM + 2) * kSoutPlane; x += 256) smem[smem_cells<NDIM, NM>() + x] = T(0);
-  }
+  __shared__ T smem[smem_cells<NDIM, NM>()];
   double vmax = 0.0;
   bool bad = false;
   int mprev = -1;
@@ -612,7 +531,7 @@ void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t tota
     if constexpr (NM == 1) {
       stage_item<T, NDIM, 8>(M, stage, local, smem, vmax, bad);
     } else if constexpr (NM == 2) {
-      stage_item<T, NDIM, 16, false, SOUT>(M, stage, local, smem, vmax, bad);
+      stage_item<T, NDIM, 16>(M, stage, local, smem, vmax, bad);
     } else if constexpr (NM == 4) {
       stage_item<T, NDIM, 32>(M, stage, local, smem, vmax, bad);
     } else {
@@ -678,16 +597,12 @@ hipError_t launch_stage(const MeshDev *d_meshes, int n_meshes, int64_t total_ite
 template <typename T, int NDIM, int NM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM, 1>())))
 void stage1_feat_kernel(const MeshDev *__restrict__ Mp, int64_t total, double *feat_raw) {
-  constexpr bool SOUT = stage_sout<T, NDIM, NM, 1>();
-  __shared__ T smem[smem_cells<NDIM, NM>() + (SOUT ? (NDIM + 2) * kSoutPlane : 0)];
-  if constexpr (SOUT) {
-    for (int x = threadIdx.x; x < (NDIM + 2) * kSoutPlane; x += 256) smem[smem_cells<NDIM, NM>() + x] = T(0);
-  }
+  __shared__ T smem[smem_cells<NDIM, NM>()];
   constexpr int N = (NM == 1) ? 8 : (NM == 2) ? 16 : 32;
   double vmax = 0.0;
   bool bad = false;
   if ((int64_t)blockIdx.x >= total) return;
-  stage_item<T, NDIM, N, true, SOUT>(*Mp, 1, blockIdx.x, smem, vmax, bad, feat_raw);
+  stage_item<T, NDIM, N, true>(*Mp, 1, blockIdx.x, smem, vmax, bad, feat_raw);
 }
 
 template <typename T, int NDIM>

@@ -1,11 +1,62 @@
 """Caller-side helpers for writing initial conditions into a mesh's state
-tensor and reading results back (host numpy work, not part of the hot path).
+tensor and reading results back (host work, not part of the hot path).
 
-Block n of the state tensor is leaf n of the mesh; its cell (i, j, k) is at
-padded index (i+g, j+g, k+g) (include/foap4.h)."""
+Block n of the state tensor is leaf n of the mesh.  Each (block, variable)
+group of P^ndim values (P = N + 2g) holds first the rows (k, j) of N interior
+x cells, then the 2g x ghosts of every row (include/foap4.h); `rows_view`,
+`to_padded` and `from_padded` convert between that and the padded cube
+[P]^ndim in which cell (i, j, k) sits at (k+g, j+g, i+g)."""
 from __future__ import annotations
 
 import numpy as np
+
+
+def rows_view(u, N, g, ndim):
+    """u: [..., P^ndim] -> view [..., P, (P,) N] of the row part (k, j, i)."""
+    P = N + 2 * g
+    R = P ** (ndim - 1)
+    lead = tuple(u.shape[:-1])
+    return u[..., : R * N].reshape(lead + (P,) * (ndim - 1) + (N,))
+
+
+def xghost_view(u, N, g, ndim):
+    """u: [..., P^ndim] -> view [..., P, (P,) 2g] of the x ghosts (c = i+g for
+    i < 0, i-N+g for i >= N)."""
+    P = N + 2 * g
+    R = P ** (ndim - 1)
+    lead = tuple(u.shape[:-1])
+    return u[..., R * N:].reshape(lead + (P,) * (ndim - 1) + (2 * g,))
+
+
+def to_padded(u, N, g, ndim):
+    """A copy of u ([..., P^ndim], torch or numpy) as padded cubes [..., P^ndim as (P,)*ndim]."""
+    P = N + 2 * g
+    shape = tuple(u.shape[:-1]) + (P,) * ndim
+    if isinstance(u, np.ndarray):
+        out = np.empty(shape, dtype=u.dtype)
+    else:
+        out = u.new_empty(shape)
+    rows, xg = rows_view(u, N, g, ndim), xghost_view(u, N, g, ndim)
+    out[..., g:g + N] = rows
+    out[..., :g] = xg[..., :g]
+    out[..., g + N:] = xg[..., g:]
+    return out
+
+
+def from_padded(cube, N, g, ndim):
+    """Inverse of to_padded: [..., (P,)*ndim] -> [..., P^ndim]."""
+    P = N + 2 * g
+    R = P ** (ndim - 1)
+    lead = tuple(cube.shape[:-ndim])
+    if isinstance(cube, np.ndarray):
+        out = np.empty(lead + (P ** ndim,), dtype=cube.dtype)
+    else:
+        out = cube.new_empty(lead + (P ** ndim,))
+    rows, xg = rows_view(out, N, g, ndim), xghost_view(out, N, g, ndim)
+    rows[...] = cube[..., g:g + N]
+    xg[..., :g] = cube[..., :g]
+    xg[..., g:] = cube[..., g + N:]
+    return out
 
 
 def global_coords(mesh):
