@@ -28,6 +28,7 @@ import numpy as np  # noqa: E402
 
 METRIC = "cell-updates/s per GPU + % HBM roofline, 16^3 blocks, FP32 batched vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
+PROFILE_CONFIG = "1,0,3,1"  # the configuration the committed counters and trace were taken in
 
 
 def halo_share(N, g=2, ndim=3):
@@ -51,6 +52,16 @@ def step_bytes_per_update(S, gather, N=16):
     fill also reads and writes h S, (2.5 + 3 h) S (4.75 S at N = 16)."""
     h = halo_share(N)
     return (2.5 + h if gather else 2.5 + 3.0 * h) * S
+
+
+def parse_config(text):
+    """'kslabs,wg_stage1,wg_stage2,xcd_order' (or 'kslabs,wg,xcd_order': both stages wg)."""
+    v = [int(x) for x in text.split(",")]
+    if len(v) == 3:
+        v = [v[0], v[1], v[1], v[2]]
+    if len(v) != 4:
+        raise SystemExit("--config takes kslabs,wg_stage1,wg_stage2,xcd_order")
+    return tuple(v)
 
 
 def log(*a):
@@ -107,7 +118,8 @@ def main():
                     help="short run for hardware-counter passes: a 1 GiB device copy (counter calibration) "
                          "then 3 batched FP32 steps in the given configuration")
     ap.add_argument("--config", default=None,
-                    help="kslabs,wg_per_cu,xcd_order instead of autotuning (--profile-run default: 1,3,1)")
+                    help="kslabs,wg_stage1,wg_stage2,xcd_order instead of autotuning "
+                         f"(--profile-run default: {PROFILE_CONFIG})")
     ap.add_argument("--counters", default=os.path.join(ROOT, "profiles", "stage_traffic_noise_shear_256cubed_b16.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -141,8 +153,8 @@ def main():
         del a, bb
         m32 = make(f4.F32)
         batch = f4.Batch([m32])
-        ks, wg, xcd = (int(x) for x in (args.config or "1,3,1").split(","))
-        batch.set_config(ks, wg, xcd, 1)
+        ks, wg1, wg2, xcd = parse_config(args.config or PROFILE_CONFIG)
+        batch.set_config(ks, wg1, xcd, 1, wg_stage2=wg2)
         batch.step(3)
         torch.cuda.synchronize()
         log("profile run done")
@@ -154,11 +166,11 @@ def main():
     m32 = make(f4.F32)
     batch = f4.Batch([m32])
     if args.config:
-        ks, wg, xcd = (int(x) for x in args.config.split(","))
-        batch.set_config(ks, wg, xcd, 1)
+        ks, wg1, wg2, xcd = parse_config(args.config)
+        batch.set_config(ks, wg1, xcd, 1, wg_stage2=wg2)
     else:
-        ks, wg, xcd = batch.autotune(args.tune_cache)
-    log(f"autotune: kslabs={ks} wg_per_cu={wg} xcd_order={xcd}")
+        ks, wg1, wg2, xcd = batch.autotune(args.tune_cache)
+    log(f"autotune: kslabs={ks} wg_per_cu stage 1={wg1} stage 2={wg2} xcd_order={xcd}")
     batch.step(args.warmup)
     secs, wall = timed_steps(batch.step, args.steps, torch.cuda.synchronize)
     gcups32 = cells * 2 * args.steps / secs / 1e9
@@ -184,7 +196,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "cells": cells, "blocks": int(np.prod(w["trees"])),
                    "block": args.block, "ghost": 2, "form": "batched: persistent stage launch, hipGraph, autotuned",
-                   "kslabs": ks, "wg_per_cu": wg, "xcd_order": xcd, "gather_halos": 1, "reductions": "f64"},
+                   "kslabs": ks, "wg_per_cu_stage1": wg1, "wg_per_cu_stage2": wg2, "xcd_order": xcd, "gather_halos": 1, "reductions": "f64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      # the committed counters cover the 256^3 workload in 16^3 blocks only

@@ -283,25 +283,29 @@ foap4_status foap4_batch_create(foap4_mesh *const *meshes, int32_t n_meshes, foa
 foap4_status foap4_batch_destroy(foap4_batch *batch);
 
 /* Work decomposition of the batched stage kernel: kslabs = 1, 2 or 4 k-slabs
- * per block tile (the LDS tile depth is N / kslabs planes), wg_per_cu =
- * resident workgroups per compute unit for the persistent grid (0: one
- * workgroup per work item, no persistence), xcd_order = 0 for plain
+ * per block tile (the LDS tile depth is N / kslabs planes), wg_stage1 and
+ * wg_stage2 = workgroups per compute unit of the persistent grid of the
+ * first and the second Heun stage (0: one workgroup per work item, no
+ * persistence; the two stages differ in registers and traffic, so their
+ * best grids differ), xcd_order = 0 for plain
  * striding of the work items over the workgroups, 1 to give each of the 8
  * XCDs a contiguous range of work items (Morton neighbours share an L2), 2 to
  * give each workgroup a contiguous chunk (a block and its Morton neighbours
  * run back to back on one CU), gather_halos = 1 to read same-level halo cells straight from the
  * neighbouring blocks instead of copying them into ghost cells first (the
  * results are identical; the SRL copies are then skipped except where the
- * coarse-to-fine prolongation reads them).  Defaults: 1, 0, 1, 1. */
-foap4_status foap4_batch_set_config(foap4_batch *batch, int32_t kslabs, int32_t wg_per_cu,
-                                    int32_t xcd_order, int32_t gather_halos);
+ * coarse-to-fine prolongation reads them).  Defaults: 1, 0, 0, 1, 1.
+ * FOAP4_E_INVALID outside those ranges (workgroups per CU: 0 .. 64). */
+foap4_status foap4_batch_set_config(foap4_batch *batch, int32_t kslabs, int32_t wg_stage1,
+                                    int32_t wg_stage2, int32_t xcd_order, int32_t gather_halos);
 
-/* Times the candidate configurations (kslabs x wg_per_cu x xcd_order) on the
- * batch itself and keeps the fastest; results are cached in the JSON file
- * cache_path (may be NULL) keyed by GPU architecture, precision and the
- * batch's block-size mix.  The meshes' states are restored afterwards.
- * Writes the chosen {kslabs, wg_per_cu, xcd_order} to cfg_out[3] (may be
- * NULL). */
+/* Times the candidate configurations (kslabs x workgroups per CU x
+ * xcd_order, each stage timed on its own) on the batch itself and keeps, per
+ * (kslabs, xcd_order), the fastest grid of each stage, then the fastest
+ * whole step; results are cached in the JSON file cache_path (may be NULL)
+ * keyed by GPU architecture, precision and the batch's block-size mix.  The
+ * meshes' states are restored afterwards.  Writes the chosen {kslabs,
+ * wg_stage1, wg_stage2, xcd_order} to cfg_out[4] (may be NULL). */
 foap4_status foap4_batch_autotune(foap4_batch *batch, const char *cache_path, int32_t *cfg_out);
 
 /* Advances every mesh of the batch by n_steps Heun steps (enqueue only). */

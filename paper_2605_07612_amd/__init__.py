@@ -56,7 +56,7 @@ EXPORTS = {
     "foap4_regrid": (I32, [P, P, P]),
     "foap4_batch_create": (I32, [P, I32, ctypes.POINTER(P)]),
     "foap4_batch_destroy": (I32, [P]),
-    "foap4_batch_set_config": (I32, [P, I32, I32, I32, I32]),
+    "foap4_batch_set_config": (I32, [P, I32, I32, I32, I32, I32]),
     "foap4_batch_autotune": (I32, [P, ctypes.c_char_p, P]),
     "foap4_batch_step": (I32, [P, I32]),
     "foap4_batch_phase_times": (I32, [P, I32, P]),
@@ -320,12 +320,15 @@ class Batch:
         except Exception:
             pass
 
-    def set_config(self, kslabs=1, wg_per_cu=0, xcd_order=1, gather_halos=1):
-        _check(lib().foap4_batch_set_config(self.h, kslabs, wg_per_cu, xcd_order, gather_halos))
+    def set_config(self, kslabs=1, wg_per_cu=0, xcd_order=1, gather_halos=1, wg_stage2=None):
+        """wg_per_cu: workgroups per CU of stage 1, and of stage 2 unless
+        wg_stage2 is given."""
+        w2 = wg_per_cu if wg_stage2 is None else wg_stage2
+        _check(lib().foap4_batch_set_config(self.h, kslabs, wg_per_cu, w2, xcd_order, gather_halos))
 
     def autotune(self, cache_path=None):
-        """Returns the chosen (kslabs, wg_per_cu, xcd_order)."""
-        cfg = np.zeros(3, np.int32)
+        """Returns the chosen (kslabs, wg_stage1, wg_stage2, xcd_order)."""
+        cfg = np.zeros(4, np.int32)
         cp = cache_path.encode() if cache_path else None
         _check(lib().foap4_batch_autotune(self.h, cp, _ptr(cfg)))
         return tuple(int(x) for x in cfg)

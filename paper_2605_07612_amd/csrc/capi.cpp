@@ -120,7 +120,7 @@ struct foap4_batch {
   std::vector<int64_t> revs;
   int ndim = 3;
   bool f64 = false;
-  int ks = 1, wg_per_cu = 0, gather = 1, xcd = 1;
+  int ks = 1, wg1 = 0, wg2 = 0, gather = 1, xcd = 1;  // wg1 / wg2: workgroups per CU of stage 1 / 2
   MeshDev *d_devs = nullptr;
   int64_t total_items = 0, r1_total = 0, r2_total = 0;
   int nmask = 0;
@@ -554,12 +554,17 @@ static foap4_status batch_upload(foap4_batch *b) {
 }
 
 // one Heun step of every mesh: 9 + 2 n_fix launches
+static int stage_grid(const foap4_batch *b, int stage) {
+  const int wg = stage == 1 ? b->wg1 : b->wg2;
+  return wg > 0 ? wg * b->n_cu : 0;
+}
+
 static hipError_t batch_enqueue_step(foap4_batch *b, hipStream_t s) {
   const int n = (int)b->meshes.size();
-  const int grid = b->wg_per_cu > 0 ? b->wg_per_cu * b->n_cu : 0;
   hipError_t e;
   for (int stage = 1; stage <= 2; stage++) {
     const int which = stage - 1;
+    const int grid = stage_grid(b, stage);
     if ((e = launch_ghost(b->d_devs, n, b->r1_total, 1, which, b->ndim, b->f64, 0, s)) != hipSuccess) return e;
     if (b->r2_total && (e = launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s)) != hipSuccess)
       return e;
@@ -643,16 +648,17 @@ foap4_status foap4_batch_destroy(foap4_batch *b) {
   return FOAP4_OK;
 }
 
-foap4_status foap4_batch_set_config(foap4_batch *b, int32_t kslabs, int32_t wg_per_cu, int32_t xcd_order,
-                                    int32_t gather_halos) {
-  if (!b || (kslabs != 1 && kslabs != 2 && kslabs != 4) || wg_per_cu < 0 || wg_per_cu > 64 ||
-      xcd_order < 0 || xcd_order > 2 || (gather_halos != 0 && gather_halos != 1))
+foap4_status foap4_batch_set_config(foap4_batch *b, int32_t kslabs, int32_t wg_stage1, int32_t wg_stage2,
+                                    int32_t xcd_order, int32_t gather_halos) {
+  if (!b || (kslabs != 1 && kslabs != 2 && kslabs != 4) || wg_stage1 < 0 || wg_stage1 > 64 || wg_stage2 < 0 ||
+      wg_stage2 > 64 || xcd_order < 0 || xcd_order > 2 || (gather_halos != 0 && gather_halos != 1))
     return batch_fail(b, FOAP4_E_INVALID,
-                      "kslabs must be 1, 2 or 4, 0 <= wg_per_cu <= 64, xcd_order 0, 1 or 2, gather_halos 0 or 1");
-  if (b->ks != kslabs || b->wg_per_cu != wg_per_cu || b->xcd != xcd_order || b->gather != gather_halos)
+                      "kslabs must be 1, 2 or 4, 0 <= workgroups per CU <= 64, xcd_order 0, 1 or 2, gather_halos 0 or 1");
+  if (b->ks != kslabs || b->wg1 != wg_stage1 || b->wg2 != wg_stage2 || b->xcd != xcd_order || b->gather != gather_halos)
     drop_graph(b);
   b->ks = kslabs;
-  b->wg_per_cu = wg_per_cu;
+  b->wg1 = wg_stage1;
+  b->wg2 = wg_stage2;
   b->xcd = xcd_order;
   b->gather = gather_halos;
   return FOAP4_OK;
@@ -675,7 +681,6 @@ foap4_status foap4_batch_phase_times(foap4_batch *b, int32_t n_steps, double *ou
   foap4_status st = batch_prepare(b);
   if (st != FOAP4_OK) return st;
   const int n = (int)b->meshes.size();
-  const int grid = b->wg_per_cu > 0 ? b->wg_per_cu * b->n_cu : 0;
   hipStream_t s = b->stream;
   // events: per step 2 x (R1, R2, stage, fix) + finalize = 9 intervals
   const int per = 9;
@@ -690,7 +695,8 @@ foap4_status foap4_batch_phase_times(foap4_batch *b, int32_t n_steps, double *ou
       B_HIP(b, hipEventRecord(ev[++k], s));
       if (b->r2_total) B_HIP(b, launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s));
       B_HIP(b, hipEventRecord(ev[++k], s));
-      B_HIP(b, launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, grid, s, b->xcd, b->nmask));
+      B_HIP(b, launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, stage_grid(b, stage), s, b->xcd,
+                            b->nmask));
       B_HIP(b, hipEventRecord(ev[++k], s));
       for (int i = 0; i < n; i++)
         if (b->meshes[i]->pat.n_fix > 0)
@@ -754,8 +760,8 @@ static std::string batch_key(const foap4_batch *b) {
   return k.str();
 }
 
-// cache entries: "key": [kslabs, wg_per_cu, xcd_order]
-static bool cache_lookup(const char *path, const std::string &key, int cfg[3]) {
+// cache entries: "key": [kslabs, workgroups per CU of stage 1, of stage 2, xcd_order]
+static bool cache_lookup(const char *path, const std::string &key, int cfg[4]) {
   if (!path) return false;
   std::ifstream f(path);
   if (!f) return false;
@@ -764,18 +770,19 @@ static bool cache_lookup(const char *path, const std::string &key, int cfg[3]) {
     const size_t q0 = line.find('"'), q1 = line.find('"', q0 + 1);
     if (q0 == std::string::npos || q1 == std::string::npos) continue;
     if (line.substr(q0 + 1, q1 - q0 - 1) != key) continue;
-    int a = 0, c = 0, x = 0;
-    if (std::sscanf(line.c_str() + q1 + 1, " : [%d , %d , %d]", &a, &c, &x) == 3) {
+    int a = 0, c1 = 0, c2 = 0, x = 0;
+    if (std::sscanf(line.c_str() + q1 + 1, " : [%d , %d , %d , %d]", &a, &c1, &c2, &x) == 4) {
       cfg[0] = a;
-      cfg[1] = c;
-      cfg[2] = x;
+      cfg[1] = c1;
+      cfg[2] = c2;
+      cfg[3] = x;
       return true;
     }
   }
   return false;
 }
 
-static void cache_store(const char *path, const std::string &key, const int cfg[3]) {
+static void cache_store(const char *path, const std::string &key, const int cfg[4]) {
   if (!path) return;
   std::vector<std::string> keep;
   {
@@ -791,7 +798,7 @@ static void cache_store(const char *path, const std::string &key, const int cfg[
     }
   }
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d]", key.c_str(), cfg[0], cfg[1], cfg[2]);
+  std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %d]", key.c_str(), cfg[0], cfg[1], cfg[2], cfg[3]);
   keep.push_back(buf);
   std::ofstream o(path);
   o << "{\n";
@@ -802,11 +809,11 @@ static void cache_store(const char *path, const std::string &key, const int cfg[
 foap4_status foap4_batch_autotune(foap4_batch *b, const char *cache_path, int32_t *cfg_out) {
   if (!b) return batch_fail(nullptr, FOAP4_E_INVALID, "null batch");
   const std::string key = batch_key(b);
-  int cached[3] = {1, 0, 1};
+  int cached[4] = {1, 0, 0, 1};
   if (cache_lookup(cache_path, key, cached)) {
-    foap4_status st = foap4_batch_set_config(b, cached[0], cached[1], cached[2], b->gather);
+    foap4_status st = foap4_batch_set_config(b, cached[0], cached[1], cached[2], cached[3], b->gather);
     if (cfg_out)
-      for (int i = 0; i < 3; i++) cfg_out[i] = cached[i];
+      for (int i = 0; i < 4; i++) cfg_out[i] = cached[i];
     return st;
   }
   // save the current states and scalars; restored after timing
@@ -834,69 +841,83 @@ foap4_status foap4_batch_autotune(foap4_batch *b, const char *cache_path, int32_
     return e;
   };
   const int ks_cand[3] = {1, 2, 4};
-  // resident workgroups per CU: the stage kernels hold 2-4 per CU, so every
-  // count up to 4 and one oversubscribed grid are tried
-  const int wg_cand[6] = {0, 1, 2, 3, 4, 6};
+  // workgroups per CU of the persistent grid: the stage kernels hold 2-4 per
+  // CU, so every count up to 4 and two oversubscribed grids are tried
+  constexpr int kWg = 7;
+  const int wg_cand[kWg] = {0, 1, 2, 3, 4, 6, 8};
   int max_ks = 1;
   for (foap4_mesh *m : b->meshes) max_ks = std::max(max_ks, m->d.block_n / 8);
   if (b->ndim == 2) max_ks = 1;
-  float best = 1e30f;
-  int best_cfg[3] = {1, 0, 1};
-  hipEvent_t e0, e1;
-  B_HIP(b, hipEventCreate(&e0));
-  B_HIP(b, hipEventCreate(&e1));
   foap4_status result = FOAP4_OK;
   // warm-up in the default configuration (clocks ramp up during the first
-  // launches), then two passes over the candidates; each keeps its best time
+  // launches), then two passes over the candidates
   if ((result = foap4_batch_step(b, 8)) == FOAP4_OK && restore() != hipSuccess) result = FOAP4_E_HIP;
+  // The two Heun stages are separate launches with the same work items, so
+  // each (kslabs, xcd_order) pair takes, per stage, the workgroup count that
+  // runs that stage fastest; the rest of a step does not depend on the grid.
   struct Cand {
     int ks, wg, x;
-    float ms;
+    float s1, s2, rest;
   };
   std::vector<Cand> cands;
   for (int a = 0; a < 3; a++)
     if (ks_cand[a] <= max_ks)
-      for (int c = 0; c < 6; c++)
-        for (int x = 0; x < 3; x++) cands.push_back({ks_cand[a], wg_cand[c], x, 3.4e38f});
-  // pass 1 times every candidate; pass 2 times again those within 10 % of
-  // the best (each keeps its fastest run: single runs jitter by a few %)
+      for (int c = 0; c < kWg; c++)
+        for (int x = 0; x < 3; x++) cands.push_back({ks_cand[a], wg_cand[c], x, 3.4e38f, 3.4e38f, 3.4e38f});
+  auto choose = [&](int &ks, int &w1, int &w2, int &x) {
+    float best = 3.4e38f;
+    for (const Cand &p : cands) {
+      // best stage-1 and stage-2 grids for this (kslabs, xcd_order)
+      float b1 = 3.4e38f, b2 = 3.4e38f, rest = 3.4e38f;
+      int g1 = 0, g2 = 0;
+      for (const Cand &q : cands) {
+        if (q.ks != p.ks || q.x != p.x) continue;
+        if (q.s1 < b1) { b1 = q.s1; g1 = q.wg; }
+        if (q.s2 < b2) { b2 = q.s2; g2 = q.wg; }
+        rest = std::min(rest, q.rest);
+      }
+      const float t = b1 + b2 + rest;
+      if (t < best) {
+        best = t;
+        ks = p.ks; w1 = g1; w2 = g2; x = p.x;
+      }
+    }
+    return best;
+  };
+  // pass 1 times every candidate; pass 2 times again those whose stage 1 or
+  // stage 2 is within 10 % of the best of that stage (each keeps its fastest
+  // run: single runs jitter by a few %)
   for (int pass = 0; pass < 2 && result == FOAP4_OK; pass++) {
-    const float cut = 1.1f * best;
+    float best1 = 3.4e38f, best2 = 3.4e38f;
+    for (const Cand &c : cands) {
+      best1 = std::min(best1, c.s1);
+      best2 = std::min(best2, c.s2);
+    }
     for (Cand &cd : cands) {
-      if (pass == 1 && cd.ms > cut) continue;
-      if ((result = foap4_batch_set_config(b, cd.ks, cd.wg, cd.x, b->gather)) != FOAP4_OK) break;
-      if ((result = foap4_batch_step(b, 2)) != FOAP4_OK) break;  // capture + warm-up
+      if (pass == 1 && cd.s1 > 1.1f * best1 && cd.s2 > 1.1f * best2) continue;
+      if ((result = foap4_batch_set_config(b, cd.ks, cd.wg, cd.wg, cd.x, b->gather)) != FOAP4_OK) break;
+      if ((result = foap4_batch_step(b, 1)) != FOAP4_OK) break;  // warm-up
       for (int rep = 0; rep < 2 && result == FOAP4_OK; rep++) {
-        float t = 0.f;
-        if (hipEventRecord(e0, b->stream) != hipSuccess) { result = FOAP4_E_HIP; break; }
-        if ((result = foap4_batch_step(b, 4)) != FOAP4_OK) break;
-        if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
-          result = FOAP4_E_HIP;
-          break;
-        }
-        cd.ms = std::min(cd.ms, t);
+        double ph[8];
+        if ((result = foap4_batch_phase_times(b, 2, ph)) != FOAP4_OK) break;
+        cd.s1 = std::min(cd.s1, (float)ph[6]);
+        cd.s2 = std::min(cd.s2, (float)ph[7]);
+        cd.rest = std::min(cd.rest, (float)(ph[5] - ph[6] - ph[7]));
       }
       if (result != FOAP4_OK) break;
-      if (cd.ms < best) {
-        best = cd.ms;
-        best_cfg[0] = cd.ks;
-        best_cfg[1] = cd.wg;
-        best_cfg[2] = cd.x;
-      }
       if (restore() != hipSuccess) { result = FOAP4_E_HIP; break; }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  int best_cfg[4] = {1, 0, 0, 1};
+  if (result == FOAP4_OK) choose(best_cfg[0], best_cfg[1], best_cfg[2], best_cfg[3]);
   const hipError_t re = restore();
   for (void *p : saved) (void)hipFree(p);
   if (result != FOAP4_OK) return result;
   if (re != hipSuccess) return batch_fail(b, FOAP4_E_HIP, "autotune restore failed");
   cache_store(cache_path, key, best_cfg);
   if (cfg_out)
-    for (int i = 0; i < 3; i++) cfg_out[i] = best_cfg[i];
-  return foap4_batch_set_config(b, best_cfg[0], best_cfg[1], best_cfg[2], b->gather);
+    for (int i = 0; i < 4; i++) cfg_out[i] = best_cfg[i];
+  return foap4_batch_set_config(b, best_cfg[0], best_cfg[1], best_cfg[2], best_cfg[3], b->gather);
 }
 
 }  // extern "C"

@@ -9,7 +9,8 @@
   leaves the mesh (leaf table, ghost pattern and state) unchanged.
 * A state with a negative density is reported as FOAP4_E_UNPHYSICAL.
 * A step count of zero changes nothing; a batch of meshes of different
-  precisions is refused."""
+  precisions is refused.
+* The autotuner leaves the meshes as it found them and caches its choice."""
 import sys
 
 import numpy as np
@@ -138,3 +139,29 @@ def test_batch_refuses_mixed_precision(f4):
     b = f4.Mesh(3, (2, 2, 2), 8, 2, 0.5, prec=f4.F64)
     with pytest.raises(f4.Foap4Error, match="E_INVALID"):
         f4.Batch([a, b])
+
+
+def test_autotune_restores_state_and_caches(f4, tmp_path):
+    """The autotuner times candidate configurations on the batch itself; the
+    meshes' states and times are restored bit for bit afterwards, the chosen
+    per-stage grids are valid, and a second call reads them from the cache."""
+    from paper_2605_07612_amd import layout
+    ws = [synth.two_level_blast(base_trees=4, block=8), synth.two_level_blast(base_trees=2, block=16)]
+    ms = []
+    for w in ws:
+        m = f4.Mesh(3, w["trees"], w["N"], 2, w["tree_size"], prec=f4.F32)
+        layout.set_from_field(m, w["field"])
+        m.step(1, sync=True)
+        ms.append(m)
+    before = [(m.current().cpu().numpy().copy(), m.time()) for m in ms]
+    b = f4.Batch(ms)
+    cache = str(tmp_path / "tune.json")
+    cfg = b.autotune(cache)
+    say("autotune", cfg)
+    ks, w1, w2, x = cfg
+    assert ks in (1, 2) and x in (0, 1, 2) and w1 in (0, 1, 2, 3, 4, 6, 8) and w2 in (0, 1, 2, 3, 4, 6, 8)
+    for (s0, t0), m in zip(before, ms):
+        assert np.array_equal(m.current().cpu().numpy(), s0)
+        assert m.time() == t0
+    assert b.autotune(cache) == cfg
+    assert '"' in open(cache).read()

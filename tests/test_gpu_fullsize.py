@@ -37,7 +37,7 @@ def test_noise_shear_256cubed_full_size(f4, prec):
     say("case 256^3 prec", prec)
     gm, om = build_pair(w, prec)
     b = f4.Batch([gm])
-    b.set_config(1, 3, 0, 1)
+    b.set_config(kslabs=1, wg_per_cu=8, xcd_order=1, wg_stage2=3)  # a configuration the benchmark times
     b.step(2)
     t, dt = gm.time()
     om.step(2)

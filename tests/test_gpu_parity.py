@@ -245,11 +245,11 @@ def test_lohner_flags_and_regrid_bit_exact(f4):
 
 # ---------------------------------------------------------------- batch
 
-@pytest.mark.parametrize("order", [0, 1, 2])
-def test_batch_equals_plain_bitwise(f4, order):
+@pytest.mark.parametrize("order,wg1,wg2", [(0, 2, 2), (1, 2, 2), (2, 2, 2), (1, 8, 3), (1, 0, 1)])
+def test_batch_equals_plain_bitwise(f4, order, wg1, wg2):
     """The persistent, graph-replayed batched form computes exactly what the
-    plain per-kernel form computes (k-slabs, workgroup mapping and item order
-    only change who computes a face, not how)."""
+    plain per-kernel form computes (k-slabs, workgroup mapping, per-stage
+    grids and item order only change who computes a face, not how)."""
     ws = [small_uniform(16, (2, 2, 2), seed=5), small_uniform(32, (1, 2, 1), seed=6),
           small_uniform(8, (3, 2, 1), seed=7)]
     plain = [build_pair(w, 0)[0] for w in ws]
@@ -257,7 +257,7 @@ def test_batch_equals_plain_bitwise(f4, order):
     for m in plain:
         m.step(4)
     b = f4.Batch(batched)
-    b.set_config(kslabs=2, wg_per_cu=2, xcd_order=order)
+    b.set_config(kslabs=2, wg_per_cu=wg1, xcd_order=order, wg_stage2=wg2)
     b.step(4)
     for w, p, q in zip(ws, plain, batched):
         a, c = interior(gpu_state(p), 2, w["N"], 3), interior(gpu_state(q), 2, w["N"], 3)
