@@ -28,7 +28,7 @@ import numpy as np  # noqa: E402
 
 METRIC = "cell-updates/s per GPU + % HBM roofline, 16^3 blocks, FP32 batched vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
-PROFILE_CONFIG = "1,0,3,1"  # the configuration the committed counters and trace were taken in
+PROFILE_CONFIG = "1,0,4,1"  # the configuration the committed counters and trace were taken in
 
 
 def halo_share(N, g=2, ndim=3):

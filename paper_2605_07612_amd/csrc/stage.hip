@@ -495,12 +495,13 @@ __device__ __forceinline__ int64_t item_of(int64_t w, int64_t it, int64_t grid, 
   return j < per_xcd ? (w & 7) * per_xcd + j : total;
 }
 
-// Target waves per SIMD: single-size FP32 kernels 4 in stage 1 (no stage-2
-// state; 3 for N = 32, whose tiles do not fit 128 registers without spills)
-// and 3 in stage 2; the mixed-size and FP64 kernels keep what their
-// registers allow.
+// Target waves per SIMD: single-size FP32 kernels 4 (4 resident workgroups
+// of 4 waves per CU: stage 1 fits 128 registers, stage 2 spills 21 values
+// per lane and still runs ~9 % faster than at 3 waves without spills, since
+// the plane loop waits on its loads); the mixed-size and FP64 kernels keep
+// what their registers allow.
 template <typename T, int NM, int STG = 2>
-constexpr int stage_waves() { return (sizeof(T) == 4 && NM != 7) ? ((STG == 1 && NM != 4) ? 4 : 3) : 1; }
+constexpr int stage_waves() { return (sizeof(T) == 4 && NM != 7) ? 4 : 1; }
 
 // NM: bit mask of the block sizes present (1: N = 8, 2: N = 16, 4: N = 32)
 // STG: the Heun stage (compiled separately: stage 1 needs no U^n stream and
