@@ -112,7 +112,7 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-batch64", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for hardware-counter passes: a 1 GiB device copy (counter calibration) "
