@@ -266,6 +266,34 @@ def test_batch_equals_plain_bitwise(f4, order, wg1, wg2):
         assert np.array_equal(a, c)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("gather", [1, 0])
+def test_batch_two_level_equals_plain(f4, prec, gather):
+    """Refinement boundaries in the batched form: restriction and
+    prolongation ghosts, halos gathered across same-level faces only, the
+    SRL copies kept where the prolongation reads them, flux fixing and the
+    per-stage grids give exactly the plain form's state, which is within
+    tolerance of the oracle."""
+    w = synth.two_level_blast(base_trees=4, block=8)
+    say("two-level batched vs plain, prec", prec, "gather", gather)
+    gp, om = build_pair(w, prec)
+    gb, _ = build_pair(w, prec)
+    assert len(set(gp.export()[0].tolist())) == 2
+    gp.step(12)
+    b = f4.Batch([gb])
+    b.set_config(kslabs=2, wg_per_cu=2, xcd_order=1, gather_halos=gather, wg_stage2=3)
+    b.step(12)
+    a, c = interior(gpu_state(gp), 2, 8, 3), interior(gpu_state(gb), 2, 8, 3)
+    say("times", gp.time(), gb.time(), "max |diff|", float(np.max(np.abs(a - c))))
+    assert gp.time() == gb.time()
+    assert np.array_equal(a, c)
+    om.step(12)
+    lev = gb.export()[0]
+    err = rel_l1_vol(c, om.interior(), lev, 3, w["tree_size"], 8)
+    say("rel L1 vs oracle", err)
+    assert err <= TOL[prec]
+
+
 def test_batch_mixed_sizes_vs_oracle(f4):
     ws = [synth.batch_problem(p) for p in (51, 34, 1, 9, 6, 52)]  # the six smallest
     pairs = [build_pair(w, 0) for w in ws]
