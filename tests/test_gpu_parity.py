@@ -99,12 +99,7 @@ def test_ghost_fill_bit_exact(f4, prec, wname):
     elif wname == "blast_small":
         w = synth.two_level_blast(base_trees=4, block=8)
     else:
-        w = dict(synth.two_level_blast(base_trees=4, block=8))
-        w.update(ndim=2, trees=(4, 4, 1))
-        base = w["refine_flags"]
-        w["refine_flags"] = lambda G: base(np.concatenate([G[:, :2], np.full((len(G), 1), 1)], axis=1))
-        w["field"] = lambda x, y: synth.conserved_from_primitive(1 + 0.3 * np.sin(7 * x) * np.cos(5 * y),
-                                                                  [0.1 + 0 * x, 0.2 + 0 * x], 1 + 0.5 * x * y, 1.4)
+        w = two_level_2d()
     say("case", wname, prec)
     gm, om = build_pair(w, prec)
     # identical inputs: the oracle takes the GPU's (possibly FP32) interior values
@@ -266,16 +261,29 @@ def test_batch_equals_plain_bitwise(f4, order, wg1, wg2):
         assert np.array_equal(a, c)
 
 
+def two_level_2d():
+    """2D two-level workload: 4x4 base blocks of 8x8 cells, the blocks that
+    meet the disc |x - 1/2| < 1/4 refined once, smooth non-trivial data."""
+    w = dict(synth.two_level_blast(base_trees=4, block=8))
+    w.update(ndim=2, trees=(4, 4, 1))
+    base = w["refine_flags"]
+    w["refine_flags"] = lambda G: base(np.concatenate([G[:, :2], np.full((len(G), 1), 1)], axis=1))
+    w["field"] = lambda x, y: synth.conserved_from_primitive(1 + 0.3 * np.sin(7 * x) * np.cos(5 * y),
+                                                              [0.1 + 0 * x, 0.2 + 0 * x], 1 + 0.5 * x * y, 1.4)
+    return w
+
+
+@pytest.mark.parametrize("ndim", [3, 2])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("gather", [1, 0])
-def test_batch_two_level_equals_plain(f4, prec, gather):
+def test_batch_two_level_equals_plain(f4, prec, gather, ndim):
     """Refinement boundaries in the batched form: restriction and
     prolongation ghosts, halos gathered across same-level faces only, the
     SRL copies kept where the prolongation reads them, flux fixing and the
     per-stage grids give exactly the plain form's state, which is within
     tolerance of the oracle."""
-    w = synth.two_level_blast(base_trees=4, block=8)
-    say("two-level batched vs plain, prec", prec, "gather", gather)
+    w = synth.two_level_blast(base_trees=4, block=8) if ndim == 3 else two_level_2d()
+    say("two-level batched vs plain, ndim", ndim, "prec", prec, "gather", gather)
     gp, om = build_pair(w, prec)
     gb, _ = build_pair(w, prec)
     assert len(set(gp.export()[0].tolist())) == 2
@@ -283,13 +291,13 @@ def test_batch_two_level_equals_plain(f4, prec, gather):
     b = f4.Batch([gb])
     b.set_config(kslabs=2, wg_per_cu=2, xcd_order=1, gather_halos=gather, wg_stage2=3)
     b.step(12)
-    a, c = interior(gpu_state(gp), 2, 8, 3), interior(gpu_state(gb), 2, 8, 3)
+    a, c = interior(gpu_state(gp), 2, 8, ndim), interior(gpu_state(gb), 2, 8, ndim)
     say("times", gp.time(), gb.time(), "max |diff|", float(np.max(np.abs(a - c))))
     assert gp.time() == gb.time()
     assert np.array_equal(a, c)
     om.step(12)
     lev = gb.export()[0]
-    err = rel_l1_vol(c, om.interior(), lev, 3, w["tree_size"], 8)
+    err = rel_l1_vol(c, om.interior(), lev, ndim, w["tree_size"], 8)
     say("rel L1 vs oracle", err)
     assert err <= TOL[prec]
 
