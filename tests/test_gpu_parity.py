@@ -302,6 +302,37 @@ def test_batch_two_level_equals_plain(f4, prec, gather, ndim):
     assert err <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_follows_regrid(f4, prec):
+    """A batch keeps working across a regrid of its mesh (new leaf table,
+    pattern and work items; the step graph is captured again): step, regrid
+    with the criterion's flags, step again - bit for bit the plain form's
+    result, and the same leaf table."""
+    w = synth.two_level_blast(base_trees=4, block=8)
+    pair = []
+    for _ in range(2):
+        gm = f4.Mesh(3, w["trees"], 8, 2, w["tree_size"], level=1, max_level=2,
+                     max_blocks=4 ** 3 * 8 * 8, prec=prec)
+        from paper_2605_07612_amd import layout
+        layout.set_from_field(gm, w["field"])
+        pair.append(gm)
+    gp, gb = pair
+    b = f4.Batch([gb])
+    b.set_config(kslabs=1, wg_per_cu=0, xcd_order=1, wg_stage2=4)
+    gp.step(4)
+    b.step(4)
+    fp, fb = gp.refine_flags(), gb.refine_flags()
+    assert np.array_equal(fp, fb) and (fp == 1).any()
+    assert gp.regrid(fp) and gb.regrid(fb)
+    say("blocks after regrid", gp.nb, gb.nb)
+    gp.step(4)
+    b.step(4)
+    assert all(np.array_equal(x, y) for x, y in zip(gp.export(), gb.export()))
+    a, c = interior(gpu_state(gp), 2, 8, 3), interior(gpu_state(gb), 2, 8, 3)
+    assert gp.time() == gb.time()
+    assert np.array_equal(a, c)
+
+
 def test_batch_mixed_sizes_vs_oracle(f4):
     ws = [synth.batch_problem(p) for p in (51, 34, 1, 9, 6, 52)]  # the six smallest
     pairs = [build_pair(w, 0) for w in ws]
