@@ -33,11 +33,13 @@ struct TileCfg {
 template <int NDIM>
 constexpr int lds_planes() { return NDIM == 3 ? 3 : 1; }
 
-// LDS elements of one work item: SUB * (planes + x faces + y faces) * NV.
+// LDS elements of one work item: SUB * (planes + x faces + y faces + the
+// edge fluxes of the next plane) * NV.
 template <int NDIM, int N>
 constexpr int item_cells() {
   using C = TileCfg<N>;
-  return C::SUB * (lds_planes<NDIM>() * (C::TILE + 4) * (C::TILE + 4) + 2 * (C::TILE + 1) * C::TILE) * (NDIM + 2);
+  return C::SUB * (lds_planes<NDIM>() * (C::TILE + 4) * (C::TILE + 4) + 2 * (C::TILE + 1) * C::TILE + 2 * C::TILE) *
+         (NDIM + 2);
 }
 
 // LDS elements per workgroup: the maximum over the block sizes in NM.
@@ -172,9 +174,10 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   auto nbr_of = [&](int f) -> int64_t { return (M.gather && finfo[f] <= -2) ? (int64_t)(-2 - finfo[f]) : -1; };
 
   constexpr int NS = lds_planes<NDIM>();
-  T *Wring = smem + sub * (NS * PLANE + 2 * NFX) * NV;  // [slot][v][PLANE]
-  T *FX = Wring + NS * PLANE * NV;                      // [v][TILE][TILE + 1]
-  T *FY = FX + NFX * NV;                                // [v][TILE + 1][TILE]
+  T *Wring = smem + sub * (NS * PLANE + 2 * NFX + 2 * TILE) * NV;  // [slot][v][PLANE]
+  T *FX = Wring + NS * PLANE * NV;                                  // [v][TILE][TILE + 1]
+  T *FY = FX + NFX * NV;                                            // [v][TILE + 1][TILE]
+  T *XE = FY + NFX * NV;  // [v][2 TILE]: edge fluxes (+x column, +y row) of plane k + 1
   auto slot = [&](int kk) -> T * { return NS == 1 ? Wring : Wring + (kk % NS) * (PLANE * NV); };
 
   auto off = [&](int ii, int jj, int kk) -> int { return cell_off<NDIM>(ii, jj, kk, N, g); };
@@ -388,9 +391,9 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     // x and y faces of the plane: every thread computes the -x and the -y
     // face of its cell (FX[v][fj][fi], FY[v][fj][fi], both NFX per variable).
     // The TILE extra +x faces of the last column and the TILE extra +y faces
-    // of the last row run together in 2 TILE lanes of one wave (the y ones
-    // on exchanged velocities); with 4 waves per tile the wave rotates with
-    // the plane so that every SIMD gets its share.
+    // of the last row run together in lanes of one wave (the y ones on
+    // exchanged velocities); with 4 waves per tile the wave rotates with the
+    // plane (pair) so that every SIMD gets its share.
     {
       T F[NV];
       plane_face<T, NDIM, PLANE>(Wp, (tj + 2) * LP + ti, 1, false, gamma, F);  // cells ti-2 .. ti+1
@@ -402,7 +405,42 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       for (int v = 0; v < NV; v++) FY[v * NFX + tj * TILE + ti] = F[v];
       if (tj == 0 && j0 == 0) store_bflux(2, i0 + ti, k, F);
     }
-    {
+    if constexpr (NDIM == 3 && TT == 256) {
+      // 3D tiles of 16 x 16: the edge faces of planes k and k + 1 together,
+      // every other plane, in the 64 lanes of one wave (one plane's 2 TILE
+      // edge faces would leave half of it idle); the fluxes of plane k + 1
+      // wait in XE and are put in place on the next plane (the planes of a
+      // slab come in pairs: N / kslabs is even).  For 8^3 blocks each wave
+      // keeps its own plane's 16 edge faces: pairing them there costs more
+      // registers (and occupancy) than it saves.
+      const int pair = (k - k0) >> 1;
+      const int e = lt - 64 * ((pair + (int)local) & 3);
+      if (((k - k0) & 1) == 0) {
+        if (e >= 0 && e < 4 * TILE) {
+          const int pk = e >= 2 * TILE ? 1 : 0;  // plane k + pk
+          const int ee = e - 2 * TILE * pk;
+          const bool sw = ee >= TILE;
+          const int m = sw ? ee - TILE : ee;
+          if (pk == 0 || k + 1 < k1) {
+            T F[NV];
+            plane_face<T, NDIM, PLANE>(pk ? slot(k + 1) : Wp, sw ? TILE * LP + m + 2 : (m + 2) * LP + TILE,
+                                       sw ? LP : 1, sw, gamma, F);
+            T *out = pk ? XE + ee : (sw ? FY + TILE * TILE + m : FX + m * (TILE + 1) + TILE);
+            const int ost = pk ? 2 * TILE : NFX;
+#pragma unroll
+            for (int v = 0; v < NV; v++) out[v * ost] = F[v];
+            if (!sw && i0 + TILE == N) store_bflux(1, j0 + m, k + pk, F);
+            if (sw && j0 + TILE == N) store_bflux(3, i0 + m, k + pk, F);
+          }
+        }
+      } else if (e >= 0 && e < 2 * TILE) {
+        const bool sw = e >= TILE;
+        const int m = sw ? e - TILE : e;
+        T *out = sw ? FY + TILE * TILE + m : FX + m * (TILE + 1) + TILE;
+#pragma unroll
+        for (int v = 0; v < NV; v++) out[v * NFX] = XE[v * 2 * TILE + e];
+      }
+    } else {
       const int e = (TT == 256) ? lt - 64 * ((k + (int)local) & 3) : lt;
       if (e >= 0 && e < 2 * TILE) {
         const bool sw = e >= TILE;
