@@ -534,10 +534,10 @@ __device__ __forceinline__ int64_t item_of(int64_t w, int64_t it, int64_t grid, 
 }
 
 // Target waves per SIMD: single-size FP32 kernels 4 (4 resident workgroups
-// of 4 waves per CU: stage 1 fits 128 registers, stage 2 spills 21 values
-// per lane and still runs ~9 % faster than at 3 waves without spills, since
-// the plane loop waits on its loads); the mixed-size and FP64 kernels keep
-// what their registers allow.
+// of 4 waves per CU: at 128 registers stage 2 spills ~25 values per lane and
+// still runs ~9 % faster than at 3 waves without spills, since the plane
+// loop waits on its loads); the mixed-size and FP64 kernels keep what their
+// registers allow.
 template <typename T, int NM, int STG = 2>
 constexpr int stage_waves() { return (sizeof(T) == 4 && NM != 7) ? 4 : 1; }
 
