@@ -134,4 +134,15 @@ __device__ __forceinline__ void atomic_max_pos(double *addr, double v) {
                          (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The same, skipped when the stored value is already at least v: a maximum
+// that only grows during a launch is read at device scope first, so the
+// thousands of waves of a launch do not all queue on one address (a stale
+// read can only be smaller, which costs one unneeded atomic).  The result is
+// the same maximum.
+__device__ __forceinline__ void atomic_max_pos_if_larger(double *addr, double v) {
+  const unsigned long long cur = __hip_atomic_load((__attribute__((address_space(1))) unsigned long long *)addr,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if ((unsigned long long)__double_as_longlong(v) > cur) atomic_max_pos(addr, v);
+}
+
 }  // namespace f4

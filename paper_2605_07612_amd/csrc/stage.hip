@@ -512,7 +512,7 @@ __device__ __forceinline__ void flush_dt(const MeshDev &M, double &vmax, bool &b
   for (int o = 32; o > 0; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
   const bool anybad = __ballot(bad) != 0;
   if ((threadIdx.x & 63) == 0) {
-    if (vmax > 0.0) atomic_max_pos(&M.scal[kMaxInv], vmax);
+    if (vmax > 0.0) atomic_max_pos_if_larger(&M.scal[kMaxInv], vmax);
     if (anybad) atomic_max_pos(&M.scal[kBad], 1.0);
   }
   vmax = 0.0;
