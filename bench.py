@@ -123,7 +123,7 @@ def main():
     ap.add_argument("--counters", default=os.path.join(ROOT, "profiles", "stage_traffic_noise_shear_256cubed_b16.json"))
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1 (the multi-GPU sharding is a design "
+        print("bench.py: this benchmark runs on one GPU; --gpus must be 1 (the multi-GPU sharding is a design "
               "note only)", file=sys.stderr)
         sys.exit(2)
 

@@ -12,8 +12,9 @@ seconds on the host:
   run; on identical states its flags are compared with the criterion's
   (confusion, missed-refinement rate), and both FP32 runs are compared with
   the oracle after restriction to uniform level 2; indicator time per regrid
-  is measured for both.  What the network gains or loses is printed and
-  written to gpurun_out/adaptive_blast_indicator.json.
+  is measured for both.  What the network gains or loses is printed, and
+  written as adaptive_blast_indicator.json into the folder that
+  FOAP4_REPORT_DIR names, if it is set.
 
 FOAP4_FULL_ADAPTIVE=1 adds the full-size run (4^3 trees, levels 0..3, 400
 steps; GPU only, compared with an FP64 GPU run)."""
@@ -35,6 +36,15 @@ pytestmark = pytest.mark.gpu
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+def write_report(name, report):
+    """Write the report as JSON into FOAP4_REPORT_DIR (if set)."""
+    d = os.environ.get("FOAP4_REPORT_DIR")
+    if d:
+        os.makedirs(d, exist_ok=True)
+        with open(os.path.join(d, name), "w") as fh:
+            json.dump(report, fh, indent=1)
 
 
 @pytest.fixture(scope="module")
@@ -167,9 +177,7 @@ def test_adaptive_blast_indicators(f4):
                   fp64_gpu_vs_oracle_l1=e64, training=tr, training_captured=trc, runs=ev, l1_vs_oracle_level2=l1,
                   indicator_cost_ratio=cost)
     say(json.dumps(report, indent=1))
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open("gpurun_out/adaptive_blast_indicator.json", "w") as fh:
-        json.dump(report, fh, indent=1)
+    write_report("adaptive_blast_indicator.json", report)
     for k in ("mlp", "mlp_captured"):
         assert ev[k]["missed_refinement"] <= 0.05, k
         assert l1[k] <= max(3.0 * l1["lohner"], 1e-5), k
@@ -192,7 +200,5 @@ def test_adaptive_blast_full_size(f4):
     report = dict(workload=w["name"], steps=w["steps"], regrid_every=w["regrid_every"], training=tr,
                   training_captured=trc, runs=ev, l1_vs_fp64_gpu_level2=l1, indicator_cost_ratio=cost)
     say(json.dumps(report, indent=1))
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open("gpurun_out/adaptive_blast_indicator_full.json", "w") as fh:
-        json.dump(report, fh, indent=1)
+    write_report("adaptive_blast_indicator_full.json", report)
     assert ev["mlp"]["missed_refinement"] <= 0.05 and ev["mlp_captured"]["missed_refinement"] <= 0.05
