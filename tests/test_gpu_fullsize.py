@@ -109,3 +109,27 @@ def test_batch_of_64_problems(f4):
         gm.time()  # raises on an unphysical state
     say("batch worst relative drift of mass/energy after 20 steps", worst)
     assert worst <= 2e-6
+
+
+def test_noise_shear_long_run_batched_equals_plain(f4):
+    """500 steps of the benchmark workload (256^3 cells, FP32): the batched
+    form in the benchmark's configuration and the plain form stay bit for bit
+    equal (state and time) over the whole run, and mass and energy are
+    conserved to FP32 rounding."""
+    w = synth.uniform_noise_shear(block=16, n=256, seed=0)
+    gp, _ = build_pair(w, 0)
+    gb, _ = build_pair(w, 0)
+    t0 = gp.totals()
+    b = f4.Batch([gb])
+    b.set_config(kslabs=1, wg_per_cu=0, xcd_order=1, wg_stage2=4)
+    for chunk in range(5):
+        gp.step(100)
+        b.step(100)
+        say("steps", 100 * (chunk + 1), "t", gp.time()[0], gb.time()[0])
+        assert gp.time() == gb.time()
+    # interiors: the plain form stores ghosts, the batched form gathers them
+    assert np.array_equal(interior(gpu_state(gp), 2, 16, 3), interior(gpu_state(gb), 2, 16, 3))
+    tot = gb.totals()
+    drift = np.abs(tot - t0) / np.maximum(np.abs(t0), 1e-300)
+    say("mass/energy drift after 500 steps", drift[0], drift[-1])
+    assert drift[0] <= 1e-5 and drift[-1] <= 1e-5
