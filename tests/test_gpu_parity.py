@@ -89,7 +89,7 @@ def test_pattern_counts_closed_forms(f4):
 # ---------------------------------------------------------- ghost-fill parity
 
 @pytest.mark.parametrize("prec", [1, 0])
-@pytest.mark.parametrize("wname", ["wave2d", "blast_small", "blast_small_2d"])
+@pytest.mark.parametrize("wname", ["wave2d", "blast_small", "blast_small_2d", "blast_b16", "blast_b32"])
 def test_ghost_fill_bit_exact(f4, prec, wname):
     """SRL copies, FP64 restriction sums and FP64 prolongation slopes equal the
     oracle bit for bit (FP32 states: the oracle on the same FP32 values, its
@@ -98,6 +98,10 @@ def test_ghost_fill_bit_exact(f4, prec, wname):
         w = synth.periodic_2d_wave()
     elif wname == "blast_small":
         w = synth.two_level_blast(base_trees=4, block=8)
+    elif wname == "blast_b16":
+        w = synth.two_level_blast(base_trees=4, block=16)
+    elif wname == "blast_b32":
+        w = synth.two_level_blast(base_trees=4, block=32)
     else:
         w = two_level_2d()
     say("case", wname, prec)
@@ -273,31 +277,32 @@ def two_level_2d():
     return w
 
 
-@pytest.mark.parametrize("ndim", [3, 2])
+@pytest.mark.parametrize("ndim,block", [(3, 8), (2, 8), (3, 16), (3, 32)])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("gather", [1, 0])
-def test_batch_two_level_equals_plain(f4, prec, gather, ndim):
+def test_batch_two_level_equals_plain(f4, prec, gather, ndim, block):
     """Refinement boundaries in the batched form: restriction and
     prolongation ghosts, halos gathered across same-level faces only, the
     SRL copies kept where the prolongation reads them, flux fixing and the
     per-stage grids give exactly the plain form's state, which is within
     tolerance of the oracle."""
-    w = synth.two_level_blast(base_trees=4, block=8) if ndim == 3 else two_level_2d()
-    say("two-level batched vs plain, ndim", ndim, "prec", prec, "gather", gather)
+    w = synth.two_level_blast(base_trees=4, block=block) if ndim == 3 else two_level_2d()
+    steps = 12 if block < 32 else 4
+    say("two-level batched vs plain, ndim", ndim, "block", block, "prec", prec, "gather", gather)
     gp, om = build_pair(w, prec)
     gb, _ = build_pair(w, prec)
     assert len(set(gp.export()[0].tolist())) == 2
-    gp.step(12)
+    gp.step(steps)
     b = f4.Batch([gb])
     b.set_config(kslabs=2, wg_per_cu=2, xcd_order=1, gather_halos=gather, wg_stage2=3)
-    b.step(12)
-    a, c = interior(gpu_state(gp), 2, 8, ndim), interior(gpu_state(gb), 2, 8, ndim)
+    b.step(steps)
+    a, c = interior(gpu_state(gp), 2, block, ndim), interior(gpu_state(gb), 2, block, ndim)
     say("times", gp.time(), gb.time(), "max |diff|", float(np.max(np.abs(a - c))))
     assert gp.time() == gb.time()
     assert np.array_equal(a, c)
-    om.step(12)
+    om.step(steps)
     lev = gb.export()[0]
-    err = rel_l1_vol(c, om.interior(), lev, ndim, w["tree_size"], 8)
+    err = rel_l1_vol(c, om.interior(), lev, ndim, w["tree_size"], block)
     say("rel L1 vs oracle", err)
     assert err <= TOL[prec]
 
