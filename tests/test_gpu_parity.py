@@ -203,14 +203,16 @@ def test_determinism_bitwise(f4):
 
 # ---------------------------------------------------------------- regrid
 
-def test_lohner_flags_and_regrid_bit_exact(f4):
+@pytest.mark.parametrize("block", [8, 16])
+def test_lohner_flags_and_regrid_bit_exact(f4, block):
     """Flags on identical states equal the oracle's; the regrid map (leaf
     table) and the remapped FP64 data equal the oracle's bit for bit."""
-    w = synth.two_level_blast(base_trees=4, block=8)
+    w = synth.two_level_blast(base_trees=4, block=block)
+    say("regrid parity, block", block)
     gm, om = build_pair(w, 1)
     gm.step(5)
     om.u[...] = 0.0
-    om.interior()[...] = interior(gpu_state(gm), 2, 8, 3)
+    om.interior()[...] = interior(gpu_state(gm), 2, block, 3)
     om.ghost_fill()
     fg = gm.refine_flags()
     fo = om.lohner_flags()
@@ -228,7 +230,7 @@ def test_lohner_flags_and_regrid_bit_exact(f4):
     om2.set_interior_from_field(w["field"])
     gm2.step(3)
     om2.u[...] = 0.0
-    om2.interior()[...] = interior(gpu_state(gm2), 2, 8, 3)
+    om2.interior()[...] = interior(gpu_state(gm2), 2, block, 3)
     flags = gm2.refine_flags()
     om2.ghost_fill()
     assert np.array_equal(flags, om2.lohner_flags())
@@ -238,7 +240,7 @@ def test_lohner_flags_and_regrid_bit_exact(f4):
     lev2, tree2, anc2 = gm2.export()
     olev, otree, oanc = om2.forest.export()
     assert np.array_equal(lev2, olev) and np.array_equal(tree2, otree) and np.array_equal(anc2, oanc)
-    a = interior(gpu_state(gm2), 2, 8, 3)
+    a = interior(gpu_state(gm2), 2, block, 3)
     assert np.array_equal(a, om2.interior())
 
 
