@@ -55,7 +55,9 @@ def noise3d_refined():
 
 
 WORKLOADS = {"wave2d_refined": wave2d_refined, "noise3d_refined": noise3d_refined,
-             "blast_small": lambda: synth.two_level_blast(base_trees=4, block=8)}
+             "blast_small": lambda: synth.two_level_blast(base_trees=4, block=8),
+             "blast_b16": lambda: synth.two_level_blast(base_trees=4, block=16),
+             "blast_b32": lambda: synth.two_level_blast(base_trees=4, block=32)}
 
 
 def oracle_features(om, lmax):
@@ -258,7 +260,7 @@ def test_regrid_uses_attached_indicator(f4):
 
 
 @pytest.mark.parametrize("wname,prec", [("noise3d_refined", 1), ("noise3d_refined", 0), ("wave2d_refined", 1),
-                                        ("blast_small", 1)])
+                                        ("blast_small", 1), ("blast_b16", 1), ("blast_b16", 0)])
 def test_captured_features_match_oracle(f4, wname, prec):
     """Features captured inside the first stage of a step describe the state
     at the start of that step: compare with the oracle's features of that
