@@ -246,8 +246,9 @@ def test_lohner_flags_and_regrid_bit_exact(f4, block):
 
 # ---------------------------------------------------------------- batch
 
-@pytest.mark.parametrize("order,wg1,wg2", [(0, 2, 2), (1, 2, 2), (2, 2, 2), (1, 8, 3), (1, 0, 1)])
-def test_batch_equals_plain_bitwise(f4, order, wg1, wg2):
+@pytest.mark.parametrize("ks,order,wg1,wg2", [(2, 0, 2, 2), (2, 1, 2, 2), (2, 2, 2, 2), (2, 1, 8, 3), (2, 1, 0, 1),
+                                             (4, 1, 0, 4), (1, 1, 3, 6)])
+def test_batch_equals_plain_bitwise(f4, ks, order, wg1, wg2):
     """The persistent, graph-replayed batched form computes exactly what the
     plain per-kernel form computes (k-slabs, workgroup mapping, per-stage
     grids and item order only change who computes a face, not how)."""
@@ -258,7 +259,7 @@ def test_batch_equals_plain_bitwise(f4, order, wg1, wg2):
     for m in plain:
         m.step(4)
     b = f4.Batch(batched)
-    b.set_config(kslabs=2, wg_per_cu=wg1, xcd_order=order, wg_stage2=wg2)
+    b.set_config(kslabs=ks, wg_per_cu=wg1, xcd_order=order, wg_stage2=wg2)
     b.step(4)
     for w, p, q in zip(ws, plain, batched):
         a, c = interior(gpu_state(p), 2, w["N"], 3), interior(gpu_state(q), 2, w["N"], 3)
