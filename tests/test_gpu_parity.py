@@ -341,6 +341,39 @@ def test_batch_follows_regrid(f4, prec):
     assert np.array_equal(a, c)
 
 
+@pytest.mark.parametrize("g", [3, 4])
+@pytest.mark.parametrize("two_level", [False, True], ids=["uniform", "two_level"])
+def test_wider_ghost_layers(f4, g, two_level):
+    """Blocks with 3 or 4 ghost layers (the stencil reads 2 of them): the
+    ghost rounds fill all g layers bit for bit as the oracle does, and the
+    plain and batched steps agree with the oracle (FP64) and with each other."""
+    if two_level:
+        w = dict(synth.two_level_blast(base_trees=4, block=16), g=g)
+    else:
+        w = dict(small_uniform(16, (2, 2, 2), seed=9), g=g)
+    say("ghost layers", g, "two-level", two_level)
+    gm, om = build_pair(w, 1)
+    gb, _ = build_pair(w, 1)
+    # ghost rounds on identical data, all g layers
+    om.u[...] = 0.0
+    om.interior()[...] = interior(gpu_state(gm), g, 16, 3)
+    gm.ghost_fill()
+    om.ghost_fill()
+    mask = face_ghost_mask(3, 16, g)
+    assert np.array_equal(gpu_state(gm)[:, :, mask], om.u[:, :, mask])
+    gm.step(6)
+    b = f4.Batch([gb])
+    b.set_config(kslabs=2, wg_per_cu=0, xcd_order=1, wg_stage2=4)
+    b.step(6)
+    om.step(6)
+    a, c = interior(gpu_state(gm), g, 16, 3), interior(gpu_state(gb), g, 16, 3)
+    assert gm.time() == gb.time() and np.array_equal(a, c)
+    lev = gm.export()[0]
+    err = rel_l1_vol(a, om.interior(), lev, 3, w["tree_size"], 16)
+    say("rel L1 vs oracle", err)
+    assert err <= TOL[1]
+
+
 def test_batch_mixed_sizes_vs_oracle(f4):
     ws = [synth.batch_problem(p) for p in (51, 34, 1, 9, 6, 52)]  # the six smallest
     pairs = [build_pair(w, 0) for w in ws]
