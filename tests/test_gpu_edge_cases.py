@@ -10,7 +10,9 @@
 * A state with a negative density is reported as FOAP4_E_UNPHYSICAL.
 * A step count of zero changes nothing; a batch of meshes of different
   precisions is refused.
-* The autotuner leaves the meshes as it found them and caches its choice."""
+* The autotuner leaves the meshes as it found them and caches its choice.
+* Creating and destroying meshes, batches and networks returns all device
+  memory the library allocated."""
 import sys
 
 import numpy as np
@@ -165,3 +167,46 @@ def test_autotune_restores_state_and_caches(f4, tmp_path):
         assert m.time() == t0
     assert b.autotune(cache) == cfg
     assert '"' in open(cache).read()
+
+
+def test_no_device_memory_leak(f4):
+    """Meshes, batches and networks created and destroyed in a loop (with
+    regrids, captured features and training in between) give back the
+    device memory the library allocates."""
+    import gc
+    import torch
+    from paper_2605_07612_amd import layout
+
+    def cycle():
+        w = synth.two_level_blast(base_trees=4, block=8)
+        m = f4.Mesh(3, w["trees"], 8, 2, w["tree_size"], level=0, max_level=2, max_blocks=4 ** 3 * 64, prec=f4.F32)
+        layout.set_from_field(m, w["field"])
+        m.capture_features(True)
+        m.step(2, sync=True)
+        m.regrid(m.refine_flags())
+        net = f4.Mlp(weights=0.1 * np.random.default_rng(0).standard_normal(f4.MLP_NPARAM).astype(np.float32))
+        x = m.block_features()
+        net.train(x, torch.zeros(m.nb, dtype=torch.int8, device=x.device), 2)
+        m.set_indicator(f4.IND_MLP, net)
+        m.step(1, sync=True)
+        m.regrid()
+        b = f4.Batch([m])
+        b.step(2)
+        m.time()
+        b.close()
+        net.close()
+        m.close()
+
+    cycle()  # first use: library-wide allocations, caches
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(20):
+        cycle()
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free1 = torch.cuda.mem_get_info()[0]
+    say("device memory free before / after 20 cycles (MB)", free0 / 2 ** 20, free1 / 2 ** 20)
+    assert free0 - free1 < 64 * 2 ** 20
