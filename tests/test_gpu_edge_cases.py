@@ -210,3 +210,21 @@ def test_no_device_memory_leak(f4):
     free1 = torch.cuda.mem_get_info()[0]
     say("device memory free before / after 20 cycles (MB)", free0 / 2 ** 20, free1 / 2 ** 20)
     assert free0 - free1 < 64 * 2 ** 20
+
+
+@pytest.mark.parametrize("kw", [dict(kslabs=3), dict(wg_per_cu=65), dict(wg_per_cu=-1), dict(wg_stage2=65),
+                                dict(xcd_order=3), dict(gather_halos=2)])
+def test_batch_config_rejects_bad_arguments(f4, kw):
+    """Batch configuration outside the documented ranges is refused with
+    FOAP4_E_INVALID and the batch keeps its previous configuration."""
+    m = f4.Mesh(3, (2, 2, 2), 8, 2, 0.5, prec=f4.F32)
+    from paper_2605_07612_amd import layout
+    layout.set_from_field(m, synth.two_level_blast(base_trees=2, block=8)["field"])
+    b = f4.Batch([m])
+    b.set_config(kslabs=2, wg_per_cu=2, xcd_order=1)
+    args = dict(kslabs=2, wg_per_cu=2, xcd_order=1)
+    args.update(kw)
+    with pytest.raises(f4.Foap4Error, match="E_INVALID"):
+        b.set_config(**args)
+    b.step(1)
+    assert m.time()[0] > 0
