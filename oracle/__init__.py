@@ -60,6 +60,9 @@ def lib():
                                          ctypes.c_double, P]
         _lib.om_remap.argtypes = [P, P, P, P, P, P, P]
         _lib.om_block_raw_features.argtypes = [P, P, P]
+        _lib.om_limiter.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double]
+        _lib.om_limiter.restype = ctypes.c_double
+        _lib.om_riemann_flux.argtypes = [P, P, P, ctypes.c_int32, P]
     return _lib
 
 
@@ -69,7 +72,8 @@ class _MeshC(ctypes.Structure):
                 ("dx0", ctypes.c_double), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("srl", ctypes.c_void_p), ("srl_off", ctypes.c_void_p),
                 ("f2c", ctypes.c_void_p), ("f2c_off", ctypes.c_void_p),
-                ("c2f", ctypes.c_void_p), ("c2f_off", ctypes.c_void_p)]
+                ("c2f", ctypes.c_void_p), ("c2f_off", ctypes.c_void_p),
+                ("limiter", ctypes.c_int32), ("flux", ctypes.c_int32), ("grav", ctypes.c_double * 3)]
 
 
 def _ptr(a):
@@ -79,18 +83,42 @@ def _ptr(a):
 # Lohner criterion constants of the paper's AMR runs (Sec. 5.4)
 LOHNER = dict(c_ref=5e-2, c_deref=6.25e-3, eps=1e-2, eps_abs=1e-10)
 
+# scheme options of Sec. 3.2: reconstruction limiter and numerical flux
+LIMITERS = {"minmod": 0, "vanleer": 1}
+FLUXES = {"rusanov": 0, "hll": 1}
+
+
+def limiter(kind, a, b):
+    """Limited slope of a cell from its backward and forward differences."""
+    return lib().om_limiter(LIMITERS[kind], float(a), float(b))
+
+
+def riemann_flux(wl, wr, ax=0, flux="rusanov", gamma=1.4, ndim=3):
+    """Numerical flux between primitive states (rho, vx, vy, vz, p) along ax,
+    in conservative variable order (rho, m_x .. m_ndim, E)."""
+    c = _MeshC()
+    c.ndim, c.nvar, c.gamma, c.flux = ndim, ndim + 2, float(gamma), FLUXES[flux]
+    a = np.ascontiguousarray(wl, dtype=np.float64)
+    b = np.ascontiguousarray(wr, dtype=np.float64)
+    F = np.zeros(5)
+    lib().om_riemann_flux(ctypes.byref(c), _ptr(a), _ptr(b), ax, _ptr(F))
+    return F[:ndim + 2]
+
 
 class OracleMesh:
     """A forest plus its FP64 state arrays [nb][nvar][P^ndim], P = N + 2g."""
 
     def __init__(self, ndim, trees, N, g=2, tree_size=1.0, level=0, gamma=1.4, cfl=0.5,
-                 periodic=(True, True, True), origin=(0.0, 0.0, 0.0)):
+                 periodic=(True, True, True), origin=(0.0, 0.0, 0.0), limiter="minmod",
+                 flux="rusanov", gravity=(0.0, 0.0, 0.0)):
         if N % 2 or N < 2 * g or g < 2:
             raise ValueError("need even N >= 2g and g >= 2")
         self.ndim, self.N, self.g = ndim, N, g
         self.nvar = 2 + ndim
         self.tree_size, self.gamma, self.cfl = float(tree_size), float(gamma), float(cfl)
         self.origin = origin
+        self.limiter, self.flux = LIMITERS[limiter], FLUXES[flux]
+        self.gravity = tuple(float(x) for x in gravity) + (0.0,) * (3 - len(gravity))
         self.forest = Forest(ndim, trees, periodic, level)
         self._refresh()
         self.u = self.alloc()
@@ -117,6 +145,8 @@ class OracleMesh:
         c.level = _ptr(self.level)
         c.dx0 = self.tree_size / self.N
         c.gamma, c.cfl = self.gamma, self.cfl
+        c.limiter, c.flux = self.limiter, self.flux
+        c.grav[:] = list(self.gravity)
         keep = []
         for name in ("srl", "srl_off", "f2c", "f2c_off", "c2f", "c2f_off"):
             arr = np.ascontiguousarray(self.pat[name], dtype=np.int32)

@@ -11,8 +11,11 @@
  * the order the paper describes, with no blocking or fusion:
  *   ghost filling          Sec. 2.6 (two rounds R1, R2), Sec. 2.2 (restriction,
  *                          limited prolongation, eq. gminmod with theta = 1)
- *   stage operator L(U)    Sec. 3.2 (primitive MUSCL reconstruction, minmod,
- *                          Rusanov flux), Sec. 3.5 (eq. euler, Einfeldt speeds)
+ *   stage operator L(U)    Sec. 3.2 (primitive MUSCL reconstruction with the
+ *                          minmod or van Leer limiter, Rusanov or HLL flux,
+ *                          source term first, then the flux divergence),
+ *                          Sec. 3.5 (eq. euler, Einfeldt speeds), Sec. 4.2
+ *                          (gravity source S = (0, rho g, rho g.u))
  *   Runge-Kutta stages     Sec. 3.1, eq. feuler and eq. heun
  *   flux fixing            Sec. 2.7
  *   CFL time step          Sec. 3.1 / Sec. 3.2 step list
@@ -47,6 +50,9 @@ typedef struct {
   const int32_t *f2c_off;
   const int32_t *c2f;     /* (q, c, h): fine q receives from coarse c            */
   const int32_t *c2f_off;
+  int32_t limiter;        /* reconstruction slope limiter: 0 minmod, 1 van Leer  */
+  int32_t flux;           /* numerical flux: 0 Rusanov, 1 HLL                     */
+  double grav[3];         /* gravitational acceleration; all zero: no source term */
 } om_mesh;
 
 /* ---------------------------------------------------------------- indexing */
@@ -83,6 +89,23 @@ static inline double minmod(double a, double b) {
   if (a > 0.0 && b > 0.0) return a < b ? a : b;
   if (a < 0.0 && b < 0.0) return a > b ? a : b;
   return 0.0;
+}
+
+/* van Leer limiter (Sec. 3.2 limiter list, van Leer 1977): the harmonic mean
+ * 2ab/(a+b) of the two one-sided slopes when they have the same strict sign,
+ * else zero; phi(r) = (r + |r|)/(1 + |r|) times b with r = a/b. */
+static inline double vanleer(double a, double b) {
+  if ((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0)) return 2.0 * a * b / (a + b);
+  return 0.0;
+}
+
+/* slope of a cell from its backward (a) and forward (b) differences */
+static inline double limited_slope(const om_mesh *m, double a, double b) {
+  return m->limiter == 1 ? vanleer(a, b) : minmod(a, b);
+}
+
+double om_limiter(int32_t kind, double a, double b) {
+  return kind == 1 ? vanleer(a, b) : minmod(a, b);
 }
 
 /* ------------------------------------------------------- ghost cells, R1/R2 */
@@ -279,14 +302,13 @@ static void state_and_flux(const om_mesh *m, const prim_t *w, int ax, double *U,
   F[nv - 1] = (E + w->p) * vn;
 }
 
-/* Rusanov flux (Sec. 3.2) with the largest Einfeldt wave speed (Sec. 3.5):
- * Roe-type averages with sqrt(rho) weights, speeds u_bar -+ d_bar,
+/* Einfeldt wave speeds (Sec. 3.5) of the face between wl and wr along ax:
+ * Roe-type averages with sqrt(rho) weights, u_bar = (sL vL + sR vR)/(sL+sR),
  * d_bar^2 = (sL cL^2 + sR cR^2)/(sL+sR) + eta2 (vR - vL)^2,
- * eta2 = sL sR / (2 (sL+sR)^2).  F = (FL+FR)/2 - a (UR-UL)/2, a = max |lambda|. */
-static void rusanov(const om_mesh *m, const prim_t *wl, const prim_t *wr, int ax, double *F) {
-  double UL[5], UR[5], FL[5], FR[5];
-  state_and_flux(m, wl, ax, UL, FL);
-  state_and_flux(m, wr, ax, UR, FR);
+ * eta2 = sL sR / (2 (sL+sR)^2); the slowest and fastest signals are
+ * u_bar - d_bar and u_bar + d_bar. */
+static void einfeldt_speeds(const om_mesh *m, const prim_t *wl, const prim_t *wr, int ax, double *smin,
+                            double *smax) {
   double sl = sqrt(wl->rho), sr = sqrt(wr->rho);
   double cl2 = m->gamma * wl->p / wl->rho, cr2 = m->gamma * wr->p / wr->rho;
   double vl = wl->v[ax], vr = wr->v[ax];
@@ -296,13 +318,59 @@ static void rusanov(const om_mesh *m, const prim_t *wl, const prim_t *wr, int ax
   double dv = vr - vl;
   double d2 = (sl * cl2 + sr * cr2) / ssum + eta2 * dv * dv;
   double dbar = sqrt(d2);
-  double lm = fabs(ubar - dbar), lp = fabs(ubar + dbar);
+  *smin = ubar - dbar;
+  *smax = ubar + dbar;
+}
+
+/* Rusanov (local Lax-Friedrichs) flux (Sec. 3.2):
+ * F = (FL+FR)/2 - a (UR-UL)/2 with a the largest |Einfeldt speed|. */
+static void rusanov(const om_mesh *m, const prim_t *wl, const prim_t *wr, int ax, double *F) {
+  double UL[5], UR[5], FL[5], FR[5];
+  state_and_flux(m, wl, ax, UL, FL);
+  state_and_flux(m, wr, ax, UR, FR);
+  double smin, smax;
+  einfeldt_speeds(m, wl, wr, ax, &smin, &smax);
+  double lm = fabs(smin), lp = fabs(smax);
   double a = lm > lp ? lm : lp;
   for (int v = 0; v < m->nvar; v++) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * a * (UR[v] - UL[v]);
 }
 
+/* HLL flux (Sec. 3.2; Harten, Lax and van Leer) with the Einfeldt speeds
+ * sL <= sR as the fastest signals: the left flux when sL >= 0, the right one
+ * when sR <= 0, else the flux of the single intermediate state,
+ * (sR FL - sL FR + sL sR (UR - UL)) / (sR - sL). */
+static void hll(const om_mesh *m, const prim_t *wl, const prim_t *wr, int ax, double *F) {
+  double UL[5], UR[5], FL[5], FR[5];
+  state_and_flux(m, wl, ax, UL, FL);
+  state_and_flux(m, wr, ax, UR, FR);
+  double sl, sr;
+  einfeldt_speeds(m, wl, wr, ax, &sl, &sr);
+  for (int v = 0; v < m->nvar; v++) {
+    if (sl >= 0.0)
+      F[v] = FL[v];
+    else if (sr <= 0.0)
+      F[v] = FR[v];
+    else
+      F[v] = (sr * FL[v] - sl * FR[v] + sl * sr * (UR[v] - UL[v])) / (sr - sl);
+  }
+}
+
+static void riemann_flux(const om_mesh *m, const prim_t *wl, const prim_t *wr, int ax, double *F) {
+  if (m->flux == 1)
+    hll(m, wl, wr, ax, F);
+  else
+    rusanov(m, wl, wr, ax, F);
+}
+
+/* The numerical flux of the mesh's scheme between two primitive states
+ * (rho, v_x, v_y, v_z, p) along axis ax. */
+void om_riemann_flux(const om_mesh *m, const double *wl, const double *wr, int32_t ax, double *F) {
+  prim_t a = {wl[0], {wl[1], wl[2], wl[3]}, wl[4]}, b = {wr[0], {wr[1], wr[2], wr[3]}, wr[4]};
+  riemann_flux(m, &a, &b, ax, F);
+}
+
 /* Numerical flux through the face between cell c and c + e_ax of block b,
- * from minmod-limited linear reconstruction of primitives (Sec. 3.2). */
+ * from limited linear reconstruction of primitives (Sec. 3.2). */
 static void face_flux(const om_mesh *m, const double *u, int64_t b, const int c[3], int ax, double *F) {
   int cm[3] = {c[0], c[1], c[2]}, cp[3] = {c[0], c[1], c[2]}, cpp[3] = {c[0], c[1], c[2]};
   cm[ax] -= 1;
@@ -316,25 +384,27 @@ static void face_flux(const om_mesh *m, const double *u, int64_t b, const int c[
   double a3[5] = {w3.rho, w3.v[0], w3.v[1], w3.v[2], w3.p};
   double L[5], R[5];
   for (int k = 0; k < 5; k++) {
-    double s1 = minmod(a1[k] - a0[k], a2[k] - a1[k]);
-    double s2 = minmod(a2[k] - a1[k], a3[k] - a2[k]);
+    double s1 = limited_slope(m, a1[k] - a0[k], a2[k] - a1[k]);
+    double s2 = limited_slope(m, a2[k] - a1[k], a3[k] - a2[k]);
     L[k] = a1[k] + 0.5 * s1;
     R[k] = a2[k] - 0.5 * s2;
   }
   prim_t wl = {L[0], {L[1], L[2], L[3]}, L[4]};
   prim_t wr = {R[0], {R[1], R[2], R[3]}, R[4]};
-  rusanov(m, &wl, &wr, ax, F);
+  riemann_flux(m, &wl, &wr, ax, F);
 }
 
 /* One Runge-Kutta sub-step of eq. feuler for Heun's method (eq. heun):
  *   stage 1: uo = dt L(ud) + ud
  *   stage 2: uo = (dt/2) L(ud) + (up + ud)/2
- * with L(U)_c = -sum_d (F_{c+1/2} - F_{c-1/2}) / dx.  uo may alias up but
- * never ud.  The source term is zero (no gravity). */
+ * with L(U)_c = S_c - sum_d (F_{c+1/2} - F_{c-1/2}) / dx, the source S of the
+ * cell's own state first (Sec. 3.2 step list): with gravity g (Sec. 4.2)
+ * S = (0, rho g, rho g.u), else zero.  uo may alias up but never ud. */
 void om_stage(const om_mesh *m, const double *ud, const double *up, double *uo, int stage, double dt) {
   int N = m->N, nv = m->nvar;
   int nk = (m->ndim == 3) ? N : 1;
   double hdt = 0.5 * dt;
+  int has_src = m->grav[0] != 0.0 || m->grav[1] != 0.0 || m->grav[2] != 0.0;
 #pragma omp parallel for schedule(static)
   for (int64_t b = 0; b < m->nb; b++) {
     double dx = dx_of(m, b);
@@ -343,6 +413,15 @@ void om_stage(const om_mesh *m, const double *ud, const double *up, double *uo, 
         for (int i = 0; i < N; i++) {
           int c[3] = {i, j, k};
           double rhs[5] = {0, 0, 0, 0, 0};
+          if (has_src) {
+            prim_t w = to_primitive(m, ud, b, c);
+            double gu = 0.0;
+            for (int d = 0; d < m->ndim; d++) {
+              rhs[1 + d] = w.rho * m->grav[d];
+              gu += m->grav[d] * w.v[d];
+            }
+            rhs[nv - 1] = w.rho * gu;
+          }
           for (int ax = 0; ax < m->ndim; ax++) {
             double Fp[5], Fm[5];
             int cl[3] = {i, j, k};

@@ -1,0 +1,282 @@
+"""Pins of the oracle's scheme options (CPU only): the van Leer limiter, the
+HLL flux and the gravity source of the Rayleigh-Taylor test (Sec. 3.2,
+Sec. 4.2).  Each check is a closed form, an exact solution, a textbook
+identity or a conservation budget fixed by the mathematics; none compares the
+oracle with itself."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import OracleMesh
+from tests.exact_riemann import sample
+
+SCHEMES = [("minmod", "rusanov"), ("vanleer", "rusanov"), ("minmod", "hll"), ("vanleer", "hll")]
+SCHEME_IDS = [f"{a}-{b}" for a, b in SCHEMES]
+
+
+def set_uniform(m, U):
+    m.interior()[...] = np.asarray(U, dtype=np.float64).reshape((1, -1) + (1,) * m.ndim)
+
+
+def two_level(ndim, nt=4, N=8, **kw):
+    m = OracleMesh(ndim, (nt,) * 3, N, 2, 1.0 / nt, **kw)
+    cent = [(np.array([G[d] for _, G in m.forest.leaves]) + 0.5) / nt for d in range(ndim)]
+    r2 = sum((cent[d] - 0.5) ** 2 for d in range(ndim))
+    m.regrid(np.where(r2 < 0.09, 1, 0).astype(np.int8), 0, 1)
+    assert set(m.level.tolist()) == {0, 1}
+    return m
+
+
+def euler_flux(w, ax, gamma, ndim):
+    """Physical flux of eq. euler along ax for a primitive state (textbook)."""
+    rho, v, p = w[0], np.asarray(w[1:4], dtype=float), w[4]
+    E = p / (gamma - 1) + 0.5 * rho * np.dot(v[:ndim], v[:ndim])
+    F = [rho * v[ax]] + [rho * v[d] * v[ax] + (p if d == ax else 0.0) for d in range(ndim)]
+    return np.array(F + [(E + p) * v[ax]])
+
+
+def euler_state(w, gamma, ndim):
+    rho, v, p = w[0], np.asarray(w[1:4], dtype=float), w[4]
+    E = p / (gamma - 1) + 0.5 * rho * np.dot(v[:ndim], v[:ndim])
+    return np.array([rho] + [rho * v[d] for d in range(ndim)] + [E])
+
+
+# ----------------------------------------------------------------- limiter
+
+def test_vanleer_closed_values():
+    vl = lambda a, b: oracle.limiter("vanleer", a, b)
+    assert vl(1.0, 3.0) == 1.5            # 2 * 3 / 4
+    assert vl(2.0, 2.0) == 2.0            # equal slopes are kept
+    assert vl(-1.0, -3.0) == -1.5
+    assert vl(1.0, -3.0) == 0.0 and vl(-2.0, 0.5) == 0.0  # extremum: flat
+    assert vl(0.0, 5.0) == 0.0 and vl(5.0, 0.0) == 0.0
+
+
+def test_vanleer_is_phi_of_r_and_in_the_tvd_region():
+    """The harmonic-mean form equals van Leer's phi(r) = (r + |r|)/(1 + |r|)
+    times the forward difference b (r = a/b), is symmetric and odd, and lies
+    in Sweby's second-order TVD region: between minmod and twice minmod."""
+    rng = np.random.default_rng(11)
+    a = rng.standard_normal(2000) * np.exp(rng.uniform(-5, 5, 2000))
+    b = rng.standard_normal(2000) * np.exp(rng.uniform(-5, 5, 2000))
+    for x, y in zip(a, b):
+        s = oracle.limiter("vanleer", x, y)
+        r = x / y
+        assert s == pytest.approx((r + abs(r)) / (1 + abs(r)) * y, rel=1e-13, abs=1e-300)
+        assert s == oracle.limiter("vanleer", y, x)
+        assert -s == oracle.limiter("vanleer", -x, -y)
+        mm = oracle.limiter("minmod", x, y)
+        assert abs(mm) <= abs(s) * (1 + 1e-15) and abs(s) <= 2 * abs(mm) * (1 + 1e-15)
+        assert s * mm >= 0
+
+
+# -------------------------------------------------------------------- flux
+
+def random_prim(rng, ndim):
+    v = list(rng.uniform(-1, 1, 3))
+    if ndim == 2:
+        v[2] = 0.0
+    return np.array([rng.uniform(0.2, 2.0)] + v + [rng.uniform(0.2, 3.0)])
+
+
+@pytest.mark.parametrize("flux", ["rusanov", "hll"])
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_flux_is_consistent(flux, ndim):
+    """F(w, w) is the physical flux of eq. euler for every state and axis."""
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        w = random_prim(rng, ndim)
+        for ax in range(ndim):
+            F = oracle.riemann_flux(w, w, ax, flux, 1.4, ndim)
+            assert np.allclose(F, euler_flux(w, ax, 1.4, ndim), rtol=1e-14, atol=1e-14)
+
+
+def test_hll_upwinds_supersonic_states():
+    """All signals moving right (left): HLL is the left (right) physical flux,
+    Rusanov is not."""
+    wl = np.array([1.0, 3.0, 0.2, -0.1, 1.0])   # c ~ 1.18, u = 3: supersonic
+    wr = np.array([0.8, 2.8, 0.1, 0.3, 0.7])
+    F = oracle.riemann_flux(wl, wr, 0, "hll", 1.4, 3)
+    assert np.allclose(F, euler_flux(wl, 0, 1.4, 3), rtol=1e-15, atol=0)
+    F = oracle.riemann_flux(wl * [1, -1, 1, 1, 1], wr * [1, -1, 1, 1, 1], 0, "hll", 1.4, 3)
+    assert np.allclose(F, euler_flux(wr * [1, -1, 1, 1, 1], 0, 1.4, 3), rtol=1e-15, atol=0)
+    Fr = oracle.riemann_flux(wl, wr, 0, "rusanov", 1.4, 3)
+    assert not np.allclose(Fr, euler_flux(wl, 0, 1.4, 3), rtol=1e-6)
+
+
+def test_hll_equals_rusanov_for_symmetric_speeds():
+    """For mirror states (normal velocity of opposite sign, all else equal)
+    the Einfeldt speeds are -a and +a, and HLL reduces to Rusanov:
+    (a FL + a FR - a^2 (UR - UL)) / 2a = (FL + FR)/2 - a (UR - UL)/2."""
+    rng = np.random.default_rng(9)
+    for _ in range(20):
+        w = random_prim(rng, 3)
+        m = w.copy()
+        m[1] = -m[1]
+        Fh = oracle.riemann_flux(w, m, 0, "hll", 1.4, 3)
+        Fr = oracle.riemann_flux(w, m, 0, "rusanov", 1.4, 3)
+        assert np.allclose(Fh, Fr, rtol=1e-13, atol=1e-13)
+
+
+def test_hll_satisfies_the_integral_consistency():
+    """The HLL flux for a subsonic face is the flux of the intermediate state
+    U* = (sR UR - sL UL - (FR - FL)) / (sR - sL) through the Rankine-Hugoniot
+    relations across both outer waves: F* = FL + sL (U* - UL) = FR + sR (U* - UR)."""
+    rng = np.random.default_rng(21)
+    gamma = 1.4
+    for _ in range(20):
+        wl, wr = random_prim(rng, 3), random_prim(rng, 3)
+        wl[1], wr[1] = 0.3 * wl[1], 0.3 * wr[1]
+        F = oracle.riemann_flux(wl, wr, 0, "hll", gamma, 3)
+        UL, UR = euler_state(wl, gamma, 3), euler_state(wr, gamma, 3)
+        FL, FR = euler_flux(wl, 0, gamma, 3), euler_flux(wr, 0, gamma, 3)
+        # Einfeldt speeds (Toro, eq. 10.52) retyped for the identity only
+        sl, sr = math.sqrt(wl[0]), math.sqrt(wr[0])
+        ub = (sl * wl[1] + sr * wr[1]) / (sl + sr)
+        d2 = (sl * gamma * wl[4] / wl[0] + sr * gamma * wr[4] / wr[0]) / (sl + sr) \
+            + 0.5 * sl * sr / (sl + sr) ** 2 * (wr[1] - wl[1]) ** 2
+        SL, SR = ub - math.sqrt(d2), ub + math.sqrt(d2)
+        assert SL < 0 < SR
+        Us = (SR * UR - SL * UL - (FR - FL)) / (SR - SL)
+        assert np.allclose(F, FL + SL * (Us - UL), rtol=1e-12, atol=1e-12)
+        assert np.allclose(F, FR + SR * (Us - UR), rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------ schemes on a mesh
+
+@pytest.mark.parametrize("lim,flux", SCHEMES, ids=SCHEME_IDS)
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_uniform_state_preserved_bitwise(ndim, lim, flux):
+    m = two_level(ndim, limiter=lim, flux=flux)
+    set_uniform(m, [1.3, 0.2, -0.1, 0.3, 2.7] if ndim == 3 else [1.3, 0.2, -0.1, 2.7])
+    u0 = m.interior().copy()
+    m.step(3)
+    assert np.array_equal(m.interior(), u0)
+
+
+@pytest.mark.parametrize("lim,flux", SCHEMES, ids=SCHEME_IDS)
+def test_two_level_conservation(lim, flux):
+    m = two_level(3, limiter=lim, flux=flux)
+    xc = m.forest.cell_centres(m.N, m.tree_size)
+    rho = 1 + 0.3 * np.sin(2 * np.pi * xc[:, 0]) * np.cos(2 * np.pi * xc[:, 1])
+    vel = [0.4 * np.cos(2 * np.pi * xc[:, 1]), 0.3 * np.sin(2 * np.pi * xc[:, 0]), 0.2 * np.sin(2 * np.pi * xc[:, 2])]
+    m.interior()[...] = np.moveaxis(synth.conserved_from_primitive(rho, vel, 1.0 + 0.2 * rho, 1.4), 0, 1)
+    t0 = m.totals()
+    vol = np.array([(m.tree_size / (m.N << l)) ** 3 for l in m.level])
+    scale = np.abs(m.interior()).reshape(m.nb, m.nvar, -1).sum(-1).T @ vol
+    m.step(4)
+    assert np.all(np.abs(m.totals() - t0) <= 1e-13 * scale)
+
+
+def sod_error(nx, lim, flux):
+    w = synth.mirrored_sod(nx, block=16, ndim=2)
+    m = OracleMesh(2, w["trees"], w["N"], 2, w["tree_size"], gamma=w["gamma"], cfl=w["cfl"],
+                   limiter=lim, flux=flux)
+    m.set_interior_from_field(w["field"])
+    t_end = 0.1
+    while m.t < t_end - 1e-15:
+        dt = m.dt()
+        if m.t + dt > t_end:
+            m.cfl = m._c.cfl = 0.5 * (t_end - m.t) / dt
+        m.step(1)
+    xc = m.forest.cell_centres(m.N, m.tree_size)[:, 0]
+    s = np.where(xc < 0.5, 0.25 - xc, xc - 0.75)
+    rho_ex, _, _ = sample(s / t_end, 1.0, 0.0, 1.0, 0.125, 0.0, 0.1)
+    rows = m.interior()[:, 0]
+    return np.sum(np.abs(rows - rho_ex)) / (m.nb * m.N ** 2)
+
+
+@pytest.mark.parametrize("lim,flux", SCHEMES[1:], ids=SCHEME_IDS[1:])
+def test_sod_converges_to_exact_solution(lim, flux):
+    """Every scheme converges to the exact Riemann solution of the mirrored
+    Sod tube; van Leer (less clipping) and HLL (less dissipation at the
+    contact) are each no less accurate than minmod with Rusanov."""
+    e = [sod_error(n, lim, flux) for n in (128, 256, 512)]
+    orders = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert e[0] < 0.02 and all(o >= 0.6 for o in orders), (e, orders)
+    assert e[1] <= sod_error(256, "minmod", "rusanov") * 1.0001
+
+
+def smooth_wave_errors(lim, flux):
+    errs = []
+    for nx in (32, 64, 128):
+        nt = nx // 8
+        m = OracleMesh(2, (nt, 1, 1), 8, 2, 1.0 / nt, gamma=1.4, cfl=0.4, limiter=lim, flux=flux)
+
+        def field(x, y):
+            rho = 1 + 0.2 * np.sin(2 * np.pi * x)
+            one = np.ones_like(x)
+            return synth.conserved_from_primitive(rho, [one, 0 * one], one, 1.4)
+
+        m.set_interior_from_field(field)
+        t_end = 0.25
+        while m.t < t_end - 1e-15:
+            dt = m.dt()
+            if m.t + dt > t_end:
+                m.cfl = m._c.cfl = 0.4 * (t_end - m.t) / dt
+            m.step(1)
+        xc = m.forest.cell_centres(m.N, m.tree_size)[:, 0]
+        dx = 1.0 / nx
+        exact = 1 + 0.2 * (np.cos(2 * np.pi * (xc - t_end - dx / 2)) - np.cos(2 * np.pi * (xc - t_end + dx / 2))) / (2 * np.pi * dx)
+        errs.append(np.mean(np.abs(m.interior()[:, 0] - exact)))
+    return errs
+
+
+@pytest.mark.parametrize("flux", ["rusanov", "hll"])
+def test_vanleer_smooth_wave_second_order(flux):
+    """A density wave advected at uniform v and p (exact solution rho(x - vt)):
+    with van Leer and Heun the L1 error falls at about second order (Sec. 4.1
+    reports close to 2 for this pairing), and below minmod's."""
+    e = smooth_wave_errors("vanleer", flux)
+    orders = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert all(o >= 1.8 for o in orders), (e, orders)
+    em = smooth_wave_errors("minmod", flux)
+    assert all(a < b for a, b in zip(e, em)), (e, em)
+
+
+# ------------------------------------------------------------------ gravity
+
+@pytest.mark.parametrize("lim,flux", SCHEMES, ids=SCHEME_IDS)
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_gravity_on_a_uniform_state_closed_form(ndim, lim, flux):
+    """A uniform state in a uniform field g stays uniform (every face flux
+    cancels) and follows the ODE rho' = 0, m' = rho g, E' = g.m, whose exact
+    solution m = m0 + rho g t, E = E0 + g.m0 t + rho |g|^2 t^2 / 2 Heun's
+    method reproduces for any sequence of steps (the solution is quadratic)."""
+    g = (0.3, -0.5, -1.0)[:ndim] if ndim == 3 else (0.3, -1.0)
+    m = two_level(ndim, limiter=lim, flux=flux, gravity=g, gamma=5.0 / 3.0)
+    rho, v, p = 1.3, np.array([0.4, -0.2, 0.1][:ndim]), 2.0
+    m0 = rho * v
+    E0 = p / (2.0 / 3.0) + 0.5 * rho * v @ v
+    set_uniform(m, [rho, *m0, E0])
+    m.step(6)
+    t = m.t
+    gv = np.array(g)
+    expect = [rho, *(m0 + rho * gv * t), E0 + gv @ m0 * t + 0.5 * rho * (gv @ gv) * t * t]
+    U = m.interior()
+    for k, e in enumerate(expect):
+        assert np.allclose(U[:, k], e, rtol=2e-14, atol=2e-14), (k, float(U[:, k].ravel()[0]), e)
+
+
+@pytest.mark.parametrize("lim,flux", [("vanleer", "rusanov"), ("minmod", "hll")])
+def test_gravity_budget_on_two_levels(lim, flux):
+    """On a periodic two-level mesh the fluxes (with flux fixing) cancel in
+    the totals, so one Heun step changes them by the source alone:
+    M' = M, P' = P + g M dt, E' = E + dt g.P + dt^2 |g|^2 M / 2."""
+    g = np.array([0.2, 0.0, -1.0])
+    m = two_level(3, limiter=lim, flux=flux, gravity=tuple(g), gamma=5.0 / 3.0)
+    xc = m.forest.cell_centres(m.N, m.tree_size)
+    rho = 1 + 0.4 * np.sin(2 * np.pi * xc[:, 0]) * np.cos(2 * np.pi * xc[:, 2])
+    vel = [0.3 * np.cos(2 * np.pi * xc[:, 1]), 0.2 * np.sin(2 * np.pi * xc[:, 2]), -0.25 * np.sin(2 * np.pi * xc[:, 0])]
+    m.interior()[...] = np.moveaxis(synth.conserved_from_primitive(rho, vel, 1.5 + 0.3 * rho, 5.0 / 3.0), 0, 1)
+    for _ in range(3):
+        M, P1, P2, P3, E = m.totals()
+        P = np.array([P1, P2, P3])
+        dt = m.step(1)[0]
+        t = m.totals()
+        assert t[0] == pytest.approx(M, rel=1e-14)
+        assert np.allclose(t[1:4], P + g * M * dt, rtol=0, atol=1e-14 * (np.abs(P).max() + M))
+        assert t[4] == pytest.approx(E + dt * g @ P + 0.5 * dt * dt * (g @ g) * M, rel=1e-14)
