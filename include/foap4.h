@@ -57,6 +57,14 @@ typedef enum {
 
 typedef enum { FOAP4_F32 = 0, FOAP4_F64 = 1 } foap4_prec;
 typedef enum { FOAP4_IND_LOHNER = 0, FOAP4_IND_MLP = 1 } foap4_indicator;
+/* Slope limiter of the primitive reconstruction and numerical flux of the
+ * stage (Sec. 3.2): minmod = the generalized minmod of eq. gminmod with
+ * theta = 1; van Leer = the harmonic mean 2ab/(a+b) of the one-sided slopes
+ * a, b when they share a strict sign, else 0.  Rusanov = local Lax-Friedrichs
+ * with the largest Einfeldt speed; HLL = Harten-Lax-van Leer with the
+ * Einfeldt speeds u_bar -+ d_bar as the slowest and fastest signals. */
+typedef enum { FOAP4_LIM_MINMOD = 0, FOAP4_LIM_VANLEER = 1 } foap4_limiter;
+typedef enum { FOAP4_FLUX_RUSANOV = 0, FOAP4_FLUX_HLL = 1 } foap4_flux;
 
 /* Mesh descriptor.  A brick of n_trees[0] x n_trees[1] (x n_trees[2]) trees
  * (the paper's p4est brick, Sec. 2.2), all periodic; cubic cells with
@@ -76,6 +84,13 @@ typedef struct {
   foap4_prec prec;     /* element type of the state buffers                          */
   double gamma;        /* ratio of specific heats (Sec. 3.5)                          */
   double cfl;          /* CFL number of the time step                                 */
+  foap4_limiter limiter; /* reconstruction limiter (zero-initialised: minmod)         */
+  foap4_flux flux;     /* numerical flux (zero-initialised: Rusanov)                  */
+  double gravity[3];   /* uniform gravitational acceleration g (Sec. 4.2): the stage
+                          adds the source S = (0, rho g, rho g.u) of each cell's own
+                          state to its right-hand side; all zero (the default): no
+                          source.  gravity[2] is ignored in 2D.  The time step stays
+                          the wave-speed CFL limit. */
 } foap4_mesh_desc;
 
 /* Creates a mesh at the uniform level desc->init_level (Sec. 2.2) and its
@@ -278,7 +293,9 @@ foap4_status foap4_mlp_train(foap4_mlp *net, const float *feat_dev, const int8_t
  * Many independent meshes of one precision advanced together: one
  * persistent launch per stage over the concatenated (mesh, block tile,
  * k-slab) work items of all meshes, one launch per ghost round, steps
- * captured once in a HIP graph and replayed.  Each mesh keeps its own dt. */
+ * captured once in a HIP graph and replayed.  Each mesh keeps its own dt.
+ * The meshes must share ndim, precision, limiter, flux and whether gravity
+ * is on (its value may differ); FOAP4_E_INVALID otherwise. */
 foap4_status foap4_batch_create(foap4_mesh *const *meshes, int32_t n_meshes, foap4_batch **out);
 foap4_status foap4_batch_destroy(foap4_batch *batch);
 

@@ -31,7 +31,12 @@ class MeshDesc(ctypes.Structure):
                 ("origin", ctypes.c_double * 3), ("tree_size", ctypes.c_double), ("block_n", ctypes.c_int32),
                 ("n_ghost", ctypes.c_int32), ("init_level", ctypes.c_int32), ("min_level", ctypes.c_int32),
                 ("max_level", ctypes.c_int32), ("max_blocks", ctypes.c_int64), ("prec", ctypes.c_int32),
-                ("gamma", ctypes.c_double), ("cfl", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("limiter", ctypes.c_int32),
+                ("flux", ctypes.c_int32), ("gravity", ctypes.c_double * 3)]
+
+# stage scheme options (include/foap4.h: foap4_limiter, foap4_flux)
+LIMITERS = {"minmod": 0, "vanleer": 1}
+FLUXES = {"rusanov": 0, "hll": 1}
 
 
 _lib = None
@@ -115,7 +120,7 @@ class Mesh:
 
     def __init__(self, ndim, trees, N, g=2, tree_size=1.0, level=0, min_level=0, max_level=None,
                  max_blocks=None, prec=F64, gamma=1.4, cfl=0.5, origin=(0.0, 0.0, 0.0), device="cuda",
-                 stream=None):
+                 stream=None, limiter="minmod", flux="rusanov", gravity=(0.0, 0.0, 0.0)):
         torch = _torch()
         self.ndim, self.N, self.g = ndim, N, g
         self.nvar = ndim + 2
@@ -144,6 +149,9 @@ class Mesh:
         d.prec = prec
         d.gamma = gamma
         d.cfl = cfl
+        d.limiter = LIMITERS[limiter]
+        d.flux = FLUXES[flux]
+        d.gravity[:] = [float(x) for x in gravity] + [0.0] * (3 - len(gravity))
         self.desc = d
         shape = (self.max_blocks, self.nvar, self.P ** ndim)  # row part, then x ghosts (include/foap4.h)
         self.state = [torch.zeros(shape, dtype=self.dtype, device=device),

@@ -44,6 +44,7 @@ MeshDev make_dev(const foap4_mesh *m, int ks, int gather) {
   d.dx0 = m->d.tree_size / m->d.block_n;
   d.gamma = m->d.gamma;
   d.cfl = m->d.cfl;
+  for (int a = 0; a < 3; a++) d.grav[a] = (a < m->d.ndim) ? m->d.gravity[a] : 0.0;
   for (int t = 0; t < kTypes; t++) {
     d.pn[t] = m->pat.n[t];
     for (int f = 0; f < 7; f++) d.poff[t][f] = m->pat.off[t][f];
@@ -124,6 +125,7 @@ struct foap4_batch {
   MeshDev *d_devs = nullptr;
   int64_t total_items = 0, r1_total = 0, r2_total = 0;
   int nmask = 0;
+  int scheme = 0;  // scheme_of() shared by all meshes
   hipStream_t stream = nullptr, cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -160,6 +162,12 @@ foap4_status foap4_mesh_create(const foap4_mesh_desc *desc, void *state0, void *
     return fail(nullptr, FOAP4_E_INVALID, "levels must satisfy 0 <= min <= max <= 14, init <= max");
   if (!(d.tree_size > 0) || !(d.gamma > 1) || !(d.cfl > 0)) return fail(nullptr, FOAP4_E_INVALID, "tree_size, gamma, cfl");
   if (d.prec != FOAP4_F32 && d.prec != FOAP4_F64) return fail(nullptr, FOAP4_E_INVALID, "prec");
+  if (d.limiter != FOAP4_LIM_MINMOD && d.limiter != FOAP4_LIM_VANLEER)
+    return fail(nullptr, FOAP4_E_INVALID, "limiter must be minmod or van Leer");
+  if (d.flux != FOAP4_FLUX_RUSANOV && d.flux != FOAP4_FLUX_HLL)
+    return fail(nullptr, FOAP4_E_INVALID, "flux must be Rusanov or HLL");
+  for (int a = 0; a < 3; a++)
+    if (!std::isfinite(d.gravity[a])) return fail(nullptr, FOAP4_E_INVALID, "gravity must be finite");
   if (!state0 || !state1 || state0 == state1) return fail(nullptr, FOAP4_E_INVALID, "two distinct state buffers needed");
   if ((((uintptr_t)state0) | ((uintptr_t)state1)) & 15u)
     return fail(nullptr, FOAP4_E_INVALID, "state buffers must be 16-byte aligned");
@@ -302,13 +310,16 @@ foap4_status foap4_step(foap4_mesh *m, int32_t n_steps, double *t_out, double *d
     if (capture && s == n_steps - 1) {
       // last step: stage 1 also reduces the features of its input state
       F4_HIP(m, hipMemsetAsync(m->d_featcap, 0, nb * 16, m->stream));
-      F4_HIP(m, launch_stage1_features(m->d_dev, items, ndim, f64, nmask_of(m->d.block_n), m->d_featcap, m->stream));
+      F4_HIP(m, launch_stage1_features(m->d_dev, items, ndim, f64, nmask_of(m->d.block_n), m->d_featcap, m->stream,
+                                       scheme_of(m->d)));
     } else {
-      F4_HIP(m, launch_stage(m->d_dev, 1, items, 1, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n)));
+      F4_HIP(m, launch_stage(m->d_dev, 1, items, 1, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n),
+                             scheme_of(m->d)));
     }
     F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, 1, m->stream));
     if ((st = fill(m, m->d_dev, 1)) != FOAP4_OK) return st;
-    F4_HIP(m, launch_stage(m->d_dev, 1, items, 2, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n)));
+    F4_HIP(m, launch_stage(m->d_dev, 1, items, 2, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n),
+                           scheme_of(m->d)));
     F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, 2, m->stream));
     F4_HIP(m, launch_finalize(m->d_dev, 1, 1, m->stream));
   }
@@ -568,7 +579,9 @@ static hipError_t batch_enqueue_step(foap4_batch *b, hipStream_t s) {
     if ((e = launch_ghost(b->d_devs, n, b->r1_total, 1, which, b->ndim, b->f64, 0, s)) != hipSuccess) return e;
     if (b->r2_total && (e = launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s)) != hipSuccess)
       return e;
-    if ((e = launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, grid, s, b->xcd, b->nmask)) != hipSuccess) return e;
+    if ((e = launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, grid, s, b->xcd, b->nmask,
+                          b->scheme)) != hipSuccess)
+      return e;
     for (int i = 0; i < n; i++)
       if (b->meshes[i]->pat.n_fix > 0 &&
           (e = launch_fluxfix(b->d_devs + i, b->ndim, b->f64, b->meshes[i]->pat.n_fix, stage, s)) != hipSuccess)
@@ -620,10 +633,14 @@ foap4_status foap4_batch_create(foap4_mesh *const *meshes, int32_t n, foap4_batc
   }
   b->ndim = meshes[0]->d.ndim;
   b->f64 = meshes[0]->d.prec == FOAP4_F64;
+  b->scheme = scheme_of(meshes[0]->d);
   for (foap4_mesh *m : b->meshes)
     if (m->d.ndim != b->ndim || (m->d.prec == FOAP4_F64) != b->f64) {
       delete b;
       return fail(nullptr, FOAP4_E_INVALID, "batch meshes must share ndim and precision");
+    } else if (scheme_of(m->d) != b->scheme) {
+      delete b;
+      return fail(nullptr, FOAP4_E_INVALID, "batch meshes must share limiter, flux and gravity on/off");
     }
   b->stream = meshes[0]->stream;
   int dev = 0;
@@ -696,7 +713,7 @@ foap4_status foap4_batch_phase_times(foap4_batch *b, int32_t n_steps, double *ou
       if (b->r2_total) B_HIP(b, launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s));
       B_HIP(b, hipEventRecord(ev[++k], s));
       B_HIP(b, launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, stage_grid(b, stage), s, b->xcd,
-                            b->nmask));
+                            b->nmask, b->scheme));
       B_HIP(b, hipEventRecord(ev[++k], s));
       for (int i = 0; i < n; i++)
         if (b->meshes[i]->pat.n_fix > 0)

@@ -67,18 +67,40 @@ __device__ __forceinline__ void to_prim(const T *U, T gamma, T *W) {
   W[NDIM + 1] = (gamma - T(1)) * (U[NDIM + 1] - T(0.5) * ke);
 }
 
-// Rusanov flux (Sec. 3.2) along axis AX between reconstructed primitive
-// states WL and WR, with the largest Einfeldt wave speed (Sec. 3.5):
-// sqrt(rho)-weighted mean velocity u_bar and
-// d_bar^2 = (sL cL^2 + sR cR^2)/(sL + sR) + sL sR/(2 (sL+sR)^2) (vR - vL)^2;
-// a = max(|u_bar - d_bar|, |u_bar + d_bar|), F = (FL+FR)/2 - a (UR-UL)/2.
-template <typename T, int NDIM, int AX>
-__device__ __forceinline__ void rusanov(const T *WL, const T *WR, T gamma, T *F) {
+// van Leer limiter (Sec. 3.2 limiter list): the harmonic mean 2ab/(a+b) of
+// the one-sided slopes when their product is positive, else zero.
+template <typename T>
+__device__ __forceinline__ T vanleer(T a, T b) {
+  const T ab = a * b;
+  return ab > T(0) ? fdiv(T(2) * ab, a + b) : T(0);
+}
+
+// Slope of the reconstruction: LIM 0 minmod, 1 van Leer.
+template <int LIM, typename T>
+__device__ __forceinline__ T limit(T a, T b) {
+  if constexpr (LIM == 1) return vanleer(a, b);
+  else return minmod(a, b);
+}
+
+// Numerical flux (Sec. 3.2) along axis AX between reconstructed primitive
+// states WL and WR from the Einfeldt speeds (Sec. 3.5): sqrt(rho)-weighted
+// mean velocity u_bar and
+// d_bar^2 = (sL cL^2 + sR cR^2)/(sL + sR) + sL sR/(2 (sL+sR)^2) (vR - vL)^2.
+// Rusanov (HLL false): a = max(|u_bar - d_bar|, |u_bar + d_bar|),
+//   F = (FL+FR)/2 - a (UR-UL)/2.
+// HLL: with s0 = min(u_bar - d_bar, 0), s1 = max(u_bar + d_bar, 0),
+//   F = (s1 FL - s0 FR + s0 s1 (UR - UL)) / (s1 - s0), which is FL when every
+//   signal moves right (s0 = 0), FR when every signal moves left (s1 = 0),
+//   and the HLL intermediate-state flux otherwise.
+// Both are evaluated as al UL + ar UR + wl PL + wr PR with the pressure terms
+// P = (0, p e_AX, p v_AX) of each side.
+template <typename T, int NDIM, int AX, bool HLL = false>
+__device__ __forceinline__ void riemann(const T *WL, const T *WR, T gamma, T *F) {
   constexpr int NV = NDIM + 2;
   const T rl = WL[0], rr = WR[0];
   const T pl = WL[NV - 1], pr = WR[NV - 1];
   const T vl = WL[1 + AX], vr = WR[1 + AX];
-  // wave speed first, so the per-component flux needs few live registers
+  // wave speeds first, so the per-component flux needs few live registers
   T sl, sr, irl, irr;
   sqrt_and_rcp(rl, sl, irl);
   sqrt_and_rcp(rr, sr, irr);
@@ -89,42 +111,63 @@ __device__ __forceinline__ void rusanov(const T *WL, const T *WR, T gamma, T *F)
   const T dv = vr - vl;
   const T d2 = (sl * cl2 + sr * cr2) * is + eta2 * dv * dv;
   const T db = fsqrt(d2);
-  const T lm = fabs(ubar - db), lp = fabs(ubar + db);
-  const T ha = T(0.5) * (lm > lp ? lm : lp);
-  // (F_L + F_R)/2 - ha (U_R - U_L) with F = U v_n + pressure terms, grouped
-  // per side: al U_L + ar U_R + pressure terms, al = vl/2 + ha, ar = vr/2 - ha
-  const T al = T(0.5) * vl + ha, ar = T(0.5) * vr - ha;
+  T al, ar, wl, wr;
+  if constexpr (!HLL) {
+    const T lm = fabs(ubar - db), lp = fabs(ubar + db);
+    const T ha = T(0.5) * (lm > lp ? lm : lp);
+    // (F_L + F_R)/2 - ha (U_R - U_L) with F = U v_n + pressure terms:
+    // al = vl/2 + ha, ar = vr/2 - ha, both pressure weights 1/2
+    al = T(0.5) * vl + ha;
+    ar = T(0.5) * vr - ha;
+    wl = wr = T(0.5);
+  } else {
+    const T m0 = ubar - db, m1 = ubar + db;
+    const T s0 = m0 < T(0) ? m0 : T(0), s1 = m1 > T(0) ? m1 : T(0);
+    const T iD = frcp(s1 - s0);
+    wl = s1 * iD;
+    wr = -s0 * iD;
+    al = wl * (vl - s0);
+    ar = wr * (vr - s1);
+  }
   F[0] = al * rl + ar * rr;
   T kel = T(0), ker = T(0);
 #pragma unroll
   for (int d = 0; d < NDIM; d++) {
     const T ml = rl * WL[1 + d], mr = rr * WR[1 + d];
     F[1 + d] = al * ml + ar * mr;
-    if (d == AX) F[1 + d] += T(0.5) * (pl + pr);
+    if (d == AX) {
+      if constexpr (!HLL) F[1 + d] += T(0.5) * (pl + pr);
+      else F[1 + d] += wl * pl + wr * pr;
+    }
     kel += ml * WL[1 + d];
     ker += mr * WR[1 + d];
   }
   const T igm1 = frcp(gamma - T(1));
   const T El = pl * igm1 + T(0.5) * kel;
   const T Er = pr * igm1 + T(0.5) * ker;
-  F[NV - 1] = al * El + ar * Er + T(0.5) * (pl * vl + pr * vr);
+  if constexpr (!HLL) F[NV - 1] = al * El + ar * Er + T(0.5) * (pl * vl + pr * vr);
+  else F[NV - 1] = al * El + ar * Er + (wl * pl * vl + wr * pr * vr);
 }
 
-// Face flux from four primitive states along the face normal: minmod-limited
+// Scheme of a stage kernel, a bit mask: limiter (bit 0: van Leer, else
+// minmod), flux (bit 1: HLL, else Rusanov), gravity source (bit 2).
+constexpr int kSchVanLeer = 1, kSchHLL = 2, kSchGravity = 4, kNSchemes = 8;
+
+// Face flux from four primitive states along the face normal: limited
 // linear reconstruction (Sec. 3.2) W_L = W1 + s1/2, W_R = W2 - s2/2.
-template <typename T, int NDIM, int AX>
+template <typename T, int NDIM, int AX, int SCH = 0>
 __device__ __forceinline__ void face_flux(const T *W0, const T *W1, const T *W2, const T *W3, T gamma,
                                           T *F) {
   constexpr int NV = NDIM + 2;
   T L[NV], R[NV];
 #pragma unroll
   for (int v = 0; v < NV; v++) {
-    const T s1 = minmod(W1[v] - W0[v], W2[v] - W1[v]);
-    const T s2 = minmod(W2[v] - W1[v], W3[v] - W2[v]);
+    const T s1 = limit<SCH & kSchVanLeer>(W1[v] - W0[v], W2[v] - W1[v]);
+    const T s2 = limit<SCH & kSchVanLeer>(W2[v] - W1[v], W3[v] - W2[v]);
     L[v] = W1[v] + T(0.5) * s1;
     R[v] = W2[v] - T(0.5) * s2;
   }
-  rusanov<T, NDIM, AX>(L, R, gamma, F);
+  riemann<T, NDIM, AX, (SCH & kSchHLL) != 0>(L, R, gamma, F);
 }
 
 // Atomic max of a non-negative double through its bit pattern (IEEE order of

@@ -96,6 +96,7 @@ struct MeshDev {
   int64_t r1_begin, r2_begin; // first ghost record of this mesh in R1 / R2 launches
   double dx0;                 // cell width at level 0
   double gamma, cfl;
+  double grav[3];             // gravitational acceleration (source term on)
   int32_t pn[4];              // record totals per type
   int32_t poff[4][7];         // CSR offsets per type and face
   int32_t n_fix;
@@ -199,13 +200,19 @@ hipError_t launch_ghost(const MeshDev *d_meshes, int n_meshes, int64_t total, in
                         int ndim, bool f64, int grid, hipStream_t s);
 // stage.hip
 int64_t stage_items_for(int ndim, int N, int64_t nb, int ks);
-// nmask: block sizes present in the launch (1: N = 8, 2: N = 16, 4: N = 32)
+// nmask: block sizes present in the launch (1: N = 8, 2: N = 16, 4: N = 32);
+// scheme: scheme_of() of the meshes in the launch
 hipError_t launch_stage(const MeshDev *d_meshes, int n_meshes, int64_t total_items, int stage,
-                        int ndim, bool f64, int grid, hipStream_t s, int xcd, int nmask);
+                        int ndim, bool f64, int grid, hipStream_t s, int xcd, int nmask, int scheme);
 // stage 1 of one mesh that also reduces the raw features of its input state
 // (feat_raw [nb][2], zeroed by the caller) by atomic maxima
 hipError_t launch_stage1_features(const MeshDev *d_mesh, int64_t total_items, int ndim, bool f64, int nmask,
-                                  double *feat_raw, hipStream_t s);
+                                  double *feat_raw, hipStream_t s, int scheme);
+// scheme bit mask of a mesh: 1 van Leer limiter, 2 HLL flux, 4 gravity source
+inline int scheme_of(const foap4_mesh_desc &d) {
+  const bool grav = d.gravity[0] != 0.0 || d.gravity[1] != 0.0 || (d.ndim == 3 && d.gravity[2] != 0.0);
+  return (d.limiter == FOAP4_LIM_VANLEER ? 1 : 0) | (d.flux == FOAP4_FLUX_HLL ? 2 : 0) | (grav ? 4 : 0);
+}
 inline int nmask_of(int N) { return N == 8 ? 1 : (N == 16 ? 2 : 4); }
 // reduce.hip
 hipError_t launch_dt_full(const foap4_mesh *m, hipStream_t s);

@@ -16,7 +16,10 @@
 // its maximum in FP64.  Items can be visited in an XCD-aware order:
 // workgroup w runs on XCD w mod 8, so each XCD is given a contiguous range of
 // items (neighbouring blocks in Morton order then share that XCD's L2).
-// The kernel is specialised on the set of block sizes present in a launch.
+// The kernel is specialised on the set of block sizes present in a launch and
+// on the scheme (limiter, flux, gravity source).  This file is compiled once
+// per scheme with F4_SCHEME set to that scheme's bit mask; the compile with
+// F4_SCHEME = 0 also holds the dispatcher over all schemes.
 #include "device_common.h"
 #include "foap4_internal.h"
 
@@ -108,7 +111,7 @@ __device__ __forceinline__ int xy_slot(int v, bool sw) { return (sw && (v == 1 |
 // Flux of one x or y face of the LDS plane Wp ([v][PLANE]) from the four cells
 // base + m * step (m = 0..3) along the face normal; F is in natural variable
 // order.  sw may differ between lanes.
-template <typename T, int NDIM, int PLANE>
+template <typename T, int NDIM, int PLANE, int SCH>
 __device__ __forceinline__ void plane_face(const T *Wp, int base, int step, bool sw, T gamma, T *F) {
   constexpr int NV = NDIM + 2;
   T A0[NV], A1[NV], A2[NV], A3[NV], G[NV];
@@ -120,7 +123,7 @@ __device__ __forceinline__ void plane_face(const T *Wp, int base, int step, bool
     A2[v] = p[2 * step];
     A3[v] = p[3 * step];
   }
-  face_flux<T, NDIM, 0>(A0, A1, A2, A3, gamma, G);
+  face_flux<T, NDIM, 0, SCH>(A0, A1, A2, A3, gamma, G);
 #pragma unroll
   for (int v = 0; v < NV; v++) F[v] = (v == 1) ? (sw ? G[2] : G[1]) : (v == 2) ? (sw ? G[1] : G[2]) : G[v];
 }
@@ -129,7 +132,7 @@ __device__ __forceinline__ void plane_face(const T *Wp, int base, int step, bool
 // r1 = max |grad p| / p over the interior cells of the stage's input state
 // (undivided central differences, squares summed x, y, z) into feat_raw[b][2]
 // by an atomic maximum; the primitive planes are already in LDS.
-template <typename T, int NDIM, int N, bool FEAT = false>
+template <typename T, int NDIM, int N, int SCH, bool FEAT = false>
 __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t local, T *smem,
                                            double &vmax, bool &bad, double *feat_raw = nullptr) {
   using C = TileCfg<N>;
@@ -166,6 +169,11 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   const T idx = (T)(1.0 / dx);
   const double dt = gload(M.scal + kDt);
   const T dts = (T)(stage == 1 ? dt : 0.5 * dt);
+  [[maybe_unused]] T grav[NDIM];
+  if constexpr ((SCH & kSchGravity) != 0) {
+#pragma unroll
+    for (int d = 0; d < NDIM; d++) grav[d] = (T)M.grav[d];
+  }
 
   // per face: refinement-face flux slot (>= 0), same-level neighbour (-2 - n) or -1
   int finfo[NF];
@@ -312,12 +320,12 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     T L[NV], Rt[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-      const T s1 = minmod(Wm1[v] - Wm2[v], W0[v] - Wm1[v]);
-      Sk[v] = minmod(W0[v] - Wm1[v], W1[v] - W0[v]);
+      const T s1 = limit<SCH & kSchVanLeer>(Wm1[v] - Wm2[v], W0[v] - Wm1[v]);
+      Sk[v] = limit<SCH & kSchVanLeer>(W0[v] - Wm1[v], W1[v] - W0[v]);
       L[v] = Wm1[v] + T(0.5) * s1;
       Rt[v] = W0[v] - T(0.5) * Sk[v];
     }
-    rusanov<T, NDIM, 2>(L, Rt, gamma, Fz);
+    riemann<T, NDIM, 2, (SCH & kSchHLL) != 0>(L, Rt, gamma, Fz);
     if (k0 == 0) store_bflux(4, I, J, Fz);
     if constexpr (FEAT) {
       zr = Wm1[0];
@@ -379,12 +387,12 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
 #pragma unroll
       for (int v = 0; v < NV; v++) {
         const T w0 = A[v * PLANE], w1 = B[v * PLANE], w2 = Cc[v * PLANE];
-        const T sn = minmod(w1 - w0, w2 - w1);
+        const T sn = limit<SCH & kSchVanLeer>(w1 - w0, w2 - w1);
         L[v] = w0 + T(0.5) * Sk[v];
         Rt[v] = w1 - T(0.5) * sn;
         Sk[v] = sn;
       }
-      rusanov<T, NDIM, 2>(L, Rt, gamma, Fz1);
+      riemann<T, NDIM, 2, (SCH & kSchHLL) != 0>(L, Rt, gamma, Fz1);
       if (k == N - 1) store_bflux(5, I, J, Fz1);
     }
 
@@ -396,11 +404,11 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     // plane (pair) so that every SIMD gets its share.
     {
       T F[NV];
-      plane_face<T, NDIM, PLANE>(Wp, (tj + 2) * LP + ti, 1, false, gamma, F);  // cells ti-2 .. ti+1
+      plane_face<T, NDIM, PLANE, SCH>(Wp, (tj + 2) * LP + ti, 1, false, gamma, F);  // cells ti-2 .. ti+1
 #pragma unroll
       for (int v = 0; v < NV; v++) FX[v * NFX + tj * (TILE + 1) + ti] = F[v];
       if (ti == 0 && i0 == 0) store_bflux(0, j0 + tj, k, F);
-      plane_face<T, NDIM, PLANE>(Wp, tj * LP + ti + 2, LP, true, gamma, F);  // cells tj-2 .. tj+1
+      plane_face<T, NDIM, PLANE, SCH>(Wp, tj * LP + ti + 2, LP, true, gamma, F);  // cells tj-2 .. tj+1
 #pragma unroll
       for (int v = 0; v < NV; v++) FY[v * NFX + tj * TILE + ti] = F[v];
       if (tj == 0 && j0 == 0) store_bflux(2, i0 + ti, k, F);
@@ -423,7 +431,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
           const int m = sw ? ee - TILE : ee;
           if (pk == 0 || k + 1 < k1) {
             T F[NV];
-            plane_face<T, NDIM, PLANE>(pk ? slot(k + 1) : Wp, sw ? TILE * LP + m + 2 : (m + 2) * LP + TILE,
+            plane_face<T, NDIM, PLANE, SCH>(pk ? slot(k + 1) : Wp, sw ? TILE * LP + m + 2 : (m + 2) * LP + TILE,
                                        sw ? LP : 1, sw, gamma, F);
             T *out = pk ? XE + ee : (sw ? FY + TILE * TILE + m : FX + m * (TILE + 1) + TILE);
             const int ost = pk ? 2 * TILE : NFX;
@@ -446,7 +454,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
         const bool sw = e >= TILE;
         const int m = sw ? e - TILE : e;
         T F[NV];
-        plane_face<T, NDIM, PLANE>(Wp, sw ? TILE * LP + m + 2 : (m + 2) * LP + TILE, sw ? LP : 1, sw, gamma, F);
+        plane_face<T, NDIM, PLANE, SCH>(Wp, sw ? TILE * LP + m + 2 : (m + 2) * LP + TILE, sw ? LP : 1, sw, gamma, F);
         T *out = sw ? FY + TILE * TILE + m : FX + m * (TILE + 1) + TILE;
 #pragma unroll
         for (int v = 0; v < NV; v++) out[v * NFX] = F[v];
@@ -457,9 +465,21 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     __syncthreads();
 
     // conservative update of the own cell (eq. feuler with Heun weights):
-    // U_out = base - (dt_s / dx) sum_d (F_d(+) - F_d(-))
+    // U_out = base - (dt_s / dx) sum_d (F_d(+) - F_d(-)) [+ dt_s S(U0)]
     T Uout[NV];
     const T cdt = dts * idx;
+    [[maybe_unused]] T src[NV];
+    if constexpr ((SCH & kSchGravity) != 0) {
+      // gravity source of the cell's stage input (Sec. 4.2): (0, rho g, g.m)
+      T gm = T(0);
+      src[0] = T(0);
+#pragma unroll
+      for (int d = 0; d < NDIM; d++) {
+        src[1 + d] = U0[0] * grav[d];
+        gm += grav[d] * U0[1 + d];
+      }
+      src[NV - 1] = gm;
+    }
 #pragma unroll
     for (int v = 0; v < NV; v++) {
       const T dfx = FX[v * NFX + tj * (TILE + 1) + ti + 1] - FX[v * NFX + tj * (TILE + 1) + ti];
@@ -467,7 +487,8 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       T div = dfx + dfy;
       if constexpr (NDIM == 3) div += Fz1[v] - Fz[v];
       const T base = (stage == 1) ? U0[v] : T(0.5) * (Up[v] + U0[v]);
-      Uout[v] = base - cdt * div;
+      if constexpr ((SCH & kSchGravity) != 0) Uout[v] = (base + dts * src[v]) - cdt * div;
+      else Uout[v] = base - cdt * div;
     }
     // a tile's rows are contiguous runs of the block's row part; the tiles
     // of a block together write each interior plane as one contiguous range
@@ -545,7 +566,7 @@ constexpr int stage_waves() { return sizeof(T) == 4 ? (NM != 7 ? 4 : 3) : 1; }
 // NM: bit mask of the block sizes present (1: N = 8, 2: N = 16, 4: N = 32)
 // STG: the Heun stage (compiled separately: stage 1 needs no U^n stream and
 // no dt epilogue, so it runs with fewer registers)
-template <typename T, int NDIM, int NM, int STG>
+template <typename T, int NDIM, int NM, int STG, int SCH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM, STG>())))
 void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t total, int xcd) {
   constexpr int stage = STG;
@@ -569,16 +590,16 @@ void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t tota
     const MeshDev &M = meshes[lo];
     const int64_t local = item - M.item_begin;
     if constexpr (NM == 1) {
-      stage_item<T, NDIM, 8>(M, stage, local, smem, vmax, bad);
+      stage_item<T, NDIM, 8, SCH>(M, stage, local, smem, vmax, bad);
     } else if constexpr (NM == 2) {
-      stage_item<T, NDIM, 16>(M, stage, local, smem, vmax, bad);
+      stage_item<T, NDIM, 16, SCH>(M, stage, local, smem, vmax, bad);
     } else if constexpr (NM == 4) {
-      stage_item<T, NDIM, 32>(M, stage, local, smem, vmax, bad);
+      stage_item<T, NDIM, 32, SCH>(M, stage, local, smem, vmax, bad);
     } else {
       switch (M.N) {
-        case 8: stage_item<T, NDIM, 8>(M, stage, local, smem, vmax, bad); break;
-        case 16: stage_item<T, NDIM, 16>(M, stage, local, smem, vmax, bad); break;
-        default: stage_item<T, NDIM, 32>(M, stage, local, smem, vmax, bad); break;
+        case 8: stage_item<T, NDIM, 8, SCH>(M, stage, local, smem, vmax, bad); break;
+        case 16: stage_item<T, NDIM, 16, SCH>(M, stage, local, smem, vmax, bad); break;
+        default: stage_item<T, NDIM, 32, SCH>(M, stage, local, smem, vmax, bad); break;
       }
     }
     __syncthreads();
@@ -586,6 +607,92 @@ void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t tota
   if (stage == 2 && mprev >= 0) flush_dt(meshes[mprev], vmax, bad);
 }
 
+template <typename T, int NDIM, int SCH>
+static void launch_t(unsigned nblk, int nmask, const MeshDev *d, int n, int64_t total, int stage, int xcd,
+                     hipStream_t s) {
+  switch (nmask) {
+    case 1:
+      if (stage == 1) stage_kernel<T, NDIM, 1, 1, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      else stage_kernel<T, NDIM, 1, 2, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      break;
+    case 2:
+      if (stage == 1) stage_kernel<T, NDIM, 2, 1, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      else stage_kernel<T, NDIM, 2, 2, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      break;
+    case 4:
+      if (stage == 1) stage_kernel<T, NDIM, 4, 1, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      else stage_kernel<T, NDIM, 4, 2, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      break;
+    default:
+      if (stage == 1) stage_kernel<T, NDIM, 7, 1, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      else stage_kernel<T, NDIM, 7, 2, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
+      break;
+  }
+}
+
+// Stage 1 of one mesh (one workgroup per work item) that also reduces the
+// per-block features of its input state into feat_raw (zeroed by the caller).
+template <typename T, int NDIM, int NM, int SCH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM, 1>())))
+void stage1_feat_kernel(const MeshDev *__restrict__ Mp, int64_t total, double *feat_raw) {
+  __shared__ T smem[smem_cells<NDIM, NM>()];
+  constexpr int N = (NM == 1) ? 8 : (NM == 2) ? 16 : 32;
+  double vmax = 0.0;
+  bool bad = false;
+  if ((int64_t)blockIdx.x >= total) return;
+  stage_item<T, NDIM, N, SCH, true>(*Mp, 1, blockIdx.x, smem, vmax, bad, feat_raw);
+}
+
+template <typename T, int NDIM, int SCH>
+static void launch_feat_t(unsigned nblk, int nmask, const MeshDev *d, int64_t total, double *fr, hipStream_t s) {
+  switch (nmask) {
+    case 1: stage1_feat_kernel<T, NDIM, 1, SCH><<<nblk, 256, 0, s>>>(d, total, fr); break;
+    case 2: stage1_feat_kernel<T, NDIM, 2, SCH><<<nblk, 256, 0, s>>>(d, total, fr); break;
+    default: stage1_feat_kernel<T, NDIM, 4, SCH><<<nblk, 256, 0, s>>>(d, total, fr); break;
+  }
+}
+
+// Launchers of one scheme; each compile of this file instantiates those of
+// its own F4_SCHEME.
+template <int SCH>
+hipError_t launch_stage_sch(const MeshDev *d_meshes, int n_meshes, int64_t total_items, int stage, int ndim,
+                            bool f64, int grid, hipStream_t s, int xcd, int nmask) {
+  int64_t nblk = (grid > 0 && grid < total_items) ? grid : total_items;
+  if (xcd == 1) nblk = (nblk + 7) / 8 * 8;  // every XCD gets the same number of workgroups
+  if (f64) {
+    if (ndim == 3) launch_t<double, 3, SCH>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);
+    else launch_t<double, 2, SCH>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);
+  } else {
+    if (ndim == 3) launch_t<float, 3, SCH>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);
+    else launch_t<float, 2, SCH>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);
+  }
+  return hipGetLastError();
+}
+
+template <int SCH>
+hipError_t launch_feat_sch(const MeshDev *d_mesh, int64_t total_items, int ndim, bool f64, int nmask,
+                           double *feat_raw, hipStream_t s) {
+  const unsigned nblk = (unsigned)total_items;
+  if (f64) {
+    if (ndim == 3) launch_feat_t<double, 3, SCH>(nblk, nmask, d_mesh, total_items, feat_raw, s);
+    else launch_feat_t<double, 2, SCH>(nblk, nmask, d_mesh, total_items, feat_raw, s);
+  } else {
+    if (ndim == 3) launch_feat_t<float, 3, SCH>(nblk, nmask, d_mesh, total_items, feat_raw, s);
+    else launch_feat_t<float, 2, SCH>(nblk, nmask, d_mesh, total_items, feat_raw, s);
+  }
+  return hipGetLastError();
+}
+
+#ifndef F4_SCHEME
+#define F4_SCHEME 0
+#endif
+static_assert(F4_SCHEME >= 0 && F4_SCHEME < kNSchemes, "F4_SCHEME is a scheme bit mask");
+
+template hipError_t launch_stage_sch<F4_SCHEME>(const MeshDev *, int, int64_t, int, int, bool, int, hipStream_t,
+                                                int, int);
+template hipError_t launch_feat_sch<F4_SCHEME>(const MeshDev *, int64_t, int, bool, int, double *, hipStream_t);
+
+#if F4_SCHEME == 0
 int64_t stage_items_for(int ndim, int N, int64_t nb, int ks) {
   const int tile = (N == 8) ? 8 : 16;
   const int sub = 256 / (tile * tile);
@@ -594,79 +701,43 @@ int64_t stage_items_for(int ndim, int N, int64_t nb, int ks) {
   return ((tiles + sub - 1) / sub) * (ndim == 3 ? ks : 1);
 }
 
-template <typename T, int NDIM>
-static void launch_t(unsigned nblk, int nmask, const MeshDev *d, int n, int64_t total, int stage, int xcd,
-                     hipStream_t s) {
-  switch (nmask) {
-    case 1:
-      if (stage == 1) stage_kernel<T, NDIM, 1, 1><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      else stage_kernel<T, NDIM, 1, 2><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      break;
-    case 2:
-      if (stage == 1) stage_kernel<T, NDIM, 2, 1><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      else stage_kernel<T, NDIM, 2, 2><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      break;
-    case 4:
-      if (stage == 1) stage_kernel<T, NDIM, 4, 1><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      else stage_kernel<T, NDIM, 4, 2><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      break;
-    default:
-      if (stage == 1) stage_kernel<T, NDIM, 7, 1><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      else stage_kernel<T, NDIM, 7, 2><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      break;
-  }
-}
+// the other schemes' launchers live in the other compiles of this file
+#define F4_EXTERN_SCHEME(S)                                                                                    \
+  extern template hipError_t launch_stage_sch<S>(const MeshDev *, int, int64_t, int, int, bool, int,          \
+                                                 hipStream_t, int, int);                                       \
+  extern template hipError_t launch_feat_sch<S>(const MeshDev *, int64_t, int, bool, int, double *, hipStream_t);
+F4_EXTERN_SCHEME(1)
+F4_EXTERN_SCHEME(2)
+F4_EXTERN_SCHEME(3)
+F4_EXTERN_SCHEME(4)
+F4_EXTERN_SCHEME(5)
+F4_EXTERN_SCHEME(6)
+F4_EXTERN_SCHEME(7)
+#undef F4_EXTERN_SCHEME
 
 hipError_t launch_stage(const MeshDev *d_meshes, int n_meshes, int64_t total_items, int stage,
-                        int ndim, bool f64, int grid, hipStream_t s, int xcd, int nmask) {
+                        int ndim, bool f64, int grid, hipStream_t s, int xcd, int nmask, int scheme) {
   if (total_items <= 0) return hipSuccess;
-  int64_t nblk = (grid > 0 && grid < total_items) ? grid : total_items;
-  if (xcd == 1) nblk = (nblk + 7) / 8 * 8;  // every XCD gets the same number of workgroups
-  if (f64) {
-    if (ndim == 3) launch_t<double, 3>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);
-    else launch_t<double, 2>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);
-  } else {
-    if (ndim == 3) launch_t<float, 3>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);
-    else launch_t<float, 2>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);
-  }
-  return hipGetLastError();
-}
-
-// Stage 1 of one mesh (one workgroup per work item) that also reduces the
-// per-block features of its input state into feat_raw (zeroed by the caller).
-template <typename T, int NDIM, int NM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM, 1>())))
-void stage1_feat_kernel(const MeshDev *__restrict__ Mp, int64_t total, double *feat_raw) {
-  __shared__ T smem[smem_cells<NDIM, NM>()];
-  constexpr int N = (NM == 1) ? 8 : (NM == 2) ? 16 : 32;
-  double vmax = 0.0;
-  bool bad = false;
-  if ((int64_t)blockIdx.x >= total) return;
-  stage_item<T, NDIM, N, true>(*Mp, 1, blockIdx.x, smem, vmax, bad, feat_raw);
-}
-
-template <typename T, int NDIM>
-static void launch_feat_t(unsigned nblk, int nmask, const MeshDev *d, int64_t total, double *fr, hipStream_t s) {
-  switch (nmask) {
-    case 1: stage1_feat_kernel<T, NDIM, 1><<<nblk, 256, 0, s>>>(d, total, fr); break;
-    case 2: stage1_feat_kernel<T, NDIM, 2><<<nblk, 256, 0, s>>>(d, total, fr); break;
-    default: stage1_feat_kernel<T, NDIM, 4><<<nblk, 256, 0, s>>>(d, total, fr); break;
+  switch (scheme) {
+#define F4_CASE(S) \
+    case S: return launch_stage_sch<S>(d_meshes, n_meshes, total_items, stage, ndim, f64, grid, s, xcd, nmask);
+    F4_CASE(0) F4_CASE(1) F4_CASE(2) F4_CASE(3) F4_CASE(4) F4_CASE(5) F4_CASE(6) F4_CASE(7)
+#undef F4_CASE
+    default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_stage1_features(const MeshDev *d_mesh, int64_t total_items, int ndim, bool f64, int nmask,
-                                  double *feat_raw, hipStream_t s) {
+                                  double *feat_raw, hipStream_t s, int scheme) {
   if (total_items <= 0) return hipSuccess;
   if (nmask != 1 && nmask != 2 && nmask != 4) return hipErrorInvalidValue;
-  const unsigned nblk = (unsigned)total_items;
-  if (f64) {
-    if (ndim == 3) launch_feat_t<double, 3>(nblk, nmask, d_mesh, total_items, feat_raw, s);
-    else launch_feat_t<double, 2>(nblk, nmask, d_mesh, total_items, feat_raw, s);
-  } else {
-    if (ndim == 3) launch_feat_t<float, 3>(nblk, nmask, d_mesh, total_items, feat_raw, s);
-    else launch_feat_t<float, 2>(nblk, nmask, d_mesh, total_items, feat_raw, s);
+  switch (scheme) {
+#define F4_CASE(S) case S: return launch_feat_sch<S>(d_mesh, total_items, ndim, f64, nmask, feat_raw, s);
+    F4_CASE(0) F4_CASE(1) F4_CASE(2) F4_CASE(3) F4_CASE(4) F4_CASE(5) F4_CASE(6) F4_CASE(7)
+#undef F4_CASE
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
+#endif
 
 }  // namespace f4

@@ -111,6 +111,44 @@ def uniform_noise_shear(block: int = 16, n: int = 256, seed: int = 0):
                 grid_field=grid_field, steps=50)
 
 
+def rayleigh_taylor(block: int = 16, n: int = 256, ndim: int = 3, p_top: float = 1.0):
+    """Rayleigh-Taylor workload of Sec. 4.2 on n^ndim cells in blocks of
+    block^ndim: heavy fluid (rho 1.0) above the interface z = h(x, y) =
+    0.8 + 0.05 sin(2 pi x) sin(2 pi y) (2D: y = 0.8 + 0.05 sin(2 pi x)), light
+    fluid (rho 0.1) below, at rest, gamma 5/3, gravity -1 along the last axis,
+    pressure in hydrostatic balance with p = p_top at the top:
+    p = p_top + rho_h (1 - z) above h, p_top + rho_h (1 - h) + rho_l (h - z)
+    below.  (The paper does not give p_top; 1.0 is this workload's choice.)
+    The state is evaluated at cell centres."""
+    gamma = 5.0 / 3.0
+    nt = n // block
+    rho_h, rho_l, h0, delta, k = 1.0, 0.1, 0.8, 0.05, 2 * math.pi
+
+    def field(x, y, z=None):
+        if ndim == 3:
+            h, zz = h0 + delta * np.sin(k * x) * np.sin(k * y), z
+        else:
+            h, zz = h0 + delta * np.sin(k * x), y
+        above = zz >= h
+        rho = np.where(above, rho_h, rho_l)
+        p = np.where(above, p_top + rho_h * (1.0 - zz), p_top + rho_h * (1.0 - h) + rho_l * (h - zz))
+        zero = np.zeros_like(rho)
+        return conserved_from_primitive(rho, [zero] * ndim, p, gamma)
+
+    def grid_field():
+        c = (np.arange(n) + 0.5) / n
+        if ndim == 3:
+            z, y, x = np.meshgrid(c, c, c, indexing="ij")
+            return field(x, y, z)
+        y, x = np.meshgrid(c, c, indexing="ij")
+        return field(x, y)
+
+    grav = (0.0, 0.0, -1.0) if ndim == 3 else (0.0, -1.0, 0.0)
+    return dict(name=f"rayleigh_taylor_{n}^{ndim}_b{block}", ndim=ndim, trees=(nt,) * ndim + (1,) * (3 - ndim),
+                N=block, g=2, tree_size=1.0 / nt, level=0, gamma=gamma, cfl=0.5, field=field,
+                grid_field=grid_field, limiter="vanleer", flux="rusanov", gravity=grav, steps=50)
+
+
 def blast_field(gamma=1.4, p_in=100.0, p_out=1e-3, r0=0.05, centre=(0.5, 0.5, 0.5)):
     def field(x, y, z, xp=np):
         r = xp.sqrt((x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2)

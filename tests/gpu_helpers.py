@@ -10,12 +10,18 @@ def gpu_mesh(w, prec, max_level=None, max_blocks=None):
     import paper_2605_07612_amd as f4
     ml = w.get("level", 0) if max_level is None else max_level
     return f4.Mesh(w["ndim"], w["trees"], w["N"], w["g"], w["tree_size"], level=w.get("level", 0),
-                   max_level=ml, max_blocks=max_blocks, prec=prec, gamma=w["gamma"], cfl=w["cfl"])
+                   max_level=ml, max_blocks=max_blocks, prec=prec, gamma=w["gamma"], cfl=w["cfl"], **scheme(w))
 
 
 def oracle_mesh(w):
     return OracleMesh(w["ndim"], w["trees"], w["N"], w["g"], w["tree_size"], level=w.get("level", 0),
-                      gamma=w["gamma"], cfl=w["cfl"])
+                      gamma=w["gamma"], cfl=w["cfl"], **scheme(w))
+
+
+def scheme(w):
+    """Limiter, flux and gravity of a workload (defaults: minmod, Rusanov, none)."""
+    return dict(limiter=w.get("limiter", "minmod"), flux=w.get("flux", "rusanov"),
+                gravity=tuple(w.get("gravity", (0.0, 0.0, 0.0))))
 
 
 def refine_flags_base(w, mesh_tree_xyz):

@@ -68,6 +68,10 @@ BAD = [
     dict(cfl=0.0),
     dict(prec=2),
     dict(max_blocks=0),
+    dict(limiter=2),
+    dict(flux=-1),
+    dict(gravity=(0.0, float("inf"), 0.0)),
+    dict(gravity=(float("nan"), 0.0, 0.0)),
 ]
 
 

@@ -35,3 +35,25 @@ def test_library_exports_every_declared_symbol():
 def test_binding_covers_the_header():
     import paper_2605_07612_amd as f4
     assert set(declared()) <= set(f4.EXPORTS)
+
+
+def test_descriptor_layout_matches_the_header(tmp_path):
+    """The binding's MeshDesc has the size and field offsets that a C
+    compiler gives foap4_mesh_desc from include/foap4.h."""
+    import ctypes
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    import paper_2605_07612_amd as f4
+    fields = [name for name, _ in f4.MeshDesc._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"foap4.h\"\nint main(void) {\n"
+                   + "  printf(\"%zu\\n\", sizeof(foap4_mesh_desc));\n"
+                   + "".join(f"  printf(\"%zu\\n\", offsetof(foap4_mesh_desc, {n}));\n" for n in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got[0] == ctypes.sizeof(f4.MeshDesc)
+    assert got[1:] == [getattr(f4.MeshDesc, n).offset for n in fields]
