@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-batch64", action="store_true")
+    ap.add_argument("--skip-rt", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--profile-run", action="store_true",
@@ -237,6 +238,51 @@ def main():
                                   "step_hbm_frac": round(gcups64b * step_bytes_per_update(S64, True, args.block) / HBM_PEAK_GBS, 4)}
         del b64, m64
         torch.cuda.empty_cache()
+
+    # ---------------- the paper's own benchmark workload: Rayleigh-Taylor with the
+    # van Leer limiter and the gravity source (Sec. 4.2), same cells and blocks
+    if not args.skip_rt:
+        wr = synth.rayleigh_taylor(block=args.block, n=args.n)
+        grid_rt = wr["grid_field"]()
+
+        def make_rt(prec):
+            m = f4.Mesh(3, wr["trees"], wr["N"], wr["g"], wr["tree_size"], prec=prec, gamma=wr["gamma"],
+                        cfl=wr["cfl"], limiter=wr["limiter"], flux=wr["flux"], gravity=wr["gravity"])
+            layout.set_from_grid(m, grid_rt)
+            return m
+
+        mr = make_rt(f4.F32)
+        br = f4.Batch([mr])
+        cfg_rt = br.autotune(args.tune_cache)
+        br.step(args.warmup)
+        sr, _ = timed_steps(br.step, args.steps, torch.cuda.synchronize)
+        g_rt = cells * 2 * args.steps / sr / 1e9
+        ph_rt = br.phase_times(5)
+        log(f"Rayleigh-Taylor FP32 batched: {sr / args.steps * 1e3:.3f} ms/step, {g_rt:.2f} Gcell-updates/s, "
+            f"config {cfg_rt}")
+        del br, mr
+        torch.cuda.empty_cache()
+        mr = make_rt(f4.F64)
+        mr.step(args.warmup)
+        sr64, _ = timed_steps(lambda n: mr.step(n), args.steps, torch.cuda.synchronize)
+        g_rt64 = cells * 2 * args.steps / sr64 / 1e9
+        log(f"Rayleigh-Taylor FP64 plain: {sr64 / args.steps * 1e3:.3f} ms/step, {g_rt64:.2f} Gcell-updates/s")
+        del mr
+        torch.cuda.empty_cache()
+        # the paper's H100 figures for this workload (other hardware: context, not the target)
+        paper = {32: (2.702, 1.366), 16: (2.599, 1.302), 8: (2.081, 1.097)}.get(args.block)
+        rt_stage_gbs = stage_bytes / (ph_rt["stage"] * 1e-3) / 1e9  # same bytes per cell as above
+        result["rayleigh_taylor"] = {
+            "workload": wr["name"], "scheme": "van Leer, Rusanov, gravity (0, 0, -1), gamma 5/3",
+            "value": round(g_rt, 4), "unit": "Gcell-updates/s", "dtype": "f32",
+            "ms_per_step": round(sr / args.steps * 1e3, 4), "config": list(cfg_rt),
+            "stage_ms": round(ph_rt["stage"], 5), "stage_hbm_frac": round(rt_stage_gbs / HBM_PEAK_GBS, 4),
+            "step_hbm_frac": round(g_rt * step_bytes_per_update(S32, True, args.block) / HBM_PEAK_GBS, 4),
+            "fp64_plain": {"value": round(g_rt64, 4), "ms_per_step": round(sr64 / args.steps * 1e3, 4)},
+            "paper_h100_context": (None if paper is None or args.n != 256 else
+                                   {"fp32": paper[0], "fp64": paper[1],
+                                    "source": "table of results on different hardware, 256^3, van Leer"}),
+        }
 
     # ---------------- the 64-problem batch (mixed 8^3/16^3/32^3 blocks), FP32
     if not args.skip_batch64:
