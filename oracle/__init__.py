@@ -73,6 +73,8 @@ class _MeshC(ctypes.Structure):
                 ("srl", ctypes.c_void_p), ("srl_off", ctypes.c_void_p),
                 ("f2c", ctypes.c_void_p), ("f2c_off", ctypes.c_void_p),
                 ("c2f", ctypes.c_void_p), ("c2f_off", ctypes.c_void_p),
+                ("bc", ctypes.c_void_p), ("bc_off", ctypes.c_void_p),
+                ("bc_type", (ctypes.c_int32 * 5) * 6), ("bc_val", (ctypes.c_double * 5) * 6),
                 ("limiter", ctypes.c_int32), ("flux", ctypes.c_int32), ("grav", ctypes.c_double * 3)]
 
 
@@ -110,7 +112,10 @@ class OracleMesh:
 
     def __init__(self, ndim, trees, N, g=2, tree_size=1.0, level=0, gamma=1.4, cfl=0.5,
                  periodic=(True, True, True), origin=(0.0, 0.0, 0.0), limiter="minmod",
-                 flux="rusanov", gravity=(0.0, 0.0, 0.0)):
+                 flux="rusanov", gravity=(0.0, 0.0, 0.0), bc_type=None, bc_value=None):
+        """bc_type / bc_value: [2 ndim faces -x, +x, -y, +y, -z, +z][nvar]
+        Dirichlet (0) or Neumann (1) conditions and their values (Sec. 2.4),
+        used on the faces of non-periodic axes."""
         if N % 2 or N < 2 * g or g < 2:
             raise ValueError("need even N >= 2g and g >= 2")
         self.ndim, self.N, self.g = ndim, N, g
@@ -119,6 +124,14 @@ class OracleMesh:
         self.origin = origin
         self.limiter, self.flux = LIMITERS[limiter], FLUXES[flux]
         self.gravity = tuple(float(x) for x in gravity) + (0.0,) * (3 - len(gravity))
+        self.bc_type = np.zeros((6, 5), np.int32)
+        self.bc_value = np.zeros((6, 5))
+        if bc_type is not None:
+            t = np.asarray(bc_type, np.int32)
+            self.bc_type[: t.shape[0], : t.shape[1]] = t
+        if bc_value is not None:
+            v = np.asarray(bc_value, np.float64)
+            self.bc_value[: v.shape[0], : v.shape[1]] = v
         self.forest = Forest(ndim, trees, periodic, level)
         self._refresh()
         self.u = self.alloc()
@@ -147,8 +160,11 @@ class OracleMesh:
         c.gamma, c.cfl = self.gamma, self.cfl
         c.limiter, c.flux = self.limiter, self.flux
         c.grav[:] = list(self.gravity)
+        for f in range(6):
+            c.bc_type[f][:] = [int(x) for x in self.bc_type[f]]
+            c.bc_val[f][:] = [float(x) for x in self.bc_value[f]]
         keep = []
-        for name in ("srl", "srl_off", "f2c", "f2c_off", "c2f", "c2f_off"):
+        for name in ("srl", "srl_off", "f2c", "f2c_off", "c2f", "c2f_off", "bc", "bc_off"):
             arr = np.ascontiguousarray(self.pat[name], dtype=np.int32)
             if arr.size == 0:
                 arr = np.zeros(1, np.int32)

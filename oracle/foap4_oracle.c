@@ -10,7 +10,9 @@
  * Every routine works one cell or one face at a time in double precision, in
  * the order the paper describes, with no blocking or fusion:
  *   ghost filling          Sec. 2.6 (two rounds R1, R2), Sec. 2.2 (restriction,
- *                          limited prolongation, eq. gminmod with theta = 1)
+ *                          limited prolongation, eq. gminmod with theta = 1),
+ *                          Sec. 2.4 (Dirichlet / Neumann physical boundaries,
+ *                          filled in R1)
  *   stage operator L(U)    Sec. 3.2 (primitive MUSCL reconstruction with the
  *                          minmod or van Leer limiter, Rusanov or HLL flux,
  *                          source term first, then the flux divergence),
@@ -50,6 +52,10 @@ typedef struct {
   const int32_t *f2c_off;
   const int32_t *c2f;     /* (q, c, h): fine q receives from coarse c            */
   const int32_t *c2f_off;
+  const int32_t *bc;      /* (b): face f of block b is a physical boundary         */
+  const int32_t *bc_off;
+  int32_t bc_type[6][5];  /* per face direction and variable: 0 Dirichlet, 1 Neumann */
+  double bc_val[6][5];    /* boundary value u_b, or outward normal derivative u'_b */
   int32_t limiter;        /* reconstruction slope limiter: 0 minmod, 1 van Leer  */
   int32_t flux;           /* numerical flux: 0 Rusanov, 1 HLL                     */
   double grav[3];         /* gravitational acceleration; all zero: no source term */
@@ -235,6 +241,32 @@ static void fill_c2f(const om_mesh *m, double *u, int f, int32_t q, int32_t cb, 
 
 /* One round of ghost filling: round 1 = SRL copies and F2C restriction,
  * round 2 = C2F prolongation (which reads round 1's ghosts). */
+/* Physical boundary face f of block b (Sec. 2.4): ghost layer l = 1..g
+ * outside the face takes, per variable, the value of its mirror cell, the
+ * l-th cell inside, reflected through the boundary condition at the face:
+ *   Dirichlet (u = u_b on the face):        2 u_b - u_in
+ *   Neumann (du/dn = u'_b, n outward):      u_in + (2l - 1) dx u'_b
+ * (the face lies (l - 1/2) dx from both cells). */
+static void fill_bc(const om_mesh *m, double *u, int f, int32_t b) {
+  int N = m->N, ax = f / 2, side = f % 2, t1, t2;
+  tangential_axes(m->ndim, ax, &t1, &t2);
+  double dx = dx_of(m, b);
+  int n2 = (t2 >= 0) ? N : 1;
+  for (int v = 0; v < m->nvar; v++)
+    for (int l = 1; l <= m->g; l++)
+      for (int p2 = 0; p2 < n2; p2++)
+        for (int p1 = 0; p1 < N; p1++) {
+          int gc[3] = {0, 0, 0}, ic[3] = {0, 0, 0};
+          gc[ax] = side ? N - 1 + l : -l;
+          ic[ax] = side ? N - l : l - 1;
+          gc[t1] = ic[t1] = p1;
+          if (t2 >= 0) gc[t2] = ic[t2] = p2;
+          double uin = u[ix(m, b, v, ic)];
+          double ub = m->bc_val[f][v];
+          u[ix(m, b, v, gc)] = (m->bc_type[f][v] == 0) ? 2.0 * ub - uin : uin + ((2 * l - 1) * dx) * ub;
+        }
+}
+
 void om_ghost_round(const om_mesh *m, double *u, int round) {
   int nf = 2 * m->ndim;
   if (round == 2) {
@@ -256,6 +288,11 @@ void om_ghost_round(const om_mesh *m, double *u, int round) {
     for (int32_t r = m->f2c_off[f]; r < m->f2c_off[f + 1]; r++)
       fill_f2c(m, u, f, m->f2c[4 * r], m->f2c[4 * r + 1], m->f2c[4 * r + 2]);
   }
+  if (m->bc)
+    for (int f = 0; f < nf; f++) {
+#pragma omp parallel for schedule(static)
+      for (int32_t r = m->bc_off[f]; r < m->bc_off[f + 1]; r++) fill_bc(m, u, f, m->bc[r]);
+    }
 }
 
 /* Round R1 (SRL copies, F2C restriction), then round R2 (C2F prolongation). */
