@@ -118,9 +118,11 @@ def main():
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for hardware-counter passes: a 1 GiB device copy (counter calibration) "
                          "then 3 batched FP32 steps in the given configuration")
+    ap.add_argument("--profile-workload", default="noise_shear", choices=["noise_shear", "rayleigh_taylor"],
+                    help="workload of --profile-run")
     ap.add_argument("--config", default=None,
-                    help="kslabs,wg_stage1,wg_stage2,xcd_order instead of autotuning "
-                         f"(--profile-run default: {PROFILE_CONFIG})")
+                    help="kslabs,wg_stage1,wg_stage2,xcd_order instead of autotuning, for every FP32 "
+                         f"single-mesh leg (--profile-run default: {PROFILE_CONFIG})")
     ap.add_argument("--counters", default=os.path.join(ROOT, "profiles", "stage_traffic_noise_shear_256cubed_b16.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -144,6 +146,15 @@ def main():
         layout.set_from_grid(m, grid)
         return m
 
+    wr = synth.rayleigh_taylor(block=args.block, n=args.n)
+
+    def make_rt(prec):
+        m = f4.Mesh(3, wr["trees"], wr["N"], wr["g"], wr["tree_size"], prec=prec, gamma=wr["gamma"],
+                    cfl=wr["cfl"], limiter=wr["limiter"], flux=wr["flux"], gravity=wr["gravity"],
+                    periodic=wr["periodic"], bc_type=wr["bc_type"], bc_value=wr["bc_value"])
+        layout.set_from_grid(m, wr["grid_field"]())
+        return m
+
     if args.profile_run:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         bb = torch.empty_like(a)
@@ -152,7 +163,7 @@ def main():
         bb.copy_(a)  # calibration: reads and writes exactly 1 GiB
         torch.cuda.synchronize()
         del a, bb
-        m32 = make(f4.F32)
+        m32 = make(f4.F32) if args.profile_workload == "noise_shear" else make_rt(f4.F32)
         batch = f4.Batch([m32])
         ks, wg1, wg2, xcd = parse_config(args.config or PROFILE_CONFIG)
         batch.set_config(ks, wg1, xcd, 1, wg_stage2=wg2)
@@ -242,18 +253,13 @@ def main():
     # ---------------- the paper's own benchmark workload: Rayleigh-Taylor with the
     # van Leer limiter and the gravity source (Sec. 4.2), same cells and blocks
     if not args.skip_rt:
-        wr = synth.rayleigh_taylor(block=args.block, n=args.n)
-        grid_rt = wr["grid_field"]()
-
-        def make_rt(prec):
-            m = f4.Mesh(3, wr["trees"], wr["N"], wr["g"], wr["tree_size"], prec=prec, gamma=wr["gamma"],
-                        cfl=wr["cfl"], limiter=wr["limiter"], flux=wr["flux"], gravity=wr["gravity"])
-            layout.set_from_grid(m, grid_rt)
-            return m
-
         mr = make_rt(f4.F32)
         br = f4.Batch([mr])
-        cfg_rt = br.autotune(args.tune_cache)
+        if args.config:
+            cfg_rt = parse_config(args.config)
+            br.set_config(cfg_rt[0], cfg_rt[1], cfg_rt[3], 1, wg_stage2=cfg_rt[2])
+        else:
+            cfg_rt = br.autotune(args.tune_cache)
         br.step(args.warmup)
         sr, _ = timed_steps(br.step, args.steps, torch.cuda.synchronize)
         g_rt = cells * 2 * args.steps / sr / 1e9
@@ -273,10 +279,14 @@ def main():
         paper = {32: (2.702, 1.366), 16: (2.599, 1.302), 8: (2.081, 1.097)}.get(args.block)
         rt_stage_gbs = stage_bytes / (ph_rt["stage"] * 1e-3) / 1e9  # same bytes per cell as above
         result["rayleigh_taylor"] = {
-            "workload": wr["name"], "scheme": "van Leer, Rusanov, gravity (0, 0, -1), gamma 5/3",
+            "workload": wr["name"], "scheme": "van Leer, Rusanov, gravity (0, 0, -1), gamma 5/3, "
+                                              "periodic x, y, reflecting walls in z",
             "value": round(g_rt, 4), "unit": "Gcell-updates/s", "dtype": "f32",
             "ms_per_step": round(sr / args.steps * 1e3, 4), "config": list(cfg_rt),
             "stage_ms": round(ph_rt["stage"], 5), "stage_hbm_frac": round(rt_stage_gbs / HBM_PEAK_GBS, 4),
+            "stage_traffic": (traffic_from_counters(os.path.join(ROOT, "profiles",
+                                                                 "stage_traffic_rayleigh_taylor_256cubed_b16.json"),
+                                                    stage_bytes) if (args.block, args.n) == (16, 256) else None),
             "step_hbm_frac": round(g_rt * step_bytes_per_update(S32, True, args.block) / HBM_PEAK_GBS, 4),
             "fp64_plain": {"value": round(g_rt64, 4), "ms_per_step": round(sr64 / args.steps * 1e3, 4)},
             "paper_h100_context": (None if paper is None or args.n != 256 else

@@ -67,12 +67,12 @@ typedef enum { FOAP4_LIM_MINMOD = 0, FOAP4_LIM_VANLEER = 1 } foap4_limiter;
 typedef enum { FOAP4_FLUX_RUSANOV = 0, FOAP4_FLUX_HLL = 1 } foap4_flux;
 
 /* Mesh descriptor.  A brick of n_trees[0] x n_trees[1] (x n_trees[2]) trees
- * (the paper's p4est brick, Sec. 2.2), all periodic; cubic cells with
- * dx_l = tree_size / (N * 2^l) at refinement level l. */
+ * (the paper's p4est brick, Sec. 2.2), periodic or bounded per axis; cubic
+ * cells with dx_l = tree_size / (N * 2^l) at refinement level l. */
 typedef struct {
   int32_t ndim;        /* 2 or 3                                                     */
   int32_t n_trees[3];  /* trees per axis (n_trees[2] ignored in 2D); product < 65536 */
-  int32_t periodic[3]; /* must be 1 for every used axis                               */
+  int32_t periodic[3]; /* 1: periodic axis; 0: bounded, by bc_type / bc_value          */
   double origin[3];    /* coordinates of the brick's low corner                      */
   double tree_size;    /* edge length of one tree                                    */
   int32_t block_n;     /* N, cells per block edge: 8, 16 or 32                        */
@@ -91,6 +91,16 @@ typedef struct {
                           state to its right-hand side; all zero (the default): no
                           source.  gravity[2] is ignored in 2D.  The time step stays
                           the wave-speed CFL limit. */
+  /* Physical boundaries (Sec. 2.4) of the non-periodic axes, per face direction
+   * f (0..5: -x, +x, -y, +y, -z, +z) and variable v (rho, m_x, m_y[, m_z], E):
+   * bc_type 0 = Dirichlet, u = bc_value on the face; 1 = Neumann, outward
+   * normal derivative du/dn = bc_value.  Ghost layer l = 1..g outside the face
+   * takes 2 u_b - u_in (Dirichlet) or u_in + (2l - 1) dx u'_b (Neumann), u_in
+   * the l-th cell inside, in FP64 rounded once; filled in ghost round R1.  A
+   * reflecting wall is Dirichlet 0 on the normal momentum and Neumann 0 on the
+   * other variables.  Entries of periodic axes are ignored. */
+  int32_t bc_type[6][5];
+  double bc_value[6][5];
 } foap4_mesh_desc;
 
 /* Creates a mesh at the uniform level desc->init_level (Sec. 2.2) and its

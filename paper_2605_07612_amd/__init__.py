@@ -32,11 +32,22 @@ class MeshDesc(ctypes.Structure):
                 ("n_ghost", ctypes.c_int32), ("init_level", ctypes.c_int32), ("min_level", ctypes.c_int32),
                 ("max_level", ctypes.c_int32), ("max_blocks", ctypes.c_int64), ("prec", ctypes.c_int32),
                 ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("limiter", ctypes.c_int32),
-                ("flux", ctypes.c_int32), ("gravity", ctypes.c_double * 3)]
+                ("flux", ctypes.c_int32), ("gravity", ctypes.c_double * 3),
+                ("bc_type", (ctypes.c_int32 * 5) * 6), ("bc_value", (ctypes.c_double * 5) * 6)]
 
 # stage scheme options (include/foap4.h: foap4_limiter, foap4_flux)
 LIMITERS = {"minmod": 0, "vanleer": 1}
 FLUXES = {"rusanov": 0, "hll": 1}
+BC_DIRICHLET, BC_NEUMANN = 0, 1
+
+
+def wall_bc(ndim):
+    """(bc_type, bc_value) [6][5] of reflecting walls on every face: the
+    normal momentum Dirichlet 0, every other variable Neumann 0."""
+    t = np.full((6, 5), BC_NEUMANN, np.int32)
+    for f in range(2 * ndim):
+        t[f, 1 + f // 2] = BC_DIRICHLET
+    return t, np.zeros((6, 5))
 
 
 _lib = None
@@ -120,7 +131,8 @@ class Mesh:
 
     def __init__(self, ndim, trees, N, g=2, tree_size=1.0, level=0, min_level=0, max_level=None,
                  max_blocks=None, prec=F64, gamma=1.4, cfl=0.5, origin=(0.0, 0.0, 0.0), device="cuda",
-                 stream=None, limiter="minmod", flux="rusanov", gravity=(0.0, 0.0, 0.0)):
+                 stream=None, limiter="minmod", flux="rusanov", gravity=(0.0, 0.0, 0.0),
+                 periodic=(True, True, True), bc_type=None, bc_value=None):
         torch = _torch()
         self.ndim, self.N, self.g = ndim, N, g
         self.nvar = ndim + 2
@@ -137,7 +149,15 @@ class Mesh:
         d = MeshDesc()
         d.ndim = ndim
         d.n_trees[:] = nt
-        d.periodic[:] = [1, 1, 1]
+        d.periodic[:] = [1 if p else 0 for p in periodic[:3]]
+        bt = np.zeros((6, 5), np.int32) if bc_type is None else np.asarray(bc_type, np.int32)
+        bv = np.zeros((6, 5)) if bc_value is None else np.asarray(bc_value, np.float64)
+        for f in range(bt.shape[0]):
+            for v in range(bt.shape[1]):
+                d.bc_type[f][v] = int(bt[f, v])
+        for f in range(bv.shape[0]):
+            for v in range(bv.shape[1]):
+                d.bc_value[f][v] = float(bv[f, v])
         d.origin[:] = list(origin)
         d.tree_size = tree_size
         d.block_n = N

@@ -33,6 +33,7 @@ MeshDev make_dev(const foap4_mesh *m, int ks, int gather) {
   d.srl = m->pat.srl;
   d.f2c = m->pat.f2c;
   d.c2f = m->pat.c2f;
+  d.bc = m->pat.bc;
   d.fix_list = m->pat.fix_list;
   d.bflux_f = m->pat.bflux_f;
   d.bflux_c = m->pat.bflux_c;
@@ -45,6 +46,11 @@ MeshDev make_dev(const foap4_mesh *m, int ks, int gather) {
   d.gamma = m->d.gamma;
   d.cfl = m->d.cfl;
   for (int a = 0; a < 3; a++) d.grav[a] = (a < m->d.ndim) ? m->d.gravity[a] : 0.0;
+  for (int f = 0; f < 6; f++)
+    for (int v = 0; v < 5; v++) {
+      d.bc_val[f][v] = m->d.bc_value[f][v];
+      d.bc_type[f][v] = m->d.bc_type[f][v];
+    }
   for (int t = 0; t < kTypes; t++) {
     d.pn[t] = m->pat.n[t];
     for (int f = 0; f < 7; f++) d.poff[t][f] = m->pat.off[t][f];
@@ -97,7 +103,7 @@ static foap4_status check_bad(foap4_mesh *m) {
 
 static foap4_status fill(foap4_mesh *m, const MeshDev *dd, int which) {
   const bool f64 = m->d.prec == FOAP4_F64;
-  const int64_t r1 = m->pat.n[kSRL] + m->pat.n[kF2C], r2 = m->pat.n[kC2F];
+  const int64_t r1 = m->pat.n[kSRL] + m->pat.n[kF2C] + m->pat.n[kBC], r2 = m->pat.n[kC2F];
   F4_HIP(m, launch_ghost(dd, 1, r1, 1, which, m->d.ndim, f64, 0, m->stream));
   if (r2) F4_HIP(m, launch_ghost(dd, 1, r2, 2, which, m->d.ndim, f64, 0, m->stream));
   return FOAP4_OK;
@@ -153,7 +159,14 @@ foap4_status foap4_mesh_create(const foap4_mesh_desc *desc, void *state0, void *
   int64_t ntrees = 1;
   for (int a = 0; a < d.ndim; a++) {
     if (d.n_trees[a] < 1) return fail(nullptr, FOAP4_E_INVALID, "n_trees must be >= 1");
-    if (!d.periodic[a]) return fail(nullptr, FOAP4_E_INVALID, "only periodic domains are supported");
+    if (d.periodic[a] != 0 && d.periodic[a] != 1) return fail(nullptr, FOAP4_E_INVALID, "periodic must be 0 or 1");
+    if (!d.periodic[a])
+      for (int f = 2 * a; f < 2 * a + 2; f++)
+        for (int v = 0; v < d.ndim + 2; v++) {
+          if (d.bc_type[f][v] != 0 && d.bc_type[f][v] != 1)
+            return fail(nullptr, FOAP4_E_INVALID, "bc_type must be 0 (Dirichlet) or 1 (Neumann)");
+          if (!std::isfinite(d.bc_value[f][v])) return fail(nullptr, FOAP4_E_INVALID, "bc_value must be finite");
+        }
     ntrees *= d.n_trees[a];
   }
   if (ntrees >= 65536) return fail(nullptr, FOAP4_E_INVALID, "at most 65535 trees");
@@ -187,6 +200,7 @@ foap4_status foap4_mesh_create(const foap4_mesh_desc *desc, void *state0, void *
     return fail(nullptr, FOAP4_E_INVALID, "state buffers smaller than max_blocks blocks");
   }
   m->topo.init_uniform(d.ndim, d.n_trees, d.init_level);
+  for (int a = 0; a < 3; a++) m->topo.periodic[a] = (a < d.ndim) ? d.periodic[a] : 1;
   if ((int64_t)m->topo.leaves.size() > d.max_blocks) {
     delete m;
     return fail(nullptr, FOAP4_E_CAPACITY, "initial mesh exceeds max_blocks");
@@ -550,7 +564,7 @@ static foap4_status batch_upload(foap4_batch *b) {
     d.r1_begin = r1;
     d.r2_begin = r2;
     it += stage_items_for(b->ndim, m->d.block_n, d.nb, d.ks);
-    r1 += d.r1_srl + m->pat.n[kF2C];
+    r1 += d.r1_srl + m->pat.n[kF2C] + m->pat.n[kBC];
     r2 += m->pat.n[kC2F];
     devs.push_back(d);
   }

@@ -63,6 +63,7 @@ class Topology {
  public:
   int ndim = 3;
   int nt[3] = {1, 1, 1};
+  int periodic[3] = {1, 1, 1};  // 0: bounded axis (no neighbours across its ends)
   std::vector<Leaf> leaves;
 
   void init_uniform(int ndim_, const int32_t nt_[3], int level);
@@ -87,7 +88,7 @@ struct MeshDev {
   // [nb][2*ndim]: -2 - n for a same-level neighbour n, -1 for a boundary,
   // 2*slot for a C2F face (fine-side flux slot), 2*slot+1 for an F2C face
   const int32_t *face_info;
-  const int32_t *srl, *f2c, *c2f, *fix_list;  // ghost pattern records
+  const int32_t *srl, *f2c, *c2f, *bc, *fix_list;  // ghost pattern records
   void *bflux_f;              // fine-side face fluxes [n_c2f][nvar][N^(d-1)]
   void *bflux_c;              // coarse-side face fluxes [n_f2c/2^(d-1)][nvar][N^(d-1)]
   double *scal;               // kDt, kTime, kMaxInv, kBad ...
@@ -97,13 +98,16 @@ struct MeshDev {
   double dx0;                 // cell width at level 0
   double gamma, cfl;
   double grav[3];             // gravitational acceleration (source term on)
+  double bc_val[6][5];        // physical boundary values per face direction and variable
+  int32_t bc_type[6][5];      // 0 Dirichlet, 1 Neumann
   int32_t pn[4];              // record totals per type
   int32_t poff[4][7];         // CSR offsets per type and face
   int32_t n_fix;
   int32_t cur;                // current state buffer
   int32_t N, g, ks;           // block size, ghost layers, k-slabs per tile
   int32_t gather;             // stage reads same-level halos from the neighbours
-  int32_t r1_srl;             // SRL records executed in round R1 (0 or pn[kSRL])
+  int32_t r1_srl;             // SRL records executed in round R1 (0 or pn[kSRL]);
+                              // R1 then runs pn[kF2C] restrictions and pn[kBC] boundary faces
 };
 
 struct Pattern {

@@ -1,6 +1,8 @@
 // Execution of the stored ghost pattern (Sec. 2.6), one workgroup per record.
-//   round R1: SRL records (copy g layers both ways across a face pair) and
+//   round R1: SRL records (copy g layers both ways across a face pair),
 //             F2C records (coarse ghost = mean of the 2^d fine cells, FP64)
+//             and physical boundary faces (Sec. 2.4: Dirichlet / Neumann
+//             values reflected through the face, FP64)
 //   round R2: C2F records (fine ghost = limited prolongation from the coarse
 //             block, FP64 slopes; reads the coarse block's R1 ghosts)
 // Work items of several meshes are concatenated (r1_begin / r2_begin).
@@ -200,6 +202,45 @@ __device__ void c2f_record(const MeshDev &M, T *u, int f, int32_t q, int32_t cb,
   }
 }
 
+// Physical boundary face f of block b: ghost layer L = 1..g outside the face
+// from the L-th cell inside, 2 u_b - u_in (Dirichlet value u_b) or
+// u_in + (2L - 1) dx u'_b (Neumann, outward derivative u'_b); FP64 without
+// contraction, rounded once.
+template <typename T, int NDIM, int N>
+__device__ void bc_record(const MeshDev &M, T *u, int f, int32_t b) {
+#pragma clang fp contract(off)
+  constexpr int NV = NDIM + 2;
+  constexpr int N2 = (NDIM == 3) ? N : 1;
+  const Geo<NDIM> G(N, M.g);
+  const int g = M.g, ax = f / 2, side = f % 2;
+  int t1, t2;
+  tangential(NDIM, ax, t1, t2);
+  T *ub = u + (int64_t)b * G.sv * NV;
+  const double dx = ldexp(M.dx0, -M.level[b]);
+  const int total = NV * N2 * N * g;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int l, p1, p2, v, r = e;
+    if (ax == 0) {
+      l = r % g; r /= g;
+      p1 = r % N; r /= N;
+    } else {
+      p1 = r % N; r /= N;
+      l = r % g; r /= g;
+    }
+    p2 = r % N2; v = r / N2;
+    const int L = l + 1;
+    int gc[3] = {0, 0, 0}, ic[3] = {0, 0, 0};
+    gc[ax] = side ? N - 1 + L : -L;
+    ic[ax] = side ? N - L : L - 1;
+    gc[t1] = ic[t1] = p1;
+    if (t2 >= 0) gc[t2] = ic[t2] = p2;
+    const double uin = (double)ub[v * G.sv + G.at(ic)];
+    const double val = M.bc_val[f][v];
+    const double out = (M.bc_type[f][v] == 0) ? 2.0 * val - uin : uin + ((double)(2 * L - 1) * dx) * val;
+    ub[v * G.sv + G.at(gc)] = (T)out;
+  }
+}
+
 template <typename T, int NDIM, int N>
 __device__ void ghost_item(const MeshDev &M, int round, int64_t r, int which) {
   T *u = (T *)M.s[which == 0 ? M.cur : 1 - M.cur];
@@ -208,11 +249,16 @@ __device__ void ghost_item(const MeshDev &M, int round, int64_t r, int which) {
       int f = 1;
       while (r >= M.poff[kSRL][f + 1]) f += 2;
       srl_record<T, NDIM, N>(M, u, f / 2, M.srl[2 * r], M.srl[2 * r + 1]);
-    } else {
+    } else if (r < M.r1_srl + M.pn[kF2C]) {
       r -= M.r1_srl;
       int f = 0;
       while (r >= M.poff[kF2C][f + 1]) f++;
       f2c_record<T, NDIM, N>(M, u, f, M.f2c[4 * r], M.f2c[4 * r + 1], M.f2c[4 * r + 2]);
+    } else {
+      r -= M.r1_srl + M.pn[kF2C];
+      int f = 0;
+      while (r >= M.poff[kBC][f + 1]) f++;
+      bc_record<T, NDIM, N>(M, u, f, M.bc[r]);
     }
   } else {
     int f = 0;

@@ -3,7 +3,8 @@
 // 1. classify: one thread per (block, face) locates the leaf covering the
 //    neighbouring region by binary search in the sorted leaf keys and
 //    classifies the face as SRL / finer neighbours (F2C into this block) /
-//    coarser neighbour (C2F into this block).
+//    coarser neighbour (C2F into this block) / physical boundary (the end of
+//    a bounded axis).
 // 2. count rows [type][face][block] and a row marking blocks with F2C faces.
 // 3. exclusive scan of every row (one workgroup per row) -> stable order
 //    "face, receiving block, hanging offset" without a sort.
@@ -26,6 +27,7 @@ struct TopoDev {
   int64_t nb;
   int32_t nt[3];
   int32_t ndim;
+  int32_t periodic[3];
 };
 
 __device__ int64_t locate(const TopoDev &T, int32_t l, const int32_t G[3]) {
@@ -55,15 +57,19 @@ __global__ void classify_kernel(TopoDev T, int8_t *kind, int32_t *nbr, int8_t *h
   int32_t H[3] = {G[0], G[1], G[2]};
   const int32_t E = T.nt[ax] << l;
   H[ax] += side ? 1 : -1;
+  int32_t *nb4 = nbr + id * 4;
+  nb4[0] = nb4[1] = nb4[2] = nb4[3] = -1;
+  hh[id] = 0;
+  if ((H[ax] < 0 || H[ax] >= E) && !T.periodic[ax]) {
+    kind[id] = kKindBC;
+    return;
+  }
   if (H[ax] < 0) H[ax] += E;
   if (H[ax] >= E) H[ax] -= E;
   int t1, t2;
   tang_axes(T.ndim, ax, t1, t2);
   const int64_t n = locate(T, l, H);
   const int32_t ln = T.level[n];
-  int32_t *nb4 = nbr + id * 4;
-  nb4[0] = nb4[1] = nb4[2] = nb4[3] = -1;
-  hh[id] = 0;
   if (ln == l) {
     kind[id] = kKindSRL;
     nb4[0] = (int32_t)n;
@@ -240,7 +246,8 @@ foap4_status build_pattern(foap4_mesh *m) {
   int8_t *hh = kind + nbf;
   int32_t *err = P.tot + rows;
 
-  TopoDev T{m->d_keys, m->d_level, m->d_gc, nb, {m->topo.nt[0], m->topo.nt[1], m->topo.nt[2]}, ndim};
+  TopoDev T{m->d_keys, m->d_level, m->d_gc, nb, {m->topo.nt[0], m->topo.nt[1], m->topo.nt[2]}, ndim,
+            {m->topo.periodic[0], m->topo.periodic[1], m->topo.periodic[2]}};
   F4_HIP(m, hipMemsetAsync(err, 0, 4, s));
   const unsigned g1 = (unsigned)((nbf + 255) / 256);
   classify_kernel<<<g1, 256, 0, s>>>(T, kind, nbr, hh, err);

@@ -56,20 +56,27 @@ namespace {
 struct Ctx {
   int ndim;
   int32_t nt[3];
+  int per[3];
   std::vector<std::array<int, 3>> offs;  // the 3^d - 1 neighbour directions
-  Ctx(int nd, const int32_t *n) : ndim(nd) {
-    for (int d = 0; d < 3; d++) nt[d] = n[d];
+  Ctx(int nd, const int32_t *n, const int *p) : ndim(nd) {
+    for (int d = 0; d < 3; d++) {
+      nt[d] = n[d];
+      per[d] = p[d];
+    }
     for (int dz = (nd == 3 ? -1 : 0); dz <= (nd == 3 ? 1 : 0); dz++)
       for (int dy = -1; dy <= 1; dy++)
         for (int dx = -1; dx <= 1; dx++)
           if (dx || dy || dz) offs.push_back({dx, dy, dz});
   }
-  // periodic wrap of region g at level l
-  void wrap(int32_t l, int32_t g[3]) const {
+  // periodic wrap of region g at level l; false if g lies beyond the end of
+  // a bounded axis (there is no region there)
+  bool wrap(int32_t l, int32_t g[3]) const {
     for (int d = 0; d < ndim; d++) {
       const int32_t E = nt[d] << l;
+      if ((g[d] < 0 || g[d] >= E) && !per[d]) return false;
       g[d] = ((g[d] % E) + E) % E;
     }
+    return true;
   }
   // leaf of s covering region (l, g) at a level <= l, as its level (-1: none)
   int32_t covering(const LeafSet &s, int32_t l, const int32_t g[3], Key4 *hit) const {
@@ -93,7 +100,7 @@ struct Ctx {
 
 bool Topology::regrid(const int8_t *flags, int lmin, int lmax, std::vector<Leaf> &out, std::vector<int32_t> &op,
                       std::vector<int32_t> &src, std::vector<int32_t> &arg) const {
-  Ctx C(ndim, nt);
+  Ctx C(ndim, nt, periodic);
   const int nch = 1 << ndim;
   // 1. refine flagged leaves
   LeafSet cur;
@@ -117,7 +124,7 @@ bool Topology::regrid(const int8_t *flags, int lmin, int lmax, std::vector<Leaf>
       if (k[0] < 2) continue;
       for (const auto &o : C.offs) {
         int32_t h[3] = {k[1] + o[0], k[2] + o[1], ndim == 3 ? k[3] + o[2] : 0};
-        C.wrap(k[0], h);
+        if (!C.wrap(k[0], h)) continue;
         Key4 hit;
         const int32_t lc = C.covering(cur, k[0], h, &hit);
         if (lc >= 0 && lc < k[0] - 1) refine.push_back(hit);
@@ -151,7 +158,7 @@ bool Topology::regrid(const int8_t *flags, int lmin, int lmax, std::vector<Leaf>
     for (const auto &o : C.offs) {
       if (!ok) break;
       int32_t r[3] = {p[1] + o[0], p[2] + o[1], ndim == 3 ? p[3] + o[2] : 0};
-      C.wrap(p[0], r);
+      if (!C.wrap(p[0], r)) continue;
       // cells of level lp + 2 in region r along the contact with the parent
       int lo[3], hi[3];
       for (int d = 0; d < 3; d++) {
@@ -179,7 +186,10 @@ bool Topology::regrid(const int8_t *flags, int lmin, int lmax, std::vector<Leaf>
   // new leaf table in key order
   Topology nt_;
   nt_.ndim = ndim;
-  for (int d = 0; d < 3; d++) nt_.nt[d] = nt[d];
+  for (int d = 0; d < 3; d++) {
+    nt_.nt[d] = nt[d];
+    nt_.periodic[d] = periodic[d];
+  }
   nt_.leaves.reserve(cur.size());
   for (const Key4 &k : cur) nt_.leaves.push_back(Leaf{k[0], {k[1], k[2], k[3]}});
   nt_.sort_and_index();

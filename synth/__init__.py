@@ -116,6 +116,8 @@ def rayleigh_taylor(block: int = 16, n: int = 256, ndim: int = 3, p_top: float =
     block^ndim: heavy fluid (rho 1.0) above the interface z = h(x, y) =
     0.8 + 0.05 sin(2 pi x) sin(2 pi y) (2D: y = 0.8 + 0.05 sin(2 pi x)), light
     fluid (rho 0.1) below, at rest, gamma 5/3, gravity -1 along the last axis,
+    periodic along the other axes and closed by reflecting walls along the
+    last one (bc_type: normal momentum Dirichlet 0, the rest Neumann 0),
     pressure in hydrostatic balance with p = p_top at the top:
     p = p_top + rho_h (1 - z) above h, p_top + rho_h (1 - h) + rho_l (h - z)
     below.  (The paper does not give p_top; 1.0 is this workload's choice.)
@@ -144,9 +146,13 @@ def rayleigh_taylor(block: int = 16, n: int = 256, ndim: int = 3, p_top: float =
         return field(x, y)
 
     grav = (0.0, 0.0, -1.0) if ndim == 3 else (0.0, -1.0, 0.0)
+    bc_type = np.ones((6, 5), np.int32)
+    bc_type[2 * (ndim - 1), ndim] = bc_type[2 * (ndim - 1) + 1, ndim] = 0  # m_z (2D: m_y) Dirichlet 0
+    periodic = tuple(d != ndim - 1 for d in range(3))
     return dict(name=f"rayleigh_taylor_{n}^{ndim}_b{block}", ndim=ndim, trees=(nt,) * ndim + (1,) * (3 - ndim),
                 N=block, g=2, tree_size=1.0 / nt, level=0, gamma=gamma, cfl=0.5, field=field,
-                grid_field=grid_field, limiter="vanleer", flux="rusanov", gravity=grav, steps=50)
+                grid_field=grid_field, limiter="vanleer", flux="rusanov", gravity=grav, steps=50,
+                periodic=periodic, bc_type=bc_type, bc_value=np.zeros((6, 5)))
 
 
 def blast_field(gamma=1.4, p_in=100.0, p_out=1e-3, r0=0.05, centre=(0.5, 0.5, 0.5)):

@@ -19,9 +19,11 @@ def oracle_mesh(w):
 
 
 def scheme(w):
-    """Limiter, flux and gravity of a workload (defaults: minmod, Rusanov, none)."""
+    """Limiter, flux, gravity and boundaries of a workload (defaults: minmod,
+    Rusanov, no source, periodic)."""
     return dict(limiter=w.get("limiter", "minmod"), flux=w.get("flux", "rusanov"),
-                gravity=tuple(w.get("gravity", (0.0, 0.0, 0.0))))
+                gravity=tuple(w.get("gravity", (0.0, 0.0, 0.0))), periodic=tuple(w.get("periodic", (True,) * 3)),
+                bc_type=w.get("bc_type"), bc_value=w.get("bc_value"))
 
 
 def refine_flags_base(w, mesh_tree_xyz):

@@ -58,7 +58,7 @@ BAD = [
     dict(n_ghost=1),
     dict(n_ghost=5),
     dict(n_trees=(0, 2, 2)),
-    dict(periodic=(1, 0, 1)),
+    dict(periodic=(1, 2, 1)),
     dict(n_trees=(256, 256, 1)),
     dict(max_level=15),
     dict(min_level=1, max_level=0),
@@ -113,3 +113,25 @@ def test_null_handles_are_refused(f4):
     assert L.foap4_time(None, None, None) == E_INVALID
     assert L.foap4_batch_create(None, 0, ctypes.byref(out)) == E_INVALID
     assert L.foap4_mesh_capture_features(None, 1) == E_INVALID
+
+
+@pytest.mark.parametrize("field,value", [("bc_type", 2), ("bc_type", -1), ("bc_value", float("inf")),
+                                         ("bc_value", float("nan"))])
+def test_bad_boundary_condition_is_refused(f4, field, value):
+    """On a bounded axis every face's boundary type must be Dirichlet (0) or
+    Neumann (1) and its value finite."""
+    d = desc(f4, periodic=(1, 0, 1))
+    getattr(d, field)[3][2] = value  # +y face, m_y
+    st, h, msg = create(f4, d)
+    assert st == E_INVALID and not h and field in msg
+
+
+def test_boundary_entries_of_periodic_axes_are_ignored(f4):
+    """Boundary entries of a periodic axis are not read: with garbage there
+    the descriptor gets past the boundary checks to the later buffer-size
+    check (one byte is too small), which refuses it before any HIP call."""
+    d = desc(f4, periodic=(1, 0, 1))
+    d.bc_type[0][0] = 7            # -x face: periodic axis
+    d.bc_value[1][1] = float("nan")
+    st, h, msg = create(f4, d, nbytes=1)
+    assert st == E_INVALID and not h and "smaller" in msg
