@@ -19,10 +19,14 @@ struct Geo {
   __device__ __forceinline__ int64_t at(const int c[3]) const { return cell_off<NDIM>(c[0], c[1], c[2], N, g); }
 };
 
-__device__ __forceinline__ void tangential(int ndim, int ax, int &t1, int &t2) {
-  t1 = (ax == 0) ? 1 : 0;
-  t2 = (ndim == 3) ? ((ax == 2) ? 1 : 2) : -1;
-}
+// Tangential axes of a face with normal AX, in increasing order.  The face
+// axis is a template parameter of every record routine, so the small
+// coordinate arrays below are indexed statically and stay in registers.
+template <int NDIM, int AX>
+struct Tang {
+  static constexpr int t1 = (AX == 0) ? 1 : 0;
+  static constexpr int t2 = (NDIM == 3) ? ((AX == 2) ? 1 : 2) : -1;
+};
 
 __device__ __forceinline__ double mm(double a, double b) {
   if (a > 0.0 && b > 0.0) return a < b ? a : b;
@@ -30,14 +34,13 @@ __device__ __forceinline__ double mm(double a, double b) {
   return 0.0;
 }
 
-template <typename T, int NDIM, int N>
-__device__ void srl_record(const MeshDev &M, T *u, int ax, int32_t a, int32_t b) {
+template <typename T, int NDIM, int N, int ax>
+__device__ void srl_record(const MeshDev &M, T *u, int32_t a, int32_t b) {
   constexpr int NV = NDIM + 2;
   constexpr int N2 = (NDIM == 3) ? N : 1;
   const Geo<NDIM> G(N, M.g);
   const int g = M.g;
-  int t1, t2;
-  tangential(NDIM, ax, t1, t2);
+  constexpr int t1 = Tang<NDIM, ax>::t1, t2 = Tang<NDIM, ax>::t2;
   const int64_t bel = G.sv * NV;
   const int total = 2 * NV * N2 * N * g;
   constexpr int B = 8;  // elements in flight per thread: loads first, then stores
@@ -50,18 +53,23 @@ __device__ void srl_record(const MeshDev &M, T *u, int ax, int32_t a, int32_t b)
       dsto[q] = -1;
       if (e >= total) continue;
       int l, p1, p2, v, side, r = e;
-      if (ax == 0) {  // x ghost layers of a row are contiguous in memory: layer fastest
+      if (ax == 0) {         // x ghost layers of a row are contiguous in memory: layer fastest
         l = r % g; r /= g;
         p1 = r % N; r /= N;
-      } else {        // rows along x are contiguous: t1 (= x) fastest
+        p2 = r % N2; r /= N2;
+      } else if (ax == 1) {  // rows along x are contiguous, the g ghost rows adjacent
         p1 = r % N; r /= N;
+        l = r % g; r /= g;
+        p2 = r % N2; r /= N2;
+      } else {               // a z ghost plane is N^2 contiguous values: x, then y
+        p1 = r % N; r /= N;
+        p2 = r % N2; r /= N2;
         l = r % g; r /= g;
       }
-      p2 = r % N2; r /= N2;
       v = r % NV; side = r / NV;
       int src[3] = {0, 0, 0}, dst[3] = {0, 0, 0};
       src[t1] = dst[t1] = p1;
-      if (t2 >= 0) src[t2] = dst[t2] = p2;
+      if constexpr (t2 >= 0) src[t2] = dst[t2] = p2;
       int64_t sb, db;
       if (side == 0) {  // b's -ax ghosts from a's last layers
         src[ax] = N - 1 - l; dst[ax] = -1 - l; sb = a; db = b;
@@ -105,15 +113,14 @@ __device__ __forceinline__ double fine_mean(const T *uq, const Geo<NDIM> &G, con
   }
 }
 
-template <typename T, int NDIM, int N>
-__device__ void f2c_record(const MeshDev &M, T *u, int f, int32_t cb, int32_t q, int32_t h) {
+template <typename T, int NDIM, int N, int ax>
+__device__ void f2c_record(const MeshDev &M, T *u, int side, int32_t cb, int32_t q, int32_t h) {
   constexpr int NV = NDIM + 2;
   constexpr int H = N / 2;
   constexpr int H2 = (NDIM == 3) ? H : 1;
   const Geo<NDIM> G(N, M.g);
-  const int g = M.g, ax = f / 2, side = f % 2;
-  int t1, t2;
-  tangential(NDIM, ax, t1, t2);
+  const int g = M.g;
+  constexpr int t1 = Tang<NDIM, ax>::t1, t2 = Tang<NDIM, ax>::t2;
   const int bt1 = h & 1, bt2 = (h >> 1) & 1;
   const int64_t bel = G.sv * NV;
   const int total = NV * H2 * H * g;
@@ -133,7 +140,7 @@ __device__ void f2c_record(const MeshDev &M, T *u, int f, int32_t cb, int32_t q,
     base[ax] = side ? 2 * (L - 1) : N - 2 * L;
     cc[t1] = bt1 * H + p1;
     base[t1] = 2 * p1;
-    if (t2 >= 0) {
+    if constexpr (t2 >= 0) {
       cc[t2] = bt2 * H + p2;
       base[t2] = 2 * p2;
     }
@@ -161,15 +168,14 @@ __device__ __forceinline__ double prolong(const T *uc, const Geo<NDIM> &G, const
   return up + 0.25 * corr;
 }
 
-template <typename T, int NDIM, int N>
-__device__ void c2f_record(const MeshDev &M, T *u, int f, int32_t q, int32_t cb, int32_t h) {
+template <typename T, int NDIM, int N, int ax>
+__device__ void c2f_record(const MeshDev &M, T *u, int side, int32_t q, int32_t cb, int32_t h) {
   constexpr int NV = NDIM + 2;
   constexpr int N2 = (NDIM == 3) ? N : 1;
   constexpr int H = N / 2;
   const Geo<NDIM> G(N, M.g);
-  const int g = M.g, ax = f / 2, side = f % 2;
-  int t1, t2;
-  tangential(NDIM, ax, t1, t2);
+  const int g = M.g;
+  constexpr int t1 = Tang<NDIM, ax>::t1, t2 = Tang<NDIM, ax>::t2;
   const int bt1 = h & 1, bt2 = (h >> 1) & 1;
   const int64_t bel = G.sv * NV;
   const int total = NV * N2 * N * g;
@@ -192,7 +198,7 @@ __device__ void c2f_record(const MeshDev &M, T *u, int f, int32_t q, int32_t cb,
     fc[t1] = p1;
     P[t1] = bt1 * H + (p1 >> 1);
     sig[t1] = (p1 & 1) ? 1 : -1;
-    if (t2 >= 0) {
+    if constexpr (t2 >= 0) {
       fc[t2] = p2;
       P[t2] = bt2 * H + (p2 >> 1);
       sig[t2] = (p2 & 1) ? 1 : -1;
@@ -205,66 +211,105 @@ __device__ void c2f_record(const MeshDev &M, T *u, int f, int32_t q, int32_t cb,
 // Physical boundary face f of block b: ghost layer L = 1..g outside the face
 // from the L-th cell inside, 2 u_b - u_in (Dirichlet value u_b) or
 // u_in + (2L - 1) dx u'_b (Neumann, outward derivative u'_b); FP64 without
-// contraction, rounded once.
-template <typename T, int NDIM, int N>
-__device__ void bc_record(const MeshDev &M, T *u, int f, int32_t b) {
+// contraction, rounded once.  As in the SRL copy, each thread keeps B
+// elements in flight (loads first, then stores).
+template <typename T, int NDIM, int N, int ax>
+__device__ void bc_record(const MeshDev &M, T *u, int side, int32_t b) {
 #pragma clang fp contract(off)
   constexpr int NV = NDIM + 2;
   constexpr int N2 = (NDIM == 3) ? N : 1;
   const Geo<NDIM> G(N, M.g);
-  const int g = M.g, ax = f / 2, side = f % 2;
-  int t1, t2;
-  tangential(NDIM, ax, t1, t2);
+  const int g = M.g, f = 2 * ax + side;
+  constexpr int t1 = Tang<NDIM, ax>::t1, t2 = Tang<NDIM, ax>::t2;
   T *ub = u + (int64_t)b * G.sv * NV;
   const double dx = ldexp(M.dx0, -M.level[b]);
   const int total = NV * N2 * N * g;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    int l, p1, p2, v, r = e;
-    if (ax == 0) {
-      l = r % g; r /= g;
-      p1 = r % N; r /= N;
-    } else {
-      p1 = r % N; r /= N;
-      l = r % g; r /= g;
+  constexpr int B = 8;
+  for (int e0 = threadIdx.x; e0 < total; e0 += B * blockDim.x) {
+    double uin[B];
+    int dsto[B], vq[B], Lq[B];
+#pragma unroll
+    for (int q = 0; q < B; q++) {
+      const int e = e0 + q * blockDim.x;
+      dsto[q] = -1;
+      if (e >= total) continue;
+      int l, p1, p2, v, r = e;
+      if (ax == 0) {         // the same element orders as the SRL copy
+        l = r % g; r /= g;
+        p1 = r % N; r /= N;
+        p2 = r % N2; r /= N2;
+      } else if (ax == 1) {
+        p1 = r % N; r /= N;
+        l = r % g; r /= g;
+        p2 = r % N2; r /= N2;
+      } else {
+        p1 = r % N; r /= N;
+        p2 = r % N2; r /= N2;
+        l = r % g; r /= g;
+      }
+      v = r;
+      const int L = l + 1;
+      int gc[3] = {0, 0, 0}, ic[3] = {0, 0, 0};
+      gc[ax] = side ? N - 1 + L : -L;
+      ic[ax] = side ? N - L : L - 1;
+      gc[t1] = ic[t1] = p1;
+      if constexpr (t2 >= 0) gc[t2] = ic[t2] = p2;
+      uin[q] = (double)ub[v * G.sv + G.at(ic)];
+      dsto[q] = (int)(v * G.sv + G.at(gc));
+      vq[q] = v;
+      Lq[q] = L;
     }
-    p2 = r % N2; v = r / N2;
-    const int L = l + 1;
-    int gc[3] = {0, 0, 0}, ic[3] = {0, 0, 0};
-    gc[ax] = side ? N - 1 + L : -L;
-    ic[ax] = side ? N - L : L - 1;
-    gc[t1] = ic[t1] = p1;
-    if (t2 >= 0) gc[t2] = ic[t2] = p2;
-    const double uin = (double)ub[v * G.sv + G.at(ic)];
-    const double val = M.bc_val[f][v];
-    const double out = (M.bc_type[f][v] == 0) ? 2.0 * val - uin : uin + ((double)(2 * L - 1) * dx) * val;
-    ub[v * G.sv + G.at(gc)] = (T)out;
+#pragma unroll
+    for (int q = 0; q < B; q++) {
+      if (dsto[q] < 0) continue;
+      const double val = M.bc_val[f][vq[q]];
+      const double out = (M.bc_type[f][vq[q]] == 0) ? 2.0 * val - uin[q]
+                                                    : uin[q] + ((double)(2 * Lq[q] - 1) * dx) * val;
+      ub[dsto[q]] = (T)out;
+    }
   }
 }
 
 template <typename T, int NDIM, int N>
 __device__ void ghost_item(const MeshDev &M, int round, int64_t r, int which) {
   T *u = (T *)M.s[which == 0 ? M.cur : 1 - M.cur];
+  // the record's face f = 2 axis + side; the axis selects the routine
+#define F4_BY_AXIS(CALL)                           \
+  switch (f >> 1) {                                \
+    case 0: CALL(0); break;                        \
+    case 1: CALL(1); break;                        \
+    default: if constexpr (NDIM == 3) CALL(2);     \
+  }
   if (round == 1) {
     if (r < M.r1_srl) {
       int f = 1;
       while (r >= M.poff[kSRL][f + 1]) f += 2;
-      srl_record<T, NDIM, N>(M, u, f / 2, M.srl[2 * r], M.srl[2 * r + 1]);
+#define F4_SRL(A) srl_record<T, NDIM, N, A>(M, u, M.srl[2 * r], M.srl[2 * r + 1])
+      F4_BY_AXIS(F4_SRL)
+#undef F4_SRL
     } else if (r < M.r1_srl + M.pn[kF2C]) {
       r -= M.r1_srl;
       int f = 0;
       while (r >= M.poff[kF2C][f + 1]) f++;
-      f2c_record<T, NDIM, N>(M, u, f, M.f2c[4 * r], M.f2c[4 * r + 1], M.f2c[4 * r + 2]);
+#define F4_F2C(A) f2c_record<T, NDIM, N, A>(M, u, f & 1, M.f2c[4 * r], M.f2c[4 * r + 1], M.f2c[4 * r + 2])
+      F4_BY_AXIS(F4_F2C)
+#undef F4_F2C
     } else {
       r -= M.r1_srl + M.pn[kF2C];
       int f = 0;
       while (r >= M.poff[kBC][f + 1]) f++;
-      bc_record<T, NDIM, N>(M, u, f, M.bc[r]);
+#define F4_BC(A) bc_record<T, NDIM, N, A>(M, u, f & 1, M.bc[r])
+      F4_BY_AXIS(F4_BC)
+#undef F4_BC
     }
   } else {
     int f = 0;
     while (r >= M.poff[kC2F][f + 1]) f++;
-    c2f_record<T, NDIM, N>(M, u, f, M.c2f[3 * r], M.c2f[3 * r + 1], M.c2f[3 * r + 2]);
+#define F4_C2F(A) c2f_record<T, NDIM, N, A>(M, u, f & 1, M.c2f[3 * r], M.c2f[3 * r + 1], M.c2f[3 * r + 2])
+    F4_BY_AXIS(F4_C2F)
+#undef F4_C2F
   }
+#undef F4_BY_AXIS
 }
 
 template <typename T, int NDIM>
