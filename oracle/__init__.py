@@ -75,6 +75,7 @@ class _MeshC(ctypes.Structure):
                 ("c2f", ctypes.c_void_p), ("c2f_off", ctypes.c_void_p),
                 ("bc", ctypes.c_void_p), ("bc_off", ctypes.c_void_p),
                 ("bc_type", (ctypes.c_int32 * 5) * 6), ("bc_val", (ctypes.c_double * 5) * 6),
+                ("bc_data", ctypes.c_void_p),
                 ("limiter", ctypes.c_int32), ("flux", ctypes.c_int32), ("grav", ctypes.c_double * 3)]
 
 
@@ -124,6 +125,8 @@ class OracleMesh:
         self.origin = origin
         self.limiter, self.flux = LIMITERS[limiter], FLUXES[flux]
         self.gravity = tuple(float(x) for x in gravity) + (0.0,) * (3 - len(gravity))
+        self.bc_data = None
+        self.bc_callback = None
         self.bc_type = np.zeros((6, 5), np.int32)
         self.bc_value = np.zeros((6, 5))
         if bc_type is not None:
@@ -160,6 +163,7 @@ class OracleMesh:
         c.gamma, c.cfl = self.gamma, self.cfl
         c.limiter, c.flux = self.limiter, self.flux
         c.grav[:] = list(self.gravity)
+        c.bc_data = _ptr(self.bc_data) if self.bc_data is not None else None
         for f in range(6):
             c.bc_type[f][:] = [int(x) for x in self.bc_type[f]]
             c.bc_val[f][:] = [float(x) for x in self.bc_value[f]]
@@ -174,6 +178,21 @@ class OracleMesh:
 
     def cref(self):
         return ctypes.byref(self._c)
+
+    def set_bc_data(self, data, callback=None):
+        """Spatially varying boundary values (eq. bc-data): [n boundary
+        records][nvar][N^(ndim-1)] in the order of pat['bc'], face cells
+        with the lower tangential axis fastest; None: the uniform values.
+        callback(mesh) -> data is called after every regrid that changes the
+        mesh (Sec. 2.4); without one the data is dropped then."""
+        self.bc_callback = callback
+        if data is None:
+            self.bc_data = None
+        else:
+            nbf = int(self.pat["bc_off"][-1])
+            self.bc_data = np.ascontiguousarray(data, dtype=np.float64).reshape(nbf, self.nvar, -1)
+            assert self.bc_data.shape[2] == self.N ** (self.ndim - 1)
+        self._c.bc_data = _ptr(self.bc_data) if self.bc_data is not None else None
 
     def interior(self, u=None):
         u = self.u if u is None else u
@@ -261,7 +280,10 @@ class OracleMesh:
         if res is None:
             return None
         op, src, arg = res
+        self.bc_data = None
         self._refresh()
+        if self.bc_callback is not None:
+            self.set_bc_data(self.bc_callback(self), self.bc_callback)
         self.u = self.alloc()
         lib().om_remap(ctypes.byref(old_c), _ptr(old_u), self.cref(), _ptr(self.u),
                        _ptr(op), _ptr(src), _ptr(arg))

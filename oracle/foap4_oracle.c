@@ -56,6 +56,9 @@ typedef struct {
   const int32_t *bc_off;
   int32_t bc_type[6][5];  /* per face direction and variable: 0 Dirichlet, 1 Neumann */
   double bc_val[6][5];    /* boundary value u_b, or outward normal derivative u'_b */
+  const double *bc_data;  /* optional spatially varying values (eq. bc-data):
+                             [boundary record][var][face cell p1 + N p2], replacing
+                             bc_val where given                                   */
   int32_t limiter;        /* reconstruction slope limiter: 0 minmod, 1 van Leer  */
   int32_t flux;           /* numerical flux: 0 Rusanov, 1 HLL                     */
   double grav[3];         /* gravitational acceleration; all zero: no source term */
@@ -246,8 +249,9 @@ static void fill_c2f(const om_mesh *m, double *u, int f, int32_t q, int32_t cb, 
  * l-th cell inside, reflected through the boundary condition at the face:
  *   Dirichlet (u = u_b on the face):        2 u_b - u_in
  *   Neumann (du/dn = u'_b, n outward):      u_in + (2l - 1) dx u'_b
- * (the face lies (l - 1/2) dx from both cells). */
-static void fill_bc(const om_mesh *m, double *u, int f, int32_t b) {
+ * (the face lies (l - 1/2) dx from both cells).  With bc_data, u_b / u'_b
+ * are given per face cell (p1, p2) of every boundary record r. */
+static void fill_bc(const om_mesh *m, double *u, int f, int32_t r, int32_t b) {
   int N = m->N, ax = f / 2, side = f % 2, t1, t2;
   tangential_axes(m->ndim, ax, &t1, &t2);
   double dx = dx_of(m, b);
@@ -262,7 +266,7 @@ static void fill_bc(const om_mesh *m, double *u, int f, int32_t b) {
           gc[t1] = ic[t1] = p1;
           if (t2 >= 0) gc[t2] = ic[t2] = p2;
           double uin = u[ix(m, b, v, ic)];
-          double ub = m->bc_val[f][v];
+          double ub = m->bc_data ? m->bc_data[((int64_t)r * m->nvar + v) * (N * n2) + p1 + N * p2] : m->bc_val[f][v];
           u[ix(m, b, v, gc)] = (m->bc_type[f][v] == 0) ? 2.0 * ub - uin : uin + ((2 * l - 1) * dx) * ub;
         }
 }
@@ -291,7 +295,7 @@ void om_ghost_round(const om_mesh *m, double *u, int round) {
   if (m->bc)
     for (int f = 0; f < nf; f++) {
 #pragma omp parallel for schedule(static)
-      for (int32_t r = m->bc_off[f]; r < m->bc_off[f + 1]; r++) fill_bc(m, u, f, m->bc[r]);
+      for (int32_t r = m->bc_off[f]; r < m->bc_off[f + 1]; r++) fill_bc(m, u, f, r, m->bc[r]);
     }
 }
 
