@@ -121,6 +121,23 @@ foap4_status foap4_mesh_destroy(foap4_mesh *mesh);
 foap4_status foap4_mesh_info(const foap4_mesh *mesh, int64_t *n_blocks, int64_t *revision,
                              int32_t *cur_state);
 
+/* Spatially varying boundary values (Sec. 2.4, eq. bc-data).  bc_data_dev
+ * is a caller-owned FP64 device array of n_values = n_bc * nvar * N^(ndim-1)
+ * values, [boundary record][variable][face cell], the boundary records in the
+ * order foap4_ghost_pattern_export returns them (grouped by face direction),
+ * face cells p1 + N p2 over the face's tangential axes in increasing order
+ * (p1 fastest).  Where given, these values replace bc_value (the types stay
+ * those of bc_type).  NULL restores the uniform values.  The array must stay
+ * valid while the mesh (or a batch holding it) uses it.  When a regrid changes
+ * the mesh, the library drops the array (its records no longer match) and, if
+ * on_change is set, calls on_change(mesh, user) on the host from inside
+ * foap4_regrid once the new pattern exists; the callback may call
+ * foap4_set_bc_data with data for the new records.  Errors: FOAP4_E_INVALID
+ * (n_values does not match). */
+typedef void (*foap4_bc_callback)(foap4_mesh *mesh, void *user);
+foap4_status foap4_set_bc_data(foap4_mesh *mesh, const double *bc_data_dev, int64_t n_values,
+                               foap4_bc_callback on_change, void *user);
+
 /* Host copies of the leaf table: level[n_blocks], tree[n_blocks] (tree id
  * t_x + n_x (t_y + n_y t_z)) and anchor[n_blocks][3] (integer position of the
  * block inside its tree at its level).  Any pointer may be NULL. */

@@ -52,12 +52,14 @@ def wall_bc(ndim):
 
 _lib = None
 P = ctypes.c_void_p
+_BC_CB = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 I32, I64, DBL = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 
 EXPORTS = {
     # name: (restype, argtypes)
     "foap4_mesh_create": (I32, [ctypes.POINTER(MeshDesc), P, P, ctypes.c_size_t, P, ctypes.POINTER(P)]),
     "foap4_mesh_destroy": (I32, [P]),
+    "foap4_set_bc_data": (I32, [P, P, I64, P, P]),
     "foap4_mesh_info": (I32, [P, P, P, P]),
     "foap4_mesh_export": (I32, [P, P, P, P]),
     "foap4_ghost_pattern_build": (I32, [P]),
@@ -291,6 +293,31 @@ class Mesh:
         r = torch.empty((max(nb, 1), 2), dtype=torch.float64, device=self.state[0].device) if raw else None
         _check(lib().foap4_captured_features(self.h, P(feat.data_ptr()), P(r.data_ptr()) if raw else None), self.h)
         return (feat[:nb], r[:nb]) if raw else feat[:nb]
+
+    def set_bc_data(self, data, callback=None):
+        """Spatially varying boundary values (eq. bc-data; include/foap4.h):
+        data is an FP64 device tensor [n_bc][nvar][N^(ndim-1)] in the order of
+        pattern_export()["bc"] (face cells with the lower tangential axis
+        fastest), or None for the uniform values.  callback(mesh) -> tensor or
+        None is called after every regrid that changes the mesh, to give the
+        values for the new boundary records."""
+        self._bc_py = callback
+        self._bc_cb = None
+        if callback is not None:
+            def trampoline(_h, _user):
+                self._apply_bc(self._bc_py(self))
+            self._bc_cb = _BC_CB(trampoline)
+        self._apply_bc(data)
+
+    def _apply_bc(self, data):
+        torch = _torch()
+        if data is not None:
+            data = data.to(device=self.state[0].device, dtype=torch.float64).contiguous()
+        self._bc_data = data  # kept alive while the library may read it
+        ptr = P(data.data_ptr()) if data is not None else None
+        n = data.numel() if data is not None else 0
+        cb = ctypes.cast(self._bc_cb, P) if self._bc_cb is not None else None
+        _check(lib().foap4_set_bc_data(self.h, ptr, n, cb, None), self.h)
 
     def set_indicator(self, indicator, mlp=None):
         """Indicator used by regrid() without flags; mlp is kept referenced."""

@@ -34,6 +34,7 @@ MeshDev make_dev(const foap4_mesh *m, int ks, int gather) {
   d.f2c = m->pat.f2c;
   d.c2f = m->pat.c2f;
   d.bc = m->pat.bc;
+  d.bc_data = m->bc_data;
   d.fix_list = m->pat.fix_list;
   d.bflux_f = m->pat.bflux_f;
   d.bflux_c = m->pat.bflux_c;
@@ -124,7 +125,7 @@ using namespace f4;
 // ------------------------------------------------------------------ batch type
 struct foap4_batch {
   std::vector<foap4_mesh *> meshes;
-  std::vector<int64_t> revs;
+  std::vector<int64_t> revs, serials;
   int ndim = 3;
   bool f64 = false;
   int ks = 1, wg1 = 0, wg2 = 0, gather = 1, xcd = 1;  // wg1 / wg2: workgroups per CU of stage 1 / 2
@@ -526,12 +527,27 @@ foap4_status foap4_regrid(foap4_mesh *m, const int8_t *flags_host, int32_t *chan
   m->topo.leaves.swap(nl);
   m->topo.sort_and_index();
   m->revision++;
+  m->bc_data = nullptr;  // its records belong to the old mesh
   if ((st = upload_leaves(m)) != FOAP4_OK) return st;
   if ((st = build_pattern(m)) != FOAP4_OK) return st;
   if ((st = upload_dev(m)) != FOAP4_OK) return st;
   m->dt_valid = false;
   if (changed) *changed = 1;
+  if (m->bc_cb) m->bc_cb(m, m->bc_user);  // may set new boundary data (Sec. 2.4)
   return FOAP4_OK;
+}
+
+foap4_status foap4_set_bc_data(foap4_mesh *m, const double *data, int64_t n_values, foap4_bc_callback on_change,
+                               void *user) {
+  if (!m) return fail(nullptr, FOAP4_E_INVALID, "null mesh");
+  const int64_t per = (int64_t)m->nvar * (m->d.ndim == 3 ? m->d.block_n * m->d.block_n : m->d.block_n);
+  if (data && n_values != (int64_t)m->pat.n[kBC] * per)
+    return fail(m, FOAP4_E_INVALID, "bc_data must hold n_bc * nvar * N^(ndim-1) values");
+  m->bc_data = data;
+  m->bc_cb = on_change;
+  m->bc_user = user;
+  m->dev_serial++;
+  return upload_dev(m);
 }
 
 // -------------------------------------------------------------------- batch
@@ -607,7 +623,7 @@ static hipError_t batch_enqueue_step(foap4_batch *b, hipStream_t s) {
 static foap4_status batch_prepare(foap4_batch *b) {
   bool stale = !b->graph_valid;
   for (size_t i = 0; i < b->meshes.size(); i++)
-    if (b->meshes[i]->revision != b->revs[i]) stale = true;
+    if (b->meshes[i]->revision != b->revs[i] || b->meshes[i]->dev_serial != b->serials[i]) stale = true;
   for (foap4_mesh *m : b->meshes)
     if (!m->dt_valid) {
       foap4_status st = ensure_dt(m);
@@ -616,7 +632,10 @@ static foap4_status batch_prepare(foap4_batch *b) {
     }
   if (!stale) return FOAP4_OK;
   drop_graph(b);
-  for (size_t i = 0; i < b->meshes.size(); i++) b->revs[i] = b->meshes[i]->revision;
+  for (size_t i = 0; i < b->meshes.size(); i++) {
+    b->revs[i] = b->meshes[i]->revision;
+    b->serials[i] = b->meshes[i]->dev_serial;
+  }
   foap4_status st = batch_upload(b);
   if (st != FOAP4_OK) return st;
   B_HIP(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -644,6 +663,7 @@ foap4_status foap4_batch_create(foap4_mesh *const *meshes, int32_t n, foap4_batc
     }
     b->meshes.push_back(meshes[i]);
     b->revs.push_back(-1);
+    b->serials.push_back(-1);
   }
   b->ndim = meshes[0]->d.ndim;
   b->f64 = meshes[0]->d.prec == FOAP4_F64;

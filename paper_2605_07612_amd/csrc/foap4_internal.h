@@ -89,6 +89,7 @@ struct MeshDev {
   // 2*slot for a C2F face (fine-side flux slot), 2*slot+1 for an F2C face
   const int32_t *face_info;
   const int32_t *srl, *f2c, *c2f, *bc, *fix_list;  // ghost pattern records
+  const double *bc_data;      // per-face-cell boundary values [bc record][var][N^(d-1)], or null
   void *bflux_f;              // fine-side face fluxes [n_c2f][nvar][N^(d-1)]
   void *bflux_c;              // coarse-side face fluxes [n_f2c/2^(d-1)][nvar][N^(d-1)]
   double *scal;               // kDt, kTime, kMaxInv, kBad ...
@@ -158,6 +159,11 @@ struct foap4_mesh {
   size_t cap_featcap = 0;      // in blocks
   int64_t steps_done = 0;      // steps taken by foap4_step since creation
   int64_t cap_at = -1, cap_rev = -1;  // steps_done and revision when captured
+  // spatially varying boundary values (caller-owned) and the mesh-change callback
+  const double *bc_data = nullptr;
+  foap4_bc_callback bc_cb = nullptr;
+  void *bc_user = nullptr;
+  int64_t dev_serial = 0;      // bumped when the device descriptor changes without a regrid
   std::string err;
 };
 

@@ -211,10 +211,12 @@ __device__ void c2f_record(const MeshDev &M, T *u, int side, int32_t q, int32_t 
 // Physical boundary face f of block b: ghost layer L = 1..g outside the face
 // from the L-th cell inside, 2 u_b - u_in (Dirichlet value u_b) or
 // u_in + (2L - 1) dx u'_b (Neumann, outward derivative u'_b); FP64 without
-// contraction, rounded once.  As in the SRL copy, each thread keeps B
+// contraction, rounded once.  u_b / u'_b come from the per-face-cell array
+// bc_data (record rec, variable, face cell p1 + N p2) when it is set, else
+// from the uniform per-face values.  As in the SRL copy, each thread keeps B
 // elements in flight (loads first, then stores).
 template <typename T, int NDIM, int N, int ax>
-__device__ void bc_record(const MeshDev &M, T *u, int side, int32_t b) {
+__device__ void bc_record(const MeshDev &M, T *u, int side, int64_t rec, int32_t b) {
 #pragma clang fp contract(off)
   constexpr int NV = NDIM + 2;
   constexpr int N2 = (NDIM == 3) ? N : 1;
@@ -227,7 +229,7 @@ __device__ void bc_record(const MeshDev &M, T *u, int side, int32_t b) {
   constexpr int B = 8;
   for (int e0 = threadIdx.x; e0 < total; e0 += B * blockDim.x) {
     double uin[B];
-    int dsto[B], vq[B], Lq[B];
+    int dsto[B], vq[B], Lq[B], cq[B];
 #pragma unroll
     for (int q = 0; q < B; q++) {
       const int e = e0 + q * blockDim.x;
@@ -258,11 +260,12 @@ __device__ void bc_record(const MeshDev &M, T *u, int side, int32_t b) {
       dsto[q] = (int)(v * G.sv + G.at(gc));
       vq[q] = v;
       Lq[q] = L;
+      cq[q] = p1 + N * p2;
     }
 #pragma unroll
     for (int q = 0; q < B; q++) {
       if (dsto[q] < 0) continue;
-      const double val = M.bc_val[f][vq[q]];
+      const double val = M.bc_data ? M.bc_data[(rec * NV + vq[q]) * (N * N2) + cq[q]] : M.bc_val[f][vq[q]];
       const double out = (M.bc_type[f][vq[q]] == 0) ? 2.0 * val - uin[q]
                                                     : uin[q] + ((double)(2 * Lq[q] - 1) * dx) * val;
       ub[dsto[q]] = (T)out;
@@ -298,7 +301,7 @@ __device__ void ghost_item(const MeshDev &M, int round, int64_t r, int which) {
       r -= M.r1_srl + M.pn[kF2C];
       int f = 0;
       while (r >= M.poff[kBC][f + 1]) f++;
-#define F4_BC(A) bc_record<T, NDIM, N, A>(M, u, f & 1, M.bc[r])
+#define F4_BC(A) bc_record<T, NDIM, N, A>(M, u, f & 1, r, M.bc[r])
       F4_BY_AXIS(F4_BC)
 #undef F4_BC
     }

@@ -113,6 +113,7 @@ def test_null_handles_are_refused(f4):
     assert L.foap4_time(None, None, None) == E_INVALID
     assert L.foap4_batch_create(None, 0, ctypes.byref(out)) == E_INVALID
     assert L.foap4_mesh_capture_features(None, 1) == E_INVALID
+    assert L.foap4_set_bc_data(None, None, 0, None, None) == E_INVALID
 
 
 @pytest.mark.parametrize("field,value", [("bc_type", 2), ("bc_type", -1), ("bc_value", float("inf")),

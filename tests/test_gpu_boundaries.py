@@ -290,3 +290,136 @@ def test_batch_equals_plain(f4, prec):
         assert np.array_equal(A, B), w["name"]
         assert p.time() == q.time()
     b.close()
+
+
+# -------------------------------------------------- spatially varying values
+
+def face_values(mesh, fn, nvar):
+    """bc_data (eq. bc-data) of a GPU mesh: fn(v, x) at the centre of every
+    face cell of every boundary record, from the mesh's own pattern export
+    and leaf coordinates."""
+    import torch
+    from paper_2605_07612_amd import layout
+    pat = mesh.pattern_export()
+    lev, G = layout.global_coords(mesh)
+    N, nd = mesh.N, mesh.ndim
+    n2 = N if nd == 3 else 1
+    p1, p2 = np.meshgrid(np.arange(N), np.arange(n2), indexing="xy")
+    p1, p2 = p1.ravel(), p2.ravel()
+    out = np.zeros((len(pat["bc"]), nvar, N * n2))
+    for f in range(2 * nd):
+        ax, side = f // 2, f % 2
+        t = [d for d in range(nd) if d != ax]
+        for r in range(pat["bc_off"][f], pat["bc_off"][f + 1]):
+            b = int(pat["bc"][r])
+            dx = mesh.desc.tree_size / (N << int(lev[b]))
+            x = [None] * nd
+            x[ax] = np.full(N * n2, (G[b, ax] * N + (N if side else 0)) * dx)
+            x[t[0]] = (G[b, t[0]] * N + p1 + 0.5) * dx
+            if nd == 3:
+                x[t[1]] = (G[b, t[1]] * N + p2 + 0.5) * dx
+            for v in range(nvar):
+                out[r, v] = fn(v, x)
+    return torch.tensor(out, device="cuda")
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_bc_data_linear_exact_through_regrids(f4, ndim):
+    """The paper's form of the Sec. 4.3 test on the GPU: Dirichlet values of
+    the linear solution at every boundary face cell through the spatially
+    varying array, renewed by the mesh-change callback at each regrid (the
+    uniform values are 1e9, so any cell that missed the array shows)."""
+    from paper_2605_07612_amd import layout
+    A = (0.0, 1.0, -1.0, 2.0, 5.0)
+    B = (1.0, -2.0, 0.5, 3.0, 0.0)
+    coef = (1.0, 2.0, 3.0)
+    nv = ndim + 2
+    fn = lambda v, x: A[v] + B[v] * sum(coef[d] * x[d] for d in range(ndim))
+    N, g = 8, 2
+    m = f4.Mesh(ndim, (2, 2, 2), N, g, 0.5, level=0, max_level=3, max_blocks=2 ** ndim * 8 ** ndim, prec=f4.F64,
+                periodic=(False,) * 3, bc_type=np.zeros((6, 5), np.int32), bc_value=np.full((6, 5), 1e9))
+    calls = []
+
+    def renew(mesh):
+        calls.append(mesh.nb)
+        return face_values(mesh, fn, nv)
+
+    m.set_bc_data(face_values(m, fn, nv), callback=renew)
+    layout.set_from_field(m, lambda *x: np.stack([fn(v, list(x)) for v in range(nv)]))
+    for lev in range(2):
+        _, G = layout.global_coords(m)
+        lv = m.export()[0]
+        m.regrid((np.all(G[:, :ndim] == 0, axis=1) & (lv == lev)).astype(np.int8))
+    assert len(calls) == 2
+    m.ghost_fill()
+    u = gpu_state(m)
+    lev, Gc = layout.global_coords(m)
+    P = N + 2 * g
+    idx = np.arange(-g, N + g) + 0.5
+    mask = face_ghost_mask(ndim, N, g)
+    for n in range(m.nb):
+        dx = 0.5 / (N << int(lev[n]))
+        cent = []
+        for d in range(ndim):
+            shape = [1] * ndim
+            shape[ndim - 1 - d] = P
+            cent.append(np.broadcast_to(((Gc[n, d] * N + idx) * dx).reshape(shape), (P,) * ndim))
+        for v in range(nv):
+            want = fn(v, cent)[mask]
+            assert np.all(np.abs(u[n, v][mask] - want) <= 1e-15 * max(1.0, abs(A[v]) + 6 * abs(B[v]))), (n, v)
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["f64", "f32"])
+def test_bc_data_step_parity_and_batch(f4, prec):
+    """A bounded two-level blast with spatially varying Dirichlet (density,
+    energy) and Neumann (momenta) values: the plain step against the oracle
+    given the same array, and a batch that picks up the array set after the
+    batch was created, bit for bit equal to the plain step."""
+    import torch
+    w = closed_box_blast(3)
+    t = np.ones((6, 5), np.int32)
+    t[:, 0] = t[:, 4] = 0
+    val = np.zeros((6, 5))
+    val[:, 0], val[:, 4] = 1.0, 0.25  # uniform values: the blast's ambient state
+    w["bc_type"], w["bc_value"] = t, val
+
+    def fn(v, x):
+        s = np.sin(2 * np.pi * x[0]) * np.cos(2 * np.pi * x[1]) + 0.5 * np.sin(2 * np.pi * x[2])
+        return (1.0 + 0.2 * s) if v == 0 else (0.3 + 0.05 * s) if v == 4 else 0.1 * s
+
+    gm, om = build_pair(w, prec)
+    gm.set_bc_data(face_values(gm, fn, 5))
+    om.set_bc_data(face_values(gm, fn, 5).cpu().numpy())
+    gm2 = build_pair(w, prec)[0]
+    b = f4.Batch([gm2])
+    b.step(1)  # the batch's descriptors without the array
+    gm2.set_bc_data(face_values(gm2, fn, 5))
+    gm.step(1)
+    steps = 8
+    om.step(steps + 1)
+    gm.step(steps)
+    b.step(steps)
+    lev = gm.export()[0]
+    a = interior(gpu_state(gm), 2, w["N"], 3)
+    err = rel_l1_vol(a, om.interior(), lev, 3, w["tree_size"], w["N"])
+    say("bc_data parity", prec, err)
+    assert err <= TOL[prec]
+    # the batch took its first step with the uniform values, so compare it
+    # with a plain mesh that did the same
+    gm3 = build_pair(w, prec)[0]
+    gm3.step(1)
+    gm3.set_bc_data(face_values(gm3, fn, 5))
+    gm3.step(steps)
+    assert np.array_equal(interior(gpu_state(gm2), 2, w["N"], 3), interior(gpu_state(gm3), 2, w["N"], 3))
+    b.close()
+
+
+def test_bc_data_size_is_checked(f4):
+    import torch
+    w = closed_box_blast(3)
+    gm, _ = build_pair(w, 0)
+    nbc = len(gm.pattern_export()["bc"])
+    with pytest.raises(f4.Foap4Error, match="E_INVALID"):
+        gm.set_bc_data(torch.zeros((nbc, 5, 63), dtype=torch.float64, device="cuda"))
+    gm.set_bc_data(None)
+    gm.step(1)
