@@ -76,7 +76,8 @@ class _MeshC(ctypes.Structure):
                 ("bc", ctypes.c_void_p), ("bc_off", ctypes.c_void_p),
                 ("bc_type", (ctypes.c_int32 * 5) * 6), ("bc_val", (ctypes.c_double * 5) * 6),
                 ("bc_data", ctypes.c_void_p),
-                ("limiter", ctypes.c_int32), ("flux", ctypes.c_int32), ("grav", ctypes.c_double * 3)]
+                ("limiter", ctypes.c_int32), ("flux", ctypes.c_int32), ("grav", ctypes.c_double * 3),
+                ("rk", ctypes.c_int32)]
 
 
 def _ptr(a):
@@ -89,6 +90,8 @@ LOHNER = dict(c_ref=5e-2, c_deref=6.25e-3, eps=1e-2, eps_abs=1e-10)
 # scheme options of Sec. 3.2: reconstruction limiter and numerical flux
 LIMITERS = {"minmod": 0, "vanleer": 1}
 FLUXES = {"rusanov": 0, "hll": 1}
+# time integrators of Sec. 3.1
+INTEGRATORS = {"heun": 0, "ssprk3": 1, "ssprk43": 2}
 
 
 def limiter(kind, a, b):
@@ -113,7 +116,7 @@ class OracleMesh:
 
     def __init__(self, ndim, trees, N, g=2, tree_size=1.0, level=0, gamma=1.4, cfl=0.5,
                  periodic=(True, True, True), origin=(0.0, 0.0, 0.0), limiter="minmod",
-                 flux="rusanov", gravity=(0.0, 0.0, 0.0), bc_type=None, bc_value=None):
+                 flux="rusanov", gravity=(0.0, 0.0, 0.0), bc_type=None, bc_value=None, integrator="heun"):
         """bc_type / bc_value: [2 ndim faces -x, +x, -y, +y, -z, +z][nvar]
         Dirichlet (0) or Neumann (1) conditions and their values (Sec. 2.4),
         used on the faces of non-periodic axes."""
@@ -124,6 +127,7 @@ class OracleMesh:
         self.tree_size, self.gamma, self.cfl = float(tree_size), float(gamma), float(cfl)
         self.origin = origin
         self.limiter, self.flux = LIMITERS[limiter], FLUXES[flux]
+        self.rk = INTEGRATORS[integrator]
         self.gravity = tuple(float(x) for x in gravity) + (0.0,) * (3 - len(gravity))
         self.bc_data = None
         self.bc_callback = None
@@ -161,7 +165,7 @@ class OracleMesh:
         c.level = _ptr(self.level)
         c.dx0 = self.tree_size / self.N
         c.gamma, c.cfl = self.gamma, self.cfl
-        c.limiter, c.flux = self.limiter, self.flux
+        c.limiter, c.flux, c.rk = self.limiter, self.flux, self.rk
         c.grav[:] = list(self.gravity)
         c.bc_data = _ptr(self.bc_data) if self.bc_data is not None else None
         for f in range(6):

@@ -18,7 +18,8 @@
  *                          source term first, then the flux divergence),
  *                          Sec. 3.5 (eq. euler, Einfeldt speeds), Sec. 4.2
  *                          (gravity source S = (0, rho g, rho g.u))
- *   Runge-Kutta stages     Sec. 3.1, eq. feuler and eq. heun
+ *   Runge-Kutta stages     Sec. 3.1, eq. feuler and eq. heun; the SSP
+ *                          schemes with three and four stages (Sec. 3.1)
  *   flux fixing            Sec. 2.7
  *   CFL time step          Sec. 3.1 / Sec. 3.2 step list
  *   refinement criterion   Sec. 3.3, eq. lohner-simple
@@ -62,6 +63,7 @@ typedef struct {
   int32_t limiter;        /* reconstruction slope limiter: 0 minmod, 1 van Leer  */
   int32_t flux;           /* numerical flux: 0 Rusanov, 1 HLL                     */
   double grav[3];         /* gravitational acceleration; all zero: no source term */
+  int32_t rk;             /* time integrator: 0 Heun (SSP-RK2), 1 SSP-RK3, 2 SSP-RK(4,3) */
 } om_mesh;
 
 /* ---------------------------------------------------------------- indexing */
@@ -482,6 +484,50 @@ void om_stage(const om_mesh *m, const double *ud, const double *up, double *uo, 
   }
 }
 
+/* One sub-step of the Runge-Kutta framework (eq. feuler):
+ *   uo = c dt L(ud) + wd ud + wp up
+ * with L as in om_stage (source first, then the flux divergence); up may be
+ * NULL when wp = 0.  uo may alias up but never ud. */
+void om_substep(const om_mesh *m, const double *ud, const double *up, double *uo, double c, double wd,
+                double wp, double dt) {
+  int N = m->N, nv = m->nvar;
+  int nk = (m->ndim == 3) ? N : 1;
+  int has_src = m->grav[0] != 0.0 || m->grav[1] != 0.0 || m->grav[2] != 0.0;
+  double cdt = c * dt;
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < m->nb; b++) {
+    double dx = dx_of(m, b);
+    for (int k = 0; k < nk; k++)
+      for (int j = 0; j < N; j++)
+        for (int i = 0; i < N; i++) {
+          int c3[3] = {i, j, k};
+          double rhs[5] = {0, 0, 0, 0, 0};
+          if (has_src) {
+            prim_t w = to_primitive(m, ud, b, c3);
+            double gu = 0.0;
+            for (int d = 0; d < m->ndim; d++) {
+              rhs[1 + d] = w.rho * m->grav[d];
+              gu += m->grav[d] * w.v[d];
+            }
+            rhs[nv - 1] = w.rho * gu;
+          }
+          for (int ax = 0; ax < m->ndim; ax++) {
+            double Fp[5], Fm[5];
+            int cl[3] = {i, j, k};
+            cl[ax] -= 1;
+            face_flux(m, ud, b, c3, ax, Fp);
+            face_flux(m, ud, b, cl, ax, Fm);
+            for (int v = 0; v < nv; v++) rhs[v] -= (Fp[v] - Fm[v]) / dx;
+          }
+          for (int v = 0; v < nv; v++) {
+            int64_t o = ix(m, b, v, c3);
+            double prev = (wp != 0.0) ? wp * up[o] : 0.0;
+            uo[o] = cdt * rhs[v] + (wd * ud[o] + prev);
+          }
+        }
+  }
+}
+
 /* Flux fixing (Sec. 2.7): every coarse cell next to a refinement boundary is
  * corrected by dt_s (F_coarse - mean F_fine) / dx_c on its +axis face and by
  * dt_s (mean F_fine - F_coarse) / dx_c on its -axis face.  Fluxes are the
@@ -593,8 +639,37 @@ int64_t om_count_unphysical(const om_mesh *m, const double *u) {
 /* One Heun step (eq. heun) with ghost filling before each evaluation of L
  * and flux fixing after each stage: u0 holds U^n on entry and U^{n+1} on
  * exit, u1 is scratch.  Returns the dt that was used. */
+/* One sub-step of a step with its ghost fill before and flux fix after. */
+static void substep(const om_mesh *m, double *ud, double *up, double *uo, double c, double wd, double wp,
+                    double dt) {
+  om_ghost_fill(m, ud);
+  om_substep(m, ud, up, uo, c, wd, wp, dt);
+  om_flux_fix(m, ud, uo, c * dt);
+}
+
 double om_step(const om_mesh *m, double *u0, double *u1) {
   double dt = om_dt(m, u0);
+  if (m->rk == 1 || m->rk == 2) {
+    /* a third state: the SSP schemes with three and four stages (Sec. 3.1) */
+    size_t n = (size_t)m->nb * m->nvar * cells_per_var(m);
+    double *u2 = (double *)calloc(n ? n : 1, sizeof(double));
+    if (m->rk == 1) {
+      /* SSP-RK3: u1 = u + dt L(u); u2 = 3/4 u + 1/4 (u1 + dt L(u1));
+       * u' = 1/3 u + 2/3 (u2 + dt L(u2)) */
+      substep(m, u0, NULL, u1, 1.0, 1.0, 0.0, dt);
+      substep(m, u1, u0, u2, 0.25, 0.25, 0.75, dt);
+      substep(m, u2, u0, u0, 2.0 / 3.0, 2.0 / 3.0, 1.0 / 3.0, dt);
+    } else {
+      /* SSP-RK(4,3): u1 = u + dt/2 L(u); u2 = u1 + dt/2 L(u1);
+       * u3 = 2/3 u + 1/3 u2 + dt/6 L(u2); u' = u3 + dt/2 L(u3) */
+      substep(m, u0, NULL, u1, 0.5, 1.0, 0.0, dt);
+      substep(m, u1, NULL, u2, 0.5, 1.0, 0.0, dt);
+      substep(m, u2, u0, u1, 1.0 / 6.0, 1.0 / 3.0, 2.0 / 3.0, dt);
+      substep(m, u1, NULL, u0, 0.5, 1.0, 0.0, dt);
+    }
+    free(u2);
+    return dt;
+  }
   om_ghost_fill(m, u0);
   om_stage(m, u0, NULL, u1, 1, dt);
   om_flux_fix(m, u0, u1, dt);
