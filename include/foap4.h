@@ -65,6 +65,13 @@ typedef enum { FOAP4_IND_LOHNER = 0, FOAP4_IND_MLP = 1 } foap4_indicator;
  * Einfeldt speeds u_bar -+ d_bar as the slowest and fastest signals. */
 typedef enum { FOAP4_LIM_MINMOD = 0, FOAP4_LIM_VANLEER = 1 } foap4_limiter;
 typedef enum { FOAP4_FLUX_RUSANOV = 0, FOAP4_FLUX_HLL = 1 } foap4_flux;
+/* Time integrators (Sec. 3.1), each a sequence of sub-steps of eq. feuler:
+ * Heun (SSP-RK2, eq. heun); SSP-RK3 (u1 = u + dt L(u), u2 = 3/4 u + 1/4 (u1 +
+ * dt L(u1)), u' = 1/3 u + 2/3 (u2 + dt L(u2))); SSP-RK(4,3) (u1 = u + dt/2
+ * L(u), u2 = u1 + dt/2 L(u1), u3 = 2/3 u + 1/3 u2 + dt/6 L(u2), u' = u3 +
+ * dt/2 L(u3)).  The last two need a third state buffer
+ * (foap4_mesh_set_third_state). */
+typedef enum { FOAP4_RK_HEUN = 0, FOAP4_RK_SSP3 = 1, FOAP4_RK_SSP43 = 2 } foap4_integrator;
 
 /* Mesh descriptor.  A brick of n_trees[0] x n_trees[1] (x n_trees[2]) trees
  * (the paper's p4est brick, Sec. 2.2), periodic or bounded per axis; cubic
@@ -101,6 +108,7 @@ typedef struct {
    * other variables.  Entries of periodic axes are ignored. */
   int32_t bc_type[6][5];
   double bc_value[6][5];
+  foap4_integrator integrator; /* time integrator (zero-initialised: Heun)          */
 } foap4_mesh_desc;
 
 /* Creates a mesh at the uniform level desc->init_level (Sec. 2.2) and its
@@ -134,6 +142,13 @@ foap4_status foap4_mesh_info(const foap4_mesh *mesh, int64_t *n_blocks, int64_t 
  * foap4_regrid once the new pattern exists; the callback may call
  * foap4_set_bc_data with data for the new records.  Errors: FOAP4_E_INVALID
  * (n_values does not match). */
+/* The third state buffer of the integrators with three or four sub-steps:
+ * caller-owned, device, at least max_blocks * nvar * P^ndim elements
+ * (state_bytes bytes), 16-byte aligned, with the layout of the other two.  It
+ * holds intermediate stages only.  foap4_step returns FOAP4_E_ORDER for such
+ * an integrator until it is set.  Errors: FOAP4_E_INVALID (size, alignment). */
+foap4_status foap4_mesh_set_third_state(foap4_mesh *mesh, void *state2, size_t state_bytes);
+
 typedef void (*foap4_bc_callback)(foap4_mesh *mesh, void *user);
 foap4_status foap4_set_bc_data(foap4_mesh *mesh, const double *bc_data_dev, int64_t n_values,
                                foap4_bc_callback on_change, void *user);
@@ -351,6 +366,9 @@ foap4_status foap4_batch_set_config(foap4_batch *batch, int32_t kslabs, int32_t 
  * meshes' states are restored afterwards.  Writes the chosen {kslabs,
  * wg_stage1, wg_stage2, xcd_order} to cfg_out[4] (may be NULL). */
 foap4_status foap4_batch_autotune(foap4_batch *batch, const char *cache_path, int32_t *cfg_out);
+/* (Phase timing and the autotuner time Heun's two stages: FOAP4_E_INVALID for
+ * a batch with another integrator, whose generic sub-steps use the stage-2
+ * grid of foap4_batch_set_config.) */
 
 /* Advances every mesh of the batch by n_steps Heun steps (enqueue only). */
 foap4_status foap4_batch_step(foap4_batch *batch, int32_t n_steps);

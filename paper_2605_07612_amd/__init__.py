@@ -33,12 +33,14 @@ class MeshDesc(ctypes.Structure):
                 ("max_level", ctypes.c_int32), ("max_blocks", ctypes.c_int64), ("prec", ctypes.c_int32),
                 ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("limiter", ctypes.c_int32),
                 ("flux", ctypes.c_int32), ("gravity", ctypes.c_double * 3),
-                ("bc_type", (ctypes.c_int32 * 5) * 6), ("bc_value", (ctypes.c_double * 5) * 6)]
+                ("bc_type", (ctypes.c_int32 * 5) * 6), ("bc_value", (ctypes.c_double * 5) * 6),
+                ("integrator", ctypes.c_int32)]
 
 # stage scheme options (include/foap4.h: foap4_limiter, foap4_flux)
 LIMITERS = {"minmod": 0, "vanleer": 1}
 FLUXES = {"rusanov": 0, "hll": 1}
 BC_DIRICHLET, BC_NEUMANN = 0, 1
+INTEGRATORS = {"heun": 0, "ssprk3": 1, "ssprk43": 2}
 
 
 def wall_bc(ndim):
@@ -60,6 +62,7 @@ EXPORTS = {
     "foap4_mesh_create": (I32, [ctypes.POINTER(MeshDesc), P, P, ctypes.c_size_t, P, ctypes.POINTER(P)]),
     "foap4_mesh_destroy": (I32, [P]),
     "foap4_set_bc_data": (I32, [P, P, I64, P, P]),
+    "foap4_mesh_set_third_state": (I32, [P, P, ctypes.c_size_t]),
     "foap4_mesh_info": (I32, [P, P, P, P]),
     "foap4_mesh_export": (I32, [P, P, P, P]),
     "foap4_ghost_pattern_build": (I32, [P]),
@@ -134,7 +137,7 @@ class Mesh:
     def __init__(self, ndim, trees, N, g=2, tree_size=1.0, level=0, min_level=0, max_level=None,
                  max_blocks=None, prec=F64, gamma=1.4, cfl=0.5, origin=(0.0, 0.0, 0.0), device="cuda",
                  stream=None, limiter="minmod", flux="rusanov", gravity=(0.0, 0.0, 0.0),
-                 periodic=(True, True, True), bc_type=None, bc_value=None):
+                 periodic=(True, True, True), bc_type=None, bc_value=None, integrator="heun"):
         torch = _torch()
         self.ndim, self.N, self.g = ndim, N, g
         self.nvar = ndim + 2
@@ -171,6 +174,7 @@ class Mesh:
         d.prec = prec
         d.gamma = gamma
         d.cfl = cfl
+        d.integrator = INTEGRATORS[integrator]
         d.limiter = LIMITERS[limiter]
         d.flux = FLUXES[flux]
         d.gravity[:] = [float(x) for x in gravity] + [0.0] * (3 - len(gravity))
@@ -185,6 +189,9 @@ class Mesh:
                                      nbytes, P(self.stream.cuda_stream), ctypes.byref(h))
         _check(st)
         self.h = h
+        if integrator != "heun":  # the third state of the 3- and 4-stage schemes
+            self.state.append(torch.zeros(shape, dtype=self.dtype, device=device))
+            _check(lib().foap4_mesh_set_third_state(self.h, P(self.state[2].data_ptr()), nbytes), self.h)
 
     def close(self):
         if getattr(self, "h", None):

@@ -28,6 +28,7 @@ MeshDev make_dev(const foap4_mesh *m, int ks, int gather) {
   MeshDev d{};
   d.s[0] = m->state[0];
   d.s[1] = m->state[1];
+  d.s[2] = m->state[2];
   d.level = m->d_level;
   d.face_info = m->pat.face_info;
   d.srl = m->pat.srl;
@@ -133,6 +134,7 @@ struct foap4_batch {
   int64_t total_items = 0, r1_total = 0, r2_total = 0;
   int nmask = 0;
   int scheme = 0;  // scheme_of() shared by all meshes
+  int integrator = 0;  // shared time integrator
   hipStream_t stream = nullptr, cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -180,6 +182,8 @@ foap4_status foap4_mesh_create(const foap4_mesh_desc *desc, void *state0, void *
     return fail(nullptr, FOAP4_E_INVALID, "limiter must be minmod or van Leer");
   if (d.flux != FOAP4_FLUX_RUSANOV && d.flux != FOAP4_FLUX_HLL)
     return fail(nullptr, FOAP4_E_INVALID, "flux must be Rusanov or HLL");
+  if (d.integrator != FOAP4_RK_HEUN && d.integrator != FOAP4_RK_SSP3 && d.integrator != FOAP4_RK_SSP43)
+    return fail(nullptr, FOAP4_E_INVALID, "integrator must be Heun, SSP-RK3 or SSP-RK(4,3)");
   for (int a = 0; a < 3; a++)
     if (!std::isfinite(d.gravity[a])) return fail(nullptr, FOAP4_E_INVALID, "gravity must be finite");
   if (!state0 || !state1 || state0 == state1) return fail(nullptr, FOAP4_E_INVALID, "two distinct state buffers needed");
@@ -303,9 +307,61 @@ foap4_status foap4_compute_dt(foap4_mesh *m) {
   return ensure_dt(m);
 }
 
+// Sub-steps of the integrators with a third state (Sec. 3.1, eq. feuler):
+// {c, wd, wp, deriv, prev, out, epi}, states by role (0 U^n, 1 the other
+// creation buffer, 2 the third state); U^{n+1} lands in role 0 again.
+static const SubStep kSSP3[3] = {{1.0, 1.0, 0.0, 0, 0, 1, 0},
+                                 {0.25, 0.25, 0.75, 1, 0, 2, 0},
+                                 {2.0 / 3.0, 2.0 / 3.0, 1.0 / 3.0, 2, 0, 0, 1}};
+static const SubStep kSSP43[4] = {{0.5, 1.0, 0.0, 0, 0, 1, 0},
+                                  {0.5, 1.0, 0.0, 1, 1, 2, 0},
+                                  {1.0 / 6.0, 1.0 / 3.0, 2.0 / 3.0, 2, 0, 1, 0},
+                                  {0.5, 1.0, 0.0, 1, 1, 0, 1}};
+static int substeps_of(int integrator, const SubStep **ss) {
+  if (integrator == FOAP4_RK_SSP3) { *ss = kSSP3; return 3; }
+  if (integrator == FOAP4_RK_SSP43) { *ss = kSSP43; return 4; }
+  *ss = nullptr;
+  return 0;
+}
+
+foap4_status foap4_mesh_set_third_state(foap4_mesh *m, void *state2, size_t bytes) {
+  if (!m || !state2) return fail(m, FOAP4_E_INVALID, "null argument");
+  if (((uintptr_t)state2) & 15u) return fail(m, FOAP4_E_INVALID, "state buffers must be 16-byte aligned");
+  if ((size_t)m->d.max_blocks * m->block_elems * m->elem > bytes)
+    return fail(m, FOAP4_E_INVALID, "third state buffer smaller than max_blocks blocks");
+  if (state2 == m->state[0] || state2 == m->state[1]) return fail(m, FOAP4_E_INVALID, "third state must be distinct");
+  m->state[2] = state2;
+  m->dev_serial++;
+  return upload_dev(m);
+}
+
 foap4_status foap4_step(foap4_mesh *m, int32_t n_steps, double *t_out, double *dt_out) {
   if (!m || n_steps < 0) return fail(m, FOAP4_E_INVALID, "bad mesh or step count");
   if (!m->pat_valid) return fail(m, FOAP4_E_ORDER, "no ghost pattern");
+  const SubStep *subs = nullptr;
+  const int nsub = substeps_of(m->d.integrator, &subs);
+  if (nsub && !m->state[2]) return fail(m, FOAP4_E_ORDER, "this integrator needs a third state buffer");
+  if (nsub && m->capture && n_steps > 0)
+    return fail(m, FOAP4_E_INVALID, "feature capture needs the Heun integrator");
+  if (nsub) {
+    const bool f64 = m->d.prec == FOAP4_F64;
+    const int ndim = m->d.ndim;
+    const int64_t items = stage_items_for(ndim, m->d.block_n, (int64_t)m->topo.leaves.size(), 1);
+    foap4_status st;
+    if ((st = ensure_dt(m)) != FOAP4_OK) return st;
+    for (int32_t s = 0; s < n_steps; s++) {
+      for (int k = 0; k < nsub; k++) {
+        if ((st = fill(m, m->d_dev, subs[k].deriv)) != FOAP4_OK) return st;
+        F4_HIP(m, launch_stage(m->d_dev, 1, items, 3, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n),
+                               scheme_of(m->d), subs[k]));
+        F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, 3, m->stream, subs[k]));
+      }
+      F4_HIP(m, launch_finalize(m->d_dev, 1, 1, m->stream));
+    }
+    m->steps_done += n_steps;
+    if (t_out || dt_out) return foap4_time(m, t_out, dt_out);
+    return FOAP4_OK;
+  }
   const bool f64 = m->d.prec == FOAP4_F64;
   const int ndim = m->d.ndim;
   const int64_t items = stage_items_for(ndim, m->d.block_n, (int64_t)m->topo.leaves.size(), 1);
@@ -603,6 +659,22 @@ static int stage_grid(const foap4_batch *b, int stage) {
 static hipError_t batch_enqueue_step(foap4_batch *b, hipStream_t s) {
   const int n = (int)b->meshes.size();
   hipError_t e;
+  const SubStep *subs = nullptr;
+  const int nsub = substeps_of(b->integrator, &subs);
+  for (int k = 0; k < nsub; k++) {  // integrators with a third state: generic sub-steps
+    const int which = subs[k].deriv;
+    if ((e = launch_ghost(b->d_devs, n, b->r1_total, 1, which, b->ndim, b->f64, 0, s)) != hipSuccess) return e;
+    if (b->r2_total && (e = launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s)) != hipSuccess)
+      return e;
+    if ((e = launch_stage(b->d_devs, n, b->total_items, 3, b->ndim, b->f64, stage_grid(b, 2), s, b->xcd, b->nmask,
+                          b->scheme, subs[k])) != hipSuccess)
+      return e;
+    for (int i = 0; i < n; i++)
+      if (b->meshes[i]->pat.n_fix > 0 &&
+          (e = launch_fluxfix(b->d_devs + i, b->ndim, b->f64, b->meshes[i]->pat.n_fix, 3, s, subs[k])) != hipSuccess)
+        return e;
+  }
+  if (nsub) return launch_finalize(b->d_devs, n, 1, s);
   for (int stage = 1; stage <= 2; stage++) {
     const int which = stage - 1;
     const int grid = stage_grid(b, stage);
@@ -668,6 +740,7 @@ foap4_status foap4_batch_create(foap4_mesh *const *meshes, int32_t n, foap4_batc
   b->ndim = meshes[0]->d.ndim;
   b->f64 = meshes[0]->d.prec == FOAP4_F64;
   b->scheme = scheme_of(meshes[0]->d);
+  b->integrator = meshes[0]->d.integrator;
   for (foap4_mesh *m : b->meshes)
     if (m->d.ndim != b->ndim || (m->d.prec == FOAP4_F64) != b->f64) {
       delete b;
@@ -675,6 +748,9 @@ foap4_status foap4_batch_create(foap4_mesh *const *meshes, int32_t n, foap4_batc
     } else if (scheme_of(m->d) != b->scheme) {
       delete b;
       return fail(nullptr, FOAP4_E_INVALID, "batch meshes must share limiter, flux and gravity on/off");
+    } else if (m->d.integrator != b->integrator) {
+      delete b;
+      return fail(nullptr, FOAP4_E_INVALID, "batch meshes must share the time integrator");
     }
   b->stream = meshes[0]->stream;
   int dev = 0;
@@ -717,8 +793,11 @@ foap4_status foap4_batch_set_config(foap4_batch *b, int32_t kslabs, int32_t wg_s
 
 foap4_status foap4_batch_step(foap4_batch *b, int32_t n_steps) {
   if (!b || n_steps < 0) return batch_fail(b, FOAP4_E_INVALID, "bad batch or step count");
-  for (foap4_mesh *m : b->meshes)
+  for (foap4_mesh *m : b->meshes) {
     if (!m->pat_valid) return batch_fail(b, FOAP4_E_ORDER, "mesh without ghost pattern");
+    if (b->integrator != FOAP4_RK_HEUN && !m->state[2])
+      return batch_fail(b, FOAP4_E_ORDER, "this integrator needs a third state buffer");
+  }
   foap4_status st = batch_prepare(b);
   if (st != FOAP4_OK) return st;
   for (int32_t s = 0; s < n_steps; s++) B_HIP(b, hipGraphLaunch(b->exec, b->stream));
@@ -729,6 +808,8 @@ foap4_status foap4_batch_step(foap4_batch *b, int32_t n_steps) {
 
 foap4_status foap4_batch_phase_times(foap4_batch *b, int32_t n_steps, double *out_ms) {
   if (!b || n_steps < 1 || !out_ms) return batch_fail(b, FOAP4_E_INVALID, "bad arguments");
+  if (b->integrator != FOAP4_RK_HEUN)
+    return batch_fail(b, FOAP4_E_INVALID, "phase timing and autotuning time the Heun stages");
   foap4_status st = batch_prepare(b);
   if (st != FOAP4_OK) return st;
   const int n = (int)b->meshes.size();

@@ -82,8 +82,21 @@ class Topology {
 };
 
 // Device descriptor of one mesh as the kernels see it (copied to the device).
+// One sub-step of the Runge-Kutta framework (eq. feuler) in its generic
+// form: u(out) = c dt L(u(deriv)) + wd u(deriv) + wp u(prev).  States are
+// named by role: 0 the current state, 1 the other of the two creation
+// buffers, 2 the third state buffer.  epi: the last sub-step of a step, which
+// evaluates the CFL limit of its output.
+struct SubStep {
+  double c, wd, wp;
+  int32_t deriv, prev, out, epi;
+};
+__host__ __device__ __forceinline__ int role_buffer(int role, int cur) {
+  return role == 0 ? cur : (role == 1 ? 1 - cur : 2);
+}
+
 struct MeshDev {
-  void *s[2];                 // state buffers
+  void *s[3];                 // state buffers: the two of creation and the optional third
   const int32_t *level;       // [nb]
   // [nb][2*ndim]: -2 - n for a same-level neighbour n, -1 for a boundary,
   // 2*slot for a C2F face (fine-side flux slot), 2*slot+1 for an F2C face
@@ -131,7 +144,7 @@ struct foap4_mesh {
   int nvar = 0, P = 0, nf = 0;
   size_t elem = 0;             // bytes per value
   int64_t block_elems = 0;     // nvar * P^ndim
-  void *state[2] = {nullptr, nullptr};
+  void *state[3] = {nullptr, nullptr, nullptr};  // the third: integrators with 3+ sub-steps
   size_t state_bytes = 0;
   hipStream_t stream = nullptr;
   int32_t cur = 0;
@@ -205,15 +218,18 @@ foap4_status upload_dev(foap4_mesh *m);
 
 // pattern.hip
 foap4_status build_pattern(foap4_mesh *m);
-// ghost.hip: round 1 = SRL + F2C, round 2 = C2F; which 0 = current state, 1 = other
+// ghost.hip: round 1 = SRL + F2C + boundary, round 2 = C2F; which = state role
+// (0 current, 1 other, 2 third)
 hipError_t launch_ghost(const MeshDev *d_meshes, int n_meshes, int64_t total, int round, int which,
                         int ndim, bool f64, int grid, hipStream_t s);
 // stage.hip
 int64_t stage_items_for(int ndim, int N, int64_t nb, int ks);
 // nmask: block sizes present in the launch (1: N = 8, 2: N = 16, 4: N = 32);
-// scheme: scheme_of() of the meshes in the launch
+// scheme: scheme_of() of the meshes in the launch; stage 1 / 2: Heun's stages,
+// stage 3: the generic sub-step ss
 hipError_t launch_stage(const MeshDev *d_meshes, int n_meshes, int64_t total_items, int stage,
-                        int ndim, bool f64, int grid, hipStream_t s, int xcd, int nmask, int scheme);
+                        int ndim, bool f64, int grid, hipStream_t s, int xcd, int nmask, int scheme,
+                        const SubStep &ss = SubStep{});
 // stage 1 of one mesh that also reduces the raw features of its input state
 // (feat_raw [nb][2], zeroed by the caller) by atomic maxima
 hipError_t launch_stage1_features(const MeshDev *d_mesh, int64_t total_items, int ndim, bool f64, int nmask,
@@ -227,7 +243,8 @@ inline int nmask_of(int N) { return N == 8 ? 1 : (N == 16 ? 2 : 4); }
 // reduce.hip
 hipError_t launch_dt_full(const foap4_mesh *m, hipStream_t s);
 hipError_t launch_finalize(const MeshDev *d_meshes, int n_meshes, int advance, hipStream_t s);
-hipError_t launch_fluxfix(const MeshDev *d_mesh, int ndim, bool f64, int n_fix, int stage, hipStream_t s);
+hipError_t launch_fluxfix(const MeshDev *d_mesh, int ndim, bool f64, int n_fix, int stage, hipStream_t s,
+                          const SubStep &ss = SubStep{});
 hipError_t launch_totals(const foap4_mesh *m, double *d_part, double *d_out, hipStream_t s);
 // regrid.hip
 // skip (may be null): blocks whose flag is already set are left alone

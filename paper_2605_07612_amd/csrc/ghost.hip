@@ -275,7 +275,7 @@ __device__ void bc_record(const MeshDev &M, T *u, int side, int64_t rec, int32_t
 
 template <typename T, int NDIM, int N>
 __device__ void ghost_item(const MeshDev &M, int round, int64_t r, int which) {
-  T *u = (T *)M.s[which == 0 ? M.cur : 1 - M.cur];
+  T *u = (T *)M.s[role_buffer(which, M.cur)];
   // the record's face f = 2 axis + side; the axis selects the routine
 #define F4_BY_AXIS(CALL)                           \
   switch (f >> 1) {                                \

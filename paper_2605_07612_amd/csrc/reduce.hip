@@ -79,7 +79,7 @@ __global__ void finalize_kernel(const MeshDev *__restrict__ meshes, int n_meshes
 // with <F_f> the FP64 pairwise mean of the 2^(d-1) fine fluxes.  In stage 2
 // the CFL limit of the corrected cells is then added to the reduction.
 template <typename T, int NDIM>
-__global__ __launch_bounds__(256) void fluxfix_kernel(const MeshDev *__restrict__ Mp, int stage) {
+__global__ __launch_bounds__(256) void fluxfix_kernel(const MeshDev *__restrict__ Mp, int stage, SubStep ss) {
   const MeshDev &M = *Mp;
   constexpr int NV = NDIM + 2;
   constexpr int NF = 2 * NDIM;
@@ -87,9 +87,10 @@ __global__ __launch_bounds__(256) void fluxfix_kernel(const MeshDev *__restrict_
   const int32_t cb = M.fix_list[blockIdx.x];
   const int N = M.N, H = N / 2, g = M.g, P = N + 2 * g;
   const int64_t sv = (NDIM == 3) ? (int64_t)P * P * P : (int64_t)P * P;
-  T *uo = (T *)M.s[stage == 1 ? 1 - M.cur : M.cur] + (int64_t)cb * sv * NV;
+  const int ob = stage == 3 ? role_buffer(ss.out, M.cur) : (stage == 1 ? 1 - M.cur : M.cur);
+  T *uo = (T *)M.s[ob] + (int64_t)cb * sv * NV;
   const double dx = ldexp(M.dx0, -M.level[cb]);
-  const double dts = stage == 1 ? M.scal[kDt] : 0.5 * M.scal[kDt];
+  const double dts = stage == 3 ? ss.c * M.scal[kDt] : (stage == 1 ? M.scal[kDt] : 0.5 * M.scal[kDt]);
   const int N2 = (NDIM == 3) ? N : 1;
   const int64_t fv = (int64_t)N * N2;  // face values per variable
   const T *bf = (const T *)M.bflux_f;
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(256) void fluxfix_kernel(const MeshDev *__restrict_
     }
     __syncthreads();
   }
-  if (stage != 2) return;
+  if (stage != 2 && !(stage == 3 && ss.epi)) return;
   double vmax = 0.0;
   bool bad = false;
   for (int f = 0; f < NF; f++) {
@@ -220,14 +221,15 @@ hipError_t launch_finalize(const MeshDev *d_meshes, int n_meshes, int advance, h
   return hipGetLastError();
 }
 
-hipError_t launch_fluxfix(const MeshDev *d_mesh, int ndim, bool f64, int n_fix, int stage, hipStream_t s) {
+hipError_t launch_fluxfix(const MeshDev *d_mesh, int ndim, bool f64, int n_fix, int stage, hipStream_t s,
+                          const SubStep &ss) {
   if (n_fix <= 0) return hipSuccess;
   if (ndim == 3) {
-    if (f64) fluxfix_kernel<double, 3><<<n_fix, 256, 0, s>>>(d_mesh, stage);
-    else fluxfix_kernel<float, 3><<<n_fix, 256, 0, s>>>(d_mesh, stage);
+    if (f64) fluxfix_kernel<double, 3><<<n_fix, 256, 0, s>>>(d_mesh, stage, ss);
+    else fluxfix_kernel<float, 3><<<n_fix, 256, 0, s>>>(d_mesh, stage, ss);
   } else {
-    if (f64) fluxfix_kernel<double, 2><<<n_fix, 256, 0, s>>>(d_mesh, stage);
-    else fluxfix_kernel<float, 2><<<n_fix, 256, 0, s>>>(d_mesh, stage);
+    if (f64) fluxfix_kernel<double, 2><<<n_fix, 256, 0, s>>>(d_mesh, stage, ss);
+    else fluxfix_kernel<float, 2><<<n_fix, 256, 0, s>>>(d_mesh, stage, ss);
   }
   return hipGetLastError();
 }

@@ -134,7 +134,8 @@ __device__ __forceinline__ void plane_face(const T *Wp, int base, int step, bool
 // by an atomic maximum; the primitive planes are already in LDS.
 template <typename T, int NDIM, int N, int SCH, bool FEAT = false>
 __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t local, T *smem,
-                                           double &vmax, bool &bad, double *feat_raw = nullptr) {
+                                           double &vmax, bool &bad, double *feat_raw = nullptr,
+                                           const SubStep &ss = SubStep{}) {
   using C = TileCfg<N>;
   constexpr int TILE = C::TILE, SUB = C::SUB, TPB = C::TPB;
   constexpr int NV = NDIM + 2;
@@ -161,14 +162,16 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   const int sv = (NDIM == 3) ? P * P * P : P * P;
   const int64_t bel = (int64_t)sv * NV;
   const int cur = M.cur;
-  const T *__restrict__ ud0 = (const T *)M.s[stage == 1 ? cur : 1 - cur];
-  T *uo = (T *)M.s[stage == 1 ? 1 - cur : cur] + b * bel;
-  const T *up = (const T *)M.s[cur] + b * bel;
+  // stage 1 / 2: Heun's stages; stage 3: the generic sub-step ss (states by role)
+  const T *__restrict__ ud0 = (const T *)M.s[stage == 3 ? role_buffer(ss.deriv, cur) : (stage == 1 ? cur : 1 - cur)];
+  T *uo = (T *)M.s[stage == 3 ? role_buffer(ss.out, cur) : (stage == 1 ? 1 - cur : cur)] + b * bel;
+  const T *up = (const T *)M.s[stage == 3 ? role_buffer(ss.prev, cur) : cur] + b * bel;
   const T gamma = (T)M.gamma;
   const double dx = ldexp(M.dx0, -gload(M.level + b));
   const T idx = (T)(1.0 / dx);
   const double dt = gload(M.scal + kDt);
-  const T dts = (T)(stage == 1 ? dt : 0.5 * dt);
+  const T dts = (T)(stage == 3 ? ss.c * dt : (stage == 1 ? dt : 0.5 * dt));
+  [[maybe_unused]] const T wd = (T)ss.wd, wp = (T)ss.wp;
   [[maybe_unused]] T grav[NDIM];
   if constexpr ((SCH & kSchGravity) != 0) {
 #pragma unroll
@@ -344,7 +347,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   }
 
   T Upn[NV];
-  if (stage == 2) load(up + off(I, J, k0), Upn);
+  if (stage >= 2) load(up + off(I, J, k0), Upn);
 
   T Uc[NV];  // conserved state of own cell k + 2
   for (int k = k0; k < k1; k++) {
@@ -359,7 +362,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     // U^n of the own cell (stage 2): loaded one plane ahead
     T Up[NV];
     const T *U0 = Ua;
-    if (stage == 2) {
+    if (stage >= 2) {
       copyv<T, NV>(Up, Upn);
       if (k + 1 < k1) load(up + off(I, J, k + 1), Upn);
     }
@@ -486,7 +489,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       const T dfy = FY[v * NFX + (tj + 1) * TILE + ti] - FY[v * NFX + tj * TILE + ti];
       T div = dfx + dfy;
       if constexpr (NDIM == 3) div += Fz1[v] - Fz[v];
-      const T base = (stage == 1) ? U0[v] : T(0.5) * (Up[v] + U0[v]);
+      const T base = (stage == 1) ? U0[v] : (stage == 2) ? T(0.5) * (Up[v] + U0[v]) : wp * Up[v] + wd * U0[v];
       if constexpr ((SCH & kSchGravity) != 0) Uout[v] = (base + dts * src[v]) - cdt * div;
       else Uout[v] = base - cdt * div;
     }
@@ -497,7 +500,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
 #pragma unroll
       for (int v = 0; v < NV; v++) gstore(uo + v * sv + o, Uout[v]);
     }
-    if (stage == 2 && valid) {
+    if ((stage == 2 || (stage == 3 && ss.epi)) && valid) {
       const bool skip = f2c_adj || (f2c_zlo && k == 0) || (f2c_zhi && k == N - 1);
       if (!skip) {
         if constexpr (sizeof(T) == 8) {
@@ -565,10 +568,11 @@ constexpr int stage_waves() { return sizeof(T) == 4 ? (NM != 7 ? 4 : 3) : 1; }
 
 // NM: bit mask of the block sizes present (1: N = 8, 2: N = 16, 4: N = 32)
 // STG: the Heun stage (compiled separately: stage 1 needs no U^n stream and
-// no dt epilogue, so it runs with fewer registers)
+// no dt epilogue, so it runs with fewer registers), or 3: the generic
+// sub-step ss of the other Runge-Kutta schemes (weights at run time)
 template <typename T, int NDIM, int NM, int STG, int SCH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM, STG>())))
-void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t total, int xcd) {
+void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t total, int xcd, SubStep ss) {
   constexpr int stage = STG;
   __shared__ T smem[smem_cells<NDIM, NM>()];
   double vmax = 0.0;
@@ -585,49 +589,42 @@ void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t tota
       const int mid = (lo + hi + 1) >> 1;
       if (meshes[mid].item_begin <= item) lo = mid; else hi = mid - 1;
     }
-    if (stage == 2 && mprev >= 0 && lo != mprev) flush_dt(meshes[mprev], vmax, bad);
+    if (stage >= 2 && mprev >= 0 && lo != mprev) flush_dt(meshes[mprev], vmax, bad);
     mprev = lo;
     const MeshDev &M = meshes[lo];
     const int64_t local = item - M.item_begin;
     if constexpr (NM == 1) {
-      stage_item<T, NDIM, 8, SCH>(M, stage, local, smem, vmax, bad);
+      stage_item<T, NDIM, 8, SCH>(M, stage, local, smem, vmax, bad, nullptr, ss);
     } else if constexpr (NM == 2) {
-      stage_item<T, NDIM, 16, SCH>(M, stage, local, smem, vmax, bad);
+      stage_item<T, NDIM, 16, SCH>(M, stage, local, smem, vmax, bad, nullptr, ss);
     } else if constexpr (NM == 4) {
-      stage_item<T, NDIM, 32, SCH>(M, stage, local, smem, vmax, bad);
+      stage_item<T, NDIM, 32, SCH>(M, stage, local, smem, vmax, bad, nullptr, ss);
     } else {
       switch (M.N) {
-        case 8: stage_item<T, NDIM, 8, SCH>(M, stage, local, smem, vmax, bad); break;
-        case 16: stage_item<T, NDIM, 16, SCH>(M, stage, local, smem, vmax, bad); break;
-        default: stage_item<T, NDIM, 32, SCH>(M, stage, local, smem, vmax, bad); break;
+        case 8: stage_item<T, NDIM, 8, SCH>(M, stage, local, smem, vmax, bad, nullptr, ss); break;
+        case 16: stage_item<T, NDIM, 16, SCH>(M, stage, local, smem, vmax, bad, nullptr, ss); break;
+        default: stage_item<T, NDIM, 32, SCH>(M, stage, local, smem, vmax, bad, nullptr, ss); break;
       }
     }
     __syncthreads();
   }
-  if (stage == 2 && mprev >= 0) flush_dt(meshes[mprev], vmax, bad);
+  if (stage >= 2 && mprev >= 0) flush_dt(meshes[mprev], vmax, bad);
 }
 
 template <typename T, int NDIM, int SCH>
 static void launch_t(unsigned nblk, int nmask, const MeshDev *d, int n, int64_t total, int stage, int xcd,
-                     hipStream_t s) {
+                     hipStream_t s, const SubStep &ss) {
+#define F4_STAGE_LAUNCH(NM)                                                                     \
+  if (stage == 1) stage_kernel<T, NDIM, NM, 1, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd, ss); \
+  else if (stage == 2) stage_kernel<T, NDIM, NM, 2, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd, ss); \
+  else stage_kernel<T, NDIM, NM, 3, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd, ss);
   switch (nmask) {
-    case 1:
-      if (stage == 1) stage_kernel<T, NDIM, 1, 1, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      else stage_kernel<T, NDIM, 1, 2, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      break;
-    case 2:
-      if (stage == 1) stage_kernel<T, NDIM, 2, 1, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      else stage_kernel<T, NDIM, 2, 2, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      break;
-    case 4:
-      if (stage == 1) stage_kernel<T, NDIM, 4, 1, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      else stage_kernel<T, NDIM, 4, 2, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      break;
-    default:
-      if (stage == 1) stage_kernel<T, NDIM, 7, 1, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      else stage_kernel<T, NDIM, 7, 2, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd);
-      break;
+    case 1: F4_STAGE_LAUNCH(1) break;
+    case 2: F4_STAGE_LAUNCH(2) break;
+    case 4: F4_STAGE_LAUNCH(4) break;
+    default: F4_STAGE_LAUNCH(7) break;
   }
+#undef F4_STAGE_LAUNCH
 }
 
 // Stage 1 of one mesh (one workgroup per work item) that also reduces the
@@ -656,15 +653,15 @@ static void launch_feat_t(unsigned nblk, int nmask, const MeshDev *d, int64_t to
 // its own F4_SCHEME.
 template <int SCH>
 hipError_t launch_stage_sch(const MeshDev *d_meshes, int n_meshes, int64_t total_items, int stage, int ndim,
-                            bool f64, int grid, hipStream_t s, int xcd, int nmask) {
+                            bool f64, int grid, hipStream_t s, int xcd, int nmask, const SubStep &ss) {
   int64_t nblk = (grid > 0 && grid < total_items) ? grid : total_items;
   if (xcd == 1) nblk = (nblk + 7) / 8 * 8;  // every XCD gets the same number of workgroups
   if (f64) {
-    if (ndim == 3) launch_t<double, 3, SCH>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);
-    else launch_t<double, 2, SCH>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);
+    if (ndim == 3) launch_t<double, 3, SCH>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s, ss);
+    else launch_t<double, 2, SCH>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s, ss);
   } else {
-    if (ndim == 3) launch_t<float, 3, SCH>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);
-    else launch_t<float, 2, SCH>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s);
+    if (ndim == 3) launch_t<float, 3, SCH>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s, ss);
+    else launch_t<float, 2, SCH>((unsigned)nblk, nmask, d_meshes, n_meshes, total_items, stage, xcd, s, ss);
   }
   return hipGetLastError();
 }
@@ -689,7 +686,7 @@ hipError_t launch_feat_sch(const MeshDev *d_mesh, int64_t total_items, int ndim,
 static_assert(F4_SCHEME >= 0 && F4_SCHEME < kNSchemes, "F4_SCHEME is a scheme bit mask");
 
 template hipError_t launch_stage_sch<F4_SCHEME>(const MeshDev *, int, int64_t, int, int, bool, int, hipStream_t,
-                                                int, int);
+                                                int, int, const SubStep &);
 template hipError_t launch_feat_sch<F4_SCHEME>(const MeshDev *, int64_t, int, bool, int, double *, hipStream_t);
 
 #if F4_SCHEME == 0
@@ -704,7 +701,7 @@ int64_t stage_items_for(int ndim, int N, int64_t nb, int ks) {
 // the other schemes' launchers live in the other compiles of this file
 #define F4_EXTERN_SCHEME(S)                                                                                    \
   extern template hipError_t launch_stage_sch<S>(const MeshDev *, int, int64_t, int, int, bool, int,          \
-                                                 hipStream_t, int, int);                                       \
+                                                 hipStream_t, int, int, const SubStep &);                      \
   extern template hipError_t launch_feat_sch<S>(const MeshDev *, int64_t, int, bool, int, double *, hipStream_t);
 F4_EXTERN_SCHEME(1)
 F4_EXTERN_SCHEME(2)
@@ -716,11 +713,12 @@ F4_EXTERN_SCHEME(7)
 #undef F4_EXTERN_SCHEME
 
 hipError_t launch_stage(const MeshDev *d_meshes, int n_meshes, int64_t total_items, int stage,
-                        int ndim, bool f64, int grid, hipStream_t s, int xcd, int nmask, int scheme) {
+                        int ndim, bool f64, int grid, hipStream_t s, int xcd, int nmask, int scheme,
+                        const SubStep &ss) {
   if (total_items <= 0) return hipSuccess;
   switch (scheme) {
 #define F4_CASE(S) \
-    case S: return launch_stage_sch<S>(d_meshes, n_meshes, total_items, stage, ndim, f64, grid, s, xcd, nmask);
+    case S: return launch_stage_sch<S>(d_meshes, n_meshes, total_items, stage, ndim, f64, grid, s, xcd, nmask, ss);
     F4_CASE(0) F4_CASE(1) F4_CASE(2) F4_CASE(3) F4_CASE(4) F4_CASE(5) F4_CASE(6) F4_CASE(7)
 #undef F4_CASE
     default: return hipErrorInvalidValue;
