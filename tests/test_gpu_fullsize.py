@@ -50,6 +50,33 @@ def test_noise_shear_256cubed_full_size(f4, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_rayleigh_taylor_256cubed_full_size(f4, prec):
+    """The benchmark's Rayleigh-Taylor leg (256^3 cells in 16^3 blocks, van
+    Leer, gravity, walls along z), batched in the profiled configuration:
+    two steps against two oracle steps, every cell compared; then the mass
+    (periodic sides, closed walls) over 20 more steps."""
+    w = synth.rayleigh_taylor(block=16, n=256)
+    say("case RT 256^3 prec", prec)
+    gm, om = build_pair(w, prec)
+    t0 = gm.totals()
+    b = f4.Batch([gm])
+    b.set_config(kslabs=1, wg_per_cu=0, xcd_order=1, wg_stage2=4)
+    b.step(2)
+    t, _ = gm.time()
+    om.step(2)
+    lev = np.zeros(gm.nb, np.int32)
+    err = rel_l1_vol(interior(gpu_state(gm), 2, 16, 3), om.interior(), lev, 3, w["tree_size"], 16)
+    say("RT 256^3 rel L1", err, "t", t, om.t)
+    assert err <= TOL[prec]
+    assert abs(t - om.t) <= (1e-14 if prec == 1 else 1e-6) * om.t
+    b.step(20)
+    drift = abs(gm.totals()[0] - t0[0]) / t0[0]
+    say("RT mass drift after 22 steps", drift)
+    assert drift <= (1e-13 if prec == 1 else 1e-6)
+    b.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_two_level_blast_full_base(f4, prec):
     """Static two-level blast at full size (128^3 base, 6952 blocks of 8^3):
     10 steps against the oracle, then conservation over 100 steps."""
