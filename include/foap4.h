@@ -194,10 +194,14 @@ foap4_status foap4_ghost_fill(foap4_mesh *mesh, int32_t state);
  * FP64.  Done automatically by the first foap4_step after create/regrid. */
 foap4_status foap4_compute_dt(foap4_mesh *mesh);
 
-/* Advances n_steps Heun (SSP-RK2) steps (eq. heun) on the current state:
- * per stage ghost fill, fused flux/update stage, flux fix at refinement
+/* Advances n_steps steps of the mesh's time integrator (Heun, eq. heun, by
+ * default; SSP-RK3 or SSP-RK(4,3), Sec. 3.1) on the current state: per
+ * sub-step ghost fill, fused flux/update stage, flux fix at refinement
  * boundaries (Sec. 2.7); the next dt comes from the new state (FP64
- * reduction on the device).  Enqueues only; if t_out/dt_out are non-NULL
+ * reduction on the device).  The result is in the current state buffer.
+ * FOAP4_E_ORDER if the integrator needs a third state buffer that is not set;
+ * FOAP4_E_INVALID if feature capture is on with an integrator other than
+ * Heun.  Enqueues only; if t_out/dt_out are non-NULL
  * the stream is synchronized and the simulation time / the dt of the next
  * step are returned, and FOAP4_E_UNPHYSICAL is reported if the state went
  * bad.  This is the plain form: one kernel launch per operation and one
