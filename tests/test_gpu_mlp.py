@@ -54,7 +54,24 @@ def noise3d_refined():
                 refine_flags=lambda G: ((G[:, 0] + G[:, 1] + G[:, 2]) % 4 == 1).astype(np.int8))
 
 
+def noise3d_bounded():
+    """noise3d_refined bounded along x and z by random Dirichlet / Neumann
+    faces: the raw features read boundary ghosts, and boundary faces have no
+    neighbour summary (zero on both sides)."""
+    w = noise3d_refined()
+    rng = np.random.default_rng(31)
+    t = rng.integers(0, 2, (6, 5)).astype(np.int32)
+    # Dirichlet values that keep mirrored ghosts physical: rho in [1, 1.5]
+    # (interior 0.7 .. 1.3), momenta small, E in [2, 3] (interior 1.25 .. 3.8)
+    lo, hi = np.array([1.0, -0.2, -0.2, -0.2, 2.0]), np.array([1.5, 0.2, 0.2, 0.2, 3.0])
+    v = rng.uniform(lo, hi, (6, 5))
+    v[t == 1] = rng.uniform(-0.3, 0.3, int((t == 1).sum()))
+    w.update(name="noise3d_bounded", periodic=(False, True, False), bc_type=t, bc_value=v)
+    return w
+
+
 WORKLOADS = {"wave2d_refined": wave2d_refined, "noise3d_refined": noise3d_refined,
+             "noise3d_bounded": noise3d_bounded,
              "blast_small": lambda: synth.two_level_blast(base_trees=4, block=8),
              "blast_b16": lambda: synth.two_level_blast(base_trees=4, block=16),
              "blast_b32": lambda: synth.two_level_blast(base_trees=4, block=32)}
@@ -259,7 +276,8 @@ def test_regrid_uses_attached_indicator(f4):
     assert np.array_equal(g1.current().cpu().numpy(), g2.current().cpu().numpy())
 
 
-@pytest.mark.parametrize("wname,prec", [("noise3d_refined", 1), ("noise3d_refined", 0), ("wave2d_refined", 1),
+@pytest.mark.parametrize("wname,prec", [("noise3d_refined", 1), ("noise3d_refined", 0), ("noise3d_bounded", 1),
+                                        ("noise3d_bounded", 0), ("wave2d_refined", 1),
                                         ("blast_small", 1), ("blast_b16", 1), ("blast_b16", 0)])
 def test_captured_features_match_oracle(f4, wname, prec):
     """Features captured inside the first stage of a step describe the state
