@@ -91,7 +91,7 @@ LOHNER = dict(c_ref=5e-2, c_deref=6.25e-3, eps=1e-2, eps_abs=1e-10)
 LIMITERS = {"minmod": 0, "vanleer": 1}
 FLUXES = {"rusanov": 0, "hll": 1}
 # time integrators of Sec. 3.1
-INTEGRATORS = {"heun": 0, "ssprk3": 1, "ssprk43": 2}
+INTEGRATORS = {"heun": 0, "ssprk3": 1, "ssprk43": 2, "rk4": 3}
 
 
 def limiter(kind, a, b):

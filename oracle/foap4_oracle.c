@@ -19,7 +19,8 @@
  *                          Sec. 3.5 (eq. euler, Einfeldt speeds), Sec. 4.2
  *                          (gravity source S = (0, rho g, rho g.u))
  *   Runge-Kutta stages     Sec. 3.1, eq. feuler and eq. heun; the SSP
- *                          schemes with three and four stages (Sec. 3.1)
+ *                          schemes with three and four stages (Sec. 3.1);
+ *                          classical RK4, eq. rk4
  *   flux fixing            Sec. 2.7
  *   CFL time step          Sec. 3.1 / Sec. 3.2 step list
  *   refinement criterion   Sec. 3.3, eq. lohner-simple
@@ -63,7 +64,8 @@ typedef struct {
   int32_t limiter;        /* reconstruction slope limiter: 0 minmod, 1 van Leer  */
   int32_t flux;           /* numerical flux: 0 Rusanov, 1 HLL                     */
   double grav[3];         /* gravitational acceleration; all zero: no source term */
-  int32_t rk;             /* time integrator: 0 Heun (SSP-RK2), 1 SSP-RK3, 2 SSP-RK(4,3) */
+  int32_t rk;             /* time integrator: 0 Heun (SSP-RK2), 1 SSP-RK3, 2 SSP-RK(4,3),
+                             3 classical RK4 (eq. rk4)                          */
 } om_mesh;
 
 /* ---------------------------------------------------------------- indexing */
@@ -484,12 +486,13 @@ void om_stage(const om_mesh *m, const double *ud, const double *up, double *uo, 
   }
 }
 
-/* One sub-step of the Runge-Kutta framework (eq. feuler):
- *   uo = c dt L(ud) + wd ud + wp up
- * with L as in om_stage (source first, then the flux divergence); up may be
- * NULL when wp = 0.  uo may alias up but never ud. */
-void om_substep(const om_mesh *m, const double *ud, const double *up, double *uo, double c, double wd,
-                double wp, double dt) {
+/* One sub-step of the Runge-Kutta framework (eq. feuler) with up to three
+ * earlier states:
+ *   uo = c dt L(ud) + wd ud + sum_i wp[i] up[i]
+ * with L as in om_stage (source first, then the flux divergence); up[i] may
+ * be NULL when wp[i] = 0.  uo may alias an up[i] but never ud. */
+void om_substep_n(const om_mesh *m, const double *ud, const double *const *up, const double *wp, int np, double *uo,
+                  double c, double wd, double dt) {
   int N = m->N, nv = m->nvar;
   int nk = (m->ndim == 3) ? N : 1;
   int has_src = m->grav[0] != 0.0 || m->grav[1] != 0.0 || m->grav[2] != 0.0;
@@ -521,8 +524,10 @@ void om_substep(const om_mesh *m, const double *ud, const double *up, double *uo
           }
           for (int v = 0; v < nv; v++) {
             int64_t o = ix(m, b, v, c3);
-            double prev = (wp != 0.0) ? wp * up[o] : 0.0;
-            uo[o] = cdt * rhs[v] + (wd * ud[o] + prev);
+            double acc = wd * ud[o];
+            for (int q = 0; q < np; q++)
+              if (wp[q] != 0.0) acc += wp[q] * up[q][o];
+            uo[o] = cdt * rhs[v] + acc;
           }
         }
   }
@@ -639,6 +644,12 @@ int64_t om_count_unphysical(const om_mesh *m, const double *u) {
 /* One Heun step (eq. heun) with ghost filling before each evaluation of L
  * and flux fixing after each stage: u0 holds U^n on entry and U^{n+1} on
  * exit, u1 is scratch.  Returns the dt that was used. */
+void om_substep(const om_mesh *m, const double *ud, const double *up, double *uo, double c, double wd,
+                double wp, double dt) {
+  const double *ups[1] = {up};
+  om_substep_n(m, ud, ups, &wp, 1, uo, c, wd, dt);
+}
+
 /* One sub-step of a step with its ghost fill before and flux fix after. */
 static void substep(const om_mesh *m, double *ud, double *up, double *uo, double c, double wd, double wp,
                     double dt) {
@@ -668,6 +679,24 @@ double om_step(const om_mesh *m, double *u0, double *u1) {
       substep(m, u1, NULL, u0, 0.5, 1.0, 0.0, dt);
     }
     free(u2);
+    return dt;
+  }
+  if (m->rk == 3) {
+    /* classical RK4 (eq. rk4): u1 = u + dt/2 L(u); u2 = u + dt/2 L(u1);
+     * u3 = u + dt L(u2); u' = dt/6 L(u3) + (-u + u1 + 2 u2 + u3)/3 */
+    size_t n = (size_t)m->nb * m->nvar * cells_per_var(m);
+    double *u2 = (double *)calloc(n ? n : 1, sizeof(double));
+    double *u3 = (double *)calloc(n ? n : 1, sizeof(double));
+    substep(m, u0, NULL, u1, 0.5, 1.0, 0.0, dt);
+    substep(m, u1, u0, u2, 0.5, 0.0, 1.0, dt);
+    substep(m, u2, u0, u3, 1.0, 0.0, 1.0, dt);
+    om_ghost_fill(m, u3);
+    const double *ups[3] = {u0, u1, u2};
+    const double wps[3] = {-1.0 / 3.0, 1.0 / 3.0, 2.0 / 3.0};
+    om_substep_n(m, u3, ups, wps, 3, u0, 1.0 / 6.0, 1.0 / 3.0, dt);
+    om_flux_fix(m, u3, u0, dt / 6.0);
+    free(u2);
+    free(u3);
     return dt;
   }
   om_ghost_fill(m, u0);
