@@ -69,9 +69,9 @@ typedef enum { FOAP4_FLUX_RUSANOV = 0, FOAP4_FLUX_HLL = 1 } foap4_flux;
  * Heun (SSP-RK2, eq. heun); SSP-RK3 (u1 = u + dt L(u), u2 = 3/4 u + 1/4 (u1 +
  * dt L(u1)), u' = 1/3 u + 2/3 (u2 + dt L(u2))); SSP-RK(4,3) (u1 = u + dt/2
  * L(u), u2 = u1 + dt/2 L(u1), u3 = 2/3 u + 1/3 u2 + dt/6 L(u2), u' = u3 +
- * dt/2 L(u3)).  The last two need a third state buffer
- * (foap4_mesh_set_third_state). */
-typedef enum { FOAP4_RK_HEUN = 0, FOAP4_RK_SSP3 = 1, FOAP4_RK_SSP43 = 2 } foap4_integrator;
+ * dt/2 L(u3)); classical RK4 (eq. rk4).  SSP-RK3 and SSP-RK(4,3) need the
+ * extra state 2, RK4 the extra states 2 and 3 (foap4_mesh_set_extra_state). */
+typedef enum { FOAP4_RK_HEUN = 0, FOAP4_RK_SSP3 = 1, FOAP4_RK_SSP43 = 2, FOAP4_RK_RK4 = 3 } foap4_integrator;
 
 /* Mesh descriptor.  A brick of n_trees[0] x n_trees[1] (x n_trees[2]) trees
  * (the paper's p4est brick, Sec. 2.2), periodic or bounded per axis; cubic
@@ -142,12 +142,13 @@ foap4_status foap4_mesh_info(const foap4_mesh *mesh, int64_t *n_blocks, int64_t 
  * foap4_regrid once the new pattern exists; the callback may call
  * foap4_set_bc_data with data for the new records.  Errors: FOAP4_E_INVALID
  * (n_values does not match). */
-/* The third state buffer of the integrators with three or four sub-steps:
- * caller-owned, device, at least max_blocks * nvar * P^ndim elements
- * (state_bytes bytes), 16-byte aligned, with the layout of the other two.  It
- * holds intermediate stages only.  foap4_step returns FOAP4_E_ORDER for such
- * an integrator until it is set.  Errors: FOAP4_E_INVALID (size, alignment). */
-foap4_status foap4_mesh_set_third_state(foap4_mesh *mesh, void *state2, size_t state_bytes);
+/* Extra state buffer `index` (2 or 3) of the integrators with more than two
+ * sub-steps: caller-owned, device, at least max_blocks * nvar * P^ndim
+ * elements (state_bytes bytes), 16-byte aligned, with the layout of the other
+ * two, distinct from them.  It holds intermediate stages only.  foap4_step
+ * returns FOAP4_E_ORDER for an integrator whose extra states are not set.
+ * Errors: FOAP4_E_INVALID (index, size, alignment, aliasing). */
+foap4_status foap4_mesh_set_extra_state(foap4_mesh *mesh, int32_t index, void *state, size_t state_bytes);
 
 typedef void (*foap4_bc_callback)(foap4_mesh *mesh, void *user);
 foap4_status foap4_set_bc_data(foap4_mesh *mesh, const double *bc_data_dev, int64_t n_values,
@@ -199,7 +200,7 @@ foap4_status foap4_compute_dt(foap4_mesh *mesh);
  * sub-step ghost fill, fused flux/update stage, flux fix at refinement
  * boundaries (Sec. 2.7); the next dt comes from the new state (FP64
  * reduction on the device).  The result is in the current state buffer.
- * FOAP4_E_ORDER if the integrator needs a third state buffer that is not set;
+ * FOAP4_E_ORDER if the integrator needs extra state buffers that are not set;
  * FOAP4_E_INVALID if feature capture is on with an integrator other than
  * Heun.  Enqueues only; if t_out/dt_out are non-NULL
  * the stream is synchronized and the simulation time / the dt of the next

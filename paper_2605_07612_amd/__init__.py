@@ -40,7 +40,7 @@ class MeshDesc(ctypes.Structure):
 LIMITERS = {"minmod": 0, "vanleer": 1}
 FLUXES = {"rusanov": 0, "hll": 1}
 BC_DIRICHLET, BC_NEUMANN = 0, 1
-INTEGRATORS = {"heun": 0, "ssprk3": 1, "ssprk43": 2}
+INTEGRATORS = {"heun": 0, "ssprk3": 1, "ssprk43": 2, "rk4": 3}
 
 
 def wall_bc(ndim):
@@ -62,7 +62,7 @@ EXPORTS = {
     "foap4_mesh_create": (I32, [ctypes.POINTER(MeshDesc), P, P, ctypes.c_size_t, P, ctypes.POINTER(P)]),
     "foap4_mesh_destroy": (I32, [P]),
     "foap4_set_bc_data": (I32, [P, P, I64, P, P]),
-    "foap4_mesh_set_third_state": (I32, [P, P, ctypes.c_size_t]),
+    "foap4_mesh_set_extra_state": (I32, [P, I32, P, ctypes.c_size_t]),
     "foap4_mesh_info": (I32, [P, P, P, P]),
     "foap4_mesh_export": (I32, [P, P, P, P]),
     "foap4_ghost_pattern_build": (I32, [P]),
@@ -189,9 +189,10 @@ class Mesh:
                                      nbytes, P(self.stream.cuda_stream), ctypes.byref(h))
         _check(st)
         self.h = h
-        if integrator != "heun":  # the third state of the 3- and 4-stage schemes
+        # the extra states of the longer integrators (SSP: one, RK4: two)
+        for idx in range(2, 2 + {"heun": 0, "rk4": 2}.get(integrator, 1)):
             self.state.append(torch.zeros(shape, dtype=self.dtype, device=device))
-            _check(lib().foap4_mesh_set_third_state(self.h, P(self.state[2].data_ptr()), nbytes), self.h)
+            _check(lib().foap4_mesh_set_extra_state(self.h, idx, P(self.state[idx].data_ptr()), nbytes), self.h)
 
     def close(self):
         if getattr(self, "h", None):

@@ -29,6 +29,7 @@ MeshDev make_dev(const foap4_mesh *m, int ks, int gather) {
   d.s[0] = m->state[0];
   d.s[1] = m->state[1];
   d.s[2] = m->state[2];
+  d.s[3] = m->state[3];
   d.level = m->d_level;
   d.face_info = m->pat.face_info;
   d.srl = m->pat.srl;
@@ -182,8 +183,9 @@ foap4_status foap4_mesh_create(const foap4_mesh_desc *desc, void *state0, void *
     return fail(nullptr, FOAP4_E_INVALID, "limiter must be minmod or van Leer");
   if (d.flux != FOAP4_FLUX_RUSANOV && d.flux != FOAP4_FLUX_HLL)
     return fail(nullptr, FOAP4_E_INVALID, "flux must be Rusanov or HLL");
-  if (d.integrator != FOAP4_RK_HEUN && d.integrator != FOAP4_RK_SSP3 && d.integrator != FOAP4_RK_SSP43)
-    return fail(nullptr, FOAP4_E_INVALID, "integrator must be Heun, SSP-RK3 or SSP-RK(4,3)");
+  if (d.integrator != FOAP4_RK_HEUN && d.integrator != FOAP4_RK_SSP3 && d.integrator != FOAP4_RK_SSP43 &&
+      d.integrator != FOAP4_RK_RK4)
+    return fail(nullptr, FOAP4_E_INVALID, "integrator must be Heun, SSP-RK3, SSP-RK(4,3) or RK4");
   for (int a = 0; a < 3; a++)
     if (!std::isfinite(d.gravity[a])) return fail(nullptr, FOAP4_E_INVALID, "gravity must be finite");
   if (!state0 || !state1 || state0 == state1) return fail(nullptr, FOAP4_E_INVALID, "two distinct state buffers needed");
@@ -307,9 +309,10 @@ foap4_status foap4_compute_dt(foap4_mesh *m) {
   return ensure_dt(m);
 }
 
-// Sub-steps of the integrators with a third state (Sec. 3.1, eq. feuler):
-// {c, wd, wp, deriv, prev, out, epi}, states by role (0 U^n, 1 the other
-// creation buffer, 2 the third state); U^{n+1} lands in role 0 again.
+// Sub-steps of the integrators with extra states (Sec. 3.1, eq. feuler):
+// {c, wd, wp, deriv, prev, out, epi[, wp2, wp3, prev2, prev3]}, states by
+// role (0 U^n, 1 the other creation buffer, 2 and 3 the extra states);
+// U^{n+1} lands in role 0 again.
 static const SubStep kSSP3[3] = {{1.0, 1.0, 0.0, 0, 0, 1, 0},
                                  {0.25, 0.25, 0.75, 1, 0, 2, 0},
                                  {2.0 / 3.0, 2.0 / 3.0, 1.0 / 3.0, 2, 0, 0, 1}};
@@ -317,20 +320,41 @@ static const SubStep kSSP43[4] = {{0.5, 1.0, 0.0, 0, 0, 1, 0},
                                   {0.5, 1.0, 0.0, 1, 1, 2, 0},
                                   {1.0 / 6.0, 1.0 / 3.0, 2.0 / 3.0, 2, 0, 1, 0},
                                   {0.5, 1.0, 0.0, 1, 1, 0, 1}};
+// classical RK4 (eq. rk4): u1 = u + dt/2 L(u), u2 = u + dt/2 L(u1),
+// u3 = u + dt L(u2), u' = dt/6 L(u3) + (-u + u1 + 2 u2 + u3)/3 (the last with
+// three earlier states: roles 0, 1, 2 with weights -1/3, 1/3, 2/3)
+static const SubStep kRK4[4] = {{0.5, 1.0, 0.0, 0, 0, 1, 0, 0.0, 0.0, 0, 0},
+                                {0.5, 0.0, 1.0, 1, 0, 2, 0, 0.0, 0.0, 0, 0},
+                                {1.0, 0.0, 1.0, 2, 0, 3, 0, 0.0, 0.0, 0, 0},
+                                {1.0 / 6.0, 1.0 / 3.0, -1.0 / 3.0, 3, 0, 0, 1, 1.0 / 3.0, 2.0 / 3.0, 1, 2}};
 static int substeps_of(int integrator, const SubStep **ss) {
   if (integrator == FOAP4_RK_SSP3) { *ss = kSSP3; return 3; }
   if (integrator == FOAP4_RK_SSP43) { *ss = kSSP43; return 4; }
+  if (integrator == FOAP4_RK_RK4) { *ss = kRK4; return 4; }
   *ss = nullptr;
   return 0;
 }
+// the stage kernel's form of a sub-step: 4 with three earlier states, else 3
+static int substep_form(const SubStep &ss) { return (ss.wp2 != 0.0 || ss.wp3 != 0.0) ? 4 : 3; }
+// extra states an integrator needs (indices 2 .. 1 + n)
+static int extra_states_of(int integrator) {
+  return integrator == FOAP4_RK_RK4 ? 2 : (integrator == FOAP4_RK_HEUN ? 0 : 1);
+}
+static bool extra_states_set(const foap4_mesh *m) {
+  for (int i = 0; i < extra_states_of(m->d.integrator); i++)
+    if (!m->state[2 + i]) return false;
+  return true;
+}
 
-foap4_status foap4_mesh_set_third_state(foap4_mesh *m, void *state2, size_t bytes) {
-  if (!m || !state2) return fail(m, FOAP4_E_INVALID, "null argument");
-  if (((uintptr_t)state2) & 15u) return fail(m, FOAP4_E_INVALID, "state buffers must be 16-byte aligned");
+foap4_status foap4_mesh_set_extra_state(foap4_mesh *m, int32_t index, void *state, size_t bytes) {
+  if (!m || !state) return fail(m, FOAP4_E_INVALID, "null argument");
+  if (index != 2 && index != 3) return fail(m, FOAP4_E_INVALID, "extra state index must be 2 or 3");
+  if (((uintptr_t)state) & 15u) return fail(m, FOAP4_E_INVALID, "state buffers must be 16-byte aligned");
   if ((size_t)m->d.max_blocks * m->block_elems * m->elem > bytes)
-    return fail(m, FOAP4_E_INVALID, "third state buffer smaller than max_blocks blocks");
-  if (state2 == m->state[0] || state2 == m->state[1]) return fail(m, FOAP4_E_INVALID, "third state must be distinct");
-  m->state[2] = state2;
+    return fail(m, FOAP4_E_INVALID, "extra state buffer smaller than max_blocks blocks");
+  for (int i = 0; i < 4; i++)
+    if (i != index && state == m->state[i]) return fail(m, FOAP4_E_INVALID, "state buffers must be distinct");
+  m->state[index] = state;
   m->dev_serial++;
   return upload_dev(m);
 }
@@ -340,7 +364,7 @@ foap4_status foap4_step(foap4_mesh *m, int32_t n_steps, double *t_out, double *d
   if (!m->pat_valid) return fail(m, FOAP4_E_ORDER, "no ghost pattern");
   const SubStep *subs = nullptr;
   const int nsub = substeps_of(m->d.integrator, &subs);
-  if (nsub && !m->state[2]) return fail(m, FOAP4_E_ORDER, "this integrator needs a third state buffer");
+  if (nsub && !extra_states_set(m)) return fail(m, FOAP4_E_ORDER, "this integrator needs its extra state buffers");
   if (nsub && m->capture && n_steps > 0)
     return fail(m, FOAP4_E_INVALID, "feature capture needs the Heun integrator");
   if (nsub) {
@@ -352,9 +376,10 @@ foap4_status foap4_step(foap4_mesh *m, int32_t n_steps, double *t_out, double *d
     for (int32_t s = 0; s < n_steps; s++) {
       for (int k = 0; k < nsub; k++) {
         if ((st = fill(m, m->d_dev, subs[k].deriv)) != FOAP4_OK) return st;
-        F4_HIP(m, launch_stage(m->d_dev, 1, items, 3, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n),
+        const int form = substep_form(subs[k]);
+        F4_HIP(m, launch_stage(m->d_dev, 1, items, form, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n),
                                scheme_of(m->d), subs[k]));
-        F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, 3, m->stream, subs[k]));
+        F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, form, m->stream, subs[k]));
       }
       F4_HIP(m, launch_finalize(m->d_dev, 1, 1, m->stream));
     }
@@ -661,17 +686,18 @@ static hipError_t batch_enqueue_step(foap4_batch *b, hipStream_t s) {
   hipError_t e;
   const SubStep *subs = nullptr;
   const int nsub = substeps_of(b->integrator, &subs);
-  for (int k = 0; k < nsub; k++) {  // integrators with a third state: generic sub-steps
+  for (int k = 0; k < nsub; k++) {  // integrators with extra states: generic sub-steps
     const int which = subs[k].deriv;
     if ((e = launch_ghost(b->d_devs, n, b->r1_total, 1, which, b->ndim, b->f64, 0, s)) != hipSuccess) return e;
     if (b->r2_total && (e = launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s)) != hipSuccess)
       return e;
-    if ((e = launch_stage(b->d_devs, n, b->total_items, 3, b->ndim, b->f64, stage_grid(b, 2), s, b->xcd, b->nmask,
-                          b->scheme, subs[k])) != hipSuccess)
+    const int form = substep_form(subs[k]);
+    if ((e = launch_stage(b->d_devs, n, b->total_items, form, b->ndim, b->f64, stage_grid(b, 2), s, b->xcd,
+                          b->nmask, b->scheme, subs[k])) != hipSuccess)
       return e;
     for (int i = 0; i < n; i++)
       if (b->meshes[i]->pat.n_fix > 0 &&
-          (e = launch_fluxfix(b->d_devs + i, b->ndim, b->f64, b->meshes[i]->pat.n_fix, 3, s, subs[k])) != hipSuccess)
+          (e = launch_fluxfix(b->d_devs + i, b->ndim, b->f64, b->meshes[i]->pat.n_fix, form, s, subs[k])) != hipSuccess)
         return e;
   }
   if (nsub) return launch_finalize(b->d_devs, n, 1, s);
@@ -795,8 +821,7 @@ foap4_status foap4_batch_step(foap4_batch *b, int32_t n_steps) {
   if (!b || n_steps < 0) return batch_fail(b, FOAP4_E_INVALID, "bad batch or step count");
   for (foap4_mesh *m : b->meshes) {
     if (!m->pat_valid) return batch_fail(b, FOAP4_E_ORDER, "mesh without ghost pattern");
-    if (b->integrator != FOAP4_RK_HEUN && !m->state[2])
-      return batch_fail(b, FOAP4_E_ORDER, "this integrator needs a third state buffer");
+    if (!extra_states_set(m)) return batch_fail(b, FOAP4_E_ORDER, "this integrator needs its extra state buffers");
   }
   foap4_status st = batch_prepare(b);
   if (st != FOAP4_OK) return st;

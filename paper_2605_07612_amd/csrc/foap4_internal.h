@@ -83,20 +83,23 @@ class Topology {
 
 // Device descriptor of one mesh as the kernels see it (copied to the device).
 // One sub-step of the Runge-Kutta framework (eq. feuler) in its generic
-// form: u(out) = c dt L(u(deriv)) + wd u(deriv) + wp u(prev).  States are
-// named by role: 0 the current state, 1 the other of the two creation
-// buffers, 2 the third state buffer.  epi: the last sub-step of a step, which
+// form: u(out) = c dt L(u(deriv)) + wd u(deriv) + wp u(prev) [+ wp2 u(prev2)
+// + wp3 u(prev3), the form with three earlier states].  States are named by
+// role: 0 the current state, 1 the other of the two creation buffers, 2 and
+// 3 the extra state buffers.  epi: the last sub-step of a step, which
 // evaluates the CFL limit of its output.
 struct SubStep {
   double c, wd, wp;
   int32_t deriv, prev, out, epi;
+  double wp2, wp3;
+  int32_t prev2, prev3;
 };
 __host__ __device__ __forceinline__ int role_buffer(int role, int cur) {
-  return role == 0 ? cur : (role == 1 ? 1 - cur : 2);
+  return role == 0 ? cur : (role == 1 ? 1 - cur : role);
 }
 
 struct MeshDev {
-  void *s[3];                 // state buffers: the two of creation and the optional third
+  void *s[4];                 // state buffers: the two of creation and the optional extra two
   const int32_t *level;       // [nb]
   // [nb][2*ndim]: -2 - n for a same-level neighbour n, -1 for a boundary,
   // 2*slot for a C2F face (fine-side flux slot), 2*slot+1 for an F2C face
@@ -144,7 +147,7 @@ struct foap4_mesh {
   int nvar = 0, P = 0, nf = 0;
   size_t elem = 0;             // bytes per value
   int64_t block_elems = 0;     // nvar * P^ndim
-  void *state[3] = {nullptr, nullptr, nullptr};  // the third: integrators with 3+ sub-steps
+  void *state[4] = {nullptr, nullptr, nullptr, nullptr};  // extra states of the longer integrators
   size_t state_bytes = 0;
   hipStream_t stream = nullptr;
   int32_t cur = 0;
@@ -226,7 +229,7 @@ hipError_t launch_ghost(const MeshDev *d_meshes, int n_meshes, int64_t total, in
 int64_t stage_items_for(int ndim, int N, int64_t nb, int ks);
 // nmask: block sizes present in the launch (1: N = 8, 2: N = 16, 4: N = 32);
 // scheme: scheme_of() of the meshes in the launch; stage 1 / 2: Heun's stages,
-// stage 3: the generic sub-step ss
+// stage 3: the generic sub-step ss, stage 4: the same with three earlier states
 hipError_t launch_stage(const MeshDev *d_meshes, int n_meshes, int64_t total_items, int stage,
                         int ndim, bool f64, int grid, hipStream_t s, int xcd, int nmask, int scheme,
                         const SubStep &ss = SubStep{});

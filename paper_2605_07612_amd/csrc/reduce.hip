@@ -87,10 +87,10 @@ __global__ __launch_bounds__(256) void fluxfix_kernel(const MeshDev *__restrict_
   const int32_t cb = M.fix_list[blockIdx.x];
   const int N = M.N, H = N / 2, g = M.g, P = N + 2 * g;
   const int64_t sv = (NDIM == 3) ? (int64_t)P * P * P : (int64_t)P * P;
-  const int ob = stage == 3 ? role_buffer(ss.out, M.cur) : (stage == 1 ? 1 - M.cur : M.cur);
+  const int ob = stage >= 3 ? role_buffer(ss.out, M.cur) : (stage == 1 ? 1 - M.cur : M.cur);
   T *uo = (T *)M.s[ob] + (int64_t)cb * sv * NV;
   const double dx = ldexp(M.dx0, -M.level[cb]);
-  const double dts = stage == 3 ? ss.c * M.scal[kDt] : (stage == 1 ? M.scal[kDt] : 0.5 * M.scal[kDt]);
+  const double dts = stage >= 3 ? ss.c * M.scal[kDt] : (stage == 1 ? M.scal[kDt] : 0.5 * M.scal[kDt]);
   const int N2 = (NDIM == 3) ? N : 1;
   const int64_t fv = (int64_t)N * N2;  // face values per variable
   const T *bf = (const T *)M.bflux_f;
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void fluxfix_kernel(const MeshDev *__restrict_
     }
     __syncthreads();
   }
-  if (stage != 2 && !(stage == 3 && ss.epi)) return;
+  if (stage != 2 && !(stage >= 3 && ss.epi)) return;
   double vmax = 0.0;
   bool bad = false;
   for (int f = 0; f < NF; f++) {

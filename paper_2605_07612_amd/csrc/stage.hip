@@ -163,15 +163,20 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   const int64_t bel = (int64_t)sv * NV;
   const int cur = M.cur;
   // stage 1 / 2: Heun's stages; stage 3: the generic sub-step ss (states by role)
-  const T *__restrict__ ud0 = (const T *)M.s[stage == 3 ? role_buffer(ss.deriv, cur) : (stage == 1 ? cur : 1 - cur)];
-  T *uo = (T *)M.s[stage == 3 ? role_buffer(ss.out, cur) : (stage == 1 ? 1 - cur : cur)] + b * bel;
-  const T *up = (const T *)M.s[stage == 3 ? role_buffer(ss.prev, cur) : cur] + b * bel;
+  const T *__restrict__ ud0 = (const T *)M.s[stage >= 3 ? role_buffer(ss.deriv, cur) : (stage == 1 ? cur : 1 - cur)];
+  T *uo = (T *)M.s[stage >= 3 ? role_buffer(ss.out, cur) : (stage == 1 ? 1 - cur : cur)] + b * bel;
+  const T *up = (const T *)M.s[stage >= 3 ? role_buffer(ss.prev, cur) : cur] + b * bel;
+  [[maybe_unused]] const T *up2 = nullptr, *up3 = nullptr;
+  if (stage == 4) {
+    up2 = (const T *)M.s[role_buffer(ss.prev2, cur)] + b * bel;
+    up3 = (const T *)M.s[role_buffer(ss.prev3, cur)] + b * bel;
+  }
   const T gamma = (T)M.gamma;
   const double dx = ldexp(M.dx0, -gload(M.level + b));
   const T idx = (T)(1.0 / dx);
   const double dt = gload(M.scal + kDt);
-  const T dts = (T)(stage == 3 ? ss.c * dt : (stage == 1 ? dt : 0.5 * dt));
-  [[maybe_unused]] const T wd = (T)ss.wd, wp = (T)ss.wp;
+  const T dts = (T)(stage >= 3 ? ss.c * dt : (stage == 1 ? dt : 0.5 * dt));
+  [[maybe_unused]] const T wd = (T)ss.wd, wp = (T)ss.wp, wp2 = (T)ss.wp2, wp3 = (T)ss.wp3;
   [[maybe_unused]] T grav[NDIM];
   if constexpr ((SCH & kSchGravity) != 0) {
 #pragma unroll
@@ -348,6 +353,11 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
 
   T Upn[NV];
   if (stage >= 2) load(up + off(I, J, k0), Upn);
+  [[maybe_unused]] T Upn2[NV], Upn3[NV];
+  if (stage == 4) {
+    load(up2 + off(I, J, k0), Upn2);
+    load(up3 + off(I, J, k0), Upn3);
+  }
 
   T Uc[NV];  // conserved state of own cell k + 2
   for (int k = k0; k < k1; k++) {
@@ -362,6 +372,15 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     // U^n of the own cell (stage 2): loaded one plane ahead
     T Up[NV];
     const T *U0 = Ua;
+    [[maybe_unused]] T Up2[NV], Up3[NV];
+    if (stage == 4) {
+      copyv<T, NV>(Up2, Upn2);
+      copyv<T, NV>(Up3, Upn3);
+      if (k + 1 < k1) {
+        load(up2 + off(I, J, k + 1), Upn2);
+        load(up3 + off(I, J, k + 1), Upn3);
+      }
+    }
     if (stage >= 2) {
       copyv<T, NV>(Up, Upn);
       if (k + 1 < k1) load(up + off(I, J, k + 1), Upn);
@@ -489,7 +508,11 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       const T dfy = FY[v * NFX + (tj + 1) * TILE + ti] - FY[v * NFX + tj * TILE + ti];
       T div = dfx + dfy;
       if constexpr (NDIM == 3) div += Fz1[v] - Fz[v];
-      const T base = (stage == 1) ? U0[v] : (stage == 2) ? T(0.5) * (Up[v] + U0[v]) : wp * Up[v] + wd * U0[v];
+      T base;
+      if (stage == 1) base = U0[v];
+      else if (stage == 2) base = T(0.5) * (Up[v] + U0[v]);
+      else if (stage == 3) base = wp * Up[v] + wd * U0[v];
+      else base = ((wp * Up[v] + wp2 * Up2[v]) + wp3 * Up3[v]) + wd * U0[v];
       if constexpr ((SCH & kSchGravity) != 0) Uout[v] = (base + dts * src[v]) - cdt * div;
       else Uout[v] = base - cdt * div;
     }
@@ -500,7 +523,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
 #pragma unroll
       for (int v = 0; v < NV; v++) gstore(uo + v * sv + o, Uout[v]);
     }
-    if ((stage == 2 || (stage == 3 && ss.epi)) && valid) {
+    if ((stage == 2 || (stage >= 3 && ss.epi)) && valid) {
       const bool skip = f2c_adj || (f2c_zlo && k == 0) || (f2c_zhi && k == N - 1);
       if (!skip) {
         if constexpr (sizeof(T) == 8) {
@@ -569,7 +592,8 @@ constexpr int stage_waves() { return sizeof(T) == 4 ? (NM != 7 ? 4 : 3) : 1; }
 // NM: bit mask of the block sizes present (1: N = 8, 2: N = 16, 4: N = 32)
 // STG: the Heun stage (compiled separately: stage 1 needs no U^n stream and
 // no dt epilogue, so it runs with fewer registers), or 3: the generic
-// sub-step ss of the other Runge-Kutta schemes (weights at run time)
+// sub-step ss of the other Runge-Kutta schemes (weights at run time), 4: the
+// same with three earlier states (classical RK4's last sub-step)
 template <typename T, int NDIM, int NM, int STG, int SCH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM, STG>())))
 void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t total, int xcd, SubStep ss) {
@@ -617,7 +641,8 @@ static void launch_t(unsigned nblk, int nmask, const MeshDev *d, int n, int64_t 
 #define F4_STAGE_LAUNCH(NM)                                                                     \
   if (stage == 1) stage_kernel<T, NDIM, NM, 1, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd, ss); \
   else if (stage == 2) stage_kernel<T, NDIM, NM, 2, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd, ss); \
-  else stage_kernel<T, NDIM, NM, 3, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd, ss);
+  else if (stage == 3) stage_kernel<T, NDIM, NM, 3, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd, ss); \
+  else stage_kernel<T, NDIM, NM, 4, SCH><<<nblk, 256, 0, s>>>(d, n, total, xcd, ss);
   switch (nmask) {
     case 1: F4_STAGE_LAUNCH(1) break;
     case 2: F4_STAGE_LAUNCH(2) break;

@@ -1,5 +1,6 @@
 """GPU parity of the SSP Runge-Kutta schemes with three and four sub-steps
-(Sec. 3.1, eq. feuler) against the FP64 oracle, through the C ABI: FP64
+(Sec. 3.1, eq. feuler) and of classical RK4 (eq. rk4, its last sub-step with
+three earlier states) against the FP64 oracle, through the C ABI: FP64
 within 1e-12 and FP32 within 2e-5 relative L1 on two-level meshes (ghost
 rounds and flux fixing in every sub-step), with walls and the scheme
 options; the batched form equal to the plain one bit for bit."""
@@ -102,7 +103,7 @@ def build(w, prec):
 
 @pytest.mark.parametrize("prec", [1, 0], ids=["f64", "f32"])
 @pytest.mark.parametrize("name", ["blast3d", "blast2d", "box3d_options", "rt3d"])
-@pytest.mark.parametrize("integ", ["ssprk3", "ssprk43"])
+@pytest.mark.parametrize("integ", ["ssprk3", "ssprk43", "rk4"])
 def test_parity(f4, integ, name, prec):
     w = case(name, integ)
     gm, om = build(w, prec)
@@ -119,7 +120,7 @@ def test_parity(f4, integ, name, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["f32", "f64"])
-@pytest.mark.parametrize("integ", ["ssprk3", "ssprk43"])
+@pytest.mark.parametrize("integ", ["ssprk3", "ssprk43", "rk4"])
 def test_batch_equals_plain(f4, integ, prec):
     """Two meshes (8^3 blocks on two levels, 16^3 blocks with z walls) of one
     scheme and integrator: the batched sub-steps equal the plain ones."""
@@ -145,8 +146,9 @@ def test_batch_equals_plain(f4, integ, prec):
 
 
 def test_refusals(f4):
-    """A third state that is too small is refused; feature capture needs the
-    Heun integrator; meshes of different integrators do not batch."""
+    """An extra state that is too small, or at an index other than 2 or 3,
+    is refused; feature capture needs the Heun integrator; meshes of
+    different integrators do not batch."""
     import ctypes
     import torch
     w = case("blast3d", "ssprk3")
@@ -154,7 +156,9 @@ def test_refusals(f4):
     small = torch.zeros(16, dtype=torch.float32, device="cuda")
     with pytest.raises(f4.Foap4Error, match="E_INVALID"):
         from paper_2605_07612_amd import _check, lib
-        _check(lib().foap4_mesh_set_third_state(gm.h, ctypes.c_void_p(small.data_ptr()), 64), gm.h)
+        _check(lib().foap4_mesh_set_extra_state(gm.h, 2, ctypes.c_void_p(small.data_ptr()), 64), gm.h)
+    with pytest.raises(f4.Foap4Error, match="E_INVALID"):
+        _check(lib().foap4_mesh_set_extra_state(gm.h, 4, ctypes.c_void_p(small.data_ptr()), 1 << 30), gm.h)
     gm.capture_features(True)
     with pytest.raises(f4.Foap4Error, match="E_INVALID"):
         gm.step(1)
