@@ -167,3 +167,69 @@ def test_refusals(f4):
     other, _ = build(case("blast3d", "ssprk43"), 0)
     with pytest.raises(f4.Foap4Error, match="E_INVALID"):
         f4.Batch([gm, other])
+
+
+@pytest.mark.parametrize("integ", ["ssprk3", "rk4"])
+def test_regrid_between_steps(f4, integ):
+    """Steps, a regrid by the Lohner flags (bit-exact maps), more steps: the
+    extra states hold intermediate stages only, so the integrators continue
+    across the mesh change and match the oracle (FP64)."""
+    w = case("blast3d", integ)
+    import paper_2605_07612_amd as f4m
+    from oracle import OracleMesh
+    from paper_2605_07612_amd import layout
+    from tests.gpu_helpers import scheme
+    gm = f4m.Mesh(3, w["trees"], 8, 2, w["tree_size"], level=0, max_level=2, max_blocks=4 ** 3 * 64, prec=f4.F64,
+                  gamma=w["gamma"], cfl=w["cfl"], integrator=integ, **scheme(w))
+    om = OracleMesh(3, w["trees"], 8, 2, w["tree_size"], gamma=w["gamma"], cfl=w["cfl"], integrator=integ,
+                    **scheme(w))
+    _, G = layout.global_coords(gm)
+    f0 = w["refine_flags"](G)
+    gm.regrid(f0)
+    om.regrid(f0, 0, 2)
+    layout.set_from_field(gm, w["field"])
+    om.set_interior_from_field(w["field"])
+    gm.step(4)
+    om.step(4)
+    flags = gm.refine_flags()
+    om.u[...] = 0.0
+    om.interior()[...] = interior(gpu_state(gm), 2, 8, 3)
+    om.ghost_fill()
+    assert np.array_equal(flags, om.lohner_flags())
+    assert gm.regrid(flags)
+    om.regrid(flags, 0, 2)
+    assert all(np.array_equal(a, b) for a, b in zip(gm.export(), om.forest.export()))
+    gm.step(4)
+    om.step(4)
+    lev = gm.export()[0]
+    err = rel_l1_vol(interior(gpu_state(gm), 2, 8, 3), om.interior(), lev, 3, w["tree_size"], 8)
+    say("regrid", integ, "levels", sorted(set(lev.tolist())), "rel L1", err)
+    assert err <= TOL[1]
+
+
+def test_bc_data_with_rk4(f4):
+    """Spatially varying boundary values under RK4 (ghost fills of every
+    sub-step read them) against the oracle given the same array (FP64)."""
+    import torch
+    w = case("box3d_options", "rk4")
+    t = np.ones((6, 5), np.int32)
+    t[:, 0] = t[:, 4] = 0
+    val = np.zeros((6, 5))
+    val[:, 0], val[:, 4] = 1.0, 0.25
+    w.update(bc_type=t, bc_value=val, gravity=(0.0, 0.0, 0.0))
+    gm, om = build(w, 1)
+    pat = gm.pattern_export()
+    nbc = len(pat["bc"])
+    rng = np.random.default_rng(5)
+    data = np.zeros((nbc, 5, 64))
+    data[:, 0] = 1.0 + 0.1 * rng.random((nbc, 64))
+    data[:, 4] = 0.25 + 0.05 * rng.random((nbc, 64))
+    data[:, 1:4] = 0.05 * rng.standard_normal((nbc, 3, 64))
+    gm.set_bc_data(torch.tensor(data, device="cuda"))
+    om.set_bc_data(data)
+    gm.step(5)
+    om.step(5)
+    lev = gm.export()[0]
+    err = rel_l1_vol(interior(gpu_state(gm), 2, 8, 3), om.interior(), lev, 3, w["tree_size"], 8)
+    say("bc_data rk4 rel L1", err)
+    assert err <= TOL[1]
