@@ -63,6 +63,8 @@ def lib():
         _lib.om_limiter.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double]
         _lib.om_limiter.restype = ctypes.c_double
         _lib.om_riemann_flux.argtypes = [P, P, P, ctypes.c_int32, P]
+        _lib.om_weno5.argtypes = [P]
+        _lib.om_weno5.restype = ctypes.c_double
     return _lib
 
 
@@ -88,7 +90,7 @@ def _ptr(a):
 LOHNER = dict(c_ref=5e-2, c_deref=6.25e-3, eps=1e-2, eps_abs=1e-10)
 
 # scheme options of Sec. 3.2: reconstruction limiter and numerical flux
-LIMITERS = {"minmod": 0, "vanleer": 1}
+LIMITERS = {"minmod": 0, "vanleer": 1, "weno5": 2}
 FLUXES = {"rusanov": 0, "hll": 1}
 # time integrators of Sec. 3.1
 INTEGRATORS = {"heun": 0, "ssprk3": 1, "ssprk43": 2, "rk4": 3}
@@ -97,6 +99,12 @@ INTEGRATORS = {"heun": 0, "ssprk3": 1, "ssprk43": 2, "rk4": 3}
 def limiter(kind, a, b):
     """Limited slope of a cell from its backward and forward differences."""
     return lib().om_limiter(LIMITERS[kind], float(a), float(b))
+
+
+def weno5(v):
+    """WENO5 value at the right face of the middle of five values."""
+    a = np.ascontiguousarray(v, dtype=np.float64)
+    return lib().om_weno5(_ptr(a))
 
 
 def riemann_flux(wl, wr, ax=0, flux="rusanov", gamma=1.4, ndim=3):
@@ -122,6 +130,8 @@ class OracleMesh:
         used on the faces of non-periodic axes."""
         if N % 2 or N < 2 * g or g < 2:
             raise ValueError("need even N >= 2g and g >= 2")
+        if limiter == "weno5" and g < 3:
+            raise ValueError("WENO5 needs g >= 3")
         self.ndim, self.N, self.g = ndim, N, g
         self.nvar = 2 + ndim
         self.tree_size, self.gamma, self.cfl = float(tree_size), float(gamma), float(cfl)

@@ -61,7 +61,7 @@ typedef struct {
   const double *bc_data;  /* optional spatially varying values (eq. bc-data):
                              [boundary record][var][face cell p1 + N p2], replacing
                              bc_val where given                                   */
-  int32_t limiter;        /* reconstruction slope limiter: 0 minmod, 1 van Leer  */
+  int32_t limiter;        /* reconstruction: 0 minmod, 1 van Leer, 2 WENO5 (g >= 3) */
   int32_t flux;           /* numerical flux: 0 Rusanov, 1 HLL                     */
   double grav[3];         /* gravitational acceleration; all zero: no source term */
   int32_t rk;             /* time integrator: 0 Heun (SSP-RK2), 1 SSP-RK3, 2 SSP-RK(4,3),
@@ -119,6 +119,35 @@ static inline double limited_slope(const om_mesh *m, double a, double b) {
 
 double om_limiter(int32_t kind, double a, double b) {
   return kind == 1 ? vanleer(a, b) : minmod(a, b);
+}
+
+/* WENO5 (Sec. 3.2 limiter list; Jiang and Shu 1996): the value at the right
+ * face of cell 2 of the five values v[0..4] (cells i-2 .. i+2), a convex
+ * combination of the three third-order candidates
+ *   q0 = (2 v0 - 7 v1 + 11 v2)/6, q1 = (-v1 + 5 v2 + 2 v3)/6,
+ *   q2 = (2 v2 + 5 v3 - v4)/6
+ * with weights alpha_k / sum alpha, alpha_k = d_k / (eps + beta_k)^2,
+ * d = (1/10, 6/10, 3/10), eps = 1e-6 and the smoothness indicators
+ *   beta_0 = 13/12 (v0 - 2 v1 + v2)^2 + 1/4 (v0 - 4 v1 + 3 v2)^2
+ *   beta_1 = 13/12 (v1 - 2 v2 + v3)^2 + 1/4 (v1 - v3)^2
+ *   beta_2 = 13/12 (v2 - 2 v3 + v4)^2 + 1/4 (3 v2 - 4 v3 + v4)^2 */
+double om_weno5(const double *v) {
+  double q0 = (2.0 * v[0] - 7.0 * v[1] + 11.0 * v[2]) / 6.0;
+  double q1 = (-v[1] + 5.0 * v[2] + 2.0 * v[3]) / 6.0;
+  double q2 = (2.0 * v[2] + 5.0 * v[3] - v[4]) / 6.0;
+  double a = v[0] - 2.0 * v[1] + v[2], b = v[0] - 4.0 * v[1] + 3.0 * v[2];
+  double b0 = 13.0 / 12.0 * a * a + 0.25 * b * b;
+  a = v[1] - 2.0 * v[2] + v[3];
+  b = v[1] - v[3];
+  double b1 = 13.0 / 12.0 * a * a + 0.25 * b * b;
+  a = v[2] - 2.0 * v[3] + v[4];
+  b = 3.0 * v[2] - 4.0 * v[3] + v[4];
+  double b2 = 13.0 / 12.0 * a * a + 0.25 * b * b;
+  double eps = 1e-6;
+  double a0 = 0.1 / ((eps + b0) * (eps + b0));
+  double a1 = 0.6 / ((eps + b1) * (eps + b1));
+  double a2 = 0.3 / ((eps + b2) * (eps + b2));
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
 }
 
 /* ------------------------------------------------------- ghost cells, R1/R2 */
@@ -417,6 +446,32 @@ void om_riemann_flux(const om_mesh *m, const double *wl, const double *wr, int32
 /* Numerical flux through the face between cell c and c + e_ax of block b,
  * from limited linear reconstruction of primitives (Sec. 3.2). */
 static void face_flux(const om_mesh *m, const double *u, int64_t b, const int c[3], int ax, double *F) {
+  if (m->limiter == 2) {
+    /* WENO5: the left state from cells c-2 .. c+2, the right state from
+     * c+3 .. c-1 (the same formula mirrored) */
+    double a[6][5];
+    for (int s = 0; s < 6; s++) {
+      int cs[3] = {c[0], c[1], c[2]};
+      cs[ax] += s - 2;
+      prim_t w = to_primitive(m, u, b, cs);
+      a[s][0] = w.rho;
+      a[s][1] = w.v[0];
+      a[s][2] = w.v[1];
+      a[s][3] = w.v[2];
+      a[s][4] = w.p;
+    }
+    double L[5], R[5];
+    for (int k = 0; k < 5; k++) {
+      double vl[5] = {a[0][k], a[1][k], a[2][k], a[3][k], a[4][k]};
+      double vr[5] = {a[5][k], a[4][k], a[3][k], a[2][k], a[1][k]};
+      L[k] = om_weno5(vl);
+      R[k] = om_weno5(vr);
+    }
+    prim_t wl = {L[0], {L[1], L[2], L[3]}, L[4]};
+    prim_t wr = {R[0], {R[1], R[2], R[3]}, R[4]};
+    riemann_flux(m, &wl, &wr, ax, F);
+    return;
+  }
   int cm[3] = {c[0], c[1], c[2]}, cp[3] = {c[0], c[1], c[2]}, cpp[3] = {c[0], c[1], c[2]};
   cm[ax] -= 1;
   cp[ax] += 1;

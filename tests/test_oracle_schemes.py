@@ -280,3 +280,119 @@ def test_gravity_budget_on_two_levels(lim, flux):
         assert t[0] == pytest.approx(M, rel=1e-14)
         assert np.allclose(t[1:4], P + g * M * dt, rtol=0, atol=1e-14 * (np.abs(P).max() + M))
         assert t[4] == pytest.approx(E + dt * g @ P + 0.5 * dt * dt * (g @ g) * M, rel=1e-14)
+
+
+# -------------------------------------------------------------------- WENO5
+
+def test_weno5_exact_for_quadratic_cell_averages():
+    """Every candidate of the WENO5 combination is exact on cell averages of
+    a quadratic, so the face value is exact whatever the weights."""
+    rng = np.random.default_rng(2)
+    h = 0.1
+    for _ in range(50):
+        a, b, c = rng.standard_normal(3)
+        x = np.arange(5) * h  # cell centres, cell 2 at 0.2, its right face at 0.25
+        avg = a + b * x + c * (x * x + h * h / 12.0)
+        xf = 2.5 * h
+        assert oracle.weno5(avg) == pytest.approx(a + b * xf + c * xf * xf, abs=1e-13)
+
+
+def test_weno5_reconstruction_is_fifth_order():
+    """Face values from the cell averages of a smooth function converge at
+    fifth order under refinement (error averaged over 97 face positions, as
+    the leading terms cancel at single points)."""
+    errs = []
+    for n in (16, 32, 64, 128):
+        h = 1.0 / n
+        e = []
+        for x0 in np.linspace(0.0, 1.0, 97, endpoint=False) + 0.013:
+            lo = x0 + (np.arange(5) - 2.5) * h
+            avg = (np.cos(2 * np.pi * lo) - np.cos(2 * np.pi * (lo + h))) / (2 * np.pi * h)
+            e.append(abs(oracle.weno5(avg) - np.sin(2 * np.pi * (x0 + 0.5 * h))))
+        errs.append(np.mean(e))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    assert all(o >= 4.7 for o in orders), (errs, orders)
+
+
+def test_weno5_does_not_oscillate_at_a_jump():
+    """Next to a jump the smooth candidate takes (almost) all the weight."""
+    assert abs(oracle.weno5([0.0, 0.0, 0.0, 1.0, 1.0])) < 1e-3
+    assert abs(oracle.weno5([0.0, 0.0, 1.0, 1.0, 1.0]) - 1.0) < 1e-3
+    for v in ([0, 0, 0, 1, 1], [0, 0, 1, 1, 1], [1, 1, 0, 0, 0], [0, 1, 1, 1, 1]):
+        assert -1e-3 <= oracle.weno5(np.asarray(v, float)) <= 1 + 1e-3
+
+
+def test_weno5_needs_three_ghost_layers():
+    with pytest.raises(ValueError):
+        OracleMesh(2, (2, 2, 1), 8, 2, 0.5, limiter="weno5")
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_weno5_uniform_state_and_conservation(ndim):
+    """A uniform state stays uniform (to rounding of the candidates'
+    coefficients) and a two-level mesh conserves its totals."""
+    m = OracleMesh(ndim, (4, 4, 4), 8, 3, 0.25, limiter="weno5")
+    cent = [(np.array([G[d] for _, G in m.forest.leaves]) + 0.5) / 4 for d in range(ndim)]
+    m.regrid(np.where(sum((c - 0.5) ** 2 for c in cent) < 0.09, 1, 0).astype(np.int8), 0, 1)
+    set_uniform(m, [1.3, 0.2, -0.1, 0.3, 2.7] if ndim == 3 else [1.3, 0.2, -0.1, 2.7])
+    u0 = m.interior().copy()
+    m.step(3)
+    assert np.max(np.abs(m.interior() - u0)) <= 1e-14 * np.max(np.abs(u0))
+    xc = m.forest.cell_centres(m.N, m.tree_size)
+    rho = 1 + 0.3 * np.sin(2 * np.pi * xc[:, 0]) * np.cos(2 * np.pi * xc[:, 1])
+    vel = [0.4 * np.cos(2 * np.pi * xc[:, 1]), 0.3 * np.sin(2 * np.pi * xc[:, 0])] + \
+        ([0.2 * np.sin(2 * np.pi * xc[:, 2])] if ndim == 3 else [])
+    m.interior()[...] = np.moveaxis(synth.conserved_from_primitive(rho, vel, 1.0 + 0.2 * rho, 1.4), 0, 1)
+    t0 = m.totals()
+    vol = np.array([(m.tree_size / (m.N << l)) ** ndim for l in m.level])
+    scale = np.abs(m.interior()).reshape(m.nb, m.nvar, -1).sum(-1).T @ vol
+    m.step(3)
+    assert np.all(np.abs(m.totals() - t0) <= 1e-13 * scale)
+
+
+def test_weno5_sod_converges():
+    errs = []
+    for nx in (128, 256, 512):
+        w = synth.mirrored_sod(nx, block=16, ndim=2)
+        m = OracleMesh(2, w["trees"], w["N"], 3, w["tree_size"], gamma=w["gamma"], cfl=w["cfl"], limiter="weno5",
+                       integrator="ssprk3")
+        m.set_interior_from_field(w["field"])
+        t_end = 0.1
+        while m.t < t_end - 1e-15:
+            dt = m.dt()
+            if m.t + dt > t_end:
+                m.cfl = m._c.cfl = 0.5 * (t_end - m.t) / dt
+            m.step(1)
+        xc = m.forest.cell_centres(m.N, m.tree_size)[:, 0]
+        s = np.where(xc < 0.5, 0.25 - xc, xc - 0.75)
+        rho_ex, _, _ = sample(s / t_end, 1.0, 0.0, 1.0, 0.125, 0.0, 0.1)
+        errs.append(np.sum(np.abs(m.interior()[:, 0] - rho_ex)) / (m.nb * m.N ** 2))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert errs[0] < 0.02 and all(o >= 0.6 for o in orders), (errs, orders)
+
+
+def test_weno5_rk4_smooth_wave_fifth_order():
+    """Sec. 4.1's observation: WENO5 with classical RK4 converges at about
+    fifth order on a smooth solution when the CFL number shrinks as
+    dx^(1/4) (so RK4's error stays below the spatial one).  An entropy wave
+    (uniform v and p) from exact cell averages; error in L1 against the
+    exact cell averages at t = 0.25."""
+    errs = []
+    for nx in (16, 32, 64):
+        nt = nx // 8
+        cfl = 0.4 * (32 / nx) ** 0.25
+        m = OracleMesh(2, (nt, 1, 1), 8, 3, 1.0 / nt, gamma=1.4, cfl=cfl, limiter="weno5", integrator="rk4")
+        xc = m.forest.cell_centres(8, m.tree_size)[:, 0]
+        h = 1.0 / nx
+        avg = lambda t: 1 + 0.2 * (np.cos(2 * np.pi * (xc - t - h / 2)) - np.cos(2 * np.pi * (xc - t + h / 2))) / (2 * np.pi * h)
+        rho = avg(0.0)
+        m.interior()[...] = np.moveaxis(np.stack([rho, rho, 0 * rho, 1.0 / 0.4 + 0.5 * rho]), 0, 1)
+        t_end = 0.25
+        while m.t < t_end - 1e-15:
+            dt = m.dt()
+            if m.t + dt > t_end:
+                m.cfl = m._c.cfl = cfl * (t_end - m.t) / dt
+            m.step(1)
+        errs.append(np.mean(np.abs(m.interior()[:, 0] - avg(t_end))))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(o >= 4.5 for o in orders), (errs, orders)
