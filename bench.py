@@ -91,7 +91,7 @@ def traffic_from_counters(path, stage_launch_bytes):
         import hashlib
         csrc = os.path.join(ROOT, "paper_2605_07612_amd", "csrc")
         src = b"".join(open(os.path.join(csrc, f), "rb").read()
-                       for f in ("stage.hip", "device_common.h", "foap4_internal.h"))
+                       for f in ("stage.hip", "device_common.h", "foap4_internal.h", "stage_common.h"))
         if hashlib.sha256(src).hexdigest() != d["source_sha256"]:
             return None  # the kernel changed since the counters were taken
         fetch = d["stage_fetch_kib"] * d["fetch_scale"]

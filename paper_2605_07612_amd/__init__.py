@@ -37,7 +37,7 @@ class MeshDesc(ctypes.Structure):
                 ("integrator", ctypes.c_int32)]
 
 # stage scheme options (include/foap4.h: foap4_limiter, foap4_flux)
-LIMITERS = {"minmod": 0, "vanleer": 1}
+LIMITERS = {"minmod": 0, "vanleer": 1, "weno5": 2}
 FLUXES = {"rusanov": 0, "hll": 1}
 BC_DIRICHLET, BC_NEUMANN = 0, 1
 INTEGRATORS = {"heun": 0, "ssprk3": 1, "ssprk43": 2, "rk4": 3}

@@ -179,8 +179,10 @@ foap4_status foap4_mesh_create(const foap4_mesh_desc *desc, void *state0, void *
     return fail(nullptr, FOAP4_E_INVALID, "levels must satisfy 0 <= min <= max <= 14, init <= max");
   if (!(d.tree_size > 0) || !(d.gamma > 1) || !(d.cfl > 0)) return fail(nullptr, FOAP4_E_INVALID, "tree_size, gamma, cfl");
   if (d.prec != FOAP4_F32 && d.prec != FOAP4_F64) return fail(nullptr, FOAP4_E_INVALID, "prec");
-  if (d.limiter != FOAP4_LIM_MINMOD && d.limiter != FOAP4_LIM_VANLEER)
-    return fail(nullptr, FOAP4_E_INVALID, "limiter must be minmod or van Leer");
+  if (d.limiter != FOAP4_LIM_MINMOD && d.limiter != FOAP4_LIM_VANLEER && d.limiter != FOAP4_LIM_WENO5)
+    return fail(nullptr, FOAP4_E_INVALID, "limiter must be minmod, van Leer or WENO5");
+  if (d.limiter == FOAP4_LIM_WENO5 && d.n_ghost < 3)
+    return fail(nullptr, FOAP4_E_INVALID, "WENO5 needs n_ghost >= 3");
   if (d.flux != FOAP4_FLUX_RUSANOV && d.flux != FOAP4_FLUX_HLL)
     return fail(nullptr, FOAP4_E_INVALID, "flux must be Rusanov or HLL");
   if (d.integrator != FOAP4_RK_HEUN && d.integrator != FOAP4_RK_SSP3 && d.integrator != FOAP4_RK_SSP43 &&
@@ -359,14 +361,27 @@ foap4_status foap4_mesh_set_extra_state(foap4_mesh *m, int32_t index, void *stat
   return upload_dev(m);
 }
 
+// One stage or sub-step of the plain form: the WENO5 kernel for a WENO5
+// mesh, else the plane-marching kernel (one workgroup per work item).
+static hipError_t mesh_stage(foap4_mesh *m, int64_t items, int stage, const SubStep &ss = SubStep{}) {
+  const bool f64 = m->d.prec == FOAP4_F64;
+  const int ndim = m->d.ndim;
+  if (m->d.limiter == FOAP4_LIM_WENO5) {
+    const int64_t cells = (int64_t)m->topo.leaves.size() * m->d.block_n * m->d.block_n * (ndim == 3 ? m->d.block_n : 1);
+    return launch_weno_stage(m->d_dev, cells, stage, ndim, f64, scheme_of(m->d), m->stream, ss);
+  }
+  return launch_stage(m->d_dev, 1, items, stage, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n), scheme_of(m->d),
+                      ss);
+}
+
 foap4_status foap4_step(foap4_mesh *m, int32_t n_steps, double *t_out, double *dt_out) {
   if (!m || n_steps < 0) return fail(m, FOAP4_E_INVALID, "bad mesh or step count");
   if (!m->pat_valid) return fail(m, FOAP4_E_ORDER, "no ghost pattern");
   const SubStep *subs = nullptr;
   const int nsub = substeps_of(m->d.integrator, &subs);
   if (nsub && !extra_states_set(m)) return fail(m, FOAP4_E_ORDER, "this integrator needs its extra state buffers");
-  if (nsub && m->capture && n_steps > 0)
-    return fail(m, FOAP4_E_INVALID, "feature capture needs the Heun integrator");
+  if ((nsub || m->d.limiter == FOAP4_LIM_WENO5) && m->capture && n_steps > 0)
+    return fail(m, FOAP4_E_INVALID, "feature capture needs the Heun integrator and a two-ghost limiter");
   if (nsub) {
     const bool f64 = m->d.prec == FOAP4_F64;
     const int ndim = m->d.ndim;
@@ -377,8 +392,7 @@ foap4_status foap4_step(foap4_mesh *m, int32_t n_steps, double *t_out, double *d
       for (int k = 0; k < nsub; k++) {
         if ((st = fill(m, m->d_dev, subs[k].deriv)) != FOAP4_OK) return st;
         const int form = substep_form(subs[k]);
-        F4_HIP(m, launch_stage(m->d_dev, 1, items, form, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n),
-                               scheme_of(m->d), subs[k]));
+        F4_HIP(m, mesh_stage(m, items, form, subs[k]));
         F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, form, m->stream, subs[k]));
       }
       F4_HIP(m, launch_finalize(m->d_dev, 1, 1, m->stream));
@@ -409,13 +423,11 @@ foap4_status foap4_step(foap4_mesh *m, int32_t n_steps, double *t_out, double *d
       F4_HIP(m, launch_stage1_features(m->d_dev, items, ndim, f64, nmask_of(m->d.block_n), m->d_featcap, m->stream,
                                        scheme_of(m->d)));
     } else {
-      F4_HIP(m, launch_stage(m->d_dev, 1, items, 1, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n),
-                             scheme_of(m->d)));
+      F4_HIP(m, mesh_stage(m, items, 1));
     }
     F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, 1, m->stream));
     if ((st = fill(m, m->d_dev, 1)) != FOAP4_OK) return st;
-    F4_HIP(m, launch_stage(m->d_dev, 1, items, 2, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n),
-                           scheme_of(m->d)));
+    F4_HIP(m, mesh_stage(m, items, 2));
     F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, 2, m->stream));
     F4_HIP(m, launch_finalize(m->d_dev, 1, 1, m->stream));
   }
@@ -777,6 +789,9 @@ foap4_status foap4_batch_create(foap4_mesh *const *meshes, int32_t n, foap4_batc
     } else if (m->d.integrator != b->integrator) {
       delete b;
       return fail(nullptr, FOAP4_E_INVALID, "batch meshes must share the time integrator");
+    } else if (m->d.limiter == FOAP4_LIM_WENO5) {
+      delete b;
+      return fail(nullptr, FOAP4_E_INVALID, "WENO5 meshes step in the plain form (foap4_step)");
     }
   b->stream = meshes[0]->stream;
   int dev = 0;
