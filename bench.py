@@ -295,6 +295,28 @@ def main():
                                     "source": "table of results on different hardware, 256^3, van Leer"}),
         }
 
+    # ---------------- the same Rayleigh-Taylor workload with WENO5 (three ghost
+    # layers), plain form (the WENO5 kernel has no batched form), Heun steps
+    if not args.skip_rt:
+        weno = {}
+        for prec, name in ((f4.F32, "fp32_plain"), (f4.F64, "fp64_plain")):
+            m = f4.Mesh(3, wr["trees"], wr["N"], 3, wr["tree_size"], prec=prec, gamma=wr["gamma"], cfl=wr["cfl"],
+                        limiter="weno5", flux=wr["flux"], gravity=wr["gravity"], periodic=wr["periodic"],
+                        bc_type=wr["bc_type"], bc_value=wr["bc_value"])
+            layout.set_from_grid(m, wr["grid_field"]())
+            m.step(2)
+            sw, _ = timed_steps(lambda n: m.step(n), 5, torch.cuda.synchronize)
+            weno[name] = {"value": round(cells * 2 * 5 / sw / 1e9, 4), "ms_per_step": round(sw / 5 * 1e3, 3)}
+            log(f"Rayleigh-Taylor WENO5 {name}: {sw / 5 * 1e3:.3f} ms/step, {weno[name]['value']:.2f} Gcell-updates/s")
+            m.close()
+            del m
+            torch.cuda.empty_cache()
+        paper_w = {32: 0.53, 16: 0.48, 8: 0.40}.get(args.block)
+        result["rayleigh_taylor_weno5"] = dict(
+            weno, unit="Gcell-updates/s", scheme="WENO5 (g = 3), Rusanov, gravity, walls in z, Heun",
+            paper_h100_context=(None if paper_w is None or args.n != 256 else
+                                {"fp64": paper_w, "source": "table of results on uniform grids, 256^3, WENO5"}))
+
     # ---------------- the 64-problem batch (mixed 8^3/16^3/32^3 blocks), FP32
     if not args.skip_batch64:
         ws = [synth.batch_problem(p) for p in range(64)]
