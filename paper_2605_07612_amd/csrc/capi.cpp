@@ -687,7 +687,8 @@ static foap4_status batch_upload(foap4_batch *b) {
   return FOAP4_OK;
 }
 
-// one Heun step of every mesh: 9 + 2 n_fix launches
+// one step of every mesh: per stage or sub-step two ghost rounds, the stage
+// launch and the flux fix of each mesh with refinement boundaries; then finalize
 static int stage_grid(const foap4_batch *b, int stage) {
   const int wg = stage == 1 ? b->wg1 : b->wg2;
   return wg > 0 ? wg * b->n_cu : 0;
