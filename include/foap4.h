@@ -61,8 +61,9 @@ typedef enum { FOAP4_IND_LOHNER = 0, FOAP4_IND_MLP = 1 } foap4_indicator;
  * stage (Sec. 3.2): minmod = the generalized minmod of eq. gminmod with
  * theta = 1; van Leer = the harmonic mean 2ab/(a+b) of the one-sided slopes
  * a, b when they share a strict sign, else 0; WENO5 = the fifth-order WENO
- * reconstruction of Jiang and Shu (eps 1e-6), which needs n_ghost >= 3, steps
- * in the plain form only (batches refuse it) and without feature capture.  Rusanov = local Lax-Friedrichs
+ * reconstruction of Jiang and Shu (eps 1e-6), which needs n_ghost >= 3 and
+ * runs without feature capture; in a batch (all meshes WENO5) its kernel is
+ * launched once per mesh inside the captured step.  Rusanov = local Lax-Friedrichs
  * with the largest Einfeldt speed; HLL = Harten-Lax-van Leer with the
  * Einfeldt speeds u_bar -+ d_bar as the slowest and fastest signals. */
 typedef enum { FOAP4_LIM_MINMOD = 0, FOAP4_LIM_VANLEER = 1, FOAP4_LIM_WENO5 = 2 } foap4_limiter;

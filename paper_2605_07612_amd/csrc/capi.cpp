@@ -136,6 +136,7 @@ struct foap4_batch {
   int nmask = 0;
   int scheme = 0;  // scheme_of() shared by all meshes
   int integrator = 0;  // shared time integrator
+  bool weno = false;   // WENO5 meshes: their own stage kernel per mesh, stored ghosts
   hipStream_t stream = nullptr, cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -668,7 +669,7 @@ static foap4_status batch_upload(foap4_batch *b) {
   std::vector<MeshDev> devs;
   int64_t it = 0, r1 = 0, r2 = 0;
   for (foap4_mesh *m : b->meshes) {
-    MeshDev d = make_dev(m, b->ks, b->gather);
+    MeshDev d = make_dev(m, b->ks, b->weno ? 0 : b->gather);
     d.item_begin = it;
     d.r1_begin = r1;
     d.r2_begin = r2;
@@ -694,6 +695,23 @@ static int stage_grid(const foap4_batch *b, int stage) {
   return wg > 0 ? wg * b->n_cu : 0;
 }
 
+// One stage or sub-step of every mesh of a batch: one persistent launch of
+// the plane-marching kernel over all work items, or for WENO5 meshes one
+// launch of the WENO5 kernel per mesh.
+static hipError_t batch_stage(foap4_batch *b, int stage, int grid, hipStream_t s, const SubStep &ss = SubStep{}) {
+  const int n = (int)b->meshes.size();
+  if (!b->weno)
+    return launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, grid, s, b->xcd, b->nmask, b->scheme, ss);
+  for (int i = 0; i < n; i++) {
+    const foap4_mesh *m = b->meshes[i];
+    const int64_t cells =
+        (int64_t)m->topo.leaves.size() * m->d.block_n * m->d.block_n * (b->ndim == 3 ? m->d.block_n : 1);
+    hipError_t e = launch_weno_stage(b->d_devs + i, cells, stage, b->ndim, b->f64, b->scheme, s, ss);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 static hipError_t batch_enqueue_step(foap4_batch *b, hipStream_t s) {
   const int n = (int)b->meshes.size();
   hipError_t e;
@@ -705,9 +723,7 @@ static hipError_t batch_enqueue_step(foap4_batch *b, hipStream_t s) {
     if (b->r2_total && (e = launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s)) != hipSuccess)
       return e;
     const int form = substep_form(subs[k]);
-    if ((e = launch_stage(b->d_devs, n, b->total_items, form, b->ndim, b->f64, stage_grid(b, 2), s, b->xcd,
-                          b->nmask, b->scheme, subs[k])) != hipSuccess)
-      return e;
+    if ((e = batch_stage(b, form, stage_grid(b, 2), s, subs[k])) != hipSuccess) return e;
     for (int i = 0; i < n; i++)
       if (b->meshes[i]->pat.n_fix > 0 &&
           (e = launch_fluxfix(b->d_devs + i, b->ndim, b->f64, b->meshes[i]->pat.n_fix, form, s, subs[k])) != hipSuccess)
@@ -720,9 +736,7 @@ static hipError_t batch_enqueue_step(foap4_batch *b, hipStream_t s) {
     if ((e = launch_ghost(b->d_devs, n, b->r1_total, 1, which, b->ndim, b->f64, 0, s)) != hipSuccess) return e;
     if (b->r2_total && (e = launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s)) != hipSuccess)
       return e;
-    if ((e = launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, grid, s, b->xcd, b->nmask,
-                          b->scheme)) != hipSuccess)
-      return e;
+    if ((e = batch_stage(b, stage, grid, s)) != hipSuccess) return e;
     for (int i = 0; i < n; i++)
       if (b->meshes[i]->pat.n_fix > 0 &&
           (e = launch_fluxfix(b->d_devs + i, b->ndim, b->f64, b->meshes[i]->pat.n_fix, stage, s)) != hipSuccess)
@@ -780,6 +794,7 @@ foap4_status foap4_batch_create(foap4_mesh *const *meshes, int32_t n, foap4_batc
   b->f64 = meshes[0]->d.prec == FOAP4_F64;
   b->scheme = scheme_of(meshes[0]->d);
   b->integrator = meshes[0]->d.integrator;
+  b->weno = meshes[0]->d.limiter == FOAP4_LIM_WENO5;
   for (foap4_mesh *m : b->meshes)
     if (m->d.ndim != b->ndim || (m->d.prec == FOAP4_F64) != b->f64) {
       delete b;
@@ -790,9 +805,9 @@ foap4_status foap4_batch_create(foap4_mesh *const *meshes, int32_t n, foap4_batc
     } else if (m->d.integrator != b->integrator) {
       delete b;
       return fail(nullptr, FOAP4_E_INVALID, "batch meshes must share the time integrator");
-    } else if (m->d.limiter == FOAP4_LIM_WENO5) {
+    } else if ((m->d.limiter == FOAP4_LIM_WENO5) != b->weno) {
       delete b;
-      return fail(nullptr, FOAP4_E_INVALID, "WENO5 meshes step in the plain form (foap4_step)");
+      return fail(nullptr, FOAP4_E_INVALID, "batch meshes must all use WENO5 or none");
     }
   b->stream = meshes[0]->stream;
   int dev = 0;
@@ -849,8 +864,8 @@ foap4_status foap4_batch_step(foap4_batch *b, int32_t n_steps) {
 
 foap4_status foap4_batch_phase_times(foap4_batch *b, int32_t n_steps, double *out_ms) {
   if (!b || n_steps < 1 || !out_ms) return batch_fail(b, FOAP4_E_INVALID, "bad arguments");
-  if (b->integrator != FOAP4_RK_HEUN)
-    return batch_fail(b, FOAP4_E_INVALID, "phase timing and autotuning time the Heun stages");
+  if (b->integrator != FOAP4_RK_HEUN || b->weno)
+    return batch_fail(b, FOAP4_E_INVALID, "phase timing and autotuning time the Heun stages of the plane kernel");
   foap4_status st = batch_prepare(b);
   if (st != FOAP4_OK) return st;
   const int n = (int)b->meshes.size();

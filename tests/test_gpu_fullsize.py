@@ -77,6 +77,24 @@ def test_rayleigh_taylor_256cubed_full_size(f4, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_rayleigh_taylor_weno5_256cubed_full_size(f4, prec):
+    """The benchmark's WENO5 leg (the same 256^3 Rayleigh-Taylor workload with
+    three ghost layers, plain form): one step against one oracle step,
+    every cell compared."""
+    w = dict(synth.rayleigh_taylor(block=16, n=256))
+    w.update(g=3, limiter="weno5")
+    say("case RT WENO5 256^3 prec", prec)
+    gm, om = build_pair(w, prec)
+    gm.step(1)
+    t, _ = gm.time()
+    om.step(1)
+    lev = np.zeros(gm.nb, np.int32)
+    err = rel_l1_vol(interior(gpu_state(gm), 3, 16, 3), om.interior(), lev, 3, w["tree_size"], 16)
+    say("RT WENO5 256^3 rel L1", err, "t", t, om.t)
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_two_level_blast_full_base(f4, prec):
     """Static two-level blast at full size (128^3 base, 6952 blocks of 8^3):
     10 steps against the oracle, then conservation over 100 steps."""

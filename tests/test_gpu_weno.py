@@ -114,16 +114,43 @@ def test_conservation_on_two_levels(f4):
 
 
 def test_refusals(f4):
-    """WENO5 needs three ghost layers, steps in the plain form only and
-    without feature capture."""
+    """WENO5 needs three ghost layers, a batch takes WENO5 meshes only
+    together, and feature capture needs a two-ghost limiter."""
     with pytest.raises(f4.Foap4Error, match="E_INVALID"):
         f4.Mesh(3, (2, 2, 2), 8, 2, 0.5, prec=f4.F32, limiter="weno5")
     w = case("blast3d", "heun")
     gm, _ = build(w, 0)
+    other = f4.Mesh(3, (2, 2, 2), 8, 3, 0.5, prec=f4.F32)
     with pytest.raises(f4.Foap4Error, match="E_INVALID"):
-        f4.Batch([gm])
+        f4.Batch([gm, other])
     gm.capture_features(True)
     with pytest.raises(f4.Foap4Error, match="E_INVALID"):
         gm.step(1)
     gm.capture_features(False)
     gm.step(1)
+
+
+@pytest.mark.parametrize("integ", ["heun", "rk4"])
+@pytest.mark.parametrize("prec", [0, 1], ids=["f32", "f64"])
+def test_batch_equals_plain(f4, integ, prec):
+    """WENO5 meshes in a batch (the two-level blast and the walled
+    Rayleigh-Taylor workload, one scheme and integrator): the captured step
+    launches the WENO5 kernel per mesh and equals the plain step bit for bit."""
+    rt = case("rt3d", integ)
+    bl = case("blast3d", integ)
+    bl.update(gravity=rt["gravity"])
+    ws = [bl, rt]
+    plain = [build(w, prec)[0] for w in ws]
+    batched = [build(w, prec)[0] for w in ws]
+    for m in plain:
+        m.step(3)
+    b = f4.Batch(batched)
+    b.step(3)
+    for w, p, q in zip(ws, plain, batched):
+        A = interior(gpu_state(p), w["g"], w["N"], w["ndim"])
+        B = interior(gpu_state(q), w["g"], w["N"], w["ndim"])
+        assert np.array_equal(A, B), w["name"]
+        assert p.time() == q.time()
+    with pytest.raises(f4.Foap4Error, match="E_INVALID"):
+        b.phase_times(1)
+    b.close()
