@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for hardware-counter passes: a 1 GiB device copy (counter calibration) "
                          "then 3 batched FP32 steps in the given configuration")
-    ap.add_argument("--profile-workload", default="noise_shear", choices=["noise_shear", "rayleigh_taylor"],
+    ap.add_argument("--profile-workload", default="noise_shear", choices=["noise_shear", "rayleigh_taylor", "rayleigh_taylor_weno5"],
                     help="workload of --profile-run")
     ap.add_argument("--config", default=None,
                     help="kslabs,wg_stage1,wg_stage2,xcd_order instead of autotuning, for every FP32 "
@@ -156,6 +156,13 @@ def main():
         layout.set_from_grid(m, wr["grid_field"]())
         return m
 
+    def make_rt_weno(prec):
+        m = f4.Mesh(3, wr["trees"], wr["N"], 3, wr["tree_size"], prec=prec, gamma=wr["gamma"], cfl=wr["cfl"],
+                    limiter="weno5", flux=wr["flux"], gravity=wr["gravity"], periodic=wr["periodic"],
+                    bc_type=wr["bc_type"], bc_value=wr["bc_value"])
+        layout.set_from_grid(m, wr["grid_field"]())
+        return m
+
     if args.profile_run:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         bb = torch.empty_like(a)
@@ -164,6 +171,16 @@ def main():
         bb.copy_(a)  # calibration: reads and writes exactly 1 GiB
         torch.cuda.synchronize()
         del a, bb
+        if args.profile_workload == "rayleigh_taylor_weno5":
+            for prec in (f4.F32, f4.F64):  # three Heun steps of each WENO5 kernel
+                m = make_rt_weno(prec)
+                m.step(3)
+                torch.cuda.synchronize()
+                m.close()
+                del m
+                torch.cuda.empty_cache()
+            log("profile run done")
+            return
         m32 = make(f4.F32) if args.profile_workload == "noise_shear" else make_rt(f4.F32)
         batch = f4.Batch([m32])
         ks, wg1, wg2, xcd = parse_config(args.config or PROFILE_CONFIG)
@@ -296,14 +313,11 @@ def main():
         }
 
     # ---------------- the same Rayleigh-Taylor workload with WENO5 (three ghost
-    # layers), plain form (the WENO5 kernel has no batched form), Heun steps
+    # layers), plain form, Heun steps
     if not args.skip_rt:
         weno = {}
         for prec, name in ((f4.F32, "fp32_plain"), (f4.F64, "fp64_plain")):
-            m = f4.Mesh(3, wr["trees"], wr["N"], 3, wr["tree_size"], prec=prec, gamma=wr["gamma"], cfl=wr["cfl"],
-                        limiter="weno5", flux=wr["flux"], gravity=wr["gravity"], periodic=wr["periodic"],
-                        bc_type=wr["bc_type"], bc_value=wr["bc_value"])
-            layout.set_from_grid(m, wr["grid_field"]())
+            m = make_rt_weno(prec)
             m.step(2)
             sw, _ = timed_steps(lambda n: m.step(n), 5, torch.cuda.synchronize)
             weno[name] = {"value": round(cells * 2 * 5 / sw / 1e9, 4), "ms_per_step": round(sw / 5 * 1e3, 3)}

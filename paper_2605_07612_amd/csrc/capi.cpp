@@ -368,8 +368,8 @@ static hipError_t mesh_stage(foap4_mesh *m, int64_t items, int stage, const SubS
   const bool f64 = m->d.prec == FOAP4_F64;
   const int ndim = m->d.ndim;
   if (m->d.limiter == FOAP4_LIM_WENO5) {
-    const int64_t cells = (int64_t)m->topo.leaves.size() * m->d.block_n * m->d.block_n * (ndim == 3 ? m->d.block_n : 1);
-    return launch_weno_stage(m->d_dev, cells, stage, ndim, f64, scheme_of(m->d), m->stream, ss);
+    return launch_weno_stage(m->d_dev, (int64_t)m->topo.leaves.size(), m->d.block_n, stage, ndim, f64, scheme_of(m->d),
+                             m->stream, ss);
   }
   return launch_stage(m->d_dev, 1, items, stage, ndim, f64, 0, m->stream, 0, nmask_of(m->d.block_n), scheme_of(m->d),
                       ss);
@@ -704,9 +704,8 @@ static hipError_t batch_stage(foap4_batch *b, int stage, int grid, hipStream_t s
     return launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, grid, s, b->xcd, b->nmask, b->scheme, ss);
   for (int i = 0; i < n; i++) {
     const foap4_mesh *m = b->meshes[i];
-    const int64_t cells =
-        (int64_t)m->topo.leaves.size() * m->d.block_n * m->d.block_n * (b->ndim == 3 ? m->d.block_n : 1);
-    hipError_t e = launch_weno_stage(b->d_devs + i, cells, stage, b->ndim, b->f64, b->scheme, s, ss);
+    hipError_t e = launch_weno_stage(b->d_devs + i, (int64_t)m->topo.leaves.size(), m->d.block_n, stage, b->ndim,
+                                     b->f64, b->scheme, s, ss);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

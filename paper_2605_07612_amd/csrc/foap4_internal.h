@@ -234,8 +234,8 @@ hipError_t launch_stage(const MeshDev *d_meshes, int n_meshes, int64_t total_ite
                         int ndim, bool f64, int grid, hipStream_t s, int xcd, int nmask, int scheme,
                         const SubStep &ss = SubStep{});
 // weno.hip: the WENO5 stage (one thread per interior cell, stored ghosts)
-hipError_t launch_weno_stage(const MeshDev *d_mesh, int64_t cells, int stage, int ndim, bool f64, int scheme,
-                             hipStream_t s, const SubStep &ss = SubStep{});
+hipError_t launch_weno_stage(const MeshDev *d_mesh, int64_t nblocks, int block_n, int stage, int ndim, bool f64,
+                             int scheme, hipStream_t s, const SubStep &ss = SubStep{});
 // stage 1 of one mesh that also reduces the raw features of its input state
 // (feat_raw [nb][2], zeroed by the caller) by atomic maxima
 hipError_t launch_stage1_features(const MeshDev *d_mesh, int64_t total_items, int ndim, bool f64, int nmask,
