@@ -154,3 +154,28 @@ def test_batch_equals_plain(f4, integ, prec):
     with pytest.raises(f4.Foap4Error, match="E_INVALID"):
         b.phase_times(1)
     b.close()
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["f64", "f32"])
+@pytest.mark.parametrize("N,g", [(32, 3), (16, 4), (8, 4)])
+def test_parity_block_shapes(f4, N, g, prec):
+    """Both 3-D WENO5 kernels on two levels (one of eight trees refined, the
+    blast across the level boundary): 32^3 blocks take the per-cell kernel,
+    16^3 and 8^3 blocks the marching kernel, here with four ghost layers of
+    which the stencil reads the inner three.  The jump is 4:1: WENO5 has no
+    positivity limiter, and a 100:1 jump over the one- and two-cell steps of
+    the sampled sphere at the level boundary drives reconstructed pressures
+    negative (the oracle reports such states as unphysical)."""
+    w = dict(name=f"blast3d_b{N}_g{g}_weno5", ndim=3, trees=(2, 2, 2), N=N, g=g, tree_size=0.5, level=0, gamma=1.4,
+             cfl=0.5, field=synth.blast_field(p_in=4.0, p_out=1.0, r0=0.15, centre=(0.42, 0.47, 0.5)),
+             refine_flags=lambda G: np.all(np.asarray(G)[:, :3] == 0, axis=1).astype(np.int8),
+             limiter="weno5", flux="hll", integrator="heun")
+    gm, om = build(w, prec)
+    steps = 4
+    gm.step(steps)
+    om.step(steps)
+    lev = gm.export()[0]
+    assert sorted(set(lev.tolist())) == [0, 1]
+    err = rel_l1_vol(interior(gpu_state(gm), g, N, 3), om.interior(), lev, 3, w["tree_size"], N)
+    say(w["name"], "prec", prec, "blocks", len(lev), "rel L1", err)
+    assert err <= TOL[prec]
