@@ -45,6 +45,31 @@ __device__ __forceinline__ T weno5(T v0, T v1, T v2, T v3, T v4) {
   return fdiv(a0 * q0 + a1 * q1 + a2 * q2, a0 + a1 + a2);
 }
 
+// FP64: the same weights with one division.  Numerator and denominator of
+// sum(alpha_k q_k) / sum(alpha_k) are multiplied by the product of the three
+// (eps + beta_k)^2, so alpha_k becomes d_k times the other two squares; the
+// products stay finite for beta_k below ~1e75.
+template <>
+__device__ __forceinline__ double weno5<double>(double v0, double v1, double v2, double v3, double v4) {
+  const double s6 = 1.0 / 6.0;
+  const double q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * s6;
+  const double q1 = (-v1 + 5.0 * v2 + 2.0 * v3) * s6;
+  const double q2 = (2.0 * v2 + 5.0 * v3 - v4) * s6;
+  const double c13 = 13.0 / 12.0, c14 = 0.25;
+  double a = v0 - 2.0 * v1 + v2, b = v0 - 4.0 * v1 + 3.0 * v2;
+  const double b0 = c13 * a * a + c14 * b * b;
+  a = v1 - 2.0 * v2 + v3;
+  b = v1 - v3;
+  const double b1 = c13 * a * a + c14 * b * b;
+  a = v2 - 2.0 * v3 + v4;
+  b = 3.0 * v2 - 4.0 * v3 + v4;
+  const double b2 = c13 * a * a + c14 * b * b;
+  const double e0 = 1e-6 + b0, e1 = 1e-6 + b1, e2 = 1e-6 + b2;
+  const double E0 = e0 * e0, E1 = e1 * e1, E2 = e2 * e2;
+  const double a0 = 0.1 * (E1 * E2), a1 = 0.6 * (E0 * E2), a2 = 0.3 * (E0 * E1);
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
 // Flux along AX through the face between cells 2 and 3 of the six primitive
 // states c[0..5] (cells f-3 .. f+2 of face f-1/2): left state reconstructed
 // from c[0..4], right state from c[5..1].
