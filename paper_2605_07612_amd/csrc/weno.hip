@@ -45,7 +45,7 @@ __device__ __forceinline__ T weno5(T v0, T v1, T v2, T v3, T v4) {
   return fdiv(a0 * q0 + a1 * q1 + a2 * q2, a0 + a1 + a2);
 }
 
-// FP64: the same weights with one division.  Numerator and denominator of
+// FP64: the same weights with one (refined) reciprocal.  Numerator and denominator of
 // sum(alpha_k q_k) / sum(alpha_k) are multiplied by the product of the three
 // (eps + beta_k)^2, so alpha_k becomes d_k times the other two squares; the
 // products stay finite for beta_k below ~1e75.
@@ -67,7 +67,7 @@ __device__ __forceinline__ double weno5<double>(double v0, double v1, double v2,
   const double e0 = 1e-6 + b0, e1 = 1e-6 + b1, e2 = 1e-6 + b2;
   const double E0 = e0 * e0, E1 = e1 * e1, E2 = e2 * e2;
   const double a0 = 0.1 * (E1 * E2), a1 = 0.6 * (E0 * E2), a2 = 0.3 * (E0 * E1);
-  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+  return (a0 * q0 + a1 * q1 + a2 * q2) * rcp_nr(a0 + a1 + a2);
 }
 
 // Flux along AX through the face between cells 2 and 3 of the six primitive
