@@ -261,7 +261,8 @@ __host__ __device__ constexpr int weno_march_lds(int N) { return 5 * ((N + 6) * 
 // evaluated once into LDS and read by the two cells that share it; the
 // z-faces come from a seven-cell register window of the column, the upper
 // face of one plane being the lower face of the next.  Per plane that is
-// 2N(N+1) + N^2 face evaluations instead of the per-cell kernel's 6 N^2.
+// 2N(N+1) + N^2 face evaluations instead of the per-cell kernel's 6 N^2;
+// the x- and y-faces share one loop, so its last round is the only partial one.
 template <typename T, int SCH, int STG>
 __global__ __launch_bounds__(256) void weno_march_kernel(const MeshDev *__restrict__ Mp, SubStep ss) {
   constexpr int NV = 5;
@@ -313,31 +314,39 @@ __global__ __launch_bounds__(256) void weno_march_kernel(const MeshDev *__restri
       for (int v = 0; v < NV; v++) Ws[(v * Q + y + 3) * Q + x + 3] = W[v];
     }
     __syncthreads();
-    for (int f = t; f < (N + 1) * N; f += nt) {
-      const int fi = f % (N + 1), fj = f / (N + 1);
+    // x- and y-faces in one loop of uniform work: a y-face's primitives are
+    // read with the first two velocity components swapped, so every face
+    // evaluates the x-normal flux, and its momentum fluxes are swapped back.
+    const int nxf = (N + 1) * N;
+    for (int f = t; f < 2 * nxf; f += nt) {
+      const bool ya = f >= nxf;
+      const int ff = ya ? f - nxf : f;
+      const int fi = ya ? ff % N : ff % (N + 1), fj = ya ? ff / N : ff / (N + 1);
+      const int base = ya ? fj * Q + fi + 3 : (fj + 3) * Q + fi;  // stencil cell 0, variable 0
+      const int step = ya ? Q : 1;
       T c6[6][NV], F[NV];
 #pragma unroll
       for (int s = 0; s < 6; s++)
 #pragma unroll
-        for (int v = 0; v < NV; v++) c6[s][v] = Ws[(v * Q + fj + 3) * Q + fi + s];
+        for (int v = 0; v < NV; v++) {
+          const int vv = (v == 1 || v == 2) && ya ? 3 - v : v;
+          c6[s][v] = Ws[vv * Q * Q + base + s * step];
+        }
       weno_face<T, 3, 0, SCH>(c6, gamma, F);
+      if (!ya) {
 #pragma unroll
-      for (int v = 0; v < NV; v++) Fx[(v * N + fj) * (N + 1) + fi] = F[v];
-      if (fi == 0) weno_bflux<T, 3>(M, B.finfo, 0, fj, k, F);
-      if (fi == N) weno_bflux<T, 3>(M, B.finfo, 1, fj, k, F);
-    }
-    for (int f = t; f < (N + 1) * N; f += nt) {
-      const int fi = f % N, fj = f / N;
-      T c6[6][NV], F[NV];
+        for (int v = 0; v < NV; v++) Fx[(v * N + fj) * (N + 1) + fi] = F[v];
+        if (fi == 0) weno_bflux<T, 3>(M, B.finfo, 0, fj, k, F);
+        if (fi == N) weno_bflux<T, 3>(M, B.finfo, 1, fj, k, F);
+      } else {
+        const T f1 = F[1];
+        F[1] = F[2];
+        F[2] = f1;
 #pragma unroll
-      for (int s = 0; s < 6; s++)
-#pragma unroll
-        for (int v = 0; v < NV; v++) c6[s][v] = Ws[(v * Q + fj + s) * Q + fi + 3];
-      weno_face<T, 3, 1, SCH>(c6, gamma, F);
-#pragma unroll
-      for (int v = 0; v < NV; v++) Fy[(v * (N + 1) + fj) * N + fi] = F[v];
-      if (fj == 0) weno_bflux<T, 3>(M, B.finfo, 2, fi, k, F);
-      if (fj == N) weno_bflux<T, 3>(M, B.finfo, 3, fi, k, F);
+        for (int v = 0; v < NV; v++) Fy[(v * (N + 1) + fj) * N + fi] = F[v];
+        if (fj == 0) weno_bflux<T, 3>(M, B.finfo, 2, fi, k, F);
+        if (fj == N) weno_bflux<T, 3>(M, B.finfo, 3, fi, k, F);
+      }
     }
     T Fzp[NV];
     weno_face<T, 3, 2, SCH>(w + 1, gamma, Fzp);
