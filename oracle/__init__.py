@@ -22,11 +22,15 @@ from .mesh import Forest
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "foap4_oracle.c")
 _LIB = os.path.join(_HERE, "libfoap4_oracle.so")
+# a separately built copy (e.g. with host sanitizers) may be named here
+_LIB_OVERRIDE = os.environ.get("FOAP4_ORACLE_LIB")
 
 
 def build(force: bool = False) -> str:
     """Compile the C oracle (gcc, FP64, no FMA contraction, OpenMP over
     independent blocks and records)."""
+    if _LIB_OVERRIDE:
+        return _LIB_OVERRIDE
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",

@@ -111,8 +111,9 @@ def test_two_level_conservation(integrator):
     assert np.all(np.abs(m.totals() - t0) <= 1e-13 * scale)
 
 
-def _wave(integrator, cfl, t_end=0.2):
-    m = OracleMesh(2, (4, 1, 1), 8, 2, 0.25, gamma=1.4, cfl=cfl, limiter="vanleer", integrator=integrator)
+def _wave(integrator, cfl, t_end=0.2, limiter="vanleer"):
+    g = 3 if limiter == "weno5" else 2
+    m = OracleMesh(2, (4, 1, 1), 8, g, 0.25, gamma=1.4, cfl=cfl, limiter=limiter, integrator=integrator)
 
     def field(x, y):
         one = np.ones_like(x)
@@ -128,16 +129,33 @@ def _wave(integrator, cfl, t_end=0.2):
 
 
 def test_time_error_below_heun():
-    """On one mesh the time-stepping error (against the same scheme at CFL
-    0.02) of the third- and fourth-order schemes at CFL 0.4 is at least 10x
-    below Heun's and falls under CFL halving at order >= 1.5, Heun's at >= 1.9
-    (the limiters' switches keep the higher orders from showing cleanly:
-    measured 1.7 to 3.0)."""
+    """On one mesh with the van Leer limiter the time-stepping error (against
+    the same scheme at CFL 0.02) of the third- and fourth-order schemes at
+    CFL 0.4 is at least 10x below Heun's; Heun and the two SSP schemes fall
+    under CFL halving at order >= 1.9.  Classical RK4 is not held to an order
+    here: van Leer's limiter is only piecewise smooth in the data, and its
+    switches cap RK4's observed order near 1.7 (its order is pinned on the
+    smooth WENO5 operator below)."""
     errs = {}
     for integ in ["heun"] + RK:
         ref = _wave(integ, 0.02)
         errs[integ] = [float(np.mean(np.abs(_wave(integ, c) - ref))) for c in (0.4, 0.2)]
     for integ in RK:
         assert errs[integ][0] * 10 <= errs["heun"][0], errs
-        assert math.log2(errs[integ][0] / errs[integ][1]) >= 1.5, errs
-    assert math.log2(errs["heun"][0] / errs["heun"][1]) >= 1.9
+    for integ in ("heun", "ssprk3", "ssprk43"):
+        assert math.log2(errs[integ][0] / errs[integ][1]) >= 1.9, (integ, errs)
+
+
+def test_time_order_on_a_smooth_operator():
+    """With WENO5 reconstruction the semi-discrete operator L is smooth in
+    the data (its nonlinear weights are differentiable), so on a fixed mesh
+    each integrator shows its classical order in time (Sec. 3.1: Heun 2,
+    SSP-RK3 and SSP-RK(4,3) 3, RK4 4): the error against the same scheme at
+    CFL 0.02 falls by 2^order per halving of CFL 0.4 -> 0.2 -> 0.1.  A wrong
+    weight in any sub-step table drops the order to at most 1 or 2."""
+    want = {"heun": 1.9, "ssprk3": 2.9, "ssprk43": 2.9, "rk4": 3.8}
+    for integ, lo in want.items():
+        ref = _wave(integ, 0.02, limiter="weno5")
+        e = [float(np.mean(np.abs(_wave(integ, c, limiter="weno5") - ref))) for c in (0.4, 0.2, 0.1)]
+        orders = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+        assert all(lo <= o <= lo + 0.4 for o in orders), (integ, e, orders)

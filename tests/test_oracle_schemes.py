@@ -3,6 +3,7 @@ HLL flux and the gravity source of the Rayleigh-Taylor test (Sec. 3.2,
 Sec. 4.2).  Each check is a closed form, an exact solution, a textbook
 identity or a conservation budget fixed by the mathematics; none compares the
 oracle with itself."""
+import functools
 import math
 
 import numpy as np
@@ -121,10 +122,85 @@ def test_hll_equals_rusanov_for_symmetric_speeds():
         assert np.allclose(Fh, Fr, rtol=1e-13, atol=1e-13)
 
 
+def roe_speed(wl, wr, gamma, ax=0):
+    """Roe's averaged normal velocity and sound speed (Roe 1981): sqrt(rho)
+    weighted velocity and total enthalpy H = (E + p)/rho, then
+    c~^2 = (gamma - 1)(H~ - |u~|^2/2).  Written from the enthalpy, not from
+    the Einfeldt form the oracle uses."""
+    sl, sr = math.sqrt(wl[0]), math.sqrt(wr[0])
+    H = [(euler_state(w, gamma, 3)[4] + w[4]) / w[0] for w in (wl, wr)]
+    Hm = (sl * H[0] + sr * H[1]) / (sl + sr)
+    u = (sl * np.asarray(wl[1:4]) + sr * np.asarray(wr[1:4])) / (sl + sr)
+    return u[ax], math.sqrt((gamma - 1.0) * (Hm - 0.5 * u @ u))
+
+
+def rusanov_speed(wl, wr, gamma, ax=0):
+    """The dissipation speed a of the oracle's Rusanov flux, recovered from
+    its mass component F = (F_L + F_R)/2 - a (rho_R - rho_L)/2."""
+    F = oracle.riemann_flux(wl, wr, ax, "rusanov", gamma, 3)
+    FL, FR = euler_flux(wl, ax, gamma, 3), euler_flux(wr, ax, gamma, 3)
+    return (0.5 * (FL[0] + FR[0]) - F[0]) / (0.5 * (wr[0] - wl[0]))
+
+
+def tangential_pair(rng, ax):
+    """Two primitive states with different densities, pressures and normal
+    velocities and equal tangential velocities."""
+    wl, wr = random_prim(rng, 3), random_prim(rng, 3)
+    wr[0] = wl[0] * rng.uniform(1.3, 3.0) ** rng.choice([-1, 1])
+    for d in range(3):
+        if d != ax:
+            wr[1 + d] = wl[1 + d]
+    return wl, wr
+
+
+def test_einfeldt_speeds_are_roe_speeds_at_gamma_two():
+    """Einfeldt's d_bar^2 = (sL cL^2 + sR cR^2)/(sL + sR) + eta2 (vR - vL)^2,
+    eta2 = sL sR / (2 (sL + sR)^2) (Sec. 3.5, Toro's form) equals Roe's
+    averaged c~^2 when gamma = 2 and the tangential velocities agree (the
+    enthalpy average carries (gamma - 1)/2 sL sR/(sL + sR)^2 |vR - vL|^2), so
+    the Rusanov speed must be |u~| + c~, and the HLL flux must be the HLL
+    formula with Roe's speeds u~ -+ c~.  A halved eta2 or an unweighted
+    mean of c^2 breaks both."""
+    rng = np.random.default_rng(41)
+    gamma = 2.0
+    for _ in range(60):
+        ax = int(rng.integers(0, 3))
+        wl, wr = tangential_pair(rng, ax)
+        u, c = roe_speed(wl, wr, gamma, ax)
+        assert rusanov_speed(wl, wr, gamma, ax) == pytest.approx(abs(u) + c, rel=1e-13)
+        SL, SR = u - c, u + c
+        UL, UR = euler_state(wl, gamma, 3), euler_state(wr, gamma, 3)
+        FL, FR = euler_flux(wl, ax, gamma, 3), euler_flux(wr, ax, gamma, 3)
+        want = FL if SL >= 0 else FR if SR <= 0 else (SR * FL - SL * FR + SL * SR * (UR - UL)) / (SR - SL)
+        F = oracle.riemann_flux(wl, wr, ax, "hll", gamma, 3)
+        assert np.allclose(F, want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
+
+
+def test_einfeldt_speed_bounds_roe_speed():
+    """For gamma < 2 Einfeldt's d_bar adds more of the velocity jump than
+    Roe's c~ does, so d_bar >= c~ (the property that makes the HLLE speeds
+    positivity preserving), with equality exactly when the normal velocities
+    agree.  d_bar is read from the Rusanov speed a = |u~| + d_bar."""
+    rng = np.random.default_rng(43)
+    gamma = 1.4
+    for _ in range(60):
+        ax = int(rng.integers(0, 3))
+        wl, wr = tangential_pair(rng, ax)
+        wr[1 + ax] = wl[1 + ax] + rng.choice([-1, 1]) * rng.uniform(0.2, 1.0)
+        u, c = roe_speed(wl, wr, gamma, ax)
+        dbar = rusanov_speed(wl, wr, gamma, ax) - abs(u)
+        assert dbar > c * (1 + 1e-4), (dbar, c)
+        wr[1 + ax] = wl[1 + ax]
+        u, c = roe_speed(wl, wr, gamma, ax)
+        assert rusanov_speed(wl, wr, gamma, ax) - abs(u) == pytest.approx(c, rel=1e-13)
+
+
 def test_hll_satisfies_the_integral_consistency():
     """The HLL flux for a subsonic face is the flux of the intermediate state
     U* = (sR UR - sL UL - (FR - FL)) / (sR - sL) through the Rankine-Hugoniot
-    relations across both outer waves: F* = FL + sL (U* - UL) = FR + sR (U* - UR)."""
+    relations across both outer waves: F* = FL + sL (U* - UL) = FR + sR (U* - UR),
+    for the HLL flux's own outer speeds, recovered from two of its components
+    (mass and energy) by solving the two relations for sL and sR."""
     rng = np.random.default_rng(21)
     gamma = 1.4
     for _ in range(20):
@@ -133,16 +209,17 @@ def test_hll_satisfies_the_integral_consistency():
         F = oracle.riemann_flux(wl, wr, 0, "hll", gamma, 3)
         UL, UR = euler_state(wl, gamma, 3), euler_state(wr, gamma, 3)
         FL, FR = euler_flux(wl, 0, gamma, 3), euler_flux(wr, 0, gamma, 3)
-        # Einfeldt speeds (Toro, eq. 10.52) retyped for the identity only
-        sl, sr = math.sqrt(wl[0]), math.sqrt(wr[0])
-        ub = (sl * wl[1] + sr * wr[1]) / (sl + sr)
-        d2 = (sl * gamma * wl[4] / wl[0] + sr * gamma * wr[4] / wr[0]) / (sl + sr) \
-            + 0.5 * sl * sr / (sl + sr) ** 2 * (wr[1] - wl[1]) ** 2
-        SL, SR = ub - math.sqrt(d2), ub + math.sqrt(d2)
-        assert SL < 0 < SR
-        Us = (SR * UR - SL * UL - (FR - FL)) / (SR - SL)
-        assert np.allclose(F, FL + SL * (Us - UL), rtol=1e-12, atol=1e-12)
-        assert np.allclose(F, FR + SR * (Us - UR), rtol=1e-12, atol=1e-12)
+        # F = FL + sL (U* - UL) with U* from the jump conditions gives, per
+        # component k, A_k (sR - sL) = sL sR dU_k - sL dF_k with A = F - FL;
+        # the mass and energy components fix sL (the pair is linear in sL
+        # once sR = sL (A_0 - dF_0)/(A_0 - sL dU_0) is eliminated), then sR.
+        A, dU, dF = F - FL, UR - UL, FR - FL
+        sl = (A[4] * dF[0] - dF[4] * A[0]) / (A[4] * dU[0] - dU[4] * (A[0] - dF[0]) - dF[4] * dU[0])
+        sr = sl * (A[0] - dF[0]) / (A[0] - sl * dU[0])
+        assert sl < 0 < sr
+        Us = (sr * UR - sl * UL - dF) / (sr - sl)
+        assert np.allclose(F, FL + sl * (Us - UL), rtol=1e-11, atol=1e-11)
+        assert np.allclose(F, FR + sr * (Us - UR), rtol=1e-11, atol=1e-11)
 
 
 # ------------------------------------------------------ schemes on a mesh
@@ -320,6 +397,70 @@ def test_weno5_does_not_oscillate_at_a_jump():
     assert abs(oracle.weno5([0.0, 0.0, 1.0, 1.0, 1.0]) - 1.0) < 1e-3
     for v in ([0, 0, 0, 1, 1], [0, 0, 1, 1, 1], [1, 1, 0, 0, 0], [0, 1, 1, 1, 1]):
         assert -1e-3 <= oracle.weno5(np.asarray(v, float)) <= 1 + 1e-3
+
+
+def _avg_poly(cells, vals):
+    """The polynomial of degree len(cells) - 1 whose averages over the unit
+    cells [j - 1/2, j + 1/2], j in cells, are vals (numpy polynomials)."""
+    from numpy.polynomial import Polynomial
+    A = np.zeros((len(cells), len(cells)))
+    for r, j in enumerate(cells):
+        for p in range(len(cells)):
+            mono = Polynomial([0.0] * p + [1.0]).integ()
+            A[r, p] = mono(j + 0.5) - mono(j - 0.5)
+    return Polynomial(np.linalg.solve(A, np.asarray(vals, float)))
+
+
+_WENO_STENCILS = [(-2, -1, 0), (-1, 0, 1), (0, 1, 2)]
+
+
+@functools.lru_cache(maxsize=1)
+def _weno5_ideal_weights():
+    """d with sum_k d_k q_k(v) = the quartic's face value for every v: solved
+    on the five unit data vectors (consistent, so the residual is zero)."""
+    Q, R = np.zeros((5, 3)), np.zeros(5)
+    for j in range(5):
+        e = np.eye(5)[j]
+        Q[j] = [_avg_poly(st, [e[i + 2] for i in st])(0.5) for st in _WENO_STENCILS]
+        R[j] = _avg_poly(range(-2, 3), e)(0.5)
+    d, res, _, _ = np.linalg.lstsq(Q, R, rcond=None)
+    assert np.abs(Q @ d - R).max() < 1e-13
+    return d
+
+
+def _weno5_from_definitions(v, eps=1e-6):
+    """WENO5 face value at x = 1/2 of cell 0 from Jiang and Shu's definitions
+    (no printed coefficient): candidates p_k = the quadratics matching the
+    cell averages of the three-cell stencils; smoothness indicators
+    beta_k = sum_{l=1,2} dx^(2l-1) int_cell (d^l p_k/dx^l)^2 dx (dx = 1);
+    ideal weights d_k = the combination of the candidates' face values that
+    equals the face value of the quartic matching all five averages;
+    alpha_k = d_k / (eps + beta_k)^2, value = sum alpha_k p_k(1/2) / sum alpha_k."""
+    cands = [_avg_poly(st, [v[j + 2] for j in st]) for st in _WENO_STENCILS]
+    beta = []
+    for p in cands:
+        b = 0.0
+        for l in (1, 2):
+            sq = (p.deriv(l) ** 2).integ()
+            b += sq(0.5) - sq(-0.5)
+        beta.append(b)
+    alpha = _weno5_ideal_weights() / (eps + np.array(beta)) ** 2
+    return float(alpha @ np.array([p(0.5) for p in cands]) / alpha.sum())
+
+
+def test_weno5_equals_the_integral_definition():
+    """The oracle's WENO5 value equals the one built from the definitions of
+    its parts (candidate polynomials, smoothness indicators as integrals of
+    squared derivatives, ideal weights from the five-cell polynomial) on
+    random, rough data at three scales, so that the indicators' sizes
+    against eps = 1e-6 matter: a wrong indicator constant (13/12 or 1/4) or
+    ideal weight changes the value far beyond the 1e-11 tolerance."""
+    rng = np.random.default_rng(17)
+    for scale in (1.0, 1e-3, 30.0):
+        for _ in range(100):
+            v = rng.uniform(-1, 1, 5) * scale
+            want = _weno5_from_definitions(v)
+            assert oracle.weno5(v) == pytest.approx(want, rel=1e-11, abs=1e-14 * scale), (v, want)
 
 
 def test_weno5_needs_three_ghost_layers():
