@@ -83,7 +83,7 @@ class _MeshC(ctypes.Structure):
                 ("bc_type", (ctypes.c_int32 * 5) * 6), ("bc_val", (ctypes.c_double * 5) * 6),
                 ("bc_data", ctypes.c_void_p),
                 ("limiter", ctypes.c_int32), ("flux", ctypes.c_int32), ("grav", ctypes.c_double * 3),
-                ("rk", ctypes.c_int32)]
+                ("rk", ctypes.c_int32), ("phys", ctypes.c_int32), ("vel", ctypes.c_double * 3)]
 
 
 def _ptr(a):
@@ -98,6 +98,8 @@ LIMITERS = {"minmod": 0, "vanleer": 1, "weno5": 2}
 FLUXES = {"rusanov": 0, "hll": 1}
 # time integrators of Sec. 3.1
 INTEGRATORS = {"heun": 0, "ssprk3": 1, "ssprk43": 2, "rk4": 3}
+# systems: the Euler equations (Sec. 3.5) and scalar advection (Sec. 3.4)
+PHYSICS = {"euler": 0, "advection": 1}
 
 
 def limiter(kind, a, b):
@@ -128,16 +130,23 @@ class OracleMesh:
 
     def __init__(self, ndim, trees, N, g=2, tree_size=1.0, level=0, gamma=1.4, cfl=0.5,
                  periodic=(True, True, True), origin=(0.0, 0.0, 0.0), limiter="minmod",
-                 flux="rusanov", gravity=(0.0, 0.0, 0.0), bc_type=None, bc_value=None, integrator="heun"):
+                 flux="rusanov", gravity=(0.0, 0.0, 0.0), bc_type=None, bc_value=None, integrator="heun",
+                 physics="euler", velocity=(0.0, 0.0, 0.0)):
         """bc_type / bc_value: [2 ndim faces -x, +x, -y, +y, -z, +z][nvar]
         Dirichlet (0) or Neumann (1) conditions and their values (Sec. 2.4),
-        used on the faces of non-periodic axes."""
+        used on the faces of non-periodic axes.  physics "advection": the
+        scalar advection problem of Sec. 3.4 (one variable rho, uniform
+        velocity `velocity`, not all zero); gamma and gravity are then unused."""
         if N % 2 or N < 2 * g or g < 2:
             raise ValueError("need even N >= 2g and g >= 2")
         if limiter == "weno5" and g < 3:
             raise ValueError("WENO5 needs g >= 3")
+        self.physics = PHYSICS[physics]
+        self.velocity = tuple(float(x) for x in velocity) + (0.0,) * (3 - len(velocity))
+        if self.physics == 1 and not any(self.velocity[:ndim]):
+            raise ValueError("scalar advection needs a non-zero velocity")
         self.ndim, self.N, self.g = ndim, N, g
-        self.nvar = 2 + ndim
+        self.nvar = 1 if self.physics == 1 else 2 + ndim
         self.tree_size, self.gamma, self.cfl = float(tree_size), float(gamma), float(cfl)
         self.origin = origin
         self.limiter, self.flux = LIMITERS[limiter], FLUXES[flux]
@@ -181,6 +190,8 @@ class OracleMesh:
         c.gamma, c.cfl = self.gamma, self.cfl
         c.limiter, c.flux, c.rk = self.limiter, self.flux, self.rk
         c.grav[:] = list(self.gravity)
+        c.phys = self.physics
+        c.vel[:] = list(self.velocity)
         c.bc_data = _ptr(self.bc_data) if self.bc_data is not None else None
         for f in range(6):
             c.bc_type[f][:] = [int(x) for x in self.bc_type[f]]
@@ -285,6 +296,8 @@ class OracleMesh:
 
     def raw_features(self, u=None):
         """[nb][2]: max |grad rho|/rho and max |grad p|/p per block (face ghosts needed)."""
+        if self.physics != 0:
+            raise ValueError("the indicator features are defined for the Euler system")
         r = np.zeros((self.nb, 2))
         lib().om_block_raw_features(self.cref(), _ptr(self.u if u is None else u), _ptr(r))
         return r

@@ -25,6 +25,10 @@
  *   CFL time step          Sec. 3.1 / Sec. 3.2 step list
  *   refinement criterion   Sec. 3.3, eq. lohner-simple
  *   regrid data remap      Sec. 2.2 (copy / prolong / restrict lists)
+ *   scalar advection       Sec. 3.4 (one conserved variable rho, uniform
+ *                          velocity v, flux rho v, wave speeds min(v_d, 0)
+ *                          and max(v_d, 0)); the same reconstructions, fluxes,
+ *                          integrators, ghost filling and flux fixing
  * Readings of points the paper leaves open are listed in the design notes:
  * the Einfeldt speed formula (Toro's form), the CFL formula
  * dt = CFL * min_cells 1 / sum_d (|v_d| + c) / dx, the placement of the flux
@@ -34,7 +38,8 @@
  * Layout: state arrays are [block][var][k][j][i] with every spatial index
  * padded by g ghost layers (i fastest), the paper's uu(i,j,k,ivar,iblock)
  * (eq. array-structure) with 0-based indices running from -g to N+g-1.
- * Variables are (rho, m_x, m_y[, m_z], E).
+ * Variables are (rho, m_x, m_y[, m_z], E) for the Euler system and the
+ * single variable rho for scalar advection.
  */
 #include <math.h>
 #include <stdint.h>
@@ -66,6 +71,9 @@ typedef struct {
   double grav[3];         /* gravitational acceleration; all zero: no source term */
   int32_t rk;             /* time integrator: 0 Heun (SSP-RK2), 1 SSP-RK3, 2 SSP-RK(4,3),
                              3 classical RK4 (eq. rk4)                          */
+  int32_t phys;           /* 0: Euler system (nvar = ndim + 2); 1: scalar advection
+                             (Sec. 3.4, nvar = 1)                               */
+  double vel[3];          /* uniform advection velocity (phys = 1)             */
 } om_mesh;
 
 /* ---------------------------------------------------------------- indexing */
@@ -443,9 +451,59 @@ void om_riemann_flux(const om_mesh *m, const double *wl, const double *wr, int32
   riemann_flux(m, &a, &b, ax, F);
 }
 
+/* ---------------------------------------------------------- scalar advection */
+
+/* Scalar advection (Sec. 3.4): rho_t + div(rho v) = 0 with a uniform velocity
+ * v, so the conserved and the primitive variable are both rho.  The face
+ * values come from the reconstruction of the mesh's limiter, exactly as for
+ * one primitive variable of the Euler system (Sec. 3.2); the physical flux
+ * on either side is rho v_ax, and the numerical flux (Rusanov or HLL) takes
+ * the slowest and fastest wave speeds min(v_ax, 0) and max(v_ax, 0) that
+ * Sec. 3.4 gives. */
+static double advection_face_flux(const om_mesh *m, const double *u, int64_t b, const int c[3], int ax) {
+  double L, R;
+  if (m->limiter == 2) {
+    double a[6];
+    for (int s = 0; s < 6; s++) {
+      int cs[3] = {c[0], c[1], c[2]};
+      cs[ax] += s - 2;
+      a[s] = u[ix(m, b, 0, cs)];
+    }
+    double vl[5] = {a[0], a[1], a[2], a[3], a[4]};
+    double vr[5] = {a[5], a[4], a[3], a[2], a[1]};
+    L = om_weno5(vl);
+    R = om_weno5(vr);
+  } else {
+    int cm[3] = {c[0], c[1], c[2]}, cp[3] = {c[0], c[1], c[2]}, cpp[3] = {c[0], c[1], c[2]};
+    cm[ax] -= 1;
+    cp[ax] += 1;
+    cpp[ax] += 2;
+    double r0 = u[ix(m, b, 0, cm)], r1 = u[ix(m, b, 0, c)], r2 = u[ix(m, b, 0, cp)], r3 = u[ix(m, b, 0, cpp)];
+    double s1 = limited_slope(m, r1 - r0, r2 - r1);
+    double s2 = limited_slope(m, r2 - r1, r3 - r2);
+    L = r1 + 0.5 * s1;
+    R = r2 - 0.5 * s2;
+  }
+  double v = m->vel[ax];
+  double smin = v < 0.0 ? v : 0.0, smax = v > 0.0 ? v : 0.0;
+  double FL = L * v, FR = R * v;
+  if (m->flux == 1) {
+    if (smin >= 0.0) return FL;
+    if (smax <= 0.0) return FR;
+    return (smax * FL - smin * FR + smin * smax * (R - L)) / (smax - smin);
+  }
+  double lm = fabs(smin), lp = fabs(smax);
+  double a = lm > lp ? lm : lp;
+  return 0.5 * (FL + FR) - 0.5 * a * (R - L);
+}
+
 /* Numerical flux through the face between cell c and c + e_ax of block b,
  * from limited linear reconstruction of primitives (Sec. 3.2). */
 static void face_flux(const om_mesh *m, const double *u, int64_t b, const int c[3], int ax, double *F) {
+  if (m->phys == 1) {
+    F[0] = advection_face_flux(m, u, b, c, ax);
+    return;
+  }
   if (m->limiter == 2) {
     /* WENO5: the left state from cells c-2 .. c+2, the right state from
      * c+3 .. c-1 (the same formula mirrored) */
@@ -504,7 +562,7 @@ void om_stage(const om_mesh *m, const double *ud, const double *up, double *uo, 
   int N = m->N, nv = m->nvar;
   int nk = (m->ndim == 3) ? N : 1;
   double hdt = 0.5 * dt;
-  int has_src = m->grav[0] != 0.0 || m->grav[1] != 0.0 || m->grav[2] != 0.0;
+  int has_src = m->phys == 0 && (m->grav[0] != 0.0 || m->grav[1] != 0.0 || m->grav[2] != 0.0);
 #pragma omp parallel for schedule(static)
   for (int64_t b = 0; b < m->nb; b++) {
     double dx = dx_of(m, b);
@@ -550,7 +608,7 @@ void om_substep_n(const om_mesh *m, const double *ud, const double *const *up, c
                   double c, double wd, double dt) {
   int N = m->N, nv = m->nvar;
   int nk = (m->ndim == 3) ? N : 1;
-  int has_src = m->grav[0] != 0.0 || m->grav[1] != 0.0 || m->grav[2] != 0.0;
+  int has_src = m->phys == 0 && (m->grav[0] != 0.0 || m->grav[1] != 0.0 || m->grav[2] != 0.0);
   double cdt = c * dt;
 #pragma omp parallel for schedule(static)
   for (int64_t b = 0; b < m->nb; b++) {
@@ -653,7 +711,9 @@ void om_flux_fix(const om_mesh *m, const double *ud, double *uo, double dt_s) {
 }
 
 /* CFL time step: dt = cfl * min over interior cells of
- * 1 / sum_d (|v_d| + c) / dx,  c = sqrt(gamma p / rho). */
+ * 1 / sum_d (|v_d| + c) / dx,  c = sqrt(gamma p / rho); for scalar
+ * advection (Sec. 3.4) the largest wave speed along d is |v_d|, so every
+ * cell of a block gives 1 / sum_d |v_d| / dx. */
 double om_dt(const om_mesh *m, const double *u) {
   int N = m->N, nk = (m->ndim == 3) ? N : 1;
   double best = INFINITY;
@@ -663,6 +723,13 @@ double om_dt(const om_mesh *m, const double *u) {
       for (int j = 0; j < N; j++)
         for (int i = 0; i < N; i++) {
           int c[3] = {i, j, k};
+          if (m->phys == 1) {
+            double s = 0.0;
+            for (int d = 0; d < m->ndim; d++) s += fabs(m->vel[d]) / dx;
+            double dtc = 1.0 / s;
+            if (dtc < best) best = dtc;
+            continue;
+          }
           prim_t w = to_primitive(m, u, b, c);
           double cs = sqrt(m->gamma * w.p / w.rho);
           double s = 0.0;
@@ -675,7 +742,8 @@ double om_dt(const om_mesh *m, const double *u) {
 }
 
 /* Returns the number of interior cells with rho <= 0, p <= 0 or a
- * non-finite variable. */
+ * non-finite variable (scalar advection: a non-finite rho; its rho may
+ * take any sign). */
 int64_t om_count_unphysical(const om_mesh *m, const double *u) {
   int N = m->N, nk = (m->ndim == 3) ? N : 1;
   int64_t bad = 0;
@@ -687,7 +755,7 @@ int64_t om_count_unphysical(const om_mesh *m, const double *u) {
           int ok = 1;
           for (int v = 0; v < m->nvar; v++)
             if (!isfinite(u[ix(m, b, v, c)])) ok = 0;
-          if (ok) {
+          if (ok && m->phys == 0) {
             prim_t w = to_primitive(m, u, b, c);
             if (!(w.rho > 0.0) || !(w.p > 0.0)) ok = 0;
           }

@@ -297,3 +297,69 @@ def blast_training_runs(n_centres=4, seed=500):
     evaluation run uses the domain centre and p_in = 100)."""
     u = uniform_pm1(seed, 3 * n_centres).reshape(n_centres, 3) * 0.05
     return [(tuple(0.5 + u[c]), p) for p in (30.0, 300.0) for c in range(n_centres)]
+
+
+# --------------------------------------------------------------------------
+# Scalar advection (Sec. 3.4, Sec. 4.1): one variable rho, uniform velocity.
+# Field functions return rho stacked as a single variable on axis 0.
+# --------------------------------------------------------------------------
+
+def advection_sphere_field(ndim, R=0.1, delta=0.05, centre=(0.5, 0.5, 0.5)):
+    """The smoothed sphere of eq. advection-sphere-sol: rho = 1 for
+    d < R - delta, 1 - 3 q^2 + 2 q^3 with q = 1 + (d - R) / delta for
+    R - delta <= d < R, and 0 for d >= R, d the distance from the centre."""
+    def field(*x, xp=np):
+        d2 = sum((x[a] - centre[a]) ** 2 for a in range(ndim))
+        d = xp.sqrt(d2)
+        q = 1.0 + (d - R) / delta
+        shell = 1.0 - 3.0 * q * q + 2.0 * q * q * q
+        rho = xp.where(d < R - delta, xp.ones_like(d), xp.where(d < R, shell, xp.zeros_like(d)))
+        return xp.stack([rho])
+    return field
+
+
+def advection_gauss_field(ndim, R=0.1, centre=(0.5, 0.5, 0.5)):
+    """The Gaussian of eq. advection-sphere-gauss: rho = exp(-d^2 / R^2)."""
+    def field(*x, xp=np):
+        d2 = sum((x[a] - centre[a]) ** 2 for a in range(ndim))
+        return xp.stack([xp.exp(-d2 / (R * R))])
+    return field
+
+
+def advection(ndim=3, block=16, n=256, init="sphere", limiter="vanleer", g=None, velocity=None, cfl=0.5):
+    """Uniform scalar-advection workload of Sec. 4.1 / Sec. 5.2 (table of
+    results on uniform grids): n^ndim cells in blocks of block^ndim on the
+    periodic unit square or cube, v = (1, 1[, 1]), the smoothed sphere of
+    radius 0.1 (init "sphere") or the Gaussian (init "gauss") at the centre."""
+    nt = n // block
+    vel = tuple(velocity) if velocity is not None else (1.0,) * ndim
+    f = advection_sphere_field(ndim) if init == "sphere" else advection_gauss_field(ndim)
+    return dict(name=f"advection_{init}_{n}^{ndim}_b{block}", ndim=ndim, trees=(nt,) * ndim + (1,) * (3 - ndim),
+                N=block, g=(3 if limiter == "weno5" else 2) if g is None else g, tree_size=1.0 / nt, level=0,
+                gamma=1.4, cfl=cfl, field=f, limiter=limiter, flux="rusanov", physics="advection",
+                velocity=vel + (0.0,) * (3 - len(vel)), steps=50)
+
+
+def advection_flux_fix(ndim=2, block=16, base_trees=4, levels=2, limiter="vanleer"):
+    """The flux-fixing test of Sec. 4.1.1: the smoothed sphere on a statically
+    refined periodic unit square or cube, v = (1, 1[, 1]), advanced to t = 1
+    so that it crosses every refinement boundary and returns to its start.
+    refine_rounds[r](level, G) gives the flags of round r: blocks of the
+    current finest level that meet the ball of radius R + 0.1 around the
+    centre are refined, `levels` times (2:1 balance applies)."""
+    ts = 1.0 / base_trees
+    centre = (0.5, 0.5, 0.5)
+
+    def flags_at(level, G):
+        size = ts / (2.0 ** np.asarray(level, dtype=np.float64))
+        G = np.asarray(G, dtype=np.float64)
+        lo = [G[:, a] * size if a < ndim else np.zeros(len(size)) for a in range(3)]
+        hi = [(G[:, a] + 1) * size if a < ndim else np.ones(len(size)) for a in range(3)]
+        c = centre if ndim == 3 else (0.5, 0.5, 0.5)
+        hit = box_intersects_ball(lo, hi, c, 0.2)
+        return np.where(hit, 1, 0).astype(np.int8)
+
+    w = advection(ndim, block, base_trees * block, init="sphere", limiter=limiter)
+    w.update(name=f"advection_flux_fix_{ndim}d_b{block}_L{levels}", max_level=levels, refine_rounds=levels,
+             refine_flags_at=flags_at, t_end=1.0)
+    return w
