@@ -17,7 +17,8 @@
  *  - The two state buffers are owned by the caller and passed at creation.
  *    Each holds [max_blocks][nvar] groups of P^ndim values, P = N + 2g (the
  *    paper's uu(i,j,k,ivar,iblock) of eq. array-structure, one padded block
- *    per group), nvar = ndim + 2, variables (rho, m_x, m_y[, m_z], E).
+ *    per group), nvar = ndim + 2, variables (rho, m_x, m_y[, m_z], E), for
+ *    the Euler system; nvar = 1 (rho) for scalar advection.
  *    Inside a group the rows (j, k) = (-g .. N+g-1)^(ndim-1), k slowest,
  *    hold the N interior x cells each (i fastest), so a plane's interior is
  *    N^2 contiguous values; then the 2g x ghosts of every row, in the same
@@ -75,6 +76,16 @@ typedef enum { FOAP4_FLUX_RUSANOV = 0, FOAP4_FLUX_HLL = 1 } foap4_flux;
  * dt/2 L(u3)); classical RK4 (eq. rk4).  SSP-RK3 and SSP-RK(4,3) need the
  * extra state 2, RK4 the extra states 2 and 3 (foap4_mesh_set_extra_state). */
 typedef enum { FOAP4_RK_HEUN = 0, FOAP4_RK_SSP3 = 1, FOAP4_RK_SSP43 = 2, FOAP4_RK_RK4 = 3 } foap4_integrator;
+/* The system of conservation laws (Sec. 3): the Euler equations of gas
+ * dynamics (Sec. 3.5; nvar = ndim + 2 variables rho, m_x, m_y[, m_z], E) or
+ * scalar advection (Sec. 3.4; nvar = 1, the variable rho carried by a
+ * uniform velocity v: rho_t + div(rho v) = 0, physical flux rho v_d, wave
+ * speeds min(v_d, 0) and max(v_d, 0) along axis d, so the CFL limit of every
+ * cell is sum_d |v_d| / dx).  Advection uses the same reconstructions,
+ * fluxes, integrators, ghost rounds, flux fixing and regrid as the Euler
+ * system; gamma is unused, gravity must be zero, and the learned indicator
+ * (whose features need a pressure) is refused. */
+typedef enum { FOAP4_PHYS_EULER = 0, FOAP4_PHYS_ADVECTION = 1 } foap4_physics;
 
 /* Mesh descriptor.  A brick of n_trees[0] x n_trees[1] (x n_trees[2]) trees
  * (the paper's p4est brick, Sec. 2.2), periodic or bounded per axis; cubic
@@ -112,6 +123,9 @@ typedef struct {
   int32_t bc_type[6][5];
   double bc_value[6][5];
   foap4_integrator integrator; /* time integrator (zero-initialised: Heun)          */
+  foap4_physics physics; /* system (zero-initialised: Euler)                            */
+  double velocity[3];    /* scalar advection: the uniform velocity, finite and not zero
+                            on every axis at once (velocity[2] ignored in 2D)             */
 } foap4_mesh_desc;
 
 /* Creates a mesh at the uniform level desc->init_level (Sec. 2.2) and its
@@ -181,8 +195,8 @@ foap4_status foap4_ghost_pattern_counts(const foap4_mesh *mesh, int32_t counts[2
  *   f2c[n][4] (c, q, h, k)     coarse c receives restricted data from fine q
  *                              at hanging offset h; k indexes q's C2F record
  *   c2f[n][3] (q, c, h)        fine q receives prolonged data from coarse c
- *   bc[n]     (b)              physical boundary face of b (always empty:
- *                              only periodic meshes are accepted)
+ *   bc[n]     (b)              physical boundary face of b on a bounded
+ *                              axis (grouped by face direction)
  * Any pointer may be NULL. */
 foap4_status foap4_ghost_pattern_export(const foap4_mesh *mesh, int32_t *srl, int32_t *f2c,
                                         int32_t *c2f, int32_t *bc);

@@ -34,13 +34,15 @@ class MeshDesc(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("limiter", ctypes.c_int32),
                 ("flux", ctypes.c_int32), ("gravity", ctypes.c_double * 3),
                 ("bc_type", (ctypes.c_int32 * 5) * 6), ("bc_value", (ctypes.c_double * 5) * 6),
-                ("integrator", ctypes.c_int32)]
+                ("integrator", ctypes.c_int32), ("physics", ctypes.c_int32), ("velocity", ctypes.c_double * 3)]
 
 # stage scheme options (include/foap4.h: foap4_limiter, foap4_flux)
 LIMITERS = {"minmod": 0, "vanleer": 1, "weno5": 2}
 FLUXES = {"rusanov": 0, "hll": 1}
 BC_DIRICHLET, BC_NEUMANN = 0, 1
 INTEGRATORS = {"heun": 0, "ssprk3": 1, "ssprk43": 2, "rk4": 3}
+# systems (include/foap4.h: foap4_physics)
+PHYSICS = {"euler": 0, "advection": 1}
 
 
 def wall_bc(ndim):
@@ -137,10 +139,12 @@ class Mesh:
     def __init__(self, ndim, trees, N, g=2, tree_size=1.0, level=0, min_level=0, max_level=None,
                  max_blocks=None, prec=F64, gamma=1.4, cfl=0.5, origin=(0.0, 0.0, 0.0), device="cuda",
                  stream=None, limiter="minmod", flux="rusanov", gravity=(0.0, 0.0, 0.0),
-                 periodic=(True, True, True), bc_type=None, bc_value=None, integrator="heun"):
+                 periodic=(True, True, True), bc_type=None, bc_value=None, integrator="heun",
+                 physics="euler", velocity=(0.0, 0.0, 0.0)):
         torch = _torch()
         self.ndim, self.N, self.g = ndim, N, g
-        self.nvar = ndim + 2
+        self.physics = physics
+        self.nvar = 1 if physics == "advection" else ndim + 2
         self.P = N + 2 * g
         self.prec = prec
         self.dtype = torch.float64 if prec == F64 else torch.float32
@@ -178,6 +182,8 @@ class Mesh:
         d.limiter = LIMITERS[limiter]
         d.flux = FLUXES[flux]
         d.gravity[:] = [float(x) for x in gravity] + [0.0] * (3 - len(gravity))
+        d.physics = PHYSICS[physics]
+        d.velocity[:] = [float(x) for x in velocity] + [0.0] * (3 - len(velocity))
         self.desc = d
         shape = (self.max_blocks, self.nvar, self.P ** ndim)  # row part, then x ghosts (include/foap4.h)
         self.state = [torch.zeros(shape, dtype=self.dtype, device=device),

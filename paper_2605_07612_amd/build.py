@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build", "foap4")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["topology.cpp", "capi.cpp", "pattern.hip", "ghost.hip", "reduce.hip", "regrid.hip", "mlp.hip", "weno.hip"]
+SOURCES = ["topology.cpp", "capi.cpp", "pattern.hip", "ghost.hip", "reduce.hip", "regrid.hip", "mlp.hip", "weno.hip", "advect.hip"]
 # the stage kernels, one compile per scheme bit mask (limiter, flux, gravity)
 N_SCHEMES = 8
 UNITS = [(s, [], s) for s in SOURCES] + [("stage.hip", [f"-DF4_SCHEME={k}"], f"stage_s{k}.hip")

@@ -49,6 +49,9 @@ MeshDev make_dev(const foap4_mesh *m, int ks, int gather) {
   d.gamma = m->d.gamma;
   d.cfl = m->d.cfl;
   for (int a = 0; a < 3; a++) d.grav[a] = (a < m->d.ndim) ? m->d.gravity[a] : 0.0;
+  d.nv = m->nvar;
+  for (int a = 0; a < 3; a++)
+    d.vel[a] = (m->d.physics == FOAP4_PHYS_ADVECTION && a < m->d.ndim) ? m->d.velocity[a] : 0.0;
   for (int f = 0; f < 6; f++)
     for (int v = 0; v < 5; v++) {
       d.bc_val[f][v] = m->d.bc_value[f][v];
@@ -107,8 +110,8 @@ static foap4_status check_bad(foap4_mesh *m) {
 static foap4_status fill(foap4_mesh *m, const MeshDev *dd, int which) {
   const bool f64 = m->d.prec == FOAP4_F64;
   const int64_t r1 = m->pat.n[kSRL] + m->pat.n[kF2C] + m->pat.n[kBC], r2 = m->pat.n[kC2F];
-  F4_HIP(m, launch_ghost(dd, 1, r1, 1, which, m->d.ndim, f64, 0, m->stream));
-  if (r2) F4_HIP(m, launch_ghost(dd, 1, r2, 2, which, m->d.ndim, f64, 0, m->stream));
+  F4_HIP(m, launch_ghost(dd, 1, r1, 1, which, m->d.ndim, f64, 0, m->stream, m->nvar));
+  if (r2) F4_HIP(m, launch_ghost(dd, 1, r2, 2, which, m->d.ndim, f64, 0, m->stream, m->nvar));
   return FOAP4_OK;
 }
 
@@ -129,6 +132,7 @@ struct foap4_batch {
   std::vector<foap4_mesh *> meshes;
   std::vector<int64_t> revs, serials;
   int ndim = 3;
+  int nv = 5;          // variables per cell, shared by all meshes
   bool f64 = false;
   int ks = 1, wg1 = 0, wg2 = 0, gather = 1, xcd = 1;  // wg1 / wg2: workgroups per CU of stage 1 / 2
   MeshDev *d_devs = nullptr;
@@ -137,6 +141,7 @@ struct foap4_batch {
   int scheme = 0;  // scheme_of() shared by all meshes
   int integrator = 0;  // shared time integrator
   bool weno = false;   // WENO5 meshes: their own stage kernel per mesh, stored ghosts
+  bool adv = false;    // scalar advection meshes: the advection kernel per mesh, stored ghosts
   hipStream_t stream = nullptr, cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -167,7 +172,7 @@ foap4_status foap4_mesh_create(const foap4_mesh_desc *desc, void *state0, void *
     if (d.periodic[a] != 0 && d.periodic[a] != 1) return fail(nullptr, FOAP4_E_INVALID, "periodic must be 0 or 1");
     if (!d.periodic[a])
       for (int f = 2 * a; f < 2 * a + 2; f++)
-        for (int v = 0; v < d.ndim + 2; v++) {
+        for (int v = 0; v < (d.physics == FOAP4_PHYS_ADVECTION ? 1 : d.ndim + 2); v++) {
           if (d.bc_type[f][v] != 0 && d.bc_type[f][v] != 1)
             return fail(nullptr, FOAP4_E_INVALID, "bc_type must be 0 (Dirichlet) or 1 (Neumann)");
           if (!std::isfinite(d.bc_value[f][v])) return fail(nullptr, FOAP4_E_INVALID, "bc_value must be finite");
@@ -191,12 +196,23 @@ foap4_status foap4_mesh_create(const foap4_mesh_desc *desc, void *state0, void *
     return fail(nullptr, FOAP4_E_INVALID, "integrator must be Heun, SSP-RK3, SSP-RK(4,3) or RK4");
   for (int a = 0; a < 3; a++)
     if (!std::isfinite(d.gravity[a])) return fail(nullptr, FOAP4_E_INVALID, "gravity must be finite");
+  if (d.physics != FOAP4_PHYS_EULER && d.physics != FOAP4_PHYS_ADVECTION)
+    return fail(nullptr, FOAP4_E_INVALID, "physics must be Euler or advection");
+  if (d.physics == FOAP4_PHYS_ADVECTION) {
+    bool moving = false;
+    for (int a = 0; a < d.ndim; a++) {
+      if (!std::isfinite(d.velocity[a])) return fail(nullptr, FOAP4_E_INVALID, "velocity must be finite");
+      moving |= d.velocity[a] != 0.0;
+    }
+    if (!moving) return fail(nullptr, FOAP4_E_INVALID, "scalar advection needs a non-zero velocity");
+    if (scheme_of(d) & 4) return fail(nullptr, FOAP4_E_INVALID, "scalar advection takes no gravity");
+  }
   if (!state0 || !state1 || state0 == state1) return fail(nullptr, FOAP4_E_INVALID, "two distinct state buffers needed");
   if ((((uintptr_t)state0) | ((uintptr_t)state1)) & 15u)
     return fail(nullptr, FOAP4_E_INVALID, "state buffers must be 16-byte aligned");
   foap4_mesh *m = new foap4_mesh();
   m->d = d;
-  m->nvar = d.ndim + 2;
+  m->nvar = d.physics == FOAP4_PHYS_ADVECTION ? 1 : d.ndim + 2;
   m->P = d.block_n + 2 * d.n_ghost;
   m->nf = 2 * d.ndim;
   m->elem = d.prec == FOAP4_F64 ? 8 : 4;
@@ -362,11 +378,15 @@ foap4_status foap4_mesh_set_extra_state(foap4_mesh *m, int32_t index, void *stat
   return upload_dev(m);
 }
 
-// One stage or sub-step of the plain form: the WENO5 kernel for a WENO5
-// mesh, else the plane-marching kernel (one workgroup per work item).
+// One stage or sub-step of the plain form: the advection kernel for scalar
+// advection, the WENO5 kernel for a WENO5 mesh, else the plane-marching
+// kernel (one workgroup per work item).
 static hipError_t mesh_stage(foap4_mesh *m, int64_t items, int stage, const SubStep &ss = SubStep{}) {
   const bool f64 = m->d.prec == FOAP4_F64;
   const int ndim = m->d.ndim;
+  if (m->d.physics == FOAP4_PHYS_ADVECTION)
+    return launch_advect_stage(m->d_dev, (int64_t)m->topo.leaves.size(), m->d.block_n, m->d.n_ghost, stage, ndim, f64,
+                               m->d.limiter, m->d.flux == FOAP4_FLUX_HLL, m->stream, ss);
   if (m->d.limiter == FOAP4_LIM_WENO5) {
     return launch_weno_stage(m->d_dev, (int64_t)m->topo.leaves.size(), m->d.block_n, stage, ndim, f64, scheme_of(m->d),
                              m->stream, ss);
@@ -381,7 +401,7 @@ foap4_status foap4_step(foap4_mesh *m, int32_t n_steps, double *t_out, double *d
   const SubStep *subs = nullptr;
   const int nsub = substeps_of(m->d.integrator, &subs);
   if (nsub && !extra_states_set(m)) return fail(m, FOAP4_E_ORDER, "this integrator needs its extra state buffers");
-  if ((nsub || m->d.limiter == FOAP4_LIM_WENO5) && m->capture && n_steps > 0)
+  if ((nsub || m->d.limiter == FOAP4_LIM_WENO5 || m->nvar == 1) && m->capture && n_steps > 0)
     return fail(m, FOAP4_E_INVALID, "feature capture needs the Heun integrator and a two-ghost limiter");
   if (nsub) {
     const bool f64 = m->d.prec == FOAP4_F64;
@@ -394,7 +414,7 @@ foap4_status foap4_step(foap4_mesh *m, int32_t n_steps, double *t_out, double *d
         if ((st = fill(m, m->d_dev, subs[k].deriv)) != FOAP4_OK) return st;
         const int form = substep_form(subs[k]);
         F4_HIP(m, mesh_stage(m, items, form, subs[k]));
-        F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, form, m->stream, subs[k]));
+        F4_HIP(m, launch_fluxfix(m->d_dev, ndim, m->nvar, f64, m->pat.n_fix, form, m->stream, subs[k]));
       }
       F4_HIP(m, launch_finalize(m->d_dev, 1, 1, m->stream));
     }
@@ -426,10 +446,10 @@ foap4_status foap4_step(foap4_mesh *m, int32_t n_steps, double *t_out, double *d
     } else {
       F4_HIP(m, mesh_stage(m, items, 1));
     }
-    F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, 1, m->stream));
+    F4_HIP(m, launch_fluxfix(m->d_dev, ndim, m->nvar, f64, m->pat.n_fix, 1, m->stream));
     if ((st = fill(m, m->d_dev, 1)) != FOAP4_OK) return st;
     F4_HIP(m, mesh_stage(m, items, 2));
-    F4_HIP(m, launch_fluxfix(m->d_dev, ndim, f64, m->pat.n_fix, 2, m->stream));
+    F4_HIP(m, launch_fluxfix(m->d_dev, ndim, m->nvar, f64, m->pat.n_fix, 2, m->stream));
     F4_HIP(m, launch_finalize(m->d_dev, 1, 1, m->stream));
   }
   m->steps_done += n_steps;
@@ -443,6 +463,7 @@ foap4_status foap4_step(foap4_mesh *m, int32_t n_steps, double *t_out, double *d
 
 foap4_status foap4_mesh_capture_features(foap4_mesh *m, int32_t on) {
   if (!m) return fail(nullptr, FOAP4_E_INVALID, "null mesh");
+  if (on && m->nvar == 1) return fail(m, FOAP4_E_INVALID, "the indicator features are defined for the Euler system");
   m->capture = on != 0;
   return FOAP4_OK;
 }
@@ -514,6 +535,7 @@ static foap4_status ind_scratch(foap4_mesh *m, IndScratch &S) {
 
 foap4_status foap4_block_features(foap4_mesh *m, float *feat_dev, double *raw_dev) {
   if (!m || !feat_dev) return fail(m, FOAP4_E_INVALID, "null argument");
+  if (m->nvar == 1) return fail(m, FOAP4_E_INVALID, "the indicator features are defined for the Euler system");
   if (((uintptr_t)feat_dev & 15u) != 0) return fail(m, FOAP4_E_INVALID, "features must be 16-byte aligned");
   foap4_status st;
   IndScratch S;
@@ -527,6 +549,8 @@ foap4_status foap4_mesh_set_indicator(foap4_mesh *m, foap4_indicator ind, const 
   if (!m) return fail(nullptr, FOAP4_E_INVALID, "null mesh");
   if (ind != FOAP4_IND_LOHNER && ind != FOAP4_IND_MLP) return fail(m, FOAP4_E_INVALID, "unknown indicator");
   if (ind == FOAP4_IND_MLP && !net) return fail(m, FOAP4_E_INVALID, "the MLP indicator needs a network");
+  if (ind == FOAP4_IND_MLP && m->nvar == 1)
+    return fail(m, FOAP4_E_INVALID, "the MLP indicator's features are defined for the Euler system");
   m->ind = ind;
   m->mlp = net;
   return FOAP4_OK;
@@ -541,6 +565,8 @@ foap4_status foap4_indicator_fallbacks(const foap4_mesh *m, int64_t *n_fallback)
 foap4_status foap4_refine_flags(foap4_mesh *m, foap4_indicator ind, int8_t *flags_host) {
   if (!m || !flags_host) return fail(m, FOAP4_E_INVALID, "null argument");
   if (ind != FOAP4_IND_LOHNER && ind != FOAP4_IND_MLP) return fail(m, FOAP4_E_INVALID, "unknown indicator");
+  if (ind == FOAP4_IND_MLP && m->nvar == 1)
+    return fail(m, FOAP4_E_INVALID, "the MLP indicator's features are defined for the Euler system");
   if (ind == FOAP4_IND_MLP && (!m->mlp || !m->mlp->has_weights))
     return fail(m, FOAP4_E_ORDER, "no MLP with weights attached to this mesh");
   const size_t nb = m->topo.leaves.size();
@@ -669,7 +695,7 @@ static foap4_status batch_upload(foap4_batch *b) {
   std::vector<MeshDev> devs;
   int64_t it = 0, r1 = 0, r2 = 0;
   for (foap4_mesh *m : b->meshes) {
-    MeshDev d = make_dev(m, b->ks, b->weno ? 0 : b->gather);
+    MeshDev d = make_dev(m, b->ks, (b->weno || b->adv) ? 0 : b->gather);
     d.item_begin = it;
     d.r1_begin = r1;
     d.r2_begin = r2;
@@ -696,10 +722,19 @@ static int stage_grid(const foap4_batch *b, int stage) {
 }
 
 // One stage or sub-step of every mesh of a batch: one persistent launch of
-// the plane-marching kernel over all work items, or for WENO5 meshes one
-// launch of the WENO5 kernel per mesh.
+// the plane-marching kernel over all work items, or for WENO5 meshes and
+// scalar advection one launch of their own kernel per mesh.
 static hipError_t batch_stage(foap4_batch *b, int stage, int grid, hipStream_t s, const SubStep &ss = SubStep{}) {
   const int n = (int)b->meshes.size();
+  if (b->adv) {
+    for (int i = 0; i < n; i++) {
+      const foap4_mesh *m = b->meshes[i];
+      hipError_t e = launch_advect_stage(b->d_devs + i, (int64_t)m->topo.leaves.size(), m->d.block_n, m->d.n_ghost,
+                                         stage, b->ndim, b->f64, m->d.limiter, m->d.flux == FOAP4_FLUX_HLL, s, ss);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   if (!b->weno)
     return launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, grid, s, b->xcd, b->nmask, b->scheme, ss);
   for (int i = 0; i < n; i++) {
@@ -718,27 +753,27 @@ static hipError_t batch_enqueue_step(foap4_batch *b, hipStream_t s) {
   const int nsub = substeps_of(b->integrator, &subs);
   for (int k = 0; k < nsub; k++) {  // integrators with extra states: generic sub-steps
     const int which = subs[k].deriv;
-    if ((e = launch_ghost(b->d_devs, n, b->r1_total, 1, which, b->ndim, b->f64, 0, s)) != hipSuccess) return e;
-    if (b->r2_total && (e = launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s)) != hipSuccess)
+    if ((e = launch_ghost(b->d_devs, n, b->r1_total, 1, which, b->ndim, b->f64, 0, s, b->nv)) != hipSuccess) return e;
+    if (b->r2_total && (e = launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s, b->nv)) != hipSuccess)
       return e;
     const int form = substep_form(subs[k]);
     if ((e = batch_stage(b, form, stage_grid(b, 2), s, subs[k])) != hipSuccess) return e;
     for (int i = 0; i < n; i++)
       if (b->meshes[i]->pat.n_fix > 0 &&
-          (e = launch_fluxfix(b->d_devs + i, b->ndim, b->f64, b->meshes[i]->pat.n_fix, form, s, subs[k])) != hipSuccess)
+          (e = launch_fluxfix(b->d_devs + i, b->ndim, b->nv, b->f64, b->meshes[i]->pat.n_fix, form, s, subs[k])) != hipSuccess)
         return e;
   }
   if (nsub) return launch_finalize(b->d_devs, n, 1, s);
   for (int stage = 1; stage <= 2; stage++) {
     const int which = stage - 1;
     const int grid = stage_grid(b, stage);
-    if ((e = launch_ghost(b->d_devs, n, b->r1_total, 1, which, b->ndim, b->f64, 0, s)) != hipSuccess) return e;
-    if (b->r2_total && (e = launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s)) != hipSuccess)
+    if ((e = launch_ghost(b->d_devs, n, b->r1_total, 1, which, b->ndim, b->f64, 0, s, b->nv)) != hipSuccess) return e;
+    if (b->r2_total && (e = launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s, b->nv)) != hipSuccess)
       return e;
     if ((e = batch_stage(b, stage, grid, s)) != hipSuccess) return e;
     for (int i = 0; i < n; i++)
       if (b->meshes[i]->pat.n_fix > 0 &&
-          (e = launch_fluxfix(b->d_devs + i, b->ndim, b->f64, b->meshes[i]->pat.n_fix, stage, s)) != hipSuccess)
+          (e = launch_fluxfix(b->d_devs + i, b->ndim, b->nv, b->f64, b->meshes[i]->pat.n_fix, stage, s)) != hipSuccess)
         return e;
   }
   return launch_finalize(b->d_devs, n, 1, s);
@@ -794,8 +829,13 @@ foap4_status foap4_batch_create(foap4_mesh *const *meshes, int32_t n, foap4_batc
   b->scheme = scheme_of(meshes[0]->d);
   b->integrator = meshes[0]->d.integrator;
   b->weno = meshes[0]->d.limiter == FOAP4_LIM_WENO5;
+  b->adv = meshes[0]->d.physics == FOAP4_PHYS_ADVECTION;
+  b->nv = meshes[0]->nvar;
   for (foap4_mesh *m : b->meshes)
-    if (m->d.ndim != b->ndim || (m->d.prec == FOAP4_F64) != b->f64) {
+    if (m->d.physics != meshes[0]->d.physics) {
+      delete b;
+      return fail(nullptr, FOAP4_E_INVALID, "batch meshes must share the system (Euler or advection)");
+    } else if (m->d.ndim != b->ndim || (m->d.prec == FOAP4_F64) != b->f64) {
       delete b;
       return fail(nullptr, FOAP4_E_INVALID, "batch meshes must share ndim and precision");
     } else if (scheme_of(m->d) != b->scheme) {
@@ -865,6 +905,8 @@ foap4_status foap4_batch_phase_times(foap4_batch *b, int32_t n_steps, double *ou
   if (!b || n_steps < 1 || !out_ms) return batch_fail(b, FOAP4_E_INVALID, "bad arguments");
   if (b->integrator != FOAP4_RK_HEUN || b->weno)
     return batch_fail(b, FOAP4_E_INVALID, "phase timing and autotuning time the Heun stages of the plane kernel");
+  if (b->adv && b->ks != 1)
+    return batch_fail(b, FOAP4_E_INVALID, "the advection kernel has no k-slabs");
   foap4_status st = batch_prepare(b);
   if (st != FOAP4_OK) return st;
   const int n = (int)b->meshes.size();
@@ -878,16 +920,15 @@ foap4_status foap4_batch_phase_times(foap4_batch *b, int32_t n_steps, double *ou
   for (int it = 0; it < n_steps; it++) {
     for (int stage = 1; stage <= 2; stage++) {
       const int which = stage - 1;
-      B_HIP(b, launch_ghost(b->d_devs, n, b->r1_total, 1, which, b->ndim, b->f64, 0, s));
+      B_HIP(b, launch_ghost(b->d_devs, n, b->r1_total, 1, which, b->ndim, b->f64, 0, s, b->nv));
       B_HIP(b, hipEventRecord(ev[++k], s));
-      if (b->r2_total) B_HIP(b, launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s));
+      if (b->r2_total) B_HIP(b, launch_ghost(b->d_devs, n, b->r2_total, 2, which, b->ndim, b->f64, 0, s, b->nv));
       B_HIP(b, hipEventRecord(ev[++k], s));
-      B_HIP(b, launch_stage(b->d_devs, n, b->total_items, stage, b->ndim, b->f64, stage_grid(b, stage), s, b->xcd,
-                            b->nmask, b->scheme));
+      B_HIP(b, batch_stage(b, stage, stage_grid(b, stage), s));
       B_HIP(b, hipEventRecord(ev[++k], s));
       for (int i = 0; i < n; i++)
         if (b->meshes[i]->pat.n_fix > 0)
-          B_HIP(b, launch_fluxfix(b->d_devs + i, b->ndim, b->f64, b->meshes[i]->pat.n_fix, stage, s));
+          B_HIP(b, launch_fluxfix(b->d_devs + i, b->ndim, b->nv, b->f64, b->meshes[i]->pat.n_fix, stage, s));
       B_HIP(b, hipEventRecord(ev[++k], s));
     }
     B_HIP(b, launch_finalize(b->d_devs, n, 1, s));
@@ -995,6 +1036,7 @@ static void cache_store(const char *path, const std::string &key, const int cfg[
 
 foap4_status foap4_batch_autotune(foap4_batch *b, const char *cache_path, int32_t *cfg_out) {
   if (!b) return batch_fail(nullptr, FOAP4_E_INVALID, "null batch");
+  if (b->adv) return batch_fail(b, FOAP4_E_INVALID, "the advection kernel has no launch configuration to tune");
   const std::string key = batch_key(b);
   int cached[4] = {1, 0, 0, 1};
   if (cache_lookup(cache_path, key, cached)) {

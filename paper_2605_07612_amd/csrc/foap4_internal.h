@@ -115,6 +115,8 @@ struct MeshDev {
   double dx0;                 // cell width at level 0
   double gamma, cfl;
   double grav[3];             // gravitational acceleration (source term on)
+  double vel[3];              // scalar advection: the uniform velocity
+  int32_t nv;                 // variables per cell: ndim + 2 (Euler) or 1 (advection)
   double bc_val[6][5];        // physical boundary values per face direction and variable
   int32_t bc_type[6][5];      // 0 Dirichlet, 1 Neumann
   int32_t pn[4];              // record totals per type
@@ -223,8 +225,9 @@ foap4_status upload_dev(foap4_mesh *m);
 foap4_status build_pattern(foap4_mesh *m);
 // ghost.hip: round 1 = SRL + F2C + boundary, round 2 = C2F; which = state role
 // (0 current, 1 other, 2 third)
+// nv: variables per cell (ndim + 2 for the Euler system, 1 for scalar advection)
 hipError_t launch_ghost(const MeshDev *d_meshes, int n_meshes, int64_t total, int round, int which,
-                        int ndim, bool f64, int grid, hipStream_t s);
+                        int ndim, bool f64, int grid, hipStream_t s, int nv);
 // stage.hip
 int64_t stage_items_for(int ndim, int N, int64_t nb, int ks);
 // nmask: block sizes present in the launch (1: N = 8, 2: N = 16, 4: N = 32);
@@ -236,6 +239,9 @@ hipError_t launch_stage(const MeshDev *d_meshes, int n_meshes, int64_t total_ite
 // weno.hip: the WENO5 stage (one thread per interior cell, stored ghosts)
 hipError_t launch_weno_stage(const MeshDev *d_mesh, int64_t nblocks, int block_n, int stage, int ndim, bool f64,
                              int scheme, hipStream_t s, const SubStep &ss = SubStep{});
+// advect.hip: the scalar advection stage (one workgroup per block, stored ghosts)
+hipError_t launch_advect_stage(const MeshDev *d_mesh, int64_t nblocks, int block_n, int n_ghost, int stage, int ndim,
+                               bool f64, int limiter, bool hll, hipStream_t s, const SubStep &ss = SubStep{});
 // stage 1 of one mesh that also reduces the raw features of its input state
 // (feat_raw [nb][2], zeroed by the caller) by atomic maxima
 hipError_t launch_stage1_features(const MeshDev *d_mesh, int64_t total_items, int ndim, bool f64, int nmask,
@@ -249,7 +255,7 @@ inline int nmask_of(int N) { return N == 8 ? 1 : (N == 16 ? 2 : 4); }
 // reduce.hip
 hipError_t launch_dt_full(const foap4_mesh *m, hipStream_t s);
 hipError_t launch_finalize(const MeshDev *d_meshes, int n_meshes, int advance, hipStream_t s);
-hipError_t launch_fluxfix(const MeshDev *d_mesh, int ndim, bool f64, int n_fix, int stage, hipStream_t s,
+hipError_t launch_fluxfix(const MeshDev *d_mesh, int ndim, int nv, bool f64, int n_fix, int stage, hipStream_t s,
                           const SubStep &ss = SubStep{});
 hipError_t launch_totals(const foap4_mesh *m, double *d_part, double *d_out, hipStream_t s);
 // regrid.hip

@@ -6,6 +6,8 @@
 //   round R2: C2F records (fine ghost = limited prolongation from the coarse
 //             block, FP64 slopes; reads the coarse block's R1 ghosts)
 // Work items of several meshes are concatenated (r1_begin / r2_begin).
+// NV, the number of variables per cell, is a template parameter: ndim + 2
+// for the Euler system, 1 for scalar advection.
 #include "foap4_internal.h"
 
 namespace f4 {
@@ -34,9 +36,8 @@ __device__ __forceinline__ double mm(double a, double b) {
   return 0.0;
 }
 
-template <typename T, int NDIM, int N, int ax>
+template <typename T, int NDIM, int NV, int N, int ax>
 __device__ void srl_record(const MeshDev &M, T *u, int32_t a, int32_t b) {
-  constexpr int NV = NDIM + 2;
   constexpr int N2 = (NDIM == 3) ? N : 1;
   const Geo<NDIM> G(N, M.g);
   const int g = M.g;
@@ -113,9 +114,8 @@ __device__ __forceinline__ double fine_mean(const T *uq, const Geo<NDIM> &G, con
   }
 }
 
-template <typename T, int NDIM, int N, int ax>
+template <typename T, int NDIM, int NV, int N, int ax>
 __device__ void f2c_record(const MeshDev &M, T *u, int side, int32_t cb, int32_t q, int32_t h) {
-  constexpr int NV = NDIM + 2;
   constexpr int H = N / 2;
   constexpr int H2 = (NDIM == 3) ? H : 1;
   const Geo<NDIM> G(N, M.g);
@@ -168,9 +168,8 @@ __device__ __forceinline__ double prolong(const T *uc, const Geo<NDIM> &G, const
   return up + 0.25 * corr;
 }
 
-template <typename T, int NDIM, int N, int ax>
+template <typename T, int NDIM, int NV, int N, int ax>
 __device__ void c2f_record(const MeshDev &M, T *u, int side, int32_t q, int32_t cb, int32_t h) {
-  constexpr int NV = NDIM + 2;
   constexpr int N2 = (NDIM == 3) ? N : 1;
   constexpr int H = N / 2;
   const Geo<NDIM> G(N, M.g);
@@ -215,10 +214,9 @@ __device__ void c2f_record(const MeshDev &M, T *u, int side, int32_t q, int32_t 
 // bc_data (record rec, variable, face cell p1 + N p2) when it is set, else
 // from the uniform per-face values.  As in the SRL copy, each thread keeps B
 // elements in flight (loads first, then stores).
-template <typename T, int NDIM, int N, int ax>
+template <typename T, int NDIM, int NV, int N, int ax>
 __device__ void bc_record(const MeshDev &M, T *u, int side, int64_t rec, int32_t b) {
 #pragma clang fp contract(off)
-  constexpr int NV = NDIM + 2;
   constexpr int N2 = (NDIM == 3) ? N : 1;
   const Geo<NDIM> G(N, M.g);
   const int g = M.g, f = 2 * ax + side;
@@ -273,7 +271,7 @@ __device__ void bc_record(const MeshDev &M, T *u, int side, int64_t rec, int32_t
   }
 }
 
-template <typename T, int NDIM, int N>
+template <typename T, int NDIM, int NV, int N>
 __device__ void ghost_item(const MeshDev &M, int round, int64_t r, int which) {
   T *u = (T *)M.s[role_buffer(which, M.cur)];
   // the record's face f = 2 axis + side; the axis selects the routine
@@ -287,35 +285,35 @@ __device__ void ghost_item(const MeshDev &M, int round, int64_t r, int which) {
     if (r < M.r1_srl) {
       int f = 1;
       while (r >= M.poff[kSRL][f + 1]) f += 2;
-#define F4_SRL(A) srl_record<T, NDIM, N, A>(M, u, M.srl[2 * r], M.srl[2 * r + 1])
+#define F4_SRL(A) srl_record<T, NDIM, NV, N, A>(M, u, M.srl[2 * r], M.srl[2 * r + 1])
       F4_BY_AXIS(F4_SRL)
 #undef F4_SRL
     } else if (r < M.r1_srl + M.pn[kF2C]) {
       r -= M.r1_srl;
       int f = 0;
       while (r >= M.poff[kF2C][f + 1]) f++;
-#define F4_F2C(A) f2c_record<T, NDIM, N, A>(M, u, f & 1, M.f2c[4 * r], M.f2c[4 * r + 1], M.f2c[4 * r + 2])
+#define F4_F2C(A) f2c_record<T, NDIM, NV, N, A>(M, u, f & 1, M.f2c[4 * r], M.f2c[4 * r + 1], M.f2c[4 * r + 2])
       F4_BY_AXIS(F4_F2C)
 #undef F4_F2C
     } else {
       r -= M.r1_srl + M.pn[kF2C];
       int f = 0;
       while (r >= M.poff[kBC][f + 1]) f++;
-#define F4_BC(A) bc_record<T, NDIM, N, A>(M, u, f & 1, r, M.bc[r])
+#define F4_BC(A) bc_record<T, NDIM, NV, N, A>(M, u, f & 1, r, M.bc[r])
       F4_BY_AXIS(F4_BC)
 #undef F4_BC
     }
   } else {
     int f = 0;
     while (r >= M.poff[kC2F][f + 1]) f++;
-#define F4_C2F(A) c2f_record<T, NDIM, N, A>(M, u, f & 1, M.c2f[3 * r], M.c2f[3 * r + 1], M.c2f[3 * r + 2])
+#define F4_C2F(A) c2f_record<T, NDIM, NV, N, A>(M, u, f & 1, M.c2f[3 * r], M.c2f[3 * r + 1], M.c2f[3 * r + 2])
     F4_BY_AXIS(F4_C2F)
 #undef F4_C2F
   }
 #undef F4_BY_AXIS
 }
 
-template <typename T, int NDIM>
+template <typename T, int NDIM, int NV>
 __global__ __launch_bounds__(256) void ghost_kernel(const MeshDev *__restrict__ meshes, int n_meshes,
                                                     int64_t total, int round, int which) {
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
@@ -328,28 +326,34 @@ __global__ __launch_bounds__(256) void ghost_kernel(const MeshDev *__restrict__ 
     const MeshDev &M = meshes[lo];
     const int64_t r = item - (round == 1 ? M.r1_begin : M.r2_begin);
     switch (M.N) {
-      case 8: ghost_item<T, NDIM, 8>(M, round, r, which); break;
-      case 16: ghost_item<T, NDIM, 16>(M, round, r, which); break;
-      default: ghost_item<T, NDIM, 32>(M, round, r, which); break;
+      case 8: ghost_item<T, NDIM, NV, 8>(M, round, r, which); break;
+      case 16: ghost_item<T, NDIM, NV, 16>(M, round, r, which); break;
+      default: ghost_item<T, NDIM, NV, 32>(M, round, r, which); break;
     }
   }
 }
 
 hipError_t launch_ghost(const MeshDev *d_meshes, int n_meshes, int64_t total, int round, int which,
-                        int ndim, bool f64, int grid, hipStream_t s) {
+                        int ndim, bool f64, int grid, hipStream_t s, int nv) {
   if (total <= 0) return hipSuccess;
   const unsigned nblk = (unsigned)((grid > 0 && grid < total) ? grid : total);
-  if (f64) {
-    if (ndim == 3)
-      ghost_kernel<double, 3><<<nblk, 256, 0, s>>>(d_meshes, n_meshes, total, round, which);
-    else
-      ghost_kernel<double, 2><<<nblk, 256, 0, s>>>(d_meshes, n_meshes, total, round, which);
+#define F4_GHOST(T, D, V) ghost_kernel<T, D, V><<<nblk, 256, 0, s>>>(d_meshes, n_meshes, total, round, which)
+  if (nv == 1) {  // scalar advection
+    if (f64) {
+      if (ndim == 3) F4_GHOST(double, 3, 1);
+      else F4_GHOST(double, 2, 1);
+    } else {
+      if (ndim == 3) F4_GHOST(float, 3, 1);
+      else F4_GHOST(float, 2, 1);
+    }
+  } else if (f64) {
+    if (ndim == 3) F4_GHOST(double, 3, 5);
+    else F4_GHOST(double, 2, 4);
   } else {
-    if (ndim == 3)
-      ghost_kernel<float, 3><<<nblk, 256, 0, s>>>(d_meshes, n_meshes, total, round, which);
-    else
-      ghost_kernel<float, 2><<<nblk, 256, 0, s>>>(d_meshes, n_meshes, total, round, which);
+    if (ndim == 3) F4_GHOST(float, 3, 5);
+    else F4_GHOST(float, 2, 4);
   }
+#undef F4_GHOST
   return hipGetLastError();
 }
 

@@ -27,6 +27,19 @@ __device__ __forceinline__ double inv_dt_cell(const double *U, double gamma, dou
   return s;
 }
 
+// Scalar advection (Sec. 3.4): the fastest wave along d is |v_d| in every
+// cell, so the CFL limit is sum_d |v_d| / dx (the definition's operation
+// order); a non-finite rho marks the state bad.
+template <int NDIM>
+__device__ __forceinline__ double inv_dt_adv(const MeshDev &M, double rho, double dx, bool &bad) {
+#pragma clang fp contract(off)
+  double s = 0.0;
+#pragma unroll
+  for (int d = 0; d < NDIM; d++) s += fabs(M.vel[d]) / dx;
+  bad |= !isfinite(rho);
+  return s;
+}
+
 __device__ __forceinline__ void wave_flush(double *scal, double vmax, bool bad) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
@@ -38,10 +51,9 @@ __device__ __forceinline__ void wave_flush(double *scal, double vmax, bool bad) 
 }
 
 // CFL limit of every interior cell of the current state (one workgroup per block)
-template <typename T, int NDIM>
+template <typename T, int NDIM, int NV>
 __global__ __launch_bounds__(256) void dt_full_kernel(const MeshDev *__restrict__ Mp) {
   const MeshDev &M = *Mp;
-  constexpr int NV = NDIM + 2;
   const int64_t b = blockIdx.x;
   const int N = M.N, g = M.g, P = N + 2 * g;
   const int64_t sv = (NDIM == 3) ? (int64_t)P * P * P : (int64_t)P * P;
@@ -56,7 +68,8 @@ __global__ __launch_bounds__(256) void dt_full_kernel(const MeshDev *__restrict_
     double U[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) U[v] = (double)u[v * sv + o];
-    vmax = fmax(vmax, inv_dt_cell<NDIM>(U, M.gamma, dx, bad));
+    if constexpr (NV == 1) vmax = fmax(vmax, inv_dt_adv<NDIM>(M, U[0], dx, bad));
+    else vmax = fmax(vmax, inv_dt_cell<NDIM>(U, M.gamma, dx, bad));
   }
   wave_flush(M.scal, vmax, bad);
 }
@@ -78,10 +91,9 @@ __global__ void finalize_kernel(const MeshDev *__restrict__ meshes, int n_meshes
 // dt_s (F_c - <F_f>) / dx on a + face, dt_s (<F_f> - F_c) / dx on a - face,
 // with <F_f> the FP64 pairwise mean of the 2^(d-1) fine fluxes.  In stage 2
 // the CFL limit of the corrected cells is then added to the reduction.
-template <typename T, int NDIM>
+template <typename T, int NDIM, int NV>
 __global__ __launch_bounds__(256) void fluxfix_kernel(const MeshDev *__restrict__ Mp, int stage, SubStep ss) {
   const MeshDev &M = *Mp;
-  constexpr int NV = NDIM + 2;
   constexpr int NF = 2 * NDIM;
   constexpr int PER = 1 << (NDIM - 1);
   const int32_t cb = M.fix_list[blockIdx.x];
@@ -145,17 +157,17 @@ __global__ __launch_bounds__(256) void fluxfix_kernel(const MeshDev *__restrict_
       double U[NV];
 #pragma unroll
       for (int v = 0; v < NV; v++) U[v] = (double)uo[v * sv + o];
-      vmax = fmax(vmax, inv_dt_cell<NDIM>(U, M.gamma, dx, bad));
+      if constexpr (NV == 1) vmax = fmax(vmax, inv_dt_adv<NDIM>(M, U[0], dx, bad));
+      else vmax = fmax(vmax, inv_dt_cell<NDIM>(U, M.gamma, dx, bad));
     }
   }
   wave_flush(M.scal, vmax, bad);
 }
 
 // per-block interior sums of every variable in FP64 times the cell volume
-template <typename T, int NDIM>
+template <typename T, int NDIM, int NV>
 __global__ __launch_bounds__(256) void totals_kernel(const MeshDev *__restrict__ Mp, double *part) {
   const MeshDev &M = *Mp;
-  constexpr int NV = NDIM + 2;
   __shared__ double red[4][NV];
   const int64_t b = blockIdx.x;
   const int N = M.N, g = M.g, P = N + 2 * g;
@@ -202,17 +214,33 @@ __global__ __launch_bounds__(256) void totals_sum_kernel(const double *part, int
   }
 }
 
+// Instantiation by (element type, dimension, variables): the Euler system
+// (ndim + 2 variables) or scalar advection (one).
+#define F4_BY_TYPE(KERNEL, GRID, ...)                                                        \
+  do {                                                                                       \
+    if (nv == 1) {                                                                           \
+      if (ndim == 3) {                                                                       \
+        if (f64) KERNEL<double, 3, 1><<<(GRID), 256, 0, s>>>(__VA_ARGS__);                   \
+        else KERNEL<float, 3, 1><<<(GRID), 256, 0, s>>>(__VA_ARGS__);                        \
+      } else {                                                                               \
+        if (f64) KERNEL<double, 2, 1><<<(GRID), 256, 0, s>>>(__VA_ARGS__);                   \
+        else KERNEL<float, 2, 1><<<(GRID), 256, 0, s>>>(__VA_ARGS__);                        \
+      }                                                                                      \
+    } else if (ndim == 3) {                                                                  \
+      if (f64) KERNEL<double, 3, 5><<<(GRID), 256, 0, s>>>(__VA_ARGS__);                     \
+      else KERNEL<float, 3, 5><<<(GRID), 256, 0, s>>>(__VA_ARGS__);                          \
+    } else {                                                                                 \
+      if (f64) KERNEL<double, 2, 4><<<(GRID), 256, 0, s>>>(__VA_ARGS__);                     \
+      else KERNEL<float, 2, 4><<<(GRID), 256, 0, s>>>(__VA_ARGS__);                          \
+    }                                                                                        \
+  } while (0)
+
 hipError_t launch_dt_full(const foap4_mesh *m, hipStream_t s) {
   if (m->topo.leaves.empty()) return hipSuccess;
   const unsigned nb = (unsigned)m->topo.leaves.size();
   const bool f64 = m->d.prec == FOAP4_F64;
-  if (m->d.ndim == 3) {
-    if (f64) dt_full_kernel<double, 3><<<nb, 256, 0, s>>>(m->d_dev);
-    else dt_full_kernel<float, 3><<<nb, 256, 0, s>>>(m->d_dev);
-  } else {
-    if (f64) dt_full_kernel<double, 2><<<nb, 256, 0, s>>>(m->d_dev);
-    else dt_full_kernel<float, 2><<<nb, 256, 0, s>>>(m->d_dev);
-  }
+  const int ndim = m->d.ndim, nv = m->nvar;
+  F4_BY_TYPE(dt_full_kernel, nb, m->d_dev);
   return hipGetLastError();
 }
 
@@ -221,16 +249,10 @@ hipError_t launch_finalize(const MeshDev *d_meshes, int n_meshes, int advance, h
   return hipGetLastError();
 }
 
-hipError_t launch_fluxfix(const MeshDev *d_mesh, int ndim, bool f64, int n_fix, int stage, hipStream_t s,
+hipError_t launch_fluxfix(const MeshDev *d_mesh, int ndim, int nv, bool f64, int n_fix, int stage, hipStream_t s,
                           const SubStep &ss) {
   if (n_fix <= 0) return hipSuccess;
-  if (ndim == 3) {
-    if (f64) fluxfix_kernel<double, 3><<<n_fix, 256, 0, s>>>(d_mesh, stage, ss);
-    else fluxfix_kernel<float, 3><<<n_fix, 256, 0, s>>>(d_mesh, stage, ss);
-  } else {
-    if (f64) fluxfix_kernel<double, 2><<<n_fix, 256, 0, s>>>(d_mesh, stage, ss);
-    else fluxfix_kernel<float, 2><<<n_fix, 256, 0, s>>>(d_mesh, stage, ss);
-  }
+  F4_BY_TYPE(fluxfix_kernel, n_fix, d_mesh, stage, ss);
   return hipGetLastError();
 }
 
@@ -238,15 +260,12 @@ hipError_t launch_totals(const foap4_mesh *m, double *d_part, double *d_out, hip
   const int64_t nb = (int64_t)m->topo.leaves.size();
   if (nb == 0) return hipSuccess;
   const bool f64 = m->d.prec == FOAP4_F64;
-  if (m->d.ndim == 3) {
-    if (f64) totals_kernel<double, 3><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, d_part);
-    else totals_kernel<float, 3><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, d_part);
-  } else {
-    if (f64) totals_kernel<double, 2><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, d_part);
-    else totals_kernel<float, 2><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, d_part);
-  }
+  const int ndim = m->d.ndim, nv = m->nvar;
+  F4_BY_TYPE(totals_kernel, (unsigned)nb, m->d_dev, d_part);
   totals_sum_kernel<<<1, 256, 0, s>>>(d_part, nb, m->nvar, d_out);
   return hipGetLastError();
 }
+
+#undef F4_BY_TYPE
 
 }  // namespace f4

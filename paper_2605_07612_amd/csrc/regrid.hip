@@ -6,13 +6,12 @@ namespace f4 {
 // Lohner-type criterion of eq. lohner-simple on the density, in FP64 with
 // the operation order of the definition and no contraction, so that the
 // flags equal a plain evaluation bit for bit.  One workgroup per block.
-template <typename T, int NDIM>
+template <typename T, int NDIM, int NV>
 __global__ __launch_bounds__(256) void lohner_kernel(const MeshDev *__restrict__ Mp, double cr2, double cd2,
                                                      double eps, double eps_abs, int8_t *flags,
                                                      const int8_t *skip) {
 #pragma clang fp contract(off)
   const MeshDev &M = *Mp;
-  constexpr int NV = NDIM + 2;
   const int64_t b = blockIdx.x;
   if (skip && skip[b]) return;
   const int N = M.N, g = M.g, P = N + 2 * g;
@@ -45,10 +44,9 @@ __global__ __launch_bounds__(256) void lohner_kernel(const MeshDev *__restrict__
 // One workgroup per new block: map[n] = (op, src, arg) with op 0 copy old
 // block src, op 1 prolong child arg (bits x + 2y + 4z) of old block src with
 // limited slopes (old ghosts filled), op 2 restrict old children src..src+2^d-1.
-template <typename T, int NDIM>
+template <typename T, int NDIM, int NV>
 __global__ __launch_bounds__(256) void remap_kernel(const T *__restrict__ uold, T *unew, const int32_t *map, int N,
                                                     int g) {
-  constexpr int NV = NDIM + 2;
   const int64_t n = blockIdx.x;
   const int P = N + 2 * g, H = N / 2;
   const int64_t sv = (NDIM == 3) ? (int64_t)P * P * P : (int64_t)P * P;
@@ -118,19 +116,35 @@ __global__ __launch_bounds__(256) void remap_kernel(const T *__restrict__ uold, 
   }
 }
 
+// Instantiation by (element type, dimension, variables): the Euler system
+// (ndim + 2 variables) or scalar advection (one).
+#define F4_BY_TYPE(KERNEL, T_, GRID, ...)                                                 \
+  do {                                                                                    \
+    if (f64) {                                                                            \
+      using T_ = double;                                                                  \
+      if (nv == 1) {                                                                      \
+        if (ndim == 3) KERNEL<T_, 3, 1><<<(GRID), 256, 0, s>>>(__VA_ARGS__);              \
+        else KERNEL<T_, 2, 1><<<(GRID), 256, 0, s>>>(__VA_ARGS__);                        \
+      } else if (ndim == 3) KERNEL<T_, 3, 5><<<(GRID), 256, 0, s>>>(__VA_ARGS__);         \
+      else KERNEL<T_, 2, 4><<<(GRID), 256, 0, s>>>(__VA_ARGS__);                          \
+    } else {                                                                              \
+      using T_ = float;                                                                   \
+      if (nv == 1) {                                                                      \
+        if (ndim == 3) KERNEL<T_, 3, 1><<<(GRID), 256, 0, s>>>(__VA_ARGS__);              \
+        else KERNEL<T_, 2, 1><<<(GRID), 256, 0, s>>>(__VA_ARGS__);                        \
+      } else if (ndim == 3) KERNEL<T_, 3, 5><<<(GRID), 256, 0, s>>>(__VA_ARGS__);         \
+      else KERNEL<T_, 2, 4><<<(GRID), 256, 0, s>>>(__VA_ARGS__);                          \
+    }                                                                                     \
+  } while (0)
+
 hipError_t launch_lohner(const foap4_mesh *m, int8_t *d_flags, const int8_t *skip, hipStream_t s) {
   const int64_t nb = (int64_t)m->topo.leaves.size();
   if (nb == 0) return hipSuccess;
   const double cr = 5e-2, cd = 6.25e-3;  // c_refine, c_derefine of the AMR runs (Sec. 5.4)
   const double cr2 = cr * cr, cd2 = cd * cd, eps = 1e-2, eps_abs = 1e-10;
   const bool f64 = m->d.prec == FOAP4_F64;
-  if (m->d.ndim == 3) {
-    if (f64) lohner_kernel<double, 3><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, cr2, cd2, eps, eps_abs, d_flags, skip);
-    else lohner_kernel<float, 3><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, cr2, cd2, eps, eps_abs, d_flags, skip);
-  } else {
-    if (f64) lohner_kernel<double, 2><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, cr2, cd2, eps, eps_abs, d_flags, skip);
-    else lohner_kernel<float, 2><<<(unsigned)nb, 256, 0, s>>>(m->d_dev, cr2, cd2, eps, eps_abs, d_flags, skip);
-  }
+  const int ndim = m->d.ndim, nv = m->nvar;
+  F4_BY_TYPE(lohner_kernel, T, (unsigned)nb, m->d_dev, cr2, cd2, eps, eps_abs, d_flags, skip);
   return hipGetLastError();
 }
 
@@ -139,14 +153,11 @@ hipError_t launch_remap(const foap4_mesh *m, const void *src_state, void *dst_st
   if (nb_new == 0) return hipSuccess;
   const bool f64 = m->d.prec == FOAP4_F64;
   const int N = m->d.block_n, g = m->d.n_ghost;
-  if (m->d.ndim == 3) {
-    if (f64) remap_kernel<double, 3><<<(unsigned)nb_new, 256, 0, s>>>((const double *)src_state, (double *)dst_state, d_map, N, g);
-    else remap_kernel<float, 3><<<(unsigned)nb_new, 256, 0, s>>>((const float *)src_state, (float *)dst_state, d_map, N, g);
-  } else {
-    if (f64) remap_kernel<double, 2><<<(unsigned)nb_new, 256, 0, s>>>((const double *)src_state, (double *)dst_state, d_map, N, g);
-    else remap_kernel<float, 2><<<(unsigned)nb_new, 256, 0, s>>>((const float *)src_state, (float *)dst_state, d_map, N, g);
-  }
+  const int ndim = m->d.ndim, nv = m->nvar;
+  F4_BY_TYPE(remap_kernel, T, (unsigned)nb_new, (const T *)src_state, (T *)dst_state, d_map, N, g);
   return hipGetLastError();
 }
+
+#undef F4_BY_TYPE
 
 }  // namespace f4

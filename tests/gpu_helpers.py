@@ -19,11 +19,12 @@ def oracle_mesh(w):
 
 
 def scheme(w):
-    """Limiter, flux, gravity and boundaries of a workload (defaults: minmod,
-    Rusanov, no source, periodic)."""
+    """Limiter, flux, gravity, boundaries and system of a workload (defaults:
+    minmod, Rusanov, no source, periodic, the Euler equations)."""
     return dict(limiter=w.get("limiter", "minmod"), flux=w.get("flux", "rusanov"),
                 gravity=tuple(w.get("gravity", (0.0, 0.0, 0.0))), periodic=tuple(w.get("periodic", (True,) * 3)),
-                bc_type=w.get("bc_type"), bc_value=w.get("bc_value"))
+                bc_type=w.get("bc_type"), bc_value=w.get("bc_value"), physics=w.get("physics", "euler"),
+                velocity=tuple(w.get("velocity", (0.0, 0.0, 0.0))))
 
 
 def refine_flags_base(w, mesh_tree_xyz):
@@ -81,3 +82,26 @@ def face_ghost_mask(ndim, N, g):
             sl[ndim - 1 - ax] = s
             m[tuple(sl)] = True
     return m
+
+
+# Bounds of a GPU state against the FP64 oracle: the volume-weighted relative
+# L1 error of the benchmark spec (FP64 1e-12, FP32 2e-5) and, so that an error
+# confined to a few cells cannot hide in the global norm, a per-element bound
+# max |a - b| <= tol * max |b| over every cell and variable (FP64 1e-10,
+# FP32 1e-5: a few hundred roundings of the state's own precision).
+REL_L1 = {0: 2e-5, 1: 1e-12}
+PER_ELEM = {0: 1e-5, 1: 1e-10}
+
+
+def max_elem_err(a, b):
+    """max |a - b| / max |b| over all cells and variables."""
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+def check_state(a, b, levels, ndim, tree_size, N, prec, l1=None, elem=None):
+    """Asserts both bounds; returns (rel L1, per-element) errors."""
+    e1 = rel_l1_vol(a, b, levels, ndim, tree_size, N)
+    e2 = max_elem_err(a, b)
+    assert e1 <= (REL_L1[prec] if l1 is None else l1), ("rel L1", e1)
+    assert e2 <= (PER_ELEM[prec] if elem is None else elem), ("per element", e2)
+    return e1, e2

@@ -72,6 +72,11 @@ BAD = [
     dict(flux=-1),
     dict(gravity=(0.0, float("inf"), 0.0)),
     dict(gravity=(float("nan"), 0.0, 0.0)),
+    dict(physics=2),
+    dict(physics=1, velocity=(0.0, 0.0, 0.0)),
+    dict(physics=1, velocity=(0.0, 0.0, 0.0), ndim=2, n_trees=(2, 2, 1)),
+    dict(physics=1, velocity=(1.0, float("nan"), 0.0)),
+    dict(physics=1, velocity=(1.0, 0.0, 0.0), gravity=(0.0, 0.0, -1.0)),
 ]
 
 
@@ -135,4 +140,27 @@ def test_boundary_entries_of_periodic_axes_are_ignored(f4):
     d.bc_type[0][0] = 7            # -x face: periodic axis
     d.bc_value[1][1] = float("nan")
     st, h, msg = create(f4, d, nbytes=1)
+    assert st == E_INVALID and not h and "smaller" in msg
+
+
+def test_advection_velocity_of_the_unused_axis_is_ignored(f4):
+    """Scalar advection in 2-D reads velocity[0..1] only: a zero velocity in
+    the plane is refused even with velocity[2] set, a non-zero one gets past
+    the checks to the buffer-size check (one byte is too small)."""
+    d = desc(f4, ndim=2, n_trees=(2, 2, 1), physics=1, velocity=(0.0, 0.0, 3.0))
+    st, h, msg = create(f4, d)
+    assert st == E_INVALID and not h and "velocity" in msg
+    d = desc(f4, ndim=2, n_trees=(2, 2, 1), physics=1, velocity=(0.0, -1.0, float("nan")))
+    st, h, msg = create(f4, d, nbytes=1)
+    assert st == E_INVALID and not h and "smaller" in msg
+
+
+def test_advection_state_holds_one_variable(f4):
+    """The state of scalar advection holds nvar = 1 variable per block: one
+    byte less than max_blocks single-variable blocks is refused by the size
+    check (before any HIP call)."""
+    d = desc(f4, physics=1, velocity=(1.0, 0.5, 0.0))
+    P = 12
+    need = 8 * 1 * P ** 3 * 4
+    st, h, msg = create(f4, d, nbytes=need - 1)
     assert st == E_INVALID and not h and "smaller" in msg

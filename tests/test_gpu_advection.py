@@ -1,0 +1,275 @@
+"""GPU parity of scalar advection (Sec. 3.4) against the FP64 oracle, through
+the C ABI, and the paper's advection tests (Sec. 4.1) on the GPU path.
+
+* Parity: uniform meshes of 8^d, 16^d and 32^d blocks in 2-D and 3-D, the
+  MUSCL limiters (g = 2) and WENO5 (g = 3), Rusanov and HLL, velocities of
+  both signs and with a zero component, every integrator; two-level meshes
+  (restriction, prolongation and flux fixing); physical boundaries; a regrid
+  by the criterion on rho.  FP64 within 1e-12 and FP32 within 2e-5 relative
+  L1, plus a per-element bound.
+* E1 (Sec. 4.1.1): the smoothed sphere crosses every refinement boundary of
+  a statically refined mesh and returns to its start at t = 1; with flux
+  fixing the total mass is conserved to rounding.
+* E2 (Sec. 4.1.2): the L1 error of the Gaussian after one period falls with
+  the grid spacing at about second order for van Leer + Heun and about fifth
+  order for WENO5 + RK4, on the GPU in FP64.
+* The batched form equals the plain form bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_helpers import check_state, gpu_state, interior
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def f4():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_07612_amd as f4
+    f4.lib()
+    return f4
+
+
+def adv_pair(f4, ndim, nt, N, prec, limiter="vanleer", flux="rusanov", velocity=(1.0, 1.0, 1.0), integrator="heun",
+             field=None, periodic=(True, True, True), bc_type=None, bc_value=None, max_level=0, cfl=0.5):
+    """(gpu mesh, oracle mesh) of the periodic unit square / cube with nt
+    trees per axis and the smoothed sphere (or `field`)."""
+    from oracle import OracleMesh
+    from paper_2605_07612_amd import layout
+    g = 3 if limiter == "weno5" else 2
+    trees = (nt,) * ndim + (1,) * (3 - ndim)
+    base = nt ** ndim
+    kw = dict(limiter=limiter, flux=flux, integrator=integrator, physics="advection", velocity=velocity,
+              periodic=periodic, bc_type=bc_type, bc_value=bc_value, cfl=cfl)
+    gm = f4.Mesh(ndim, trees, N, g, 1.0 / nt, level=0, max_level=max_level,
+                 max_blocks=base * (1 << (ndim * max_level)), prec=prec, **kw)
+    om = OracleMesh(ndim, trees, N, g, 1.0 / nt, level=0, **kw)
+    f = synth.advection_sphere_field(ndim, R=0.2, delta=0.1) if field is None else field
+    layout.set_from_field(gm, f)
+    om.set_interior_from_field(f)
+    return gm, om
+
+
+def compare(gm, om, prec, label):
+    lev = gm.export()[0]
+    a = interior(gpu_state(gm), gm.g, gm.N, gm.ndim)
+    e1, e2 = check_state(a, om.interior(), lev, gm.ndim, gm.desc.tree_size, gm.N, prec)
+    t, _ = gm.time()
+    say(label, "rel L1", e1, "per element", e2, "t", t, om.t)
+    assert abs(t - om.t) <= (1e-13 if prec == 1 else 1e-6) * om.t
+    return e1
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["f64", "f32"])
+@pytest.mark.parametrize("ndim,nt,N,limiter,flux,vel", [
+    (3, 4, 8, "minmod", "rusanov", (1.0, 1.0, 1.0)),
+    (3, 2, 16, "vanleer", "rusanov", (0.7, -1.3, 0.4)),
+    (3, 2, 16, "vanleer", "hll", (-0.5, 0.0, 1.2)),
+    (3, 1, 32, "minmod", "hll", (1.0, 0.5, -0.25)),
+    (3, 2, 16, "weno5", "rusanov", (1.0, 1.0, 1.0)),
+    (3, 4, 8, "weno5", "hll", (-1.0, 0.6, 0.3)),
+    (2, 4, 8, "vanleer", "rusanov", (1.0, -0.5)),
+    (2, 2, 32, "weno5", "hll", (0.3, 1.1)),
+])
+def test_parity_uniform(f4, ndim, nt, N, limiter, flux, vel, prec):
+    gm, om = adv_pair(f4, ndim, nt, N, prec, limiter, flux, vel + (0.0,) * (3 - len(vel)))
+    gm.step(8)
+    om.step(8)
+    compare(gm, om, prec, f"adv {ndim}d N={N} {limiter} {flux} v={vel}")
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["f64", "f32"])
+@pytest.mark.parametrize("integrator,limiter", [("ssprk3", "vanleer"), ("ssprk43", "minmod"), ("rk4", "weno5")])
+def test_parity_integrators(f4, integrator, limiter, prec):
+    gm, om = adv_pair(f4, 3, 2, 16, prec, limiter, "rusanov", (1.0, -0.7, 0.5), integrator=integrator)
+    gm.step(5)
+    om.step(5)
+    compare(gm, om, prec, f"adv {integrator} {limiter}")
+
+
+def two_level(f4, ndim, N, prec, limiter, flux="rusanov", vel=(1.0, 1.0, 1.0), integrator="heun"):
+    """The central 2^d base blocks of a 4^d brick refined once."""
+    from paper_2605_07612_amd import layout
+    gm, om = adv_pair(f4, ndim, 4, N, prec, limiter, flux, vel, integrator=integrator, max_level=1)
+    _, G = layout.global_coords(gm)
+    flags = np.all((G[:, :ndim] == 1) | (G[:, :ndim] == 2), axis=1).astype(np.int8)
+    gm.regrid(flags)
+    om.regrid(flags, 0, 1)
+    f = synth.advection_sphere_field(ndim, R=0.2, delta=0.1, centre=(0.45, 0.55, 0.5))
+    layout.set_from_field(gm, f)
+    om.set_interior_from_field(f)
+    return gm, om
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["f64", "f32"])
+@pytest.mark.parametrize("ndim,N,limiter,flux,integrator", [(3, 8, "vanleer", "rusanov", "heun"),
+                                                            (3, 16, "minmod", "hll", "ssprk3"),
+                                                            (3, 8, "weno5", "rusanov", "rk4"),
+                                                            (2, 16, "vanleer", "hll", "heun"),
+                                                            (2, 8, "weno5", "hll", "ssprk43")])
+def test_parity_two_levels(f4, ndim, N, limiter, flux, integrator, prec):
+    gm, om = two_level(f4, ndim, N, prec, limiter, flux, (1.0, -0.6, 0.8)[:ndim] + (0.0,) * (3 - ndim),
+                       integrator)
+    assert len(set(gm.export()[0].tolist())) == 2
+    gm.step(10)
+    om.step(10)
+    compare(gm, om, prec, f"adv two-level {ndim}d N={N} {limiter} {flux} {integrator}")
+
+
+def test_flux_fixing_conserves_mass_to_rounding(f4):
+    """E1 (Sec. 4.1.1): the sphere advected to t = 1 across the refinement
+    boundaries of a mesh refined twice around it: the total mass stays
+    within rounding of its start (FP64), and the GPU state matches the
+    oracle's at the end."""
+    from oracle import OracleMesh
+    from paper_2605_07612_amd import layout
+    w = synth.advection_flux_fix(ndim=2, block=16, base_trees=4, levels=2, limiter="vanleer")
+    nt = w["trees"][0]
+    gm = f4.Mesh(2, w["trees"], 16, 2, w["tree_size"], level=0, max_level=2, max_blocks=nt * nt * 16, prec=f4.F64,
+                 limiter="vanleer", physics="advection", velocity=w["velocity"], cfl=w["cfl"])
+    om = OracleMesh(2, w["trees"], 16, 2, w["tree_size"], level=0, limiter="vanleer", physics="advection",
+                    velocity=w["velocity"], cfl=w["cfl"])
+    for r in range(w["refine_rounds"]):
+        lev, G = layout.global_coords(gm)
+        flags = w["refine_flags_at"](lev, G)
+        gm.regrid(flags)
+        om.regrid(flags, 0, 2)
+    assert np.array_equal(gm.export()[0], np.asarray(om.level))
+    layout.set_from_field(gm, w["field"])
+    om.set_interior_from_field(w["field"])
+    m0 = gm.totals()[0]
+    t = 0.0
+    nsteps = 0
+    while t < w["t_end"] - 1e-12:
+        t, dt = gm.step(1, sync=True)
+        nsteps += 1
+        if t + dt > w["t_end"]:
+            break
+    drift = abs(gm.totals()[0] - m0) / abs(m0)
+    say("E1 on the GPU: steps", nsteps, "t", t, "mass drift", drift)
+    assert drift <= 1e-13
+    om.step(nsteps)
+    compare(gm, om, 1, "E1 end state")
+
+
+def gauss_errors_gpu(f4, n, limiter, integrator, cfl, t_end=0.25):
+    """L1 error of the Gaussian advected with v = (1, 1) on n^2 cells in
+    16^2 blocks (FP64), against the exact solution rho0(x - v t)."""
+    from paper_2605_07612_amd import layout
+    w = synth.advection(2, 16, n, init="gauss", limiter=limiter, cfl=cfl)
+    gm = f4.Mesh(2, w["trees"], 16, w["g"], w["tree_size"], prec=f4.F64, limiter=limiter, integrator=integrator,
+                 physics="advection", velocity=(1.0, 1.0), cfl=cfl)
+    layout.set_from_field(gm, w["field"])
+    gm.compute_dt()
+    _, dt = gm.time()
+    t, _ = gm.step(int(np.ceil(t_end / dt - 1e-12)), sync=True)
+    xc = layout.cell_centres(gm)
+    exact = w["field"](*[(xc[:, d] - t) % 1.0 for d in range(2)])[0]
+    a = gm.interior().double().cpu().numpy()[:, 0]
+    gm.close()
+    return float(np.mean(np.abs(a - exact)))
+
+
+@pytest.mark.parametrize("limiter,integrator,lo,hi", [("vanleer", "heun", 1.75, 2.2), ("weno5", "rk4", 4.6, 5.4)])
+def test_convergence_on_the_gpu(f4, limiter, integrator, lo, hi):
+    """E2 (Sec. 4.1.2) on the GPU path in FP64: the Gaussian of 16^2-cell
+    blocks advected to t = 1/4; the L1 order between 128^2 and 256^2 cells is
+    close to 2 for van Leer + Heun (CFL 0.5) and close to 5 for WENO5 + RK4
+    (CFL scaled with dx^(1/4), so that the time error stays below the space
+    error)."""
+    ns = (64, 128, 256)
+    cfl = [0.5 if limiter != "weno5" else 0.5 * (ns[0] / n) ** 0.25 for n in ns]
+    errs = [gauss_errors_gpu(f4, n, limiter, integrator, c) for n, c in zip(ns[1:], cfl[1:])]
+    p = np.log2(errs[0] / errs[1])
+    say("E2 on the GPU", limiter, integrator, "L1 errors", errs, "order", p)
+    assert lo <= p <= hi
+
+
+def test_physical_boundaries_and_regrid(f4):
+    """Bounded x axis (Dirichlet rho = 0.25 at -x, Neumann 0 at +x), periodic
+    y and z, inflow through the Dirichlet face; then a regrid by the
+    gradient criterion on rho (flags computed on identical states equal the
+    oracle's), and more steps on the new mesh: leaf tables bit-exact, the
+    remapped data bit-exact, states within the FP64 bounds."""
+    import paper_2605_07612_amd as f4m
+    bt = np.zeros((6, 5), np.int32)
+    bv = np.zeros((6, 5))
+    bt[0, 0], bv[0, 0] = f4m.BC_DIRICHLET, 0.25
+    bt[1, 0], bv[1, 0] = f4m.BC_NEUMANN, 0.0
+    gm, om = adv_pair(f4, 3, 4, 8, f4.F64, "vanleer", "hll", (0.8, 0.3, -0.2), periodic=(False, True, True),
+                      bc_type=bt, bc_value=bv, max_level=1)
+    assert gm.pattern_counts()[3].sum() > 0
+    gm.step(4)
+    om.step(4)
+    compare(gm, om, 1, "adv walls before regrid")
+    # flags of identical states
+    om.u[...] = 0.0
+    om.interior()[...] = interior(gpu_state(gm), gm.g, gm.N, 3)
+    om.ghost_fill()
+    flags = gm.refine_flags()
+    assert np.array_equal(flags, om.lohner_flags())
+    assert (flags == 1).any()
+    gm.regrid(flags)
+    om.regrid(flags, 0, 1)
+    lev, tree, anc = gm.export()
+    olev, otree, oanc = om.forest.export()
+    assert np.array_equal(lev, olev) and np.array_equal(tree, otree) and np.array_equal(anc, oanc)
+    assert np.array_equal(interior(gpu_state(gm), gm.g, gm.N, 3), om.interior())
+    gm.step(4)
+    om.step(4)
+    compare(gm, om, 1, "adv walls after regrid")
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["f64", "f32"])
+def test_batched_equals_plain(f4, prec):
+    """Three advection meshes of different block sizes and levels in one
+    batch (graph-captured steps) against the same meshes stepped alone."""
+    vel = (0.9, -0.4, 0.6)
+
+    def make(k):
+        if k == 1:
+            return two_level(f4, 3, 8, prec, "vanleer", "rusanov", vel)[0]
+        return adv_pair(f4, 3, (2, 4, 1)[k], (16, 8, 32)[k], prec, "vanleer", "rusanov", vel)[0]
+
+    meshes = [make(k) for k in range(3)]
+    b = f4.Batch(meshes)
+    b.step(6)
+    batched = [gpu_state(gm).copy() for gm in meshes]
+    b.close()
+    for k, gm in enumerate(meshes):
+        ref = make(k)
+        ref.step(6)
+        assert np.array_equal(gpu_state(ref), batched[k]), k
+        assert ref.time() == gm.time()
+        ref.close()
+        gm.close()
+
+
+def test_refusals(f4):
+    """Advection needs a non-zero finite velocity and takes no gravity; the
+    learned indicator's features are refused; a batch takes one system."""
+    with pytest.raises(f4.Foap4Error, match="E_INVALID"):
+        f4.Mesh(3, (2, 2, 2), 8, 2, 0.5, physics="advection", velocity=(0.0, 0.0, 0.0))
+    with pytest.raises(f4.Foap4Error, match="E_INVALID"):
+        f4.Mesh(3, (2, 2, 2), 8, 2, 0.5, physics="advection", velocity=(1.0, 0.0, 0.0), gravity=(0.0, 0.0, -1.0))
+    m = f4.Mesh(3, (2, 2, 2), 8, 2, 0.5, physics="advection", velocity=(1.0, 0.0, 0.0))
+    assert m.nvar == 1
+    with pytest.raises(f4.Foap4Error, match="E_INVALID"):
+        m.block_features()
+    with pytest.raises(f4.Foap4Error, match="E_INVALID"):
+        m.capture_features(True)
+    e = f4.Mesh(3, (2, 2, 2), 8, 2, 0.5)
+    with pytest.raises(f4.Foap4Error, match="E_INVALID"):
+        f4.Batch([m, e])
+    m.close()
+    e.close()
