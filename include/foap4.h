@@ -235,6 +235,21 @@ foap4_status foap4_time(foap4_mesh *mesh, double *t_out, double *dt_out);
  * (out[nvar], host).  Synchronizes. */
 foap4_status foap4_conserved_totals(foap4_mesh *mesh, double *out);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the totals of
+ * foap4_conserved_totals, computed by the same kernels in the same order
+ * (bit-identical), written to out_dev[nvar] (FP64, device, caller-owned) on
+ * the mesh's stream.  Enqueue only; allocates nothing and synchronizes
+ * nothing.  Its per-block partial sums live in a fixed device array of
+ * 262144 FP64 values (2 MiB) per GPU, set up by foap4_mesh_create on that
+ * GPU and held until the process ends.  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (several streams, several threads)
+ * race and must be ordered by the caller.  The mesh's device must be
+ * current.  Errors: FOAP4_E_CAPACITY if n_blocks * nvar > 262144 (nothing
+ * is enqueued), FOAP4_E_INVALID (null pointer, another device current),
+ * FOAP4_E_HIP (launch failure). */
+foap4_status foap4_conserved_totals_noalloc(foap4_mesh *mesh, double *out_dev);
+
 /* Per-block refinement flags (+1 refine, 0 keep, -1 derefine; Sec. 2.2) of
  * the current state, written to flags_host[n_blocks].  Both indicators fill
  * ghosts first.  FOAP4_IND_LOHNER is the paper's criterion (Sec. 3.3, eq.

@@ -75,6 +75,7 @@ EXPORTS = {
     "foap4_step": (I32, [P, I32, P, P]),
     "foap4_time": (I32, [P, P, P]),
     "foap4_conserved_totals": (I32, [P, P]),
+    "foap4_conserved_totals_noalloc": (I32, [P, P]),
     "foap4_refine_flags": (I32, [P, I32, P]),
     "foap4_regrid": (I32, [P, P, P]),
     "foap4_batch_create": (I32, [P, I32, ctypes.POINTER(P)]),
@@ -277,6 +278,15 @@ class Mesh:
     def totals(self):
         out = np.zeros(self.nvar)
         _check(lib().foap4_conserved_totals(self.h, _ptr(out)), self.h)
+        return out
+
+    def totals_noalloc(self, out):
+        """Conserved totals into the caller's device tensor `out` (FP64, at
+        least nvar values) without any allocation; enqueue only."""
+        torch = _torch()
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() < self.nvar or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device tensor of at least nvar values")
+        _check(lib().foap4_conserved_totals_noalloc(self.h, P(out.data_ptr())), self.h)
         return out
 
     def refine_flags(self, indicator=IND_LOHNER):

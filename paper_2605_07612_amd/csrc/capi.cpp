@@ -245,6 +245,11 @@ foap4_status foap4_mesh_create(const foap4_mesh_desc *desc, void *state0, void *
     return bail(FOAP4_E_HIP);
   }
   m->cap_blocks = cap;
+  // set-up of the allocation-free totals on this device (once per device)
+  if (hipGetDevice(&m->device) != hipSuccess || noalloc_scratch_init(m->device) != hipSuccess) {
+    m->err = "device scratch lookup failed";
+    return bail(FOAP4_E_HIP);
+  }
   if (hipMemsetAsync(m->d_scal, 0, kNScal * 8, m->stream) != hipSuccess) {
     m->err = "memset failed";
     return bail(FOAP4_E_HIP);
@@ -503,6 +508,22 @@ foap4_status foap4_conserved_totals(foap4_mesh *m, double *out) {
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   (void)hipFree(d_part);
   if (e != hipSuccess) return fail(m, FOAP4_E_HIP, std::string("totals: ") + hipGetErrorString(e));
+  return FOAP4_OK;
+}
+
+foap4_status foap4_conserved_totals_noalloc(foap4_mesh *m, double *out_dev) {
+  if (!m || !out_dev) return fail(m, FOAP4_E_INVALID, "null argument");
+  const int64_t nb = (int64_t)m->topo.leaves.size();
+  if (nb * m->nvar > kNoAllocScratchDoubles)
+    return fail(m, FOAP4_E_CAPACITY, "foap4_conserved_totals_noalloc: n_blocks * nvar = " + std::to_string(nb * m->nvar) +
+                                         " exceeds its fixed scratch of " + std::to_string(kNoAllocScratchDoubles) +
+                                         " values");
+  int dev = -1;
+  F4_HIP(m, hipGetDevice(&dev));
+  if (dev != m->device) return fail(m, FOAP4_E_INVALID, "the mesh's device must be current");
+  double *part = noalloc_scratch(dev);
+  if (!part) return fail(m, FOAP4_E_ORDER, "device scratch not set up");
+  F4_HIP(m, launch_totals(m, part, out_dev, m->stream));
   return FOAP4_OK;
 }
 

@@ -152,6 +152,7 @@ struct foap4_mesh {
   void *state[4] = {nullptr, nullptr, nullptr, nullptr};  // extra states of the longer integrators
   size_t state_bytes = 0;
   hipStream_t stream = nullptr;
+  int device = 0;              // HIP device current at creation
   int32_t cur = 0;
   f4::Topology topo;
   int64_t revision = 0;
@@ -258,6 +259,14 @@ hipError_t launch_finalize(const MeshDev *d_meshes, int n_meshes, int advance, h
 hipError_t launch_fluxfix(const MeshDev *d_mesh, int ndim, int nv, bool f64, int n_fix, int stage, hipStream_t s,
                           const SubStep &ss = SubStep{});
 hipError_t launch_totals(const foap4_mesh *m, double *d_part, double *d_out, hipStream_t s);
+// The allocation-free totals: a fixed device array of kNoAllocScratchDoubles
+// FP64 values (2 MiB) per GPU, looked up once per device (with that device
+// current) by noalloc_scratch_init; noalloc_scratch returns the looked-up
+// device address (null before the lookup).
+constexpr int64_t kNoAllocScratchDoubles = 262144;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch_init(int device);
+double *noalloc_scratch(int device);
 // regrid.hip
 // skip (may be null): blocks whose flag is already set are left alone
 hipError_t launch_lohner(const foap4_mesh *m, int8_t *d_flags, const int8_t *skip, hipStream_t s);

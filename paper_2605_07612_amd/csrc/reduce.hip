@@ -4,6 +4,8 @@
 #include "device_common.h"
 #include "foap4_internal.h"
 
+#include <mutex>
+
 namespace f4 {
 
 // sum_d (|v_d| + c) / dx of one cell in FP64, operation order of the
@@ -254,6 +256,34 @@ hipError_t launch_fluxfix(const MeshDev *d_mesh, int ndim, int nv, bool f64, int
   if (n_fix <= 0) return hipSuccess;
   F4_BY_TYPE(fluxfix_kernel, n_fix, d_mesh, stage, ss);
   return hipGetLastError();
+}
+
+// Fixed device scratch of foap4_conserved_totals_noalloc: the per-block
+// partial sums of launch_totals.  One copy per GPU, held until the process
+// ends; its address on a device comes from hipGetSymbolAddress with that
+// device current (the array's name is not a device address in host code).
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  double *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+double *noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 hipError_t launch_totals(const foap4_mesh *m, double *d_part, double *d_out, hipStream_t s) {
