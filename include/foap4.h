@@ -389,8 +389,9 @@ foap4_status foap4_batch_destroy(foap4_batch *batch);
  * give each workgroup a contiguous chunk (a block and its Morton neighbours
  * run back to back on one CU), gather_halos = 1 to read same-level halo cells straight from the
  * neighbouring blocks instead of copying them into ghost cells first (the
- * results are identical; the SRL copies are then skipped except where the
- * coarse-to-fine prolongation reads them).  Defaults: 1, 0, 0, 1, 1.
+ * results are identical; round R1 then runs only the SRL copies whose ghosts
+ * a coarse-to-fine prolongation reads: the records with a side that is the
+ * coarse block of a C2F record).  Defaults: 1, 0, 0, 1, 1.
  * FOAP4_E_INVALID outside those ranges (workgroups per CU: 0 .. 64). */
 foap4_status foap4_batch_set_config(foap4_batch *batch, int32_t kslabs, int32_t wg_stage1,
                                     int32_t wg_stage2, int32_t xcd_order, int32_t gather_halos);

@@ -6,9 +6,11 @@
 //
 // One workgroup per block and one thread per (i, j) column, which marches
 // along k.  Per plane the workgroup stages the plane with its x and y face
-// ghosts in LDS (the interior from the threads' own z windows, the ghosts
-// from the block's stored ghost cells, filled by the ghost rounds), double
-// buffered so that one barrier per plane suffices; every thread then
+// halos in LDS (the interior from the threads' own z windows; the halo of a
+// same-level face straight from the neighbouring block's interior when the
+// mesh gathers halos, else - and always across refinement and boundary
+// faces - from the block's stored ghosts, filled by the ghost rounds),
+// double buffered so that one barrier per plane suffices; every thread then
 // evaluates the two x faces and two y faces of its cell from LDS and the
 // upper z face from its register window of the column (the lower one is the
 // upper face of the previous plane).  The update, the refinement-face flux
@@ -16,7 +18,7 @@
 // Heun's stages, 3 the generic sub-step, 4 the generic sub-step with three
 // earlier states.  With a single variable the work per cell is small, so the
 // kernel is bound by its HBM traffic: the state is read once per stage (plus
-// the face ghosts, and Heun's second stage reads U^n) and written once.
+// the face halos, and Heun's second stage reads U^n) and written once.
 #include "device_common.h"
 #include "foap4_internal.h"
 
@@ -87,19 +89,29 @@ __device__ __forceinline__ void adv_bflux(const MeshDev &M, int info, int t1, in
 // LDS elements: two planes of (N + 2g)^2 cells.
 __host__ __device__ constexpr int adv_lds(int N, int g) { return 2 * (N + 2 * g) * (N + 2 * g); }
 
-template <typename T, int NDIM, int LIM, bool HLL, int STG>
-__global__ __launch_bounds__(1024) void advect_kernel(const MeshDev *__restrict__ Mp, SubStep ss) {
+// MAXT: the largest workgroup (N^2 threads) the instantiation serves: 1024
+// for 32^2 columns, 256 for 8^2 and 16^2 (which leaves the compiler up to 512
+// registers per thread instead of 128).
+template <typename T, int NDIM, int LIM, bool HLL, int STG, int MAXT>
+__global__ __launch_bounds__(MAXT) void advect_kernel(const MeshDev *__restrict__ Mp, SubStep ss) {
   constexpr int R = AdvStencil<LIM>::R;
   extern __shared__ __align__(16) unsigned char adv_smem[];
   const MeshDev &M = *Mp;
   const int N = M.N, g = M.g, P = N + 2 * g, Q = P;
   const int rows = (NDIM == 3) ? P * P : P;  // rows (k, j) of the row part of a block
   const int64_t sv = (NDIM == 3) ? (int64_t)P * P * P : (int64_t)P * P;
-  const int64_t b = blockIdx.x;
+  // XCD-aware block order: workgroup w runs on XCD w mod 8, so XCD x is
+  // given the contiguous range of blocks [x q + min(x, r), ...) of q or q + 1
+  // blocks (nb = 8 q + r): blocks that are neighbours in Morton order, whose
+  // face halos each reads, share that XCD's L2.  A bijection onto 0 .. nb-1.
+  const int64_t nbk = M.nb, xq = nbk / 8, xr = nbk % 8;
+  const int64_t xid = blockIdx.x % 8, xi = blockIdx.x / 8;
+  const int64_t b = xid * xq + (xid < xr ? xid : xr) + xi;
   const int t = threadIdx.x, i = t % N, j = t / N;
   const int cur = M.cur;
   const int64_t boff = b * sv;
-  const T *ud = (const T *)M.s[STG >= 3 ? role_buffer(ss.deriv, cur) : (STG == 1 ? cur : 1 - cur)] + boff;
+  const T *ud0 = (const T *)M.s[STG >= 3 ? role_buffer(ss.deriv, cur) : (STG == 1 ? cur : 1 - cur)];
+  const T *ud = ud0 + boff;
   T *uo = (T *)M.s[STG >= 3 ? role_buffer(ss.out, cur) : (STG == 1 ? 1 - cur : cur)] + boff;
   const T *up = (const T *)M.s[STG >= 3 ? role_buffer(ss.prev, cur) : cur] + boff;
   const double dx = ldexp(M.dx0, -gload(M.level + b));
@@ -108,20 +120,80 @@ __global__ __launch_bounds__(1024) void advect_kernel(const MeshDev *__restrict_
   const T dts = (T)(STG >= 3 ? ss.c * dt : (STG == 1 ? dt : 0.5 * dt));
   const T cdt = dts * idx;
   int finfo[2 * NDIM];
+  // with gathered halos, the block data of the same-level neighbour across
+  // each face (null: the face's halo comes from this block's stored ghosts)
+  const T *nbp[2 * NDIM];
 #pragma unroll
-  for (int f = 0; f < 2 * NDIM; f++) finfo[f] = gload(M.face_info + b * 2 * NDIM + f);
+  for (int f = 0; f < 2 * NDIM; f++) {
+    finfo[f] = gload(M.face_info + b * 2 * NDIM + f);
+    nbp[f] = (M.gather && finfo[f] <= -2) ? ud0 + (int64_t)(-2 - finfo[f]) * sv : nullptr;
+  }
   const T vx = (T)M.vel[0], vy = (T)M.vel[1], vz = (T)M.vel[2];
   T *lds = (T *)adv_smem;
   // halo cells of one plane: the 2g y-ghost rows (x inside) and the 2g
   // x-ghosts of the N interior rows
   const int nhalo = 4 * g * N;
   auto row_of = [&](int jj, int kk) { return (NDIM == 3) ? (kk + g) * P + (jj + g) : (jj + g); };
+  // a cell of the block or of its face halo (at most one coordinate outside
+  // 0 .. N-1): across a same-level face from the neighbour's interior when
+  // gathering, else from the stored ghosts
+  auto cell = [&](int x, int y, int kk) -> T {
+    if (x < 0) return nbp[0] ? gload(nbp[0] + row_of(y, kk) * N + x + N) : gload(ud + rows * N + row_of(y, kk) * 2 * g + x + g);
+    if (x >= N) return nbp[1] ? gload(nbp[1] + row_of(y, kk) * N + x - N) : gload(ud + rows * N + row_of(y, kk) * 2 * g + x - N + g);
+    const T *src = ud;
+    if (y < 0 && nbp[2]) { src = nbp[2]; y += N; }
+    else if (y >= N && nbp[3]) { src = nbp[3]; y -= N; }
+    if constexpr (NDIM == 3) {
+      if (kk < 0 && nbp[4]) { src = nbp[4]; kk += N; }
+      else if (kk >= N && nbp[5]) { src = nbp[5]; kk -= N; }
+    }
+    return gload(src + row_of(y, kk) * N + x);
+  };
+  // this thread's halo cells of a plane (the same (x, y) in every plane):
+  // at most 4 g N / N^2 <= 2 of them, since N >= 2 g
+  constexpr int HMAX = 2;
+  int hx[HMAX], hy[HMAX];
+  bool hv[HMAX];
+#pragma unroll
+  for (int q = 0; q < HMAX; q++) {
+    const int h = t + q * N * N;
+    hv[q] = h < nhalo;
+    if (h < 2 * g * N) {  // y ghost rows: y = -g .. -1, N .. N + g - 1
+      const int r = h / N;
+      hx[q] = h % N;
+      hy[q] = r < g ? r - g : N + r - g;
+    } else {              // x ghosts of rows 0 .. N-1, c = 0 .. 2g-1
+      const int e = h - 2 * g * N, cc = e % (2 * g);
+      hy[q] = e / (2 * g);
+      hx[q] = cc < g ? cc - g : N + cc - g;
+    }
+  }
+  // Loads run one plane ahead of use: the next plane's window cell, halo
+  // cells and earlier-state cells are in flight while the current plane is
+  // computed.
+  const T *up2 = (const T *)M.s[STG == 4 ? role_buffer(ss.prev2, cur) : cur] + boff;
+  const T *up3 = (const T *)M.s[STG == 4 ? role_buffer(ss.prev3, cur) : cur] + boff;
+  T hval[HMAX], pv = T(0), pv2 = T(0), pv3 = T(0), wnext;
+  auto fetch = [&](int kk) {  // the values plane kk needs beyond the window
+#pragma unroll
+    for (int q = 0; q < HMAX; q++)
+      if (hv[q]) hval[q] = cell(hx[q], hy[q], kk);
+    const int64_t o = row_of(j, kk) * N + i;
+    if constexpr (STG >= 2) pv = gload(up + o);
+    if constexpr (STG == 4) {
+      pv2 = gload(up2 + o);
+      pv3 = gload(up3 + o);
+    }
+    if constexpr (NDIM == 3) wnext = cell(i, j, kk + R);
+    else wnext = gload(ud + o);
+  };
   // the z window of column (i, j): cells k - R + 1 .. k + R (3-D)
   T w[2 * R];
   if constexpr (NDIM == 3) {
 #pragma unroll
-    for (int s = 1; s < 2 * R; s++) w[s] = gload(ud + row_of(j, s - R) * N + i);
+    for (int s = 1; s < 2 * R; s++) w[s] = cell(i, j, s - R);
   }
+  fetch(0);
   T Fz = T(0);  // flux through the lower z face of the current plane
   const int nk = (NDIM == 3) ? N : 1;
   for (int k = 0; k < nk; k++) {
@@ -130,23 +202,17 @@ __global__ __launch_bounds__(1024) void advect_kernel(const MeshDev *__restrict_
     if constexpr (NDIM == 3) {
 #pragma unroll
       for (int s = 0; s < 2 * R - 1; s++) w[s] = w[s + 1];
-      w[2 * R - 1] = gload(ud + row_of(j, k + R) * N + i);
+      w[2 * R - 1] = wnext;
       c = w[R - 1];
     } else {
-      c = gload(ud + row_of(j, 0) * N + i);
+      c = wnext;
     }
     pl[(j + g) * Q + i + g] = c;
-    for (int h = t; h < nhalo; h += N * N) {
-      if (h < 2 * g * N) {  // y ghost rows: y = -g .. -1, N .. N + g - 1
-        const int x = h % N, r = h / N;
-        const int y = r < g ? r - g : N + r - g;
-        pl[(y + g) * Q + x + g] = gload(ud + row_of(y, k) * N + x);
-      } else {              // x ghosts of rows 0 .. N-1, c = 0 .. 2g-1
-        const int e = h - 2 * g * N, cc = e % (2 * g), y = e / (2 * g);
-        const int x = cc < g ? cc - g : N + cc - g;
-        pl[(y + g) * Q + x + g] = gload(ud + rows * N + row_of(y, k) * 2 * g + cc);
-      }
-    }
+#pragma unroll
+    for (int q = 0; q < HMAX; q++)
+      if (hv[q]) pl[(hy[q] + g) * Q + hx[q] + g] = hval[q];
+    const T cp = pv, cp2 = pv2, cp3 = pv3;
+    if (k + 1 < nk) fetch(k + 1);
     __syncthreads();
     // x faces i - 1/2 and i + 1/2, then y faces, from the staged plane
     T sx[2 * R + 1], sy[2 * R + 1];
@@ -166,7 +232,7 @@ __global__ __launch_bounds__(1024) void advect_kernel(const MeshDev *__restrict_
     if constexpr (NDIM == 3) {
       if (k == 0) {  // the block's lower z face, from cells -R .. R-1
         T w0[2 * R];
-        w0[0] = gload(ud + row_of(j, -R) * N + i);
+        w0[0] = cell(i, j, -R);
 #pragma unroll
         for (int s = 1; s < 2 * R; s++) w0[s] = w[s - 1];
         Fz = adv_flux<T, LIM, HLL>(w0, vz);
@@ -180,13 +246,9 @@ __global__ __launch_bounds__(1024) void advect_kernel(const MeshDev *__restrict_
     const int64_t o = row_of(j, k) * N + i;
     T base;
     if constexpr (STG == 1) base = c;
-    else if constexpr (STG == 2) base = T(0.5) * (gload(up + o) + c);
-    else if constexpr (STG == 3) base = (T)ss.wp * gload(up + o) + (T)ss.wd * c;
-    else {
-      const T *up2 = (const T *)M.s[role_buffer(ss.prev2, cur)] + boff;
-      const T *up3 = (const T *)M.s[role_buffer(ss.prev3, cur)] + boff;
-      base = (((T)ss.wp * gload(up + o) + (T)ss.wp2 * gload(up2 + o)) + (T)ss.wp3 * gload(up3 + o)) + (T)ss.wd * c;
-    }
+    else if constexpr (STG == 2) base = T(0.5) * (cp + c);
+    else if constexpr (STG == 3) base = (T)ss.wp * cp + (T)ss.wd * c;
+    else base = (((T)ss.wp * cp + (T)ss.wp2 * cp2) + (T)ss.wp3 * cp3) + (T)ss.wd * c;
     const T out = base - cdt * div;
     gstore(uo + o, out);
     if (STG == 2 || (STG >= 3 && ss.epi)) {
@@ -208,12 +270,23 @@ template <typename T, int NDIM, int LIM, bool HLL>
 static void launch_adv(unsigned nb, int N, int g, const MeshDev *d, int stage, const SubStep &ss, hipStream_t s) {
   const unsigned threads = (unsigned)(N * N);
   const size_t lds = (size_t)adv_lds(N, g) * sizeof(T);
-  switch (stage) {
-    case 1: advect_kernel<T, NDIM, LIM, HLL, 1><<<nb, threads, lds, s>>>(d, ss); break;
-    case 2: advect_kernel<T, NDIM, LIM, HLL, 2><<<nb, threads, lds, s>>>(d, ss); break;
-    case 3: advect_kernel<T, NDIM, LIM, HLL, 3><<<nb, threads, lds, s>>>(d, ss); break;
-    default: advect_kernel<T, NDIM, LIM, HLL, 4><<<nb, threads, lds, s>>>(d, ss); break;
+#define F4_ADV(STG, MAXT) advect_kernel<T, NDIM, LIM, HLL, STG, MAXT><<<nb, threads, lds, s>>>(d, ss)
+  if (threads > 256) {
+    switch (stage) {
+      case 1: F4_ADV(1, 1024); break;
+      case 2: F4_ADV(2, 1024); break;
+      case 3: F4_ADV(3, 1024); break;
+      default: F4_ADV(4, 1024); break;
+    }
+  } else {
+    switch (stage) {
+      case 1: F4_ADV(1, 256); break;
+      case 2: F4_ADV(2, 256); break;
+      case 3: F4_ADV(3, 256); break;
+      default: F4_ADV(4, 256); break;
+    }
   }
+#undef F4_ADV
 }
 
 template <typename T, int NDIM>

@@ -68,8 +68,10 @@ MeshDev make_dev(const foap4_mesh *m, int ks, int gather) {
   d.ks = std::max(1, std::min(ks, m->d.block_n / 8));
   d.gather = gather;
   // with gathered halos the SRL ghosts are needed only as input of the C2F
-  // prolongation stencils, i.e. on meshes with refinement boundaries
-  d.r1_srl = (gather && m->pat.n[kC2F] == 0) ? 0 : m->pat.n[kSRL];
+  // prolongation stencils: the SRL records with a side that is the coarse
+  // block of a C2F record
+  d.r1_srl = gather ? m->pat.n_srl_c2f : m->pat.n[kSRL];
+  d.srl_sub = gather ? m->pat.srl_c2f : nullptr;
   return d;
 }
 
@@ -267,7 +269,7 @@ foap4_status foap4_mesh_destroy(foap4_mesh *m) {
   if (m->stream) (void)hipStreamSynchronize(m->stream);
   void *ptrs[] = {m->d_level, m->d_gc, m->d_keys, m->d_scal, m->d_dev, m->d_item_begin,
                   m->pat.srl, m->pat.f2c, m->pat.c2f, m->pat.bc, m->pat.face_info, m->pat.fix_list,
-                  m->pat.cnt, m->pat.tot, m->pat.bflux_f, m->pat.bflux_c, m->d_ind, m->d_featcap};
+                  m->pat.cnt, m->pat.tot, m->pat.bflux_f, m->pat.bflux_c, m->pat.srl_c2f, m->d_ind, m->d_featcap};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -716,7 +718,7 @@ static foap4_status batch_upload(foap4_batch *b) {
   std::vector<MeshDev> devs;
   int64_t it = 0, r1 = 0, r2 = 0;
   for (foap4_mesh *m : b->meshes) {
-    MeshDev d = make_dev(m, b->ks, (b->weno || b->adv) ? 0 : b->gather);
+    MeshDev d = make_dev(m, b->ks, b->weno ? 0 : b->gather);
     d.item_begin = it;
     d.r1_begin = r1;
     d.r2_begin = r2;
@@ -998,7 +1000,8 @@ static std::string batch_key(const foap4_batch *b) {
   for (char *c = arch; *c; c++)
     if (*c == ':' || *c == '"') *c = '_';
   std::ostringstream k;
-  k << arch << "|" << (b->f64 ? "f64" : "f32") << "|" << b->ndim << "d|meshes" << b->meshes.size();
+  k << arch << "|" << (b->f64 ? "f64" : "f32") << "|" << b->ndim << "d|scheme" << b->scheme << "|meshes"
+    << b->meshes.size();
   for (auto &kv : mix) {
     // block counts rounded to two significant digits so that nearby sizes share an entry
     const double share = (double)kv.second / (double)std::max<int64_t>(total, 1);
@@ -1066,7 +1069,14 @@ foap4_status foap4_batch_autotune(foap4_batch *b, const char *cache_path, int32_
       for (int i = 0; i < 4; i++) cfg_out[i] = cached[i];
     return st;
   }
-  // save the current states and scalars; restored after timing
+  // save the current states and scalars; restored after timing.  The time
+  // step of every mesh is computed first, so that the saved scalars hold a
+  // valid dt (restoring the scalars of a mesh whose dt is still pending would
+  // leave dt = 0 behind a mesh that counts its dt as computed)
+  {
+    foap4_status st = batch_prepare(b);
+    if (st != FOAP4_OK) return st;
+  }
   std::vector<void *> saved;
   std::vector<std::array<double, kNScal>> scal(b->meshes.size());
   for (size_t i = 0; i < b->meshes.size(); i++) {

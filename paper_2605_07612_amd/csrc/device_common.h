@@ -41,16 +41,15 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return fma(r, e, r);
 }
 
-// sqrt(r) and 1/r of a positive density from one reciprocal square root
-// (FP32), or IEEE square root and the refined reciprocal (FP64).
-__device__ __forceinline__ void sqrt_and_rcp(float r, float &s, float &ir) {
-  const float q = __builtin_amdgcn_rsqf(r);
+// sqrt(r) and 1/sqrt(r) of a positive density: one reciprocal square root
+// (FP32), or IEEE square root and the refined reciprocal of it (FP64).
+__device__ __forceinline__ void sqrt_and_rsq(float r, float &s, float &q) {
+  q = __builtin_amdgcn_rsqf(r);
   s = r * q;
-  ir = q * q;
 }
-__device__ __forceinline__ void sqrt_and_rcp(double r, double &s, double &ir) {
+__device__ __forceinline__ void sqrt_and_rsq(double r, double &s, double &q) {
   s = sqrt(r);
-  ir = rcp_nr(r);
+  q = rcp_nr(s);
 }
 
 // Reciprocal and square root: the hardware approximations (about 1 ulp) for
@@ -99,7 +98,7 @@ __device__ __forceinline__ T limit(T a, T b) {
 // states WL and WR from the Einfeldt speeds (Sec. 3.5): sqrt(rho)-weighted
 // mean velocity u_bar and
 // d_bar^2 = (sL cL^2 + sR cR^2)/(sL + sR) + sL sR/(2 (sL+sR)^2) (vR - vL)^2.
-// Rusanov (HLL false): a = max(|u_bar - d_bar|, |u_bar + d_bar|),
+// Rusanov (HLL false): a = max(|u_bar - d_bar|, |u_bar + d_bar|) = |u_bar| + d_bar,
 //   F = (FL+FR)/2 - a (UR-UL)/2.
 // HLL: with s0 = min(u_bar - d_bar, 0), s1 = max(u_bar + d_bar, 0),
 //   F = (s1 FL - s0 FR + s0 s1 (UR - UL)) / (s1 - s0), which is FL when every
@@ -113,21 +112,26 @@ __device__ __forceinline__ void riemann(const T *WL, const T *WR, T gamma, T *F)
   const T rl = WL[0], rr = WR[0];
   const T pl = WL[NV - 1], pr = WR[NV - 1];
   const T vl = WL[1 + AX], vr = WR[1 + AX];
-  // wave speeds first, so the per-component flux needs few live registers
-  T sl, sr, irl, irr;
-  sqrt_and_rcp(rl, sl, irl);
-  sqrt_and_rcp(rr, sr, irr);
+  // wave speeds first, so the per-component flux needs few live registers;
+  // with the weights w = sqrt(rho) / (sL + sR) of each side,
+  // u_bar = wL vL + wR vR and d_bar^2 = gamma (pL / sL + pR / sR) / (sL + sR)
+  // + wL wR dv^2 / 2 (s c^2 = gamma p / s = gamma p / sqrt(rho))
+  T sl, sr, ql, qr;  // sqrt(rho) and 1 / sqrt(rho) of each side
+  sqrt_and_rsq(rl, sl, ql);
+  sqrt_and_rsq(rr, sr, qr);
   const T is = frcp(sl + sr);
-  const T cl2 = gamma * pl * irl, cr2 = gamma * pr * irr;
-  const T ubar = (sl * vl + sr * vr) * is;
-  const T eta2 = T(0.5) * sl * sr * is * is;
+  const T wlw = sl * is, wrw = sr * is;
+  const T ubar = wlw * vl + wrw * vr;
   const T dv = vr - vl;
-  const T d2 = (sl * cl2 + sr * cr2) * is + eta2 * dv * dv;
+  const T d2 = gamma * (pl * ql + pr * qr) * is + (T(0.5) * wlw * wrw) * (dv * dv);
   const T db = fsqrt(d2);
   T al, ar, wl, wr;
   if constexpr (!HLL) {
-    const T lm = fabs(ubar - db), lp = fabs(ubar + db);
-    const T ha = T(0.5) * (lm > lp ? lm : lp);
+    // max(|u_bar - d_bar|, |u_bar + d_bar|) with d_bar >= 0 is |u_bar| + d_bar,
+    // bit for bit: the rounding of u_bar - d_bar and u_bar + d_bar is
+    // symmetric in the sign of u_bar, so the larger magnitude is the
+    // rounded |u_bar| + d_bar
+    const T ha = T(0.5) * (fabs(ubar) + db);
     // (F_L + F_R)/2 - ha (U_R - U_L) with F = U v_n + pressure terms:
     // al = vl/2 + ha, ar = vr/2 - ha, both pressure weights 1/2
     al = T(0.5) * vl + ha;

@@ -125,8 +125,11 @@ struct MeshDev {
   int32_t cur;                // current state buffer
   int32_t N, g, ks;           // block size, ghost layers, k-slabs per tile
   int32_t gather;             // stage reads same-level halos from the neighbours
-  int32_t r1_srl;             // SRL records executed in round R1 (0 or pn[kSRL]);
-                              // R1 then runs pn[kF2C] restrictions and pn[kBC] boundary faces
+  int32_t r1_srl;             // SRL records executed in round R1: all pn[kSRL] with stored
+                              // ghosts, with gathered halos only those C2F prolongation
+                              // reads (indices in srl_sub); R1 then runs pn[kF2C]
+                              // restrictions and pn[kBC] boundary faces
+  const int32_t *srl_sub;     // with gathered halos: the SRL records R1 runs, else null
 };
 
 struct Pattern {
@@ -140,6 +143,9 @@ struct Pattern {
   void *bflux_f = nullptr, *bflux_c = nullptr;
   size_t cap[8] = {};           // capacities in bytes of the buffers above
   size_t cap_bflux[2] = {};
+  int32_t *srl_c2f = nullptr;   // SRL record indices whose ghosts C2F prolongation reads
+  int32_t n_srl_c2f = 0;
+  size_t cap_srl_c2f = 0;
 };
 
 }  // namespace f4

@@ -86,6 +86,59 @@ __device__ void srl_record(const MeshDev &M, T *u, int32_t a, int32_t b) {
   }
 }
 
+// x faces with two ghost layers: a row's two ghost layers are one aligned
+// pair of values on both sides of the copy (the last or first two interior
+// cells of the source row, the two x-ghost slots of the destination row), so
+// each thread moves pairs with one vector load and one vector store.  Every
+// offset is even (N, P, the variable and block strides are even), and state
+// buffers are 16-byte aligned.
+template <typename T>
+struct Pair {
+  typedef T type __attribute__((ext_vector_type(2)));
+};
+
+template <typename T, int NDIM, int NV, int N>
+__device__ void srl_record_x2(const MeshDev &M, T *u, int32_t a, int32_t b) {
+  using PT = typename Pair<T>::type;
+  constexpr int N2 = (NDIM == 3) ? N : 1;
+  constexpr int P = N + 4;
+  constexpr int64_t SV = (NDIM == 3) ? (int64_t)P * P * P : (int64_t)P * P;
+  constexpr int ROWS = (NDIM == 3) ? P * P : P;
+  constexpr int64_t BEL = SV * NV;
+  constexpr int total = 2 * NV * N2 * N;
+  constexpr int B = 4;  // pairs in flight per thread (8 values): loads first, then stores
+  for (int e0 = threadIdx.x; e0 < total; e0 += B * blockDim.x) {
+    PT val[B];
+    int64_t dsto[B];
+#pragma unroll
+    for (int q = 0; q < B; q++) {
+      const int e = e0 + q * blockDim.x;
+      dsto[q] = -1;
+      if (e >= total) continue;
+      int r = e;
+      const int p1 = r % N;  // y: consecutive threads take consecutive rows
+      r /= N;
+      const int p2 = r % N2;
+      r /= N2;
+      const int v = r % NV, side = r / NV;
+      const int row = (NDIM == 3) ? (p2 + 2) * P + (p1 + 2) : (p1 + 2);
+      int64_t src, dst;
+      if (side == 0) {  // b's -x ghosts (slots 0, 1) from a's last two cells
+        src = a * BEL + v * SV + row * N + (N - 2);
+        dst = b * BEL + v * SV + ROWS * N + row * 4;
+      } else {          // a's +x ghosts (slots 2, 3) from b's first two cells
+        src = b * BEL + v * SV + row * N;
+        dst = a * BEL + v * SV + ROWS * N + row * 4 + 2;
+      }
+      val[q] = *(const PT *)(u + src);
+      dsto[q] = dst;
+    }
+#pragma unroll
+    for (int q = 0; q < B; q++)
+      if (dsto[q] >= 0) *(PT *)(u + dsto[q]) = val[q];
+  }
+}
+
 // mean of the 2^d fine cells base + {0,1}^d of block q, summed in pairs
 // along x, then y, then z, in FP64
 template <typename T, int NDIM>
@@ -154,6 +207,9 @@ __device__ void f2c_record(const MeshDev &M, T *u, int side, int32_t cb, int32_t
 // summed in order x, y, z
 template <typename T, int NDIM>
 __device__ __forceinline__ double prolong(const T *uc, const Geo<NDIM> &G, const int P[3], const int sig[3]) {
+  // no contraction: u_P + corr / 4 rounded twice as written, which also
+  // holds when corr / 4 is subnormal (where a fused multiply-add would differ)
+#pragma clang fp contract(off)
   const double up = uc[G.at(P)];
   double corr = 0.0;
 #pragma unroll
@@ -212,8 +268,10 @@ __device__ void c2f_record(const MeshDev &M, T *u, int side, int32_t q, int32_t 
 // u_in + (2L - 1) dx u'_b (Neumann, outward derivative u'_b); FP64 without
 // contraction, rounded once.  u_b / u'_b come from the per-face-cell array
 // bc_data (record rec, variable, face cell p1 + N p2) when it is set, else
-// from the uniform per-face values.  As in the SRL copy, each thread keeps B
-// elements in flight (loads first, then stores).
+// from the uniform per-face values.  Each thread keeps B elements in flight
+// (loads first, then stores); only the loaded values and the element indices
+// stay live between the two passes (the cell coordinates are decoded again),
+// which keeps this routine from setting the ghost kernel's register count.
 template <typename T, int NDIM, int NV, int N, int ax>
 __device__ void bc_record(const MeshDev &M, T *u, int side, int64_t rec, int32_t b) {
 #pragma clang fp contract(off)
@@ -224,49 +282,53 @@ __device__ void bc_record(const MeshDev &M, T *u, int side, int64_t rec, int32_t
   T *ub = u + (int64_t)b * G.sv * NV;
   const double dx = ldexp(M.dx0, -M.level[b]);
   const int total = NV * N2 * N * g;
-  constexpr int B = 8;
+  // element e -> layer l, face cell (p1, p2), variable v (the SRL copy's orders)
+  auto decode = [&](int e, int &l, int &p1, int &p2, int &v) {
+    int r = e;
+    if (ax == 0) {
+      l = r % g; r /= g;
+      p1 = r % N; r /= N;
+      p2 = r % N2; r /= N2;
+    } else if (ax == 1) {
+      p1 = r % N; r /= N;
+      l = r % g; r /= g;
+      p2 = r % N2; r /= N2;
+    } else {
+      p1 = r % N; r /= N;
+      p2 = r % N2; r /= N2;
+      l = r % g; r /= g;
+    }
+    v = r;
+  };
+  constexpr int B = 4;
   for (int e0 = threadIdx.x; e0 < total; e0 += B * blockDim.x) {
     double uin[B];
-    int dsto[B], vq[B], Lq[B], cq[B];
 #pragma unroll
     for (int q = 0; q < B; q++) {
       const int e = e0 + q * blockDim.x;
-      dsto[q] = -1;
       if (e >= total) continue;
-      int l, p1, p2, v, r = e;
-      if (ax == 0) {         // the same element orders as the SRL copy
-        l = r % g; r /= g;
-        p1 = r % N; r /= N;
-        p2 = r % N2; r /= N2;
-      } else if (ax == 1) {
-        p1 = r % N; r /= N;
-        l = r % g; r /= g;
-        p2 = r % N2; r /= N2;
-      } else {
-        p1 = r % N; r /= N;
-        p2 = r % N2; r /= N2;
-        l = r % g; r /= g;
-      }
-      v = r;
-      const int L = l + 1;
-      int gc[3] = {0, 0, 0}, ic[3] = {0, 0, 0};
-      gc[ax] = side ? N - 1 + L : -L;
-      ic[ax] = side ? N - L : L - 1;
-      gc[t1] = ic[t1] = p1;
-      if constexpr (t2 >= 0) gc[t2] = ic[t2] = p2;
+      int l, p1, p2, v;
+      decode(e, l, p1, p2, v);
+      int ic[3] = {0, 0, 0};
+      ic[ax] = side ? N - 1 - l : l;
+      ic[t1] = p1;
+      if constexpr (t2 >= 0) ic[t2] = p2;
       uin[q] = (double)ub[v * G.sv + G.at(ic)];
-      dsto[q] = (int)(v * G.sv + G.at(gc));
-      vq[q] = v;
-      Lq[q] = L;
-      cq[q] = p1 + N * p2;
     }
 #pragma unroll
     for (int q = 0; q < B; q++) {
-      if (dsto[q] < 0) continue;
-      const double val = M.bc_data ? M.bc_data[(rec * NV + vq[q]) * (N * N2) + cq[q]] : M.bc_val[f][vq[q]];
-      const double out = (M.bc_type[f][vq[q]] == 0) ? 2.0 * val - uin[q]
-                                                    : uin[q] + ((double)(2 * Lq[q] - 1) * dx) * val;
-      ub[dsto[q]] = (T)out;
+      const int e = e0 + q * blockDim.x;
+      if (e >= total) continue;
+      int l, p1, p2, v;
+      decode(e, l, p1, p2, v);
+      const int L = l + 1;
+      int gc[3] = {0, 0, 0};
+      gc[ax] = side ? N - 1 + L : -L;
+      gc[t1] = p1;
+      if constexpr (t2 >= 0) gc[t2] = p2;
+      const double val = M.bc_data ? M.bc_data[(rec * NV + v) * (N * N2) + p1 + N * p2] : M.bc_val[f][v];
+      const double out = (M.bc_type[f][v] == 0) ? 2.0 * val - uin[q] : uin[q] + ((double)(2 * L - 1) * dx) * val;
+      ub[v * G.sv + G.at(gc)] = (T)out;
     }
   }
 }
@@ -283,9 +345,16 @@ __device__ void ghost_item(const MeshDev &M, int round, int64_t r, int which) {
   }
   if (round == 1) {
     if (r < M.r1_srl) {
+      if (M.srl_sub) r = M.srl_sub[r];
       int f = 1;
       while (r >= M.poff[kSRL][f + 1]) f += 2;
-#define F4_SRL(A) srl_record<T, NDIM, NV, N, A>(M, u, M.srl[2 * r], M.srl[2 * r + 1])
+#define F4_SRL(A)                                                      \
+  do {                                                                 \
+    if ((A) == 0 && M.g == 2)                                          \
+      srl_record_x2<T, NDIM, NV, N>(M, u, M.srl[2 * r], M.srl[2 * r + 1]); \
+    else                                                               \
+      srl_record<T, NDIM, NV, N, A>(M, u, M.srl[2 * r], M.srl[2 * r + 1]); \
+  } while (0)
       F4_BY_AXIS(F4_SRL)
 #undef F4_SRL
     } else if (r < M.r1_srl + M.pn[kF2C]) {
@@ -316,7 +385,15 @@ __device__ void ghost_item(const MeshDev &M, int round, int64_t r, int which) {
 template <typename T, int NDIM, int NV>
 __global__ __launch_bounds__(256) void ghost_kernel(const MeshDev *__restrict__ meshes, int n_meshes,
                                                     int64_t total, int round, int which) {
-  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+  // one workgroup per record (grid = total): XCD-aware record order, as
+  // workgroup w runs on XCD w mod 8; XCD x takes the contiguous range of
+  // records [x q + min(x, r), ...) (total = 8 q + r), so consecutive records,
+  // which touch the same blocks (the +x copies of (a, b) and (b, c) both read
+  // rows of b), share that XCD's L2.  A bijection onto 0 .. total-1.
+  const bool one_each = (int64_t)gridDim.x == total;
+  const int64_t xq = total / 8, xr = total % 8, xid = blockIdx.x % 8;
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const int64_t item = one_each ? xid * xq + (xid < xr ? xid : xr) + w / 8 : w;
     int lo = 0, hi = n_meshes - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;

@@ -216,6 +216,27 @@ __global__ void scatter_kernel(ScatterArgs A) {
   }
 }
 
+// SRL records whose ghosts a coarse-to-fine prolongation reads: those with a
+// side that is the coarse block of some C2F record (its stencils reach into
+// the ghosts of that block's other faces).  Meshes that read same-level halos
+// straight from the neighbours run only these in round R1.
+__global__ void mark_c2f_coarse_kernel(const int32_t *c2f, int64_t n_c2f, int8_t *coarse) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n_c2f) coarse[c2f[3 * r + 1]] = 1;
+}
+
+__global__ void srl_need_kernel(const int32_t *srl, int64_t n_srl, const int8_t *coarse, int32_t *need) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n_srl) need[r] = (coarse[srl[2 * r]] | coarse[srl[2 * r + 1]]) ? 1 : 0;
+}
+
+// need[] holds the exclusive prefix sums of the flags (recomputed here)
+__global__ void srl_compact_kernel(const int32_t *srl, int64_t n_srl, const int8_t *coarse, const int32_t *pos,
+                                   int32_t *sub) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n_srl && (coarse[srl[2 * r]] | coarse[srl[2 * r + 1]])) sub[pos[r]] = (int32_t)r;
+}
+
 static foap4_status ensure(foap4_mesh *m, void **p, size_t &cap, size_t bytes) {
   if (bytes == 0) bytes = 16;
   if (cap >= bytes) return FOAP4_OK;
@@ -239,7 +260,8 @@ foap4_status build_pattern(foap4_mesh *m) {
   const size_t nbf = (size_t)nb * nf;
   const size_t ws_bytes = nbf * (1 + 16 + 1) + 64;
   if ((st = ensure(m, (void **)&P.cnt, P.cap[0], (size_t)rows * nb * 4 + ws_bytes)) != FOAP4_OK) return st;
-  if ((st = ensure(m, (void **)&P.tot, P.cap[1], (size_t)(rows + 1) * 4)) != FOAP4_OK) return st;
+  // row totals, the balance error flag, the count of SRL records C2F needs
+  if ((st = ensure(m, (void **)&P.tot, P.cap[1], (size_t)(rows + 2) * 4)) != FOAP4_OK) return st;
   int32_t *cnt = P.cnt;
   int32_t *nbr = cnt + (size_t)rows * nb;
   int8_t *kind = (int8_t *)(nbr + nbf * 4);
@@ -294,6 +316,26 @@ foap4_status build_pattern(foap4_mesh *m) {
   A.fix_list = P.fix_list;
   scatter_kernel<<<g1, 256, 0, s>>>(A);
   F4_HIP(m, hipGetLastError());
+  // the SRL records that C2F prolongation depends on (ordered by record);
+  // the classification workspace is free again and holds the flags and sums
+  P.n_srl_c2f = 0;
+  if (P.n[kC2F] > 0 && P.n[kSRL] > 0) {
+    int8_t *coarse = (int8_t *)(cnt + 3 * (size_t)nb + 64);
+    int32_t *pos = cnt;  // n[kSRL] <= 3 nb entries
+    F4_HIP(m, hipMemsetAsync(coarse, 0, (size_t)nb, s));
+    mark_c2f_coarse_kernel<<<(unsigned)((P.n[kC2F] + 255) / 256), 256, 0, s>>>(P.c2f, P.n[kC2F], coarse);
+    srl_need_kernel<<<(unsigned)((P.n[kSRL] + 255) / 256), 256, 0, s>>>(P.srl, P.n[kSRL], coarse, pos);
+    scan_rows_kernel<<<1, 1024, 0, s>>>(pos, P.n[kSRL], P.tot + rows + 1);
+    F4_HIP(m, hipGetLastError());
+    int32_t n_sub = 0;
+    F4_HIP(m, hipMemcpyAsync(&n_sub, P.tot + rows + 1, 4, hipMemcpyDeviceToHost, s));
+    F4_HIP(m, hipStreamSynchronize(s));
+    if ((st = ensure(m, (void **)&P.srl_c2f, P.cap_srl_c2f, (size_t)n_sub * 4)) != FOAP4_OK) return st;
+    srl_compact_kernel<<<(unsigned)((P.n[kSRL] + 255) / 256), 256, 0, s>>>(P.srl, P.n[kSRL], coarse, pos,
+                                                                            P.srl_c2f);
+    F4_HIP(m, hipGetLastError());
+    P.n_srl_c2f = n_sub;
+  }
   m->pat_valid = true;
   return FOAP4_OK;
 }

@@ -47,6 +47,9 @@ __global__ __launch_bounds__(256) void lohner_kernel(const MeshDev *__restrict__
 template <typename T, int NDIM, int NV>
 __global__ __launch_bounds__(256) void remap_kernel(const T *__restrict__ uold, T *unew, const int32_t *map, int N,
                                                     int g) {
+  // FP64 in the operation order of the definitions, no contraction (the
+  // prolonged value u_P + corr / 4 stays bit-exact when corr / 4 is subnormal)
+#pragma clang fp contract(off)
   const int64_t n = blockIdx.x;
   const int P = N + 2 * g, H = N / 2;
   const int64_t sv = (NDIM == 3) ? (int64_t)P * P * P : (int64_t)P * P;
