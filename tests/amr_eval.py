@@ -31,7 +31,9 @@ def restrict_to_level(mesh_levels, mesh_G, interior, N, trees, level):
 def oracle_adaptive_run(w, steps, regrid_every, log=None):
     """The adaptive run of workload w in the FP64 oracle with the paper's
     criterion: geometric initial refinement, then `steps` steps with a
-    regrid after every `regrid_every` steps.  Returns the oracle mesh."""
+    regrid after every `regrid_every` steps.  log(steps_done, oracle_mesh),
+    if given, is called after each regrid and at the end.  Returns the
+    oracle mesh."""
     from oracle import OracleMesh
     om = OracleMesh(w["ndim"], w["trees"], w["N"], w["g"], w["tree_size"], level=w.get("level", 0),
                     gamma=w["gamma"], cfl=w["cfl"])
@@ -52,5 +54,5 @@ def oracle_adaptive_run(w, steps, regrid_every, log=None):
             om.ghost_fill()
             om.regrid(om.lohner_flags(), 0, lmax)
         if log:
-            log(done, om.nb)
+            log(done, om)
     return om

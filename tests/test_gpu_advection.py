@@ -233,7 +233,10 @@ def test_physical_boundaries_and_regrid(f4):
 @pytest.mark.parametrize("prec", [1, 0], ids=["f64", "f32"])
 def test_batched_equals_plain(f4, prec):
     """Three advection meshes of different block sizes and levels in one
-    batch (graph-captured steps) against the same meshes stepped alone."""
+    batch (graph-captured steps, same-level halos gathered from the
+    neighbours) against the same meshes stepped alone (stored ghosts): the
+    interiors and times agree bit for bit (the batch leaves same-level ghost
+    cells unfilled)."""
     vel = (0.9, -0.4, 0.6)
 
     def make(k):
@@ -249,7 +252,7 @@ def test_batched_equals_plain(f4, prec):
     for k, gm in enumerate(meshes):
         ref = make(k)
         ref.step(6)
-        assert np.array_equal(gpu_state(ref), batched[k]), k
+        assert np.array_equal(interior(gpu_state(ref), ref.g, ref.N, 3), interior(batched[k], ref.g, ref.N, 3)), k
         assert ref.time() == gm.time()
         ref.close()
         gm.close()

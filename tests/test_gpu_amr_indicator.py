@@ -5,8 +5,8 @@ Reduced adaptive blast (2^3 trees of 8^3 cells, levels 0..3, regrid every
 seconds on the host:
 
 * FP64 GPU run with the paper's criterion against the oracle's run: the same
-  mesh after every regrid (bit-exact refinement maps) and the state within
-  1e-12 relative L1.
+  leaf table (level, tree, anchor of every block) after every regrid
+  (bit-exact refinement maps) and the state within 1e-12 relative L1.
 * The learned indicator is trained on the GPU from runs with perturbed blast
   centres and p_in in {30, 300} (never the evaluated run), then drives an FP32
   run; on identical states its flags are compared with the criterion's
@@ -16,8 +16,13 @@ seconds on the host:
   written as adaptive_blast_indicator.json into the folder that
   FOAP4_REPORT_DIR names, if it is set.
 
-FOAP4_FULL_ADAPTIVE=1 adds the full-size run (4^3 trees, levels 0..3, 400
-steps; GPU only, compared with an FP64 GPU run)."""
+The full-size run (4^3 trees of 16^3 cells, levels 0..3, regrid every 10
+steps, 400 steps) is too long for the oracle to step through; there the
+FP64 GPU run is checked at every regrid against the oracle's criterion and
+regrid on the same state (flags, leaf table and remapped data bit for bit),
+and the learned indicators are measured against it: missed refinements at
+most 5 %, and the captured-feature indicator cheaper per regrid than the
+criterion."""
 import json
 import os
 import sys
@@ -146,16 +151,22 @@ def test_adaptive_blast_indicators(f4):
     # FP64 GPU run with the paper's criterion vs the oracle's adaptive run
     from paper_2605_07612_amd import amr
     m64 = make(f4, w, f4.F64)
-    meshes_gpu = []
+    meshes_gpu = []  # leaf tables before every regrid, then the final one
     amr.advance(m64, w["steps"], w["regrid_every"],
-                before_regrid=lambda mesh, flags: meshes_gpu.append(mesh.export()[0].copy()))
-    meshes_gpu.append(m64.export()[0].copy())
+                before_regrid=lambda mesh, flags: meshes_gpu.append(tuple(x.copy() for x in mesh.export())))
+    meshes_gpu.append(tuple(x.copy() for x in m64.export()))
     t0 = time.perf_counter()
-    meshes_or = []
-    om = oracle_adaptive_run(w, w["steps"], w["regrid_every"], log=lambda s, nb: meshes_or.append(None))
+    meshes_or = []  # leaf tables after every regrid and at the end
+    om = oracle_adaptive_run(w, w["steps"], w["regrid_every"],
+                             log=lambda s, o: meshes_or.append(tuple(x.copy() for x in o.forest.export())))
     oracle_s = time.perf_counter() - t0
     say("oracle run", round(oracle_s, 1), "s, blocks", om.nb)
-    assert m64.export()[0].tolist() == om.level.tolist()
+    # the GPU's table before regrid k + 1 is the one regrid k produced; both
+    # lists end with the final mesh (no regrid after the last steps)
+    assert len(meshes_gpu) == len(meshes_or) == w["steps"] // w["regrid_every"]
+    for k, (g, o) in enumerate(zip(meshes_gpu[1:], meshes_or[:-1])):
+        assert all(np.array_equal(a, b) for a, b in zip(g, o)), f"leaf tables differ after regrid {k + 1}"
+    assert all(np.array_equal(a, b) for a, b in zip(meshes_gpu[-1], meshes_or[-1]))
     lev_or = om.level
     G_or = np.array([g for _, g in om.forest.leaves])
     ref = restrict_to_level(lev_or, G_or, om.interior(), w["N"], w["trees"], 2)
@@ -163,7 +174,7 @@ def test_adaptive_blast_indicators(f4):
     e64 = float(np.abs(g64 - ref).sum() / np.abs(ref).sum())
     say("FP64 GPU vs oracle (level 2)", e64)
     assert e64 <= 1e-12
-    changes = len(set(tuple(np.bincount(x, minlength=3)) for x in meshes_gpu))
+    changes = len(set(tuple(np.bincount(x[0], minlength=4)) for x in meshes_gpu))
     assert changes >= 2, "the mesh never changed: the workload does not exercise regrid"
 
     net, tr = train_indicator(f4, cfg)
@@ -184,21 +195,80 @@ def test_adaptive_blast_indicators(f4):
     assert l1["lohner"] <= 1e-4
 
 
-@pytest.mark.skipif(os.environ.get("FOAP4_FULL_ADAPTIVE") != "1", reason="full-size run on request only")
 def test_adaptive_blast_full_size(f4):
+    """The stated adaptive blast: 4^3 trees of 16^3 cells, levels 0..3,
+    regrid every 10 steps, 400 steps."""
     cfg = dict(trees=4, block=16, max_level=3, steps=400, regrid_every=10)
     w = synth.adaptive_blast(**cfg)
-    from paper_2605_07612_amd import amr
+    from oracle import OracleMesh
     m64 = make(f4, w, f4.F64)
-    amr.advance(m64, w["steps"], w["regrid_every"])
+    # an oracle mesh follows the GPU run's mesh: at every regrid the GPU's
+    # FP64 state is copied in, and the oracle's own criterion, regrid and
+    # remap must reproduce the GPU's flags, leaf table and data bit for bit
+    om = OracleMesh(3, w["trees"], w["N"], w["g"], w["tree_size"], gamma=w["gamma"], cfl=w["cfl"])
+    for _ in range(w["max_level"]):
+        lev = np.array([l for l, _ in om.forest.leaves])
+        G = np.array([g for _, g in om.forest.leaves])
+        if om.regrid(w["init_flags"](lev, G), 0, w["max_level"]) is None:
+            break
+    assert all(np.array_equal(a, b) for a, b in zip(m64.export(), om.forest.export()))
+    checks = dict(regrids=0, changed=0, max_blocks=0, oracle_s=0.0)
+
+    def check(mesh, flags):
+        t0 = time.perf_counter()
+        om.u[...] = 0.0
+        om.interior()[...] = mesh.interior().double().cpu().numpy()
+        om.ghost_fill()
+        assert np.array_equal(om.lohner_flags(), flags), f"flags differ at regrid {checks['regrids'] + 1}"
+        res = om.regrid(flags, 0, w["max_level"])
+        checks["regrids"] += 1
+        checks["changed"] += res is not None
+        checks["oracle_s"] += time.perf_counter() - t0
+        pending.append(res is not None)
+
+    pending = []
+    done = 0
+    while done < w["steps"]:
+        k = min(w["regrid_every"], w["steps"] - done)
+        m64.step(k)
+        done += k
+        if done >= w["steps"]:
+            break
+        flags = m64.refine_flags()
+        check(m64, flags)
+        changed = m64.regrid(flags)
+        assert changed == pending[-1]
+        t0 = time.perf_counter()
+        assert all(np.array_equal(a, b) for a, b in zip(m64.export(), om.forest.export()))
+        if changed:
+            a = m64.interior().double().cpu().numpy()
+            bad = np.any(a != om.interior(), axis=tuple(range(1, a.ndim)))
+            if bad.any():
+                lev_new = m64.export()[0]
+                d = np.abs(a - om.interior())[bad]
+                say("regrid", checks["regrids"], "blocks with different remapped data:", int(bad.sum()), "of",
+                    len(bad), "levels", np.bincount(lev_new[bad], minlength=4).tolist(), "max |diff|",
+                    float(d.max()), "relative", float(d.max() / np.abs(om.interior()).max()))
+            assert not bad.any(), "remapped data differ"
+        checks["oracle_s"] += time.perf_counter() - t0
+        checks["max_blocks"] = max(checks["max_blocks"], m64.nb)
+    say("full adaptive blast: FP64 GPU run checked at", checks)
+    assert checks["changed"] >= 2
     ref = restricted(f4, m64, 2)
     net, tr = train_indicator(f4, cfg)
     netc, trc = train_indicator(f4, cfg, captured=True)
     ev, runs = evaluate(f4, {"mlp": (net, False), "mlp_captured": (netc, True)}, w, 2)
     l1 = {k: float(np.abs(v - ref).sum() / np.abs(ref).sum()) for k, v in runs.items()}
     cost = {k: ev[k]["indicator_ms_per_regrid"] / ev["lohner"]["indicator_ms_per_regrid"] for k in ev}
-    report = dict(workload=w["name"], steps=w["steps"], regrid_every=w["regrid_every"], training=tr,
-                  training_captured=trc, runs=ev, l1_vs_fp64_gpu_level2=l1, indicator_cost_ratio=cost)
+    report = dict(workload=w["name"], steps=w["steps"], regrid_every=w["regrid_every"], oracle_checks=checks,
+                  training=tr, training_captured=trc, runs=ev, l1_vs_fp64_gpu_level2=l1,
+                  indicator_cost_ratio=cost)
     say(json.dumps(report, indent=1))
     write_report("adaptive_blast_indicator_full.json", report)
     assert ev["mlp"]["missed_refinement"] <= 0.05 and ev["mlp_captured"]["missed_refinement"] <= 0.05
+    # what the network gains: the captured-feature indicator needs no pass
+    # over the state at a regrid, so it costs less than the criterion
+    assert cost["mlp_captured"] < 1.0, cost
+    # and the solution it drives stays as close to the FP64 criterion run as
+    # the FP32 criterion run does (within a factor of three)
+    assert l1["mlp_captured"] <= max(3.0 * l1["lohner"], 1e-5), l1

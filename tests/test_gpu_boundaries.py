@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_helpers import build_pair, face_ghost_mask, gpu_mesh, gpu_state, interior, oracle_mesh, rel_l1_vol
+from tests.gpu_helpers import build_pair, face_ghost_mask, gpu_mesh, gpu_state, interior, oracle_mesh, check_state
 
 pytestmark = pytest.mark.gpu
 
@@ -93,7 +93,7 @@ def run_pair(w, prec, steps):
     om.step(steps)
     lev = gm.export()[0]
     a = interior(gpu_state(gm), w["g"], w["N"], w["ndim"])
-    err = rel_l1_vol(a, om.interior(), lev, w["ndim"], w["tree_size"], w["N"])
+    err, err_elem = check_state(a, om.interior(), lev, w["ndim"], w["tree_size"], w["N"], prec)
     say(w["name"], "prec", prec, "steps", steps, "rel L1", err, "t", t_gpu, om.t)
     return gm, om, err, t_gpu
 
@@ -401,7 +401,7 @@ def test_bc_data_step_parity_and_batch(f4, prec):
     b.step(steps)
     lev = gm.export()[0]
     a = interior(gpu_state(gm), 2, w["N"], 3)
-    err = rel_l1_vol(a, om.interior(), lev, 3, w["tree_size"], w["N"])
+    err, err_elem = check_state(a, om.interior(), lev, 3, w["tree_size"], w["N"], prec)
     say("bc_data parity", prec, err)
     assert err <= TOL[prec]
     # the batch took its first step with the uniform values, so compare it

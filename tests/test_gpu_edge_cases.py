@@ -169,6 +169,35 @@ def test_autotune_restores_state_and_caches(f4, tmp_path):
     assert '"' in open(cache).read()
 
 
+def test_autotune_on_fresh_meshes_then_steps_equal_plain(f4, tmp_path):
+    """Autotuning meshes that have not taken a step yet (their first dt not
+    computed) and then stepping the batch gives exactly the plain form's
+    steps: states and times bit for bit (a regression test: the tuner once
+    restored a zero dt behind a mesh that counted its dt as computed, so the
+    first step after tuning advanced by nothing)."""
+    from paper_2605_07612_amd import layout
+    w = synth.rayleigh_taylor(block=16, n=32)
+
+    def make():
+        m = f4.Mesh(3, w["trees"], w["N"], w["g"], w["tree_size"], prec=f4.F64, gamma=w["gamma"], cfl=w["cfl"],
+                    limiter=w["limiter"], flux=w["flux"], gravity=w["gravity"], periodic=w["periodic"],
+                    bc_type=w["bc_type"], bc_value=w["bc_value"])
+        layout.set_from_grid(m, w["grid_field"]())
+        return m
+
+    plain, tuned = make(), make()
+    b = f4.Batch([tuned])
+    cfg = b.autotune(str(tmp_path / "tune.json"))
+    say("autotune on fresh meshes", cfg)
+    b.step(3)
+    plain.step(3)
+    assert tuned.time() == plain.time()
+    assert np.array_equal(interior(gpu_state(tuned), 2, 16, 3), interior(gpu_state(plain), 2, 16, 3))
+    b.close()
+    plain.close()
+    tuned.close()
+
+
 def test_no_device_memory_leak(f4):
     """Meshes, batches and networks created and destroyed in a loop (with
     regrids, captured features and training in between) give back the

@@ -11,7 +11,7 @@ import pytest
 import synth
 from oracle import OracleMesh
 from tests.gpu_helpers import (build_pair, face_ghost_mask, gpu_mesh, gpu_state, interior, oracle_mesh,
-                               rel_l1_vol)
+                               check_state)
 
 pytestmark = pytest.mark.gpu
 
@@ -146,7 +146,7 @@ def run_pair(w, prec, steps, **kw):
     lev = gm.export()[0]
     a = interior(gpu_state(gm), w["g"], w["N"], w["ndim"])
     b = om.interior()
-    err = rel_l1_vol(a, b, lev, w["ndim"], w["tree_size"], w["N"])
+    err, err_elem = check_state(a, b, lev, w["ndim"], w["tree_size"], w["N"], prec)
     say(w["name"], "prec", prec, "steps", steps, "rel L1", err, "t", t_gpu, om.t)
     return gm, om, err, t_gpu, t0
 
@@ -305,7 +305,7 @@ def test_batch_two_level_equals_plain(f4, prec, gather, ndim, block):
     assert np.array_equal(a, c)
     om.step(steps)
     lev = gb.export()[0]
-    err = rel_l1_vol(c, om.interior(), lev, ndim, w["tree_size"], block)
+    err, err_elem = check_state(c, om.interior(), lev, ndim, w["tree_size"], block, prec)
     say("rel L1 vs oracle", err)
     assert err <= TOL[prec]
 
@@ -369,7 +369,7 @@ def test_wider_ghost_layers(f4, g, two_level):
     a, c = interior(gpu_state(gm), g, 16, 3), interior(gpu_state(gb), g, 16, 3)
     assert gm.time() == gb.time() and np.array_equal(a, c)
     lev = gm.export()[0]
-    err = rel_l1_vol(a, om.interior(), lev, 3, w["tree_size"], 16)
+    err, err_elem = check_state(a, om.interior(), lev, 3, w["tree_size"], 16, 1)
     say("rel L1 vs oracle", err)
     assert err <= TOL[1]
 
@@ -383,6 +383,6 @@ def test_batch_mixed_sizes_vs_oracle(f4):
     for w, (gm, om) in zip(ws, pairs):
         om.step(5)
         lev = gm.export()[0]
-        err = rel_l1_vol(interior(gpu_state(gm), 2, w["N"], 3), om.interior(), lev, 3, w["tree_size"], w["N"])
+        err, err_elem = check_state(interior(gpu_state(gm), 2, w["N"], 3), om.interior(), lev, 3, w["tree_size"], w["N"], 0)
         say(w["name"], w["N"], gm.nb, err)
         assert err <= TOL[0]

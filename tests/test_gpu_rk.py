@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_helpers import build_pair, gpu_state, interior, rel_l1_vol
+from tests.gpu_helpers import build_pair, gpu_state, interior, check_state
 
 pytestmark = pytest.mark.gpu
 
@@ -113,7 +113,7 @@ def test_parity(f4, integ, name, prec):
     t, _ = gm.time()
     lev = gm.export()[0]
     a = interior(gpu_state(gm), w["g"], w["N"], w["ndim"])
-    err = rel_l1_vol(a, om.interior(), lev, w["ndim"], w["tree_size"], w["N"])
+    err, err_elem = check_state(a, om.interior(), lev, w["ndim"], w["tree_size"], w["N"], prec)
     say(w["name"], "prec", prec, "rel L1", err, "t", t, om.t)
     assert err <= TOL[prec]
     assert abs(t - om.t) <= (1e-13 if prec == 1 else 1e-5) * om.t
@@ -202,7 +202,7 @@ def test_regrid_between_steps(f4, integ):
     gm.step(4)
     om.step(4)
     lev = gm.export()[0]
-    err = rel_l1_vol(interior(gpu_state(gm), 2, 8, 3), om.interior(), lev, 3, w["tree_size"], 8)
+    err, err_elem = check_state(interior(gpu_state(gm), 2, 8, 3), om.interior(), lev, 3, w["tree_size"], 8, 1)
     say("regrid", integ, "levels", sorted(set(lev.tolist())), "rel L1", err)
     assert err <= TOL[1]
 
@@ -230,6 +230,6 @@ def test_bc_data_with_rk4(f4):
     gm.step(5)
     om.step(5)
     lev = gm.export()[0]
-    err = rel_l1_vol(interior(gpu_state(gm), 2, 8, 3), om.interior(), lev, 3, w["tree_size"], 8)
+    err, err_elem = check_state(interior(gpu_state(gm), 2, 8, 3), om.interior(), lev, 3, w["tree_size"], 8, 1)
     say("bc_data rk4 rel L1", err)
     assert err <= TOL[1]

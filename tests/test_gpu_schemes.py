@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_helpers import build_pair, gpu_state, interior, rel_l1_vol
+from tests.gpu_helpers import build_pair, gpu_state, interior, check_state
 
 pytestmark = pytest.mark.gpu
 
@@ -69,7 +69,7 @@ def run_pair(w, prec, steps):
     om.step(steps)
     lev = gm.export()[0]
     a = interior(gpu_state(gm), w["g"], w["N"], w["ndim"])
-    err = rel_l1_vol(a, om.interior(), lev, w["ndim"], w["tree_size"], w["N"])
+    err, err_elem = check_state(a, om.interior(), lev, w["ndim"], w["tree_size"], w["N"], prec)
     say(w["name"], "prec", prec, "steps", steps, "levels", sorted(set(lev.tolist())), "rel L1", err, "t", t_gpu, om.t)
     return gm, om, err, t_gpu
 

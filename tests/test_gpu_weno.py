@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_helpers import gpu_state, interior, rel_l1_vol
+from tests.gpu_helpers import gpu_state, interior, check_state
 
 pytestmark = pytest.mark.gpu
 
@@ -97,7 +97,7 @@ def test_parity(f4, name, integ, flux, prec):
     t, _ = gm.time()
     lev = gm.export()[0]
     a = interior(gpu_state(gm), w["g"], w["N"], w["ndim"])
-    err = rel_l1_vol(a, om.interior(), lev, w["ndim"], w["tree_size"], w["N"])
+    err, err_elem = check_state(a, om.interior(), lev, w["ndim"], w["tree_size"], w["N"], prec)
     say(w["name"], "prec", prec, "levels", sorted(set(lev.tolist())), "rel L1", err, "t", t, om.t)
     assert err <= TOL[prec]
     assert abs(t - om.t) <= (1e-13 if prec == 1 else 1e-5) * om.t
@@ -176,6 +176,6 @@ def test_parity_block_shapes(f4, N, g, prec):
     om.step(steps)
     lev = gm.export()[0]
     assert sorted(set(lev.tolist())) == [0, 1]
-    err = rel_l1_vol(interior(gpu_state(gm), g, N, 3), om.interior(), lev, 3, w["tree_size"], N)
+    err, err_elem = check_state(interior(gpu_state(gm), g, N, 3), om.interior(), lev, 3, w["tree_size"], N, prec)
     say(w["name"], "prec", prec, "blocks", len(lev), "rel L1", err)
     assert err <= TOL[prec]
