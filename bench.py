@@ -28,7 +28,11 @@ import numpy as np  # noqa: E402
 
 METRIC = "cell-updates/s per GPU + % HBM roofline, 16^3 blocks, FP32 batched vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
-PROFILE_CONFIG = "1,0,4,1"  # the configuration the committed counters and trace were taken in
+# the autotuner's choices for the benchmark's batches on MI355X, cached by
+# foap4_batch_autotune (keyed by architecture, precision, scheme and block
+# mix); the timed runs, the committed profiles and the full-size parity tests
+# all take their launch configuration from here
+TUNE_CACHE = os.path.join(ROOT, "paper_2605_07612_amd", "autotune_mi355x.json")
 
 
 def halo_share(N, g=2, ndim=3):
@@ -81,23 +85,27 @@ def timed_steps(run, steps, sync):
     return start.elapsed_time(end) / 1e3, wall
 
 
-def traffic_from_counters(path, stage_launch_bytes):
-    """HBM bytes per stage launch from a rocprofv3 --pmc counter summary
-    (profiles/*.json written from two counter passes, FETCH_SIZE and
-    WRITE_SIZE in KiB per dispatch), each scaled by the factor that makes the
-    same counter read the known size of a plain 1 GiB device copy."""
+def traffic_from_counters(path, kernel, launch_bytes):
+    """HBM bytes per launch of the kernels matching `kernel` (a regular
+    expression; the mean over them, e.g. the two Heun stages) from a counter
+    summary under profiles/ (paper_2605_07612_amd.profiling: two rocprofv3
+    --pmc passes, FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled
+    by the factor that makes the same counter read the known size of a plain
+    1 GiB device copy).  None once the kernel's sources differ from the ones
+    the counters were taken on."""
+    import re
+    from paper_2605_07612_amd.profiling import sources_sha256
     try:
         d = json.load(open(path))
-        import hashlib
-        csrc = os.path.join(ROOT, "paper_2605_07612_amd", "csrc")
-        src = b"".join(open(os.path.join(csrc, f), "rb").read()
-                       for f in ("stage.hip", "device_common.h", "foap4_internal.h", "stage_common.h"))
-        if hashlib.sha256(src).hexdigest() != d["source_sha256"]:
+        if sources_sha256([os.path.join(ROOT, f) for f in d["source_files"]]) != d["source_sha256"]:
             return None  # the kernel changed since the counters were taken
-        fetch = d["stage_fetch_kib"] * d["fetch_scale"]
-        write = d["stage_write_kib"] * d["write_scale"]
+        recs = [r for r in d["dispatch_means"] if re.search(kernel, r["kernel"])]
+        if not recs:
+            return None
+        fetch = sum(r["FETCH_SIZE_scaled"] for r in recs) / len(recs)
+        write = sum(r["WRITE_SIZE_scaled"] for r in recs) / len(recs)
         return {"bytes_per_launch": int((fetch + write) * 1024), "fetch_kib": round(fetch, 1),
-                "write_kib": round(write, 1), "algorithmic_bytes_per_launch": int(stage_launch_bytes),
+                "write_kib": round(write, 1), "algorithmic_bytes_per_launch": int(launch_bytes),
                 "source": os.path.relpath(path, ROOT)}
     except (OSError, KeyError, ValueError):
         return None
@@ -114,16 +122,21 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-batch64", action="store_true")
     ap.add_argument("--skip-rt", action="store_true")
+    ap.add_argument("--skip-adv", action="store_true")
+    ap.add_argument("--skip-two-level", action="store_true")
+    ap.add_argument("--skip-sweep", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=5)
-    ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="autotuner cache (JSON); entries missing from it are tuned and added")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for hardware-counter passes: a 1 GiB device copy (counter calibration) "
                          "then 3 batched FP32 steps in the given configuration")
-    ap.add_argument("--profile-workload", default="noise_shear", choices=["noise_shear", "rayleigh_taylor", "rayleigh_taylor_weno5"],
+    ap.add_argument("--profile-workload", default="noise_shear",
+                    choices=["noise_shear", "rayleigh_taylor", "rayleigh_taylor_weno5", "advection", "two_level"],
                     help="workload of --profile-run")
     ap.add_argument("--config", default=None,
-                    help="kslabs,wg_stage1,wg_stage2,xcd_order instead of autotuning, for every FP32 "
-                         f"single-mesh leg (--profile-run default: {PROFILE_CONFIG})")
+                    help="kslabs,wg_stage1,wg_stage2,xcd_order instead of the autotuner's cached choice, for "
+                         "every FP32 single-mesh leg (and --profile-run)")
     ap.add_argument("--counters", default=os.path.join(ROOT, "profiles", "stage_traffic_noise_shear_256cubed_b16.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -171,6 +184,47 @@ def main():
         bb.copy_(a)  # calibration: reads and writes exactly 1 GiB
         torch.cuda.synchronize()
         del a, bb
+        if args.profile_workload == "two_level":
+            wt = synth.two_level_blast(base_trees=16, block=8)
+            for prec in (f4.F32, f4.F64):  # three steps batched FP32 (cached configuration), plain FP64
+                m = f4.Mesh(3, wt["trees"], wt["N"], wt["g"], wt["tree_size"], max_level=1,
+                            max_blocks=int(np.prod(wt["trees"])) * 8, prec=prec, gamma=wt["gamma"], cfl=wt["cfl"])
+                _, G = layout.global_coords(m)
+                m.regrid(wt["refine_flags"](G))
+                layout.set_from_field_device(m, wt["field"])
+                if prec == f4.F32:
+                    bt = f4.Batch([m])
+                    log("two-level profile run, batch configuration", bt.autotune(args.tune_cache))
+                    bt.step(3)
+                    torch.cuda.synchronize()
+                    bt.close()
+                else:
+                    m.step(3)
+                    torch.cuda.synchronize()
+                m.close()
+                del m
+                torch.cuda.empty_cache()
+            log("profile run done")
+            return
+        if args.profile_workload == "advection":
+            wa = synth.advection(3, args.block, args.n, init="sphere", limiter="vanleer")
+            for prec in (f4.F32, f4.F64):  # three Heun steps of each advection kernel, batched FP32, plain FP64
+                m = f4.Mesh(3, wa["trees"], wa["N"], wa["g"], wa["tree_size"], prec=prec, cfl=wa["cfl"],
+                            limiter="vanleer", physics="advection", velocity=wa["velocity"])
+                layout.set_from_field_device(m, wa["field"])
+                if prec == f4.F32:
+                    ba = f4.Batch([m])
+                    ba.step(3)
+                    torch.cuda.synchronize()
+                    ba.close()
+                else:
+                    m.step(3)
+                    torch.cuda.synchronize()
+                m.close()
+                del m
+                torch.cuda.empty_cache()
+            log("profile run done")
+            return
         if args.profile_workload == "rayleigh_taylor_weno5":
             for prec in (f4.F32, f4.F64):  # three Heun steps of each WENO5 kernel
                 m = make_rt_weno(prec)
@@ -183,8 +237,12 @@ def main():
             return
         m32 = make(f4.F32) if args.profile_workload == "noise_shear" else make_rt(f4.F32)
         batch = f4.Batch([m32])
-        ks, wg1, wg2, xcd = parse_config(args.config or PROFILE_CONFIG)
-        batch.set_config(ks, wg1, xcd, 1, wg_stage2=wg2)
+        if args.config:  # else the configuration the timed run uses
+            ks, wg1, wg2, xcd = parse_config(args.config)
+            batch.set_config(ks, wg1, xcd, 1, wg_stage2=wg2)
+        else:
+            ks, wg1, wg2, xcd = batch.autotune(args.tune_cache)
+        log(f"profile run in configuration kslabs={ks} wg_per_cu stage 1={wg1} stage 2={wg2} xcd_order={xcd}")
         batch.step(3)
         torch.cuda.synchronize()
         log("profile run done")
@@ -230,8 +288,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      # the committed counters cover the 256^3 workload in 16^3 blocks only
-                     "traffic": (traffic_from_counters(args.counters, stage_bytes)
-                                 if (args.block, args.n) == (16, 256) else None),
+                     "traffic": (traffic_from_counters(args.counters, r"stage_kernel<float, 3, 2, [12], 0>",
+                                                       stage_bytes) if (args.block, args.n) == (16, 256) else None),
                      "kernel": f"stage_kernel<float,3,N={args.block}>", "bytes_per_launch": int(stage_bytes),
                      "avg_launch_ms": round(phases["stage"], 5)},
         "step_hbm": {"bytes_per_update": step_bytes_per_update(S32, True, args.block), "achieved_gbs": round(step_gbs, 1),
@@ -304,7 +362,8 @@ def main():
             "stage_ms": round(ph_rt["stage"], 5), "stage_hbm_frac": round(rt_stage_gbs / HBM_PEAK_GBS, 4),
             "stage_traffic": (traffic_from_counters(os.path.join(ROOT, "profiles",
                                                                  "stage_traffic_rayleigh_taylor_256cubed_b16.json"),
-                                                    stage_bytes) if (args.block, args.n) == (16, 256) else None),
+                                                    r"stage_kernel<float, 3, 2, [12], 5>", stage_bytes)
+                              if (args.block, args.n) == (16, 256) else None),
             "step_hbm_frac": round(g_rt * step_bytes_per_update(S32, True, args.block) / HBM_PEAK_GBS, 4),
             "fp64_plain": {"value": round(g_rt64, 4), "ms_per_step": round(sr64 / args.steps * 1e3, 4)},
             "paper_h100_context": (None if paper is None or args.n != 256 else
@@ -330,6 +389,152 @@ def main():
             weno, unit="Gcell-updates/s", scheme="WENO5 (g = 3), Rusanov, gravity, walls in z, Heun",
             paper_h100_context=(None if paper_w is None or args.n != 256 else
                                 {"fp64": paper_w, "source": "table of results on uniform grids, 256^3, WENO5"}))
+
+    # ---------------- block-size sweep: the same 256^3 workload in 8^3 (32768)
+    # and 32^3 (512) blocks, as the paper's table of results on different
+    # hardware has them; FP32 batched (the autotuner's cached choice) and
+    # FP64 plain
+    if not args.skip_sweep and args.n == 256:
+        sweep = {}
+        for nb_ in (8, 32):
+            if nb_ == args.block:
+                continue
+            ws_ = synth.uniform_noise_shear(block=nb_, n=args.n, seed=0)
+
+            def make_s(prec):
+                m = f4.Mesh(3, ws_["trees"], ws_["N"], ws_["g"], ws_["tree_size"], prec=prec, gamma=ws_["gamma"],
+                            cfl=ws_["cfl"])
+                layout.set_from_grid(m, grid)
+                return m
+
+            m = make_s(f4.F32)
+            bs = f4.Batch([m])
+            cfg_s = bs.autotune(args.tune_cache)
+            bs.step(args.warmup)
+            ss_, _ = timed_steps(bs.step, args.steps, torch.cuda.synchronize)
+            g_s = cells * 2 * args.steps / ss_ / 1e9
+            ph_s = bs.phase_times(5)
+            del bs, m
+            torch.cuda.empty_cache()
+            m = make_s(f4.F64)
+            m.step(args.warmup)
+            ss64, _ = timed_steps(lambda k: m.step(k), args.steps, torch.cuda.synchronize)
+            g_s64 = cells * 2 * args.steps / ss64 / 1e9
+            del m
+            torch.cuda.empty_cache()
+            sb = cells * stage_bytes_per_cell(S32, nb_)
+            paper_s = {32: (2.702, 1.366), 8: (2.081, 1.097)}.get(nb_)
+            sweep[f"b{nb_}"] = {
+                "blocks": int(np.prod(ws_["trees"])), "value": round(g_s, 4), "unit": "Gcell-updates/s",
+                "dtype": "f32", "ms_per_step": round(ss_ / args.steps * 1e3, 4), "config": list(cfg_s),
+                "stage_ms": round(ph_s["stage"], 5),
+                "stage_hbm_frac": round(sb / (ph_s["stage"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "step_hbm_frac": round(g_s * step_bytes_per_update(S32, True, nb_) / HBM_PEAK_GBS, 4),
+                "fp64_plain": {"value": round(g_s64, 4), "ms_per_step": round(ss64 / args.steps * 1e3, 4),
+                               "step_hbm_frac": round(g_s64 * step_bytes_per_update(S64, False, nb_) / HBM_PEAK_GBS,
+                                                      4)},
+                "paper_h100_context_rt": (None if paper_s is None else
+                                          {"fp32": paper_s[0], "fp64": paper_s[1],
+                                           "source": "table of results on different hardware, Rayleigh-Taylor, "
+                                                     "256^3, van Leer"})}
+            log(f"noise/shear 256^3 in {nb_}^3 blocks: FP32 batched {g_s:.2f}, FP64 plain {g_s64:.2f} "
+                f"Gcell-updates/s, config {cfg_s}")
+        result["block_sweep"] = sweep
+
+    # ---------------- the static two-level blast (128^3 base in 8^3 blocks, the
+    # ball |x - 1/2| < 1/4 refined once: 6952 blocks, 3.56e6 cells): every
+    # stage restricts, prolongs and fixes fluxes at the level boundaries
+    if not args.skip_two_level:
+        wt = synth.two_level_blast(base_trees=16, block=8)
+
+        def make_tl(prec):
+            m = f4.Mesh(3, wt["trees"], wt["N"], wt["g"], wt["tree_size"], max_level=1,
+                        max_blocks=int(np.prod(wt["trees"])) * 8, prec=prec, gamma=wt["gamma"], cfl=wt["cfl"])
+            _, G = layout.global_coords(m)
+            m.regrid(wt["refine_flags"](G))
+            layout.set_from_field_device(m, wt["field"])
+            return m
+
+        tl = {}
+        m = make_tl(f4.F32)
+        cells_tl = m.nb * wt["N"] ** 3
+        bt = f4.Batch([m])
+        cfg_tl = bt.autotune(args.tune_cache)
+        bt.step(args.warmup)
+        st_, _ = timed_steps(bt.step, args.steps, torch.cuda.synchronize)
+        g_tl = cells_tl * 2 * args.steps / st_ / 1e9
+        ph_tl = bt.phase_times(5)
+        ghost_share = 2 * (ph_tl["ghost_r1"] + ph_tl["ghost_r2"]) / ph_tl["step"]
+        tl.update(workload=wt["name"], blocks=int(m.nb), cells=int(cells_tl), value=round(g_tl, 4),
+                  unit="Gcell-updates/s", dtype="f32", ms_per_step=round(st_ / args.steps * 1e3, 4),
+                  config=list(cfg_tl), phases_ms={k: round(v, 5) for k, v in ph_tl.items()},
+                  ghost_share=round(ghost_share, 4),
+                  stage_share=round(2 * ph_tl["stage"] / ph_tl["step"], 4),
+                  fluxfix_share=round(ph_tl["fluxfix"] / ph_tl["step"], 4))
+        del bt, m
+        torch.cuda.empty_cache()
+        m = make_tl(f4.F64)
+        m.step(args.warmup)
+        st64, _ = timed_steps(lambda k: m.step(k), args.steps, torch.cuda.synchronize)
+        tl["fp64_plain"] = {"value": round(cells_tl * 2 * args.steps / st64 / 1e9, 4),
+                            "ms_per_step": round(st64 / args.steps * 1e3, 4)}
+        del m
+        torch.cuda.empty_cache()
+        log(f"two-level blast: FP32 batched {g_tl:.2f} Gcell-updates/s (ghost rounds {100 * ghost_share:.1f} % "
+            f"of the step), FP64 plain {tl['fp64_plain']['value']:.2f}")
+        result["two_level_blast"] = tl
+
+    # ---------------- scalar advection (Sec. 3.4): the paper's highest-throughput
+    # workload (its table of results on uniform grids, advection rows): the
+    # smoothed sphere, v = (1, 1, 1), van Leer, Heun, 16^3 blocks, at 256^3 and
+    # 512^3 cells; FP32 batched (graph-replayed) and FP64 plain
+    if not args.skip_adv:
+        adv = {}
+        for n_adv in (256, 512):
+            wa = synth.advection(3, args.block, n_adv, init="sphere", limiter="vanleer")
+            cells_a = n_adv ** 3
+
+            def make_adv(prec):
+                m = f4.Mesh(3, wa["trees"], wa["N"], wa["g"], wa["tree_size"], prec=prec, cfl=wa["cfl"],
+                            limiter="vanleer", physics="advection", velocity=wa["velocity"])
+                layout.set_from_field_device(m, wa["field"])
+                return m
+
+            ma = make_adv(f4.F32)
+            ba = f4.Batch([ma])
+            ba.step(args.warmup)
+            sa, _ = timed_steps(ba.step, args.steps, torch.cuda.synchronize)
+            ga = cells_a * 2 * args.steps / sa / 1e9
+            pha = ba.phase_times(5)
+            del ba, ma
+            torch.cuda.empty_cache()
+            ma = make_adv(f4.F64)
+            ma.step(args.warmup)
+            sa64, _ = timed_steps(lambda k: ma.step(k), args.steps, torch.cuda.synchronize)
+            ga64 = cells_a * 2 * args.steps / sa64 / 1e9
+            del ma
+            torch.cuda.empty_cache()
+            adv_stage_bytes = cells_a * stage_bytes_per_cell(4, args.block)
+            adv_gbs = adv_stage_bytes / (pha["stage"] * 1e-3) / 1e9
+            paper_a = ({256: {32: 7.59, 16: 8.64, 8: 6.95}, 512: {32: 12.27, 16: 10.89, 8: 7.79}}
+                       .get(n_adv, {}).get(args.block))
+            adv[f"{n_adv}^3"] = {
+                "value": round(ga, 4), "unit": "Gcell-updates/s", "dtype": "f32",
+                "ms_per_step": round(sa / args.steps * 1e3, 4),
+                "stage_ms": round(pha["stage"], 5), "ghost_r1_ms": round(pha["ghost_r1"], 5),
+                "stage_bytes_per_launch": int(adv_stage_bytes),
+                "stage_hbm_frac": round(adv_gbs / HBM_PEAK_GBS, 4),
+                "step_hbm_frac": round(ga * step_bytes_per_update(4, False, args.block) / HBM_PEAK_GBS, 4),
+                "fp64_plain": {"value": round(ga64, 4), "ms_per_step": round(sa64 / args.steps * 1e3, 4),
+                               "step_hbm_frac": round(ga64 * step_bytes_per_update(8, False, args.block)
+                                                      / HBM_PEAK_GBS, 4)},
+                "paper_h100_context": (None if paper_a is None else
+                                       {"fp64": paper_a, "source": "table of results on uniform grids, "
+                                                                   "advection, van Leer"})}
+            log(f"advection {n_adv}^3: FP32 batched {ga:.2f}, FP64 plain {ga64:.2f} Gcell-updates/s, "
+                f"stage {pha['stage']:.4f} ms")
+        result["advection"] = dict(adv, workload="advection_sphere_b16", scheme="van Leer, Rusanov, Heun, "
+                                                                              "v = (1, 1, 1), stored ghosts")
 
     # ---------------- the 64-problem batch (mixed 8^3/16^3/32^3 blocks), FP32
     if not args.skip_batch64:
@@ -360,20 +565,44 @@ def main():
         del b64, ms
         torch.cuda.empty_cache()
 
-    # ---------------- CPU baseline: the FP64 oracle on a bounded sample
+    # ---------------- CPU baseline: the FP64 oracle on a bounded sample, with
+    # OpenMP over blocks on every thread the runtime gives it, and on one thread
     if not args.skip_cpu:
+        import ctypes
+        import ctypes.util
         from oracle import OracleMesh
+        gomp = ctypes.CDLL(ctypes.util.find_library("gomp") or "libgomp.so.1")
+        threads = int(gomp.omp_get_max_threads())
+        nproc = len(os.sched_getaffinity(0))
         om = OracleMesh(3, w["trees"], w["N"], w["g"], w["tree_size"], gamma=w["gamma"], cfl=w["cfl"])
         om.set_interior_from_grid(grid)
         t0 = time.perf_counter()
         om.step(args.cpu_steps)
         el = time.perf_counter() - t0
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         result["cpu_baseline"] = {"value": round(cells * 2 * args.cpu_steps / el / 1e9, 5),
                                   "unit": "Gcell-updates/s", "cores": threads, "kind": "oracle",
                                   "sample": f"{args.cpu_steps} Heun steps of the same {args.n}^3 workload "
-                                            f"({el:.1f} s, FP64, OpenMP over blocks)"}
+                                            f"({el:.1f} s, FP64, OpenMP over blocks on {threads} threads; "
+                                            f"nproc {nproc})"}
         log(f"CPU oracle: {result['cpu_baseline']['value']} Gcell-updates/s on {threads} threads")
+        del om
+        # one thread: the same workload (same blocks, fields and scheme) on a
+        # 128^3 domain, so that the sample stays at a few seconds
+        n1 = min(args.n, 128)
+        w1 = synth.uniform_noise_shear(block=args.block, n=n1, seed=0)
+        om = OracleMesh(3, w1["trees"], w1["N"], w1["g"], w1["tree_size"], gamma=w1["gamma"], cfl=w1["cfl"])
+        om.set_interior_from_grid(w1["grid_field"]())
+        gomp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        om.step(2)
+        el1 = time.perf_counter() - t0
+        gomp.omp_set_num_threads(threads)
+        result["cpu_baseline_single_thread"] = {"value": round(n1 ** 3 * 2 * 2 / el1 / 1e9, 5),
+                                                "unit": "Gcell-updates/s", "cores": 1, "kind": "oracle",
+                                                "sample": f"2 Heun steps of the same workload on {n1}^3 cells in "
+                                                          f"{args.block}^3 blocks ({el1:.1f} s, FP64, one thread)"}
+        log(f"CPU oracle, one thread: {result['cpu_baseline_single_thread']['value']} Gcell-updates/s")
+        del om
     print(json.dumps(result), flush=True)
 
 
