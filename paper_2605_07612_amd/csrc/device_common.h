@@ -19,6 +19,18 @@ template <typename T>
 __device__ __forceinline__ void gstore(T *p, T v) {
   *(__attribute__((address_space(1))) T *)p = v;
 }
+// The same at base + byte_off with a 32-bit byte offset: with a wave-uniform
+// base the hardware adds the per-lane offset to a scalar base address, so no
+// 64-bit address arithmetic runs per lane.
+template <typename T>
+__device__ __forceinline__ T gload_at(const T *base, uint32_t byte_off) {
+  return *(const __attribute__((address_space(1))) T *)((const __attribute__((address_space(1))) char *)base +
+                                                        byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void gstore_at(T *base, uint32_t byte_off, T v) {
+  *(__attribute__((address_space(1))) T *)((__attribute__((address_space(1))) char *)base + byte_off) = v;
+}
 
 // Generalized minmod G(a, b, theta = 1) (eq. gminmod): zero unless a and b
 // have the same strict sign, else the one of smaller magnitude.  That value is
@@ -146,24 +158,25 @@ __device__ __forceinline__ void riemann(const T *WL, const T *WR, T gamma, T *F)
     al = wl * (vl - s0);
     ar = wr * (vr - s1);
   }
-  F[0] = al * rl + ar * rr;
-  T kel = T(0), ker = T(0);
+  // With A = al rho_L and B = ar rho_R: mass A + B, momentum A v_L + B v_R
+  // (plus the pressure weights on the normal component), and energy
+  // al E_L + ar E_R + wl pL vL + wr pR vR with E = p / (gamma - 1) + rho |v|^2 / 2,
+  // grouped as (A |v_L|^2 + B |v_R|^2) / 2 + pL (al / (gamma-1) + wl vL)
+  // + pR (ar / (gamma-1) + wr vR)
+  const T A = al * rl, B = ar * rr;
+  F[0] = A + B;
+  T ql2 = T(0), qr2 = T(0);
 #pragma unroll
   for (int d = 0; d < NDIM; d++) {
-    const T ml = rl * WL[1 + d], mr = rr * WR[1 + d];
-    F[1 + d] = al * ml + ar * mr;
-    if (d == AX) {
-      if constexpr (!HLL) F[1 + d] += T(0.5) * (pl + pr);
-      else F[1 + d] += wl * pl + wr * pr;
-    }
-    kel += ml * WL[1 + d];
-    ker += mr * WR[1 + d];
+    const T ul = WL[1 + d], ur = WR[1 + d];
+    F[1 + d] = A * ul + B * ur;
+    if (d == AX) F[1 + d] += wl * pl + wr * pr;
+    ql2 += ul * ul;
+    qr2 += ur * ur;
   }
   const T igm1 = frcp(gamma - T(1));
-  const T El = pl * igm1 + T(0.5) * kel;
-  const T Er = pr * igm1 + T(0.5) * ker;
-  if constexpr (!HLL) F[NV - 1] = al * El + ar * Er + T(0.5) * (pl * vl + pr * vr);
-  else F[NV - 1] = al * El + ar * Er + (wl * pl * vl + wr * pr * vr);
+  const T cl = al * igm1 + wl * vl, cr = ar * igm1 + wr * vr;
+  F[NV - 1] = T(0.5) * (A * ql2 + B * qr2) + (pl * cl + pr * cr);
 }
 
 // Scheme of a stage kernel, a bit mask: limiter (bit 0: van Leer, else

@@ -20,6 +20,8 @@
 // on the scheme (limiter, flux, gravity source).  This file is compiled once
 // per scheme with F4_SCHEME set to that scheme's bit mask; the compile with
 // F4_SCHEME = 0 also holds the dispatcher over all schemes.
+#include <type_traits>
+
 #include "device_common.h"
 #include "foap4_internal.h"
 #include "stage_common.h"
@@ -54,12 +56,6 @@ constexpr int smem_cells() {
   if (NM & 2) c = item_cells<NDIM, 16>() > c ? item_cells<NDIM, 16>() : c;
   if (NM & 4) c = item_cells<NDIM, 32>() > c ? item_cells<NDIM, 32>() : c;
   return c;
-}
-
-template <typename T, int NV>
-__device__ __forceinline__ void copyv(T *dst, const T *src) {
-#pragma unroll
-  for (int v = 0; v < NV; v++) dst[v] = src[v];
 }
 
 // Variable slot of v when the velocity components x and y are exchanged
@@ -106,7 +102,9 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   constexpr int NF = 2 * NDIM;
 
   const int tid = threadIdx.x;
-  const int sub = tid / TT, lt = tid % TT;
+  // a sub-tile is one or more whole waves (TT >= 64): its block, tile and
+  // slab are wave-uniform, and so are the base addresses derived from them
+  const int sub = __builtin_amdgcn_readfirstlane(tid / TT), lt = tid % TT;
   const int ti = lt % TILE, tj = lt / TILE;
   const int ks = (NDIM == 3) ? M.ks : 1;
   const int kslab = (int)(local % ks);
@@ -210,17 +208,26 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     ring_p = ud0 + blk * bel + off(RI, RJ, 0);
     ring_sk = ((unsigned)RI < (unsigned)N) ? sk : P * 2 * g;
   }
-  const T *own_p = ud0 + b * bel + off(I, J, 0);
-  const T *zlo_p = nullptr, *zhi_p = nullptr;  // neighbour columns across -z / +z (gather)
+  // The own column: plane kk of variable v of block B at the wave-uniform
+  // base B + v sv + kk sk plus the lane's byte offset own_ob (interior cells:
+  // the offset of (I, J, kk) is that of (I, J, 0) plus kk sk).  colb(kk) is
+  // the base of plane kk, in the neighbour block across -z / +z (gather).
+  const T *own_b = ud0 + b * bel;
+  const uint32_t own_ob = (uint32_t)off(I, J, 0) * (uint32_t)sizeof(T);
+  const T *zlo_b = nullptr, *zhi_b = nullptr;
   if constexpr (NDIM == 3) {
     const int64_t nlo = nbr_of(4 % NF), nhi = nbr_of(5 % NF);
-    if (nlo >= 0) zlo_p = ud0 + nlo * bel + off(I, J, 0);
-    if (nhi >= 0) zhi_p = ud0 + nhi * bel + off(I, J, 0);
+    if (nlo >= 0) zlo_b = ud0 + nlo * bel;
+    if (nhi >= 0) zhi_b = ud0 + nhi * bel;
   }
-  auto col = [&](int kk) -> const T * {
-    if (kk < 0 && zlo_p) return zlo_p + (kk + N) * sk;
-    if (kk >= N && zhi_p) return zhi_p + (kk - N) * sk;
-    return own_p + kk * sk;
+  auto colb = [&](int kk) -> const T * {
+    if (kk < 0 && zlo_b) return zlo_b + (kk + N) * sk;
+    if (kk >= N && zhi_b) return zhi_b + (kk - N) * sk;
+    return own_b + kk * sk;
+  };
+  auto loadc = [&](const T *base, T *U) {
+#pragma unroll
+    for (int v = 0; v < NV; v++) U[v] = gload_at(base + v * sv, own_ob);
   };
 
   // cells next to F2C faces are finished (and their dt taken) by the flux fix
@@ -232,9 +239,12 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   // Primitive planes live in a ring of LDS slots (plane kk in slot kk % 3):
   // at iteration k the slots hold planes k, k+1, k+2; the own column's z
   // stencil reads them there, so only the conserved state of the own column
-  // (cells k, k+1, k+2, needed by the update) is kept in registers.
-  T Q[NV], R[NV], Sk[NV], Fz[NV];  // prefetch (own, ring), z slope of cell k, flux of face k - 1/2
-  T Ua[NV], Ub[NV];                // conserved state of own cells k, k+1
+  // (cells k .. k+2, needed by the update, and the prefetched k+3) is kept in
+  // registers.  Those four states rotate through the register sets X (plane
+  // kk in set (kk - k0) % 4), the fluxes of faces k -+ 1/2 through Fz2 and
+  // the prefetched U^n through P1: the plane loop is unrolled by four, so
+  // every set is named by a constant and no state is copied between planes.
+  T X[4][NV], Fz2[2][NV], R[NV], Sk[NV];  // ..., ring prefetch, z slope of cell k
   auto put = [&](T *S, int at, const T *U) {
     T W[NV];
     to_prim<T, NDIM>(U, gamma, W);
@@ -265,14 +275,14 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
 
   if constexpr (NDIM == 3) {
     T tmp[NV], Wm2[NV], Wm1[NV], W0[NV], W1[NV];
-    load(col(k0 - 2), tmp);
+    loadc(colb(k0 - 2), tmp);
     to_prim<T, NDIM>(tmp, gamma, Wm2);
-    load(col(k0 - 1), tmp);
+    loadc(colb(k0 - 1), tmp);
     to_prim<T, NDIM>(tmp, gamma, Wm1);
-    load(col(k0), Ua);
-    to_prim<T, NDIM>(Ua, gamma, W0);
-    load(col(k0 + 1), Ub);
-    to_prim<T, NDIM>(Ub, gamma, W1);
+    loadc(colb(k0), X[0]);
+    to_prim<T, NDIM>(X[0], gamma, W0);
+    loadc(colb(k0 + 1), X[1]);
+    to_prim<T, NDIM>(X[1], gamma, W1);
 #pragma unroll
     for (int v = 0; v < NV; v++) {
       slot(k0)[v * PLANE + own_lds] = W0[v];
@@ -293,58 +303,50 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       L[v] = Wm1[v] + T(0.5) * s1;
       Rt[v] = W0[v] - T(0.5) * Sk[v];
     }
-    riemann<T, NDIM, 2, (SCH & kSchHLL) != 0>(L, Rt, gamma, Fz);
-    if (k0 == 0) store_bflux(4, I, J, Fz);
+    riemann<T, NDIM, 2, (SCH & kSchHLL) != 0>(L, Rt, gamma, Fz2[0]);
+    if (k0 == 0) store_bflux(4, I, J, Fz2[0]);
     if constexpr (FEAT) {
       zr = Wm1[0];
       zp = Wm1[NV - 1];
     }
-    load(col(k0 + 2), Q);
+    loadc(colb(k0 + 2), X[2]);
     if (ring) load(ring_p + (k0 + 2) * ring_sk, R);
   } else {
     T tmp[NV];
-    load(own_p, Ua);
-    put(slot(0), own_lds, Ua);
+    loadc(own_b, X[0]);
+    put(slot(0), own_lds, X[0]);
     if (ring) {
       load(ring_p, tmp);
       put(slot(0), ring_lds, tmp);
     }
   }
 
-  T Upn[NV];
-  if (stage >= 2) load(up + off(I, J, k0), Upn);
-  [[maybe_unused]] T Upn2[NV], Upn3[NV];
+  // U^n (stage >= 2) and the two earlier states of RK4's last sub-step of
+  // the own cell, loaded one plane ahead (plane kk in set (kk - k0) % 2)
+  [[maybe_unused]] T P1[2][NV], P2[2][NV], P3[2][NV];
+  if (stage >= 2) loadc(up + k0 * sk, P1[0]);
   if (stage == 4) {
-    load(up2 + off(I, J, k0), Upn2);
-    load(up3 + off(I, J, k0), Upn3);
+    loadc(up2 + k0 * sk, P2[0]);
+    loadc(up3 + k0 * sk, P3[0]);
   }
 
-  T Uc[NV];  // conserved state of own cell k + 2
-  for (int k = k0; k < k1; k++) {
+  // plane k, PH = (k - k0) % 4
+  auto plane = [&](auto phase, const int k) __attribute__((always_inline)) {
+    constexpr int PH = decltype(phase)::value;
     if constexpr (NDIM == 3) {
       // plane k + 2 into the slot plane k - 1 used; prefetch plane k + 3
-      put(slot(k + 2), own_lds, Q);
-      copyv<T, NV>(Uc, Q);
+      put(slot(k + 2), own_lds, X[(PH + 2) & 3]);
       if (ring && k + 2 < k1) put(slot(k + 2), ring_lds, R);
-      if (k + 3 <= k1 + 1) load(col(k + 3), Q);
+      if (k + 3 <= k1 + 1) loadc(colb(k + 3), X[(PH + 3) & 3]);
       if (ring && k + 3 < k1) load(ring_p + (k + 3) * ring_sk, R);
     }
-    // U^n of the own cell (stage 2): loaded one plane ahead
-    T Up[NV];
-    const T *U0 = Ua;
-    [[maybe_unused]] T Up2[NV], Up3[NV];
-    if (stage == 4) {
-      copyv<T, NV>(Up2, Upn2);
-      copyv<T, NV>(Up3, Upn3);
-      if (k + 1 < k1) {
-        load(up2 + off(I, J, k + 1), Upn2);
-        load(up3 + off(I, J, k + 1), Upn3);
-      }
+    const T *U0 = X[PH & 3];
+    [[maybe_unused]] const T *Up = P1[PH & 1], *Up2 = P2[PH & 1], *Up3 = P3[PH & 1];
+    if (stage == 4 && k + 1 < k1) {
+      loadc(up2 + (k + 1) * sk, P2[(PH + 1) & 1]);
+      loadc(up3 + (k + 1) * sk, P3[(PH + 1) & 1]);
     }
-    if (stage >= 2) {
-      copyv<T, NV>(Up, Upn);
-      if (k + 1 < k1) load(up + off(I, J, k + 1), Upn);
-    }
+    if (stage >= 2 && k + 1 < k1) loadc(up + (k + 1) * sk, P1[(PH + 1) & 1]);
     const T *Wp = slot(k);
     __syncthreads();
 
@@ -361,7 +363,8 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       }
     }
 
-    T Fz1[NV];
+    [[maybe_unused]] const T *Fz = Fz2[PH & 1];
+    [[maybe_unused]] T *Fz1 = Fz2[(PH + 1) & 1];
     if constexpr (NDIM == 3) {
       // face k + 1/2 with the carried slope of cell k
       const T *A = Wp + own_lds, *B = slot(k + 1) + own_lds, *Cc = slot(k + 2) + own_lds;
@@ -478,10 +481,9 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     }
     // a tile's rows are contiguous runs of the block's row part; the tiles
     // of a block together write each interior plane as one contiguous range
-    const int o = off(I, J, k);
     if (valid) {
 #pragma unroll
-      for (int v = 0; v < NV; v++) gstore(uo + v * sv + o, Uout[v]);
+      for (int v = 0; v < NV; v++) gstore_at(uo + v * sv + k * sk, own_ob, Uout[v]);
     }
     if ((stage == 2 || (stage >= 3 && ss.epi)) && valid) {
       const bool skip = f2c_adj || (f2c_zlo && k == 0) || (f2c_zhi && k == N - 1);
@@ -493,12 +495,15 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
         }
       }
     }
-
-    if constexpr (NDIM == 3) {
-      copyv<T, NV>(Fz, Fz1);
-      copyv<T, NV>(Ua, Ub);
-      copyv<T, NV>(Ub, Uc);
-    }
+  };
+  for (int k = k0; k < k1; k += 4) {
+    plane(std::integral_constant<int, 0>{}, k);
+    if (k + 1 >= k1) break;
+    plane(std::integral_constant<int, 1>{}, k + 1);
+    if (k + 2 >= k1) break;
+    plane(std::integral_constant<int, 2>{}, k + 2);
+    if (k + 3 >= k1) break;
+    plane(std::integral_constant<int, 3>{}, k + 3);
   }
   if constexpr (FEAT) {
     double dr = (double)fr, dp = (double)fp;
