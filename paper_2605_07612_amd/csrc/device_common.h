@@ -19,17 +19,26 @@ template <typename T>
 __device__ __forceinline__ void gstore(T *p, T v) {
   *(__attribute__((address_space(1))) T *)p = v;
 }
-// The same at base + byte_off with a 32-bit byte offset: with a wave-uniform
-// base the hardware adds the per-lane offset to a scalar base address, so no
-// 64-bit address arithmetic runs per lane.
-template <typename T>
-__device__ __forceinline__ T gload_at(const T *base, uint32_t byte_off) {
-  return *(const __attribute__((address_space(1))) T *)((const __attribute__((address_space(1))) char *)base +
-                                                        byte_off);
+// Raw buffer access: a descriptor in scalar registers for a wave-uniform
+// base address, then per access the lane's 32-bit byte offset and a scalar
+// byte offset, so no per-lane 64-bit address arithmetic runs.  Every offset
+// used with these stays far below the descriptor's 2^31 - 1 byte range.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, 0x7fffffff, 0x00020000);
 }
 template <typename T>
-__device__ __forceinline__ void gstore_at(T *base, uint32_t byte_off, T v) {
-  *(__attribute__((address_space(1))) T *)((__attribute__((address_space(1))) char *)base + byte_off) = v;
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+  } else {
+    using U64 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U64, v), r, voff, soff, 0);
+  }
 }
 
 // Generalized minmod G(a, b, theta = 1) (eq. gminmod): zero unless a and b

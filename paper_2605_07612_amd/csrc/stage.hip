@@ -44,7 +44,7 @@ constexpr int lds_planes() { return NDIM == 3 ? 3 : 1; }
 template <int NDIM, int N>
 constexpr int item_cells() {
   using C = TileCfg<N>;
-  return C::SUB * (lds_planes<NDIM>() * (C::TILE + 4) * (C::TILE + 4) + 2 * (C::TILE + 1) * C::TILE + 2 * C::TILE) *
+  return C::SUB * (lds_planes<NDIM>() * (C::TILE + 4) * (C::TILE + 4) + 2 * (C::TILE + 1) * (C::TILE + 4) + 2 * C::TILE) *
          (NDIM + 2);
 }
 
@@ -97,7 +97,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   constexpr int NV = NDIM + 2;
   constexpr int LP = TILE + 4;
   constexpr int PLANE = LP * LP;
-  constexpr int NFX = (TILE + 1) * TILE;  // x (and y) face fluxes per variable
+  constexpr int NFX = (TILE + 1) * LP;  // x (and y) face flux slots per variable (rows of LP)
   constexpr int TT = TILE * TILE;
   constexpr int NF = 2 * NDIM;
 
@@ -105,7 +105,24 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   // a sub-tile is one or more whole waves (TT >= 64): its block, tile and
   // slab are wave-uniform, and so are the base addresses derived from them
   const int sub = __builtin_amdgcn_readfirstlane(tid / TT), lt = tid % TT;
-  const int ti = lt % TILE, tj = lt / TILE;
+  // Lanes to cells: LDS has 32 banks of 4 bytes and serves a wave in two
+  // halves of 32 lanes.  With the row stride LP = TILE + 4 (20, or 12 for
+  // 8 x 8 tiles), rows r and r + 4 (r + 2) start 16 (24) banks apart, so a
+  // half wave that holds two rows of 16 (four rows of 8) spaced that way
+  // reads and writes every plane and face array without bank conflicts;
+  // adjacent rows would share 4 banks.  Each wave thus holds the rows
+  // w, w + 4, w + 8, w + 12 of a 16 x 16 tile (w the wave), or the even rows
+  // then the odd rows of an 8 x 8 tile.
+  int ti, tj;
+  if constexpr (TILE == 16) {
+    const int w = lt >> 6, l = lt & 63;
+    ti = l & 15;
+    tj = w + 4 * (l >> 4);
+  } else {
+    const int q = lt >> 3;
+    ti = lt & 7;
+    tj = 2 * (q & 3) + (q >> 2);
+  }
   const int ks = (NDIM == 3) ? M.ks : 1;
   const int kslab = (int)(local % ks);
   const int64_t s = (local / ks) * SUB + sub;
@@ -149,8 +166,8 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
 
   constexpr int NS = lds_planes<NDIM>();
   T *Wring = smem + sub * (NS * PLANE + 2 * NFX + 2 * TILE) * NV;  // [slot][v][PLANE]
-  T *FX = Wring + NS * PLANE * NV;                                  // [v][TILE][TILE + 1]
-  T *FY = FX + NFX * NV;                                            // [v][TILE + 1][TILE]
+  T *FX = Wring + NS * PLANE * NV;                                  // [v][TILE (+ 1)][LP]: TILE + 1 x faces a row
+  T *FY = FX + NFX * NV;                                            // [v][TILE + 1][LP]: TILE y faces a row
   T *XE = FY + NFX * NV;  // [v][2 TILE]: edge fluxes (+x column, +y row) of plane k + 1
   auto slot = [&](int kk) -> T * { return NS == 1 ? Wring : Wring + (kk % NS) * (PLANE * NV); };
 
@@ -226,8 +243,9 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     return own_b + kk * sk;
   };
   auto loadc = [&](const T *base, T *U) {
+    const auto r = buf_rsrc(base);
 #pragma unroll
-    for (int v = 0; v < NV; v++) U[v] = gload_at(base + v * sv, own_ob);
+    for (int v = 0; v < NV; v++) U[v] = buf_load<T>(r, own_ob, (uint32_t)(v * sv * (int)sizeof(T)));
   };
 
   // cells next to F2C faces are finished (and their dt taken) by the flux fix
@@ -330,6 +348,8 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     loadc(up3 + k0 * sk, P3[0]);
   }
 
+  T vloc = T(0);  // running maximum of the CFL limits of the item's cells
+
   // plane k, PH = (k - k0) % 4
   auto plane = [&](auto phase, const int k) __attribute__((always_inline)) {
     constexpr int PH = decltype(phase)::value;
@@ -382,7 +402,8 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     }
 
     // x and y faces of the plane: every thread computes the -x and the -y
-    // face of its cell (FX[v][fj][fi], FY[v][fj][fi], both NFX per variable).
+    // face of its cell (FX[v][fj][fi], FY[v][fj][fi], rows of LP, both NFX per
+    // variable).
     // The TILE extra +x faces of the last column and the TILE extra +y faces
     // of the last row run together in lanes of one wave (the y ones on
     // exchanged velocities); with 4 waves per tile the wave rotates with the
@@ -391,11 +412,11 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       T F[NV];
       plane_face<T, NDIM, PLANE, SCH>(Wp, (tj + 2) * LP + ti, 1, false, gamma, F);  // cells ti-2 .. ti+1
 #pragma unroll
-      for (int v = 0; v < NV; v++) FX[v * NFX + tj * (TILE + 1) + ti] = F[v];
+      for (int v = 0; v < NV; v++) FX[v * NFX + tj * LP + ti] = F[v];
       if (ti == 0 && i0 == 0) store_bflux(0, j0 + tj, k, F);
       plane_face<T, NDIM, PLANE, SCH>(Wp, tj * LP + ti + 2, LP, true, gamma, F);  // cells tj-2 .. tj+1
 #pragma unroll
-      for (int v = 0; v < NV; v++) FY[v * NFX + tj * TILE + ti] = F[v];
+      for (int v = 0; v < NV; v++) FY[v * NFX + tj * LP + ti] = F[v];
       if (tj == 0 && j0 == 0) store_bflux(2, i0 + ti, k, F);
     }
     if constexpr (NDIM == 3 && TT == 256) {
@@ -418,7 +439,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
             T F[NV];
             plane_face<T, NDIM, PLANE, SCH>(pk ? slot(k + 1) : Wp, sw ? TILE * LP + m + 2 : (m + 2) * LP + TILE,
                                        sw ? LP : 1, sw, gamma, F);
-            T *out = pk ? XE + ee : (sw ? FY + TILE * TILE + m : FX + m * (TILE + 1) + TILE);
+            T *out = pk ? XE + ee : (sw ? FY + TILE * LP + m : FX + m * LP + TILE);
             const int ost = pk ? 2 * TILE : NFX;
 #pragma unroll
             for (int v = 0; v < NV; v++) out[v * ost] = F[v];
@@ -429,7 +450,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       } else if (e >= 0 && e < 2 * TILE) {
         const bool sw = e >= TILE;
         const int m = sw ? e - TILE : e;
-        T *out = sw ? FY + TILE * TILE + m : FX + m * (TILE + 1) + TILE;
+        T *out = sw ? FY + TILE * LP + m : FX + m * LP + TILE;
 #pragma unroll
         for (int v = 0; v < NV; v++) out[v * NFX] = XE[v * 2 * TILE + e];
       }
@@ -440,7 +461,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
         const int m = sw ? e - TILE : e;
         T F[NV];
         plane_face<T, NDIM, PLANE, SCH>(Wp, sw ? TILE * LP + m + 2 : (m + 2) * LP + TILE, sw ? LP : 1, sw, gamma, F);
-        T *out = sw ? FY + TILE * TILE + m : FX + m * (TILE + 1) + TILE;
+        T *out = sw ? FY + TILE * LP + m : FX + m * LP + TILE;
 #pragma unroll
         for (int v = 0; v < NV; v++) out[v * NFX] = F[v];
         if (!sw && i0 + TILE == N) store_bflux(1, j0 + m, k, F);
@@ -467,8 +488,8 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     }
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-      const T dfx = FX[v * NFX + tj * (TILE + 1) + ti + 1] - FX[v * NFX + tj * (TILE + 1) + ti];
-      const T dfy = FY[v * NFX + (tj + 1) * TILE + ti] - FY[v * NFX + tj * TILE + ti];
+      const T dfx = FX[v * NFX + tj * LP + ti + 1] - FX[v * NFX + tj * LP + ti];
+      const T dfy = FY[v * NFX + (tj + 1) * LP + ti] - FY[v * NFX + tj * LP + ti];
       T div = dfx + dfy;
       if constexpr (NDIM == 3) div += Fz1[v] - Fz[v];
       T base;
@@ -482,16 +503,17 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     // a tile's rows are contiguous runs of the block's row part; the tiles
     // of a block together write each interior plane as one contiguous range
     if (valid) {
+      const auto r = buf_rsrc(uo + k * sk);
 #pragma unroll
-      for (int v = 0; v < NV; v++) gstore_at(uo + v * sv + k * sk, own_ob, Uout[v]);
+      for (int v = 0; v < NV; v++) buf_store<T>(Uout[v], r, own_ob, (uint32_t)(v * sv * (int)sizeof(T)));
     }
     if ((stage == 2 || (stage >= 3 && ss.epi)) && valid) {
       const bool skip = f2c_adj || (f2c_zlo && k == 0) || (f2c_zhi && k == N - 1);
       if (!skip) {
         if constexpr (sizeof(T) == 8) {
-          vmax = fmax(vmax, cell_inv_dt<NDIM>((const double *)Uout, M.gamma, dx, bad));
+          vloc = fmax(vloc, cell_inv_dt<NDIM>((const double *)Uout, M.gamma, dx, bad));
         } else {
-          vmax = fmax(vmax, cell_inv_dt<NDIM>((const float *)Uout, (float)gamma, (float)idx, bad));
+          vloc = fmaxf(vloc, cell_inv_dt<NDIM>((const float *)Uout, (float)gamma, (float)idx, bad));
         }
       }
     }
@@ -505,6 +527,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     if (k + 3 >= k1) break;
     plane(std::integral_constant<int, 3>{}, k + 3);
   }
+  vmax = fmax(vmax, (double)vloc);
   if constexpr (FEAT) {
     double dr = (double)fr, dp = (double)fp;
 #pragma unroll

@@ -10,7 +10,8 @@ namespace f4 {
 // CFL inverse time step sum_d (|v_d| + c) / dx of one cell.  FP64 states use
 // the operation order of the definition without contraction (equal to a plain
 // evaluation); FP32 states evaluate it in FP32 with the hardware reciprocal
-// and square root, and the maximum over cells is reduced in FP64.
+// and square root, and the maximum over cells is reduced in FP64 (an FP32
+// maximum converts exactly, so a kernel may keep its running maximum in FP32).
 template <int NDIM>
 __device__ __forceinline__ double cell_inv_dt(const double *U, double gamma, double dx, bool &bad) {
 #pragma clang fp contract(off)
@@ -31,7 +32,7 @@ __device__ __forceinline__ double cell_inv_dt(const double *U, double gamma, dou
 }
 
 template <int NDIM>
-__device__ __forceinline__ double cell_inv_dt(const float *U, float gamma, float idx, bool &bad) {
+__device__ __forceinline__ float cell_inv_dt(const float *U, float gamma, float idx, bool &bad) {
   const float r = U[0];
   const float ir = __builtin_amdgcn_rcpf(r);
   float ke = 0.0f, sv = 0.0f;
@@ -45,7 +46,7 @@ __device__ __forceinline__ double cell_inv_dt(const float *U, float gamma, float
   const float cs = __builtin_amdgcn_sqrtf(gamma * p * ir);
   const float s = (sv + NDIM * cs) * idx;
   bad |= !(r > 0.0f) || !(p > 0.0f) || !isfinite(s);
-  return (double)s;
+  return s;
 }
 
 // Wave-level maximum of the CFL limits and the unphysical flag of the
