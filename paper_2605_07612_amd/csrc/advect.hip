@@ -19,6 +19,8 @@
 // earlier states.  With a single variable the work per cell is small, so the
 // kernel is bound by its HBM traffic: the state is read once per stage (plus
 // the face halos, and Heun's second stage reads U^n) and written once.
+#include <type_traits>
+
 #include "device_common.h"
 #include "foap4_internal.h"
 
@@ -168,51 +170,106 @@ __global__ __launch_bounds__(MAXT) void advect_kernel(const MeshDev *__restrict_
       hx[q] = cc < g ? cc - g : N + cc - g;
     }
   }
-  // Loads run one plane ahead of use: the next plane's window cell, halo
-  // cells and earlier-state cells are in flight while the current plane is
-  // computed.
+  // Loads run D planes ahead of use: with one variable a plane holds little
+  // work, so the window cells, halo cells and earlier-state cells of the next
+  // D planes are in flight together (in register slots: plane kk in slot
+  // kk % D; the plane loop is unrolled by D so that every slot is named by a
+  // constant).  FP64 workgroups of 1024 threads (128 registers) keep D = 2,
+  // or D = 1 with WENO5.
+  constexpr int D = (sizeof(T) == 8 && MAXT > 256) ? (LIM == 2 ? 1 : 2) : 4;
   const T *up2 = (const T *)M.s[STG == 4 ? role_buffer(ss.prev2, cur) : cur] + boff;
   const T *up3 = (const T *)M.s[STG == 4 ? role_buffer(ss.prev3, cur) : cur] + boff;
-  T hval[HMAX], pv = T(0), pv2 = T(0), pv3 = T(0), wnext;
-  auto fetch = [&](int kk) {  // the values plane kk needs beyond the window
+  // Addresses: cell (i, j, kk) of the own column is at the wave-uniform
+  // plane base wbase(kk) (this block, or across -z / +z the neighbour's when
+  // gathering) plus the lane's byte offset lo, read and written through
+  // buffer descriptors; a halo cell of this thread is at hp[q] + kk hs[q].
+  const int pstride = (NDIM == 3) ? P * N : 0;  // elements per plane of the row part
+  const uint32_t lo = (uint32_t)(row_of(j, 0) * N + i) * (uint32_t)sizeof(T);
+  auto wbase = [&](int kk) -> const T * {
+    if constexpr (NDIM == 3) {
+      if (kk < 0 && nbp[4]) return nbp[4] + (kk + N) * pstride;
+      if (kk >= N && nbp[5]) return nbp[5] + (kk - N) * pstride;
+    }
+    return ud + kk * pstride;
+  };
+  const T *hp[HMAX];
+  int hs[HMAX];
+#pragma unroll
+  for (int q = 0; q < HMAX; q++) {
+    const int x = hx[q], y = hy[q];
+    hp[q] = ud;
+    hs[q] = 0;
+    if (!hv[q]) continue;
+    if (x < 0 || x >= N) {
+      const T *nb = nbp[x < 0 ? 0 : 1];
+      if (nb) {
+        hp[q] = nb + row_of(y, 0) * N + (x < 0 ? x + N : x - N);
+        hs[q] = pstride;
+      } else {  // stored x ghosts: rows of 2 g after the row part
+        hp[q] = ud + rows * N + row_of(y, 0) * 2 * g + (x < 0 ? x + g : x - N + g);
+        hs[q] = (NDIM == 3) ? P * 2 * g : 0;
+      }
+    } else {
+      const T *src = ud;
+      int yy = y;
+      if (y < 0 && nbp[2]) { src = nbp[2]; yy += N; }
+      else if (y >= N && nbp[3]) { src = nbp[3]; yy -= N; }
+      hp[q] = src + row_of(yy, 0) * N + x;
+      hs[q] = pstride;
+    }
+  }
+  T hq[D][HMAX], pq[D], pq2[D], pq3[D], wq[D];
+  auto fetch = [&](int kk, auto slot) {  // the values plane kk needs beyond the window
+    constexpr int S = decltype(slot)::value;
 #pragma unroll
     for (int q = 0; q < HMAX; q++)
-      if (hv[q]) hval[q] = cell(hx[q], hy[q], kk);
-    const int64_t o = row_of(j, kk) * N + i;
-    if constexpr (STG >= 2) pv = gload(up + o);
+      if (hv[q]) hq[S][q] = gload(hp[q] + kk * hs[q]);
+    if constexpr (STG >= 2) pq[S] = buf_load<T>(buf_rsrc(up + kk * pstride), lo, 0);
     if constexpr (STG == 4) {
-      pv2 = gload(up2 + o);
-      pv3 = gload(up3 + o);
+      pq2[S] = buf_load<T>(buf_rsrc(up2 + kk * pstride), lo, 0);
+      pq3[S] = buf_load<T>(buf_rsrc(up3 + kk * pstride), lo, 0);
     }
-    if constexpr (NDIM == 3) wnext = cell(i, j, kk + R);
-    else wnext = gload(ud + o);
+    wq[S] = buf_load<T>(buf_rsrc(wbase((NDIM == 3) ? kk + R : 0)), lo, 0);
   };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
   // the z window of column (i, j): cells k - R + 1 .. k + R (3-D)
   T w[2 * R];
   if constexpr (NDIM == 3) {
 #pragma unroll
     for (int s = 1; s < 2 * R; s++) w[s] = cell(i, j, s - R);
   }
-  fetch(0);
-  T Fz = T(0);  // flux through the lower z face of the current plane
   const int nk = (NDIM == 3) ? N : 1;
-  for (int k = 0; k < nk; k++) {
+  fetch(0, I0{});
+  if constexpr (D > 1) {
+    if (1 < nk) fetch(1, I1{});
+  }
+  if constexpr (D > 2) {
+    if (2 < nk) fetch(2, I2{});
+    if (3 < nk) fetch(3, I3{});
+  }
+  T Fz = T(0);  // flux through the lower z face of the current plane
+  auto plane = [&](const int k, auto slot) __attribute__((always_inline)) {
+    constexpr int S = decltype(slot)::value;
     T *pl = lds + (k & 1) * Q * Q;  // cell (x, y) at (y + g) Q + x + g
     T c;
     if constexpr (NDIM == 3) {
 #pragma unroll
       for (int s = 0; s < 2 * R - 1; s++) w[s] = w[s + 1];
-      w[2 * R - 1] = wnext;
+      w[2 * R - 1] = wq[S];
       c = w[R - 1];
     } else {
-      c = wnext;
+      c = wq[S];
     }
     pl[(j + g) * Q + i + g] = c;
 #pragma unroll
     for (int q = 0; q < HMAX; q++)
-      if (hv[q]) pl[(hy[q] + g) * Q + hx[q] + g] = hval[q];
-    const T cp = pv, cp2 = pv2, cp3 = pv3;
-    if (k + 1 < nk) fetch(k + 1);
+      if (hv[q]) pl[(hy[q] + g) * Q + hx[q] + g] = hq[S][q];
+    const T cp = (STG >= 2) ? pq[S] : T(0);
+    const T cp2 = (STG == 4) ? pq2[S] : T(0), cp3 = (STG == 4) ? pq3[S] : T(0);
+    if (k + D < nk) fetch(k + D, slot);
     __syncthreads();
     // x faces i - 1/2 and i + 1/2, then y faces, from the staged plane
     T sx[2 * R + 1], sy[2 * R + 1];
@@ -243,19 +300,31 @@ __global__ __launch_bounds__(MAXT) void advect_kernel(const MeshDev *__restrict_
       if (k == N - 1) adv_bflux<T, NDIM>(M, finfo[5], i, j, fzp);
       Fz = fzp;
     }
-    const int64_t o = row_of(j, k) * N + i;
     T base;
     if constexpr (STG == 1) base = c;
     else if constexpr (STG == 2) base = T(0.5) * (cp + c);
     else if constexpr (STG == 3) base = (T)ss.wp * cp + (T)ss.wd * c;
     else base = (((T)ss.wp * cp + (T)ss.wp2 * cp2) + (T)ss.wp3 * cp3) + (T)ss.wd * c;
     const T out = base - cdt * div;
-    gstore(uo + o, out);
+    buf_store<T>(out, buf_rsrc(uo + k * pstride), lo, 0);
     if (STG == 2 || (STG >= 3 && ss.epi)) {
       // the CFL limit of advection is the same in every cell of the block;
       // only the state's finiteness is per cell (cells next to F2C faces
       // are checked after the flux fix)
       if (!isfinite(out)) atomic_max_pos(&M.scal[kBad], 1.0);
+    }
+  };
+  for (int k = 0; k < nk; k += D) {
+    plane(k, I0{});
+    if constexpr (D > 1) {
+      if (k + 1 >= nk) break;
+      plane(k + 1, I1{});
+    }
+    if constexpr (D > 2) {
+      if (k + 2 >= nk) break;
+      plane(k + 2, I2{});
+      if (k + 3 >= nk) break;
+      plane(k + 3, I3{});
     }
   }
   if ((STG == 2 || (STG >= 3 && ss.epi)) && t == 0) {
