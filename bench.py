@@ -72,9 +72,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Before each timed region the leg's own steps run, untimed, for up to
+# SPINUP_S seconds (at most SPINUP_MAX_STEPS steps), so that the GPU's
+# clocks have left their idle state: a timed region of a few milliseconds
+# right after host-side set-up otherwise reads up to ~10 % low.
+SPINUP_S = 0.3
+SPINUP_MAX_STEPS = 200
+
+
 def timed_steps(run, steps, sync):
     import torch
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sync()
+    t0, done = time.perf_counter(), 0
+    while time.perf_counter() - t0 < SPINUP_S and done < SPINUP_MAX_STEPS:
+        run(10)
+        sync()
+        done += 10
     sync()
     t0 = time.perf_counter()
     start.record()
@@ -276,6 +290,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "spinup": {"seconds": SPINUP_S, "max_steps": SPINUP_MAX_STEPS},
         "ms_per_step": round(secs / args.steps * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
