@@ -3,7 +3,7 @@ no GPU work): kernel durations from a kernel trace and per-dispatch hardware
 counters, written as the short text summaries kept beside the results.
 
     python -m paper_2605_07612_amd.profiling trace RUN_kernel_trace.csv OUT.md \\
-        --title "..." --command "rocprofv3 ..." [--match REGEX] [--top 16]
+        --title "..." --command "rocprofv3 ..." [--match REGEX] [--top 16] [--window REGEX:FIRST:COUNT]
     python -m paper_2605_07612_amd.profiling counters OUT.json --kernel REGEX \\
         --csv FETCH_SIZE=RUN1_counter_collection.csv --csv WRITE_SIZE=RUN2_counter_collection.csv \\
         [--csv SQ_INSTS_VALU,SQ_WAVES=RUN3_counter_collection.csv] --command "..." \\
@@ -45,24 +45,48 @@ def _short(name: str) -> str:
 
 
 def read_trace(path):
-    """Kernel dispatches of a rocprofv3 --kernel-trace CSV: (name, grid
-    threads, workgroup, duration in ns)."""
+    """Kernel dispatches of a rocprofv3 --kernel-trace CSV in start order:
+    (name, grid threads, workgroup, duration in ns, start in ns)."""
     out = []
     with open(path) as fh:
         for r in csv.DictReader(fh):
             grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
             wg = int(r["Workgroup_Size_X"]) * int(r["Workgroup_Size_Y"]) * int(r["Workgroup_Size_Z"])
-            out.append((_short(r["Kernel_Name"]), grid, wg, int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+            t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            out.append((_short(r["Kernel_Name"]), grid, wg, t1 - t0, t0))
+    out.sort(key=lambda x: x[4])
     return out
+
+
+def window_table(rows, regex, first, count):
+    """Launches first .. first + count - 1 (in start order) of every kernel
+    whose name matches `regex`, e.g. the steps of a timed region that follow
+    a known number of untimed ones: per kernel the mean duration, and the
+    span from the window's first start to its last end per launch index."""
+    rx = re.compile(regex)
+    per = OrderedDict()
+    for name, grid, wg, ns, t0 in rows:
+        if rx.search(name):
+            per.setdefault(name, []).append((t0, ns))
+    stats, starts, ends = [], [], []
+    for name, v in per.items():
+        w = v[first:first + count]
+        if not w:
+            continue
+        stats.append(dict(kernel=name, launches=len(w), avg_us=sum(ns for _, ns in w) / len(w) / 1e3))
+        starts.append(w[0][0])
+        ends.append(max(t0 + ns for t0, ns in w))
+    span = (max(ends) - min(starts)) / count / 1e3 if stats else 0.0
+    return stats, span
 
 
 def trace_table(rows, match=None, top=16):
     """Per (kernel, grid) statistics, largest total first: the `top` largest
     and every other row whose name matches `match`."""
     groups = OrderedDict()
-    for name, grid, wg, ns in rows:
+    for name, grid, wg, ns, _ in rows:
         groups.setdefault((name, grid, wg), []).append(ns)
-    total = sum(ns for *_, ns in rows) or 1
+    total = sum(r[3] for r in rows) or 1
     stats = []
     for (name, grid, wg), v in groups.items():
         stats.append(dict(kernel=name, grid=grid, workgroup=wg, calls=len(v), avg_us=sum(v) / len(v) / 1e3,
@@ -75,7 +99,7 @@ def trace_table(rows, match=None, top=16):
     return keep
 
 
-def trace_markdown(stats, title, command, note=""):
+def trace_markdown(stats, title, command, note="", window=None):
     lines = [f"# {title}", "", "Command (committed files only):", "", f"    {command}", ""]
     if note:
         lines += [note, ""]
@@ -84,6 +108,14 @@ def trace_markdown(stats, title, command, note=""):
     for s in stats:
         lines.append(f"| {s['kernel']} | {s['grid']} | {s['workgroup']} | {s['calls']} | {s['avg_us']:.1f} | "
                      f"{s['min_us']:.1f} | {s['max_us']:.1f} | {100 * s['share']:.1f} % |")
+    if window:
+        (wstats, span), (regex, first, count) = window
+        lines += ["", f"Window: launches {first} .. {first + count - 1} of each kernel matching `{regex}`", "",
+                  "| kernel | launches | average (us) |", "|---|---:|---:|"]
+        for s in wstats:
+            lines.append(f"| {s['kernel']} | {s['launches']} | {s['avg_us']:.1f} |")
+        lines += ["", f"Sum of the means: {sum(s['avg_us'] for s in wstats):.1f} us; span from the window's first "
+                      f"start to its last end: {span:.1f} us per launch index."]
     return "\n".join(lines) + "\n"
 
 
@@ -154,6 +186,7 @@ def main(argv=None):
     t.add_argument("--note", default="")
     t.add_argument("--match", default=None)
     t.add_argument("--top", type=int, default=16)
+    t.add_argument("--window", default=None, help="KERNEL_REGEX:FIRST:COUNT")
     c = sub.add_parser("counters")
     c.add_argument("out")
     c.add_argument("--kernel", required=True)
@@ -164,9 +197,14 @@ def main(argv=None):
     c.add_argument("--describe", default="")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
-        stats = trace_table(read_trace(a.csv), a.match, a.top)
+        rows = read_trace(a.csv)
+        stats = trace_table(rows, a.match, a.top)
+        window = None
+        if a.window:
+            regex, first, count = a.window.rsplit(":", 2)
+            window = (window_table(rows, regex, int(first), int(count)), (regex, int(first), int(count)))
         with open(a.out, "w") as fh:
-            fh.write(trace_markdown(stats, a.title, a.command, a.note))
+            fh.write(trace_markdown(stats, a.title, a.command, a.note, window))
         return 0
     csvs = []
     for spec in a.csv:
