@@ -277,6 +277,11 @@ def main():
     secs, wall = timed_steps(batch.step, args.steps, torch.cuda.synchronize)
     gcups32 = cells * 2 * args.steps / secs / 1e9
     log(f"FP32 batched: {secs / args.steps * 1e3:.3f} ms/step, {gcups32:.2f} Gcell-updates/s (wall {wall:.3f}s)")
+    # four more timed regions of the same K steps, reported beside the value
+    # (the value is the first region): the spread of repeated measurements
+    reps = [secs] + [timed_steps(batch.step, args.steps, torch.cuda.synchronize)[0] for _ in range(4)]
+    rep_ms = sorted(r / args.steps * 1e3 for r in reps)
+    log("repeats (ms/step):", " ".join(f"{x:.4f}" for x in rep_ms))
     phases = batch.phase_times(5)
     log("phases (ms):", json.dumps({k: round(v, 4) for k, v in phases.items()}))
     stage_bytes = cells * stage_bytes_per_cell(S32, args.block)
@@ -310,6 +315,10 @@ def main():
         "step_hbm": {"bytes_per_update": step_bytes_per_update(S32, True, args.block), "achieved_gbs": round(step_gbs, 1),
                      "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
         "phases_ms": {k: round(v, 5) for k, v in phases.items()},
+        "repeats": {"timed_regions": len(rep_ms), "ms_per_step_min": round(rep_ms[0], 4),
+                    "ms_per_step_median": round(rep_ms[len(rep_ms) // 2], 4),
+                    "ms_per_step_max": round(rep_ms[-1], 4),
+                    "value_at_median": round(cells * 2 / (rep_ms[len(rep_ms) // 2] * 1e-3) / 1e9, 4)},
     }
     del batch, m32
     torch.cuda.empty_cache()
