@@ -557,11 +557,11 @@ __device__ __forceinline__ int64_t item_of(int64_t w, int64_t it, int64_t grid, 
 }
 
 // Target waves per SIMD: single-size FP32 kernels 4 (4 resident workgroups
-// of 4 waves per CU: at 128 registers stage 2 spills ~25 values per lane and
-// still runs ~9 % faster than at 3 waves without spills, since the plane
-// loop waits on its loads); the mixed-size FP32 kernel 3 (its LDS allows 3
-// workgroups per CU; at 168 registers it spills a little and runs ~14 %
-// faster than at 2 waves); FP64 kernels keep what their registers allow.
+// of 4 waves per CU: stage 2 then spills a few values per lane at 128
+// registers, which ran faster than 3 waves without spills); the mixed-size
+// FP32 kernel 3 (its LDS allows 3 workgroups per CU; at 168 registers it
+// spills a little and ran ~14 % faster than at 2 waves); FP64 kernels keep
+// what their registers allow.
 template <typename T, int NM, int STG = 2>
 constexpr int stage_waves() { return sizeof(T) == 4 ? (NM != 7 ? 4 : 3) : 1; }
 

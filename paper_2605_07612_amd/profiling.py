@@ -14,8 +14,8 @@ WRITE_SIZE in KiB).  With --calibrate, FETCH_SIZE and WRITE_SIZE are scaled
 by the factor that makes them read BYTES for the calibration kernel (a plain
 device copy of known size), as the counters of different passes need not
 count whole lines the same way.  --source records a SHA-256 of the kernel's
-source files, so that a reader can tell whether the counters still describe
-the code.
+source files (their code without comments), so that a reader can tell whether
+the counters still describe the code.
 """
 from __future__ import annotations
 
@@ -167,11 +167,31 @@ def counter_summary(csvs, kernel, calibrate=None):
     return out, scale
 
 
+_COMMENT = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
+_STRING = re.compile(r'"(?:\\.|[^"\\\n])*"')
+
+
+def code_text(src: str) -> str:
+    """C/C++ source without comments and with whitespace runs collapsed: two
+    sources that differ only in comments or layout give the same text.
+    String literals are kept (a comment marker inside one is not a comment)."""
+    out, pos = [], 0
+    for m in _STRING.finditer(src):
+        out.append(_COMMENT.sub(" ", src[pos:m.start()]))
+        out.append(m.group(0))
+        pos = m.end()
+    out.append(_COMMENT.sub(" ", src[pos:]))
+    return " ".join("".join(out).split())
+
+
 def sources_sha256(paths):
+    """SHA-256 over the code text (code_text) of the given source files, in
+    order: it changes when the code changes, not when a comment does."""
     h = hashlib.sha256()
     for p in paths:
-        with open(p, "rb") as fh:
-            h.update(fh.read())
+        with open(p, encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
+        h.update(b"\0")
     return h.hexdigest()
 
 
