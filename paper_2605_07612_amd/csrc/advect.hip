@@ -93,8 +93,11 @@ __host__ __device__ constexpr int adv_lds(int N, int g) { return 2 * (N + 2 * g)
 
 // MAXT: the largest workgroup (N^2 threads) the instantiation serves: 1024
 // for 32^2 columns, 256 for 8^2 and 16^2 (which leaves the compiler up to 512
-// registers per thread instead of 128).
-template <typename T, int NDIM, int LIM, bool HLL, int STG, int MAXT>
+// registers per thread instead of 128).  HS: halo cells per thread and
+// plane, ceil(4 g N / N^2): 1, or 2 for 8^2 columns with g >= 3 (N >= 2 g
+// bounds it by 2).  Every register saved is worth it here: the kernel waits
+// on its loads, and more waves per SIMD hide more of that.
+template <typename T, int NDIM, int LIM, bool HLL, int STG, int MAXT, int HS>
 __global__ __launch_bounds__(MAXT) void advect_kernel(const MeshDev *__restrict__ Mp, SubStep ss) {
   constexpr int R = AdvStencil<LIM>::R;
   extern __shared__ __align__(16) unsigned char adv_smem[];
@@ -151,9 +154,8 @@ __global__ __launch_bounds__(MAXT) void advect_kernel(const MeshDev *__restrict_
     }
     return gload(src + row_of(y, kk) * N + x);
   };
-  // this thread's halo cells of a plane (the same (x, y) in every plane):
-  // at most 4 g N / N^2 <= 2 of them, since N >= 2 g
-  constexpr int HMAX = 2;
+  // this thread's halo cells of a plane (the same (x, y) in every plane)
+  constexpr int HMAX = HS;
   int hx[HMAX], hy[HMAX];
   bool hv[HMAX];
 #pragma unroll
@@ -339,22 +341,24 @@ template <typename T, int NDIM, int LIM, bool HLL>
 static void launch_adv(unsigned nb, int N, int g, const MeshDev *d, int stage, const SubStep &ss, hipStream_t s) {
   const unsigned threads = (unsigned)(N * N);
   const size_t lds = (size_t)adv_lds(N, g) * sizeof(T);
-#define F4_ADV(STG, MAXT) advect_kernel<T, NDIM, LIM, HLL, STG, MAXT><<<nb, threads, lds, s>>>(d, ss)
-  if (threads > 256) {
-    switch (stage) {
-      case 1: F4_ADV(1, 1024); break;
-      case 2: F4_ADV(2, 1024); break;
-      case 3: F4_ADV(3, 1024); break;
-      default: F4_ADV(4, 1024); break;
-    }
-  } else {
-    switch (stage) {
-      case 1: F4_ADV(1, 256); break;
-      case 2: F4_ADV(2, 256); break;
-      case 3: F4_ADV(3, 256); break;
-      default: F4_ADV(4, 256); break;
-    }
+#define F4_ADV(STG, MAXT, HS) advect_kernel<T, NDIM, LIM, HLL, STG, MAXT, HS><<<nb, threads, lds, s>>>(d, ss)
+#define F4_ADV_STAGES(MAXT, HS)                \
+  switch (stage) {                             \
+    case 1: F4_ADV(1, MAXT, HS); break;        \
+    case 2: F4_ADV(2, MAXT, HS); break;        \
+    case 3: F4_ADV(3, MAXT, HS); break;        \
+    default: F4_ADV(4, MAXT, HS); break;       \
   }
+  // halo cells of a plane: 4 g N (2-D: also 4 g N per row of planes)
+  const bool two_halo = 4 * g * N > N * N;
+  if (threads > 256) {
+    F4_ADV_STAGES(1024, 1)  // N = 32 with g <= 4: 4 g N <= N^2
+  } else if (two_halo) {
+    F4_ADV_STAGES(256, 2)
+  } else {
+    F4_ADV_STAGES(256, 1)
+  }
+#undef F4_ADV_STAGES
 #undef F4_ADV
 }
 
