@@ -167,20 +167,31 @@ def counter_summary(csvs, kernel, calibrate=None):
     return out, scale
 
 
-_COMMENT = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
-_STRING = re.compile(r'"(?:\\.|[^"\\\n])*"')
-
-
 def code_text(src: str) -> str:
     """C/C++ source without comments and with whitespace runs collapsed: two
-    sources that differ only in comments or layout give the same text.
-    String literals are kept (a comment marker inside one is not a comment)."""
-    out, pos = [], 0
-    for m in _STRING.finditer(src):
-        out.append(_COMMENT.sub(" ", src[pos:m.start()]))
-        out.append(m.group(0))
-        pos = m.end()
-    out.append(_COMMENT.sub(" ", src[pos:]))
+    sources that differ only in comments or layout give the same text.  One
+    pass in source order, so a quote inside a comment starts nothing and a
+    comment marker inside a string or character literal is kept."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c == "/" and src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+            out.append(" ")
+        elif c == "/" and src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c and src[j] != "\n":
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
     return " ".join("".join(out).split())
 
 
