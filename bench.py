@@ -146,7 +146,8 @@ def main():
                     help="short run for hardware-counter passes: a 1 GiB device copy (counter calibration) "
                          "then 3 batched FP32 steps in the given configuration")
     ap.add_argument("--profile-workload", default="noise_shear",
-                    choices=["noise_shear", "rayleigh_taylor", "rayleigh_taylor_weno5", "advection", "two_level"],
+                    choices=["noise_shear", "noise_shear_fp64_plain", "rayleigh_taylor", "rayleigh_taylor_weno5",
+                             "advection", "two_level"],
                     help="workload of --profile-run")
     ap.add_argument("--config", default=None,
                     help="kslabs,wg_stage1,wg_stage2,xcd_order instead of the autotuner's cached choice, for "
@@ -237,6 +238,12 @@ def main():
                 m.close()
                 del m
                 torch.cuda.empty_cache()
+            log("profile run done")
+            return
+        if args.profile_workload == "noise_shear_fp64_plain":  # three plain FP64 steps (stored ghosts)
+            m = make(f4.F64)
+            m.step(3)
+            torch.cuda.synchronize()
             log("profile run done")
             return
         if args.profile_workload == "rayleigh_taylor_weno5":
