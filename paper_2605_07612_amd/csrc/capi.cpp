@@ -24,7 +24,12 @@ foap4_status fail(foap4_mesh *m, foap4_status s, const std::string &msg) {
   return s;
 }
 
-MeshDev make_dev(const foap4_mesh *m, int ks, int gather) {
+// The single-mesh fill copies the x-face SRL records by block for 3D blocks of
+// 16^3 and 32^3; an 8^3 block is too little work for a workgroup, and its
+// records measure faster.
+static bool srl_x_by_block(const foap4_mesh *m) { return m->d.ndim == 3 && m->d.block_n >= 16; }
+
+MeshDev make_dev(const foap4_mesh *m, int ks, int gather, bool x_by_block) {
   MeshDev d{};
   d.s[0] = m->state[0];
   d.s[1] = m->state[1];
@@ -72,11 +77,16 @@ MeshDev make_dev(const foap4_mesh *m, int ks, int gather) {
   // block of a C2F record
   d.r1_srl = gather ? m->pat.n_srl_c2f : m->pat.n[kSRL];
   d.srl_sub = gather ? m->pat.srl_c2f : nullptr;
+  // with stored ghosts, the single mesh's fill copies the x faces by block
+  // (launch_srl_x_blocks) and R1 runs the SRL records from the first y face on
+  // (records are grouped by face direction, the x faces first)
+  d.srl_first = (!gather && x_by_block && srl_x_by_block(m)) ? m->pat.off[kSRL][2] : 0;
+  d.r1_srl -= d.srl_first;
   return d;
 }
 
 foap4_status upload_dev(foap4_mesh *m) {
-  MeshDev d = make_dev(m, 1, 0);
+  MeshDev d = make_dev(m, 1, 0, true);
   F4_HIP(m, hipMemcpyAsync(m->d_dev, &d, sizeof(d), hipMemcpyHostToDevice, m->stream));
   F4_HIP(m, hipStreamSynchronize(m->stream));
   return FOAP4_OK;
@@ -109,9 +119,16 @@ static foap4_status check_bad(foap4_mesh *m) {
   return FOAP4_OK;
 }
 
+// Ghost rounds R1 and R2 of the single mesh (its own descriptor m->d_dev, with
+// the x-face SRL copies done by block): the x faces by block and the other
+// R1 records, then R2, which reads what R1 wrote.
 static foap4_status fill(foap4_mesh *m, const MeshDev *dd, int which) {
   const bool f64 = m->d.prec == FOAP4_F64;
-  const int64_t r1 = m->pat.n[kSRL] + m->pat.n[kF2C] + m->pat.n[kBC], r2 = m->pat.n[kC2F];
+  // x-face SRL records, copied by block where srl_x_by_block holds
+  const int64_t nx = srl_x_by_block(m) ? m->pat.off[kSRL][2] : 0;
+  const int64_t r1 = m->pat.n[kSRL] - nx + m->pat.n[kF2C] + m->pat.n[kBC], r2 = m->pat.n[kC2F];
+  if (nx) F4_HIP(m, launch_srl_x_blocks(dd, (int64_t)m->topo.leaves.size(), which, m->d.ndim, f64, m->stream,
+                                        m->nvar));
   F4_HIP(m, launch_ghost(dd, 1, r1, 1, which, m->d.ndim, f64, 0, m->stream, m->nvar));
   if (r2) F4_HIP(m, launch_ghost(dd, 1, r2, 2, which, m->d.ndim, f64, 0, m->stream, m->nvar));
   return FOAP4_OK;

@@ -130,6 +130,9 @@ struct MeshDev {
                               // reads (indices in srl_sub); R1 then runs pn[kF2C]
                               // restrictions and pn[kBC] boundary faces
   const int32_t *srl_sub;     // with gathered halos: the SRL records R1 runs, else null
+  int32_t srl_first;          // without srl_sub: the first SRL record R1 runs (the
+                              // records before it, the x faces, are copied by block in
+                              // launch_srl_x_blocks)
 };
 
 struct Pattern {
@@ -224,8 +227,11 @@ foap4_status fail(foap4_mesh *m, foap4_status s, const std::string &msg);
   } while (0)
 
 // ks: k-slabs per tile; gather: same-level halos read from the neighbours,
-// so round R1 runs its SRL copies only where R2's prolongation needs them
-MeshDev make_dev(const foap4_mesh *m, int ks, int gather);
+// so round R1 runs its SRL copies only where R2's prolongation needs them;
+// x_by_block (a mesh's own descriptor, stored ghosts): for 3D blocks of 16^3
+// and 32^3, R1 skips the x-face SRL records, which the single-mesh fill copies
+// by block
+MeshDev make_dev(const foap4_mesh *m, int ks, int gather, bool x_by_block = false);
 foap4_status upload_dev(foap4_mesh *m);
 
 // pattern.hip
@@ -235,6 +241,12 @@ foap4_status build_pattern(foap4_mesh *m);
 // nv: variables per cell (ndim + 2 for the Euler system, 1 for scalar advection)
 hipError_t launch_ghost(const MeshDev *d_meshes, int n_meshes, int64_t total, int round, int which,
                         int ndim, bool f64, int grid, hipStream_t s, int nv);
+// Same-level x faces of a single 3D mesh with stored ghosts, by block: block
+// b's first g columns into its -x neighbour's +x ghosts, its last g columns
+// into its +x neighbour's -x ghosts (the x-face SRL records, done by block).
+// Blocks of 16^3 or 32^3 only; ndim other than 3 returns hipErrorInvalidValue.
+hipError_t launch_srl_x_blocks(const MeshDev *d_mesh, int64_t nblocks, int which, int ndim, bool f64, hipStream_t s,
+                               int nv);
 // stage.hip
 int64_t stage_items_for(int ndim, int N, int64_t nb, int ks);
 // nmask: block sizes present in the launch (1: N = 8, 2: N = 16, 4: N = 32);

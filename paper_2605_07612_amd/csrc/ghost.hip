@@ -345,7 +345,7 @@ __device__ void ghost_item(const MeshDev &M, int round, int64_t r, int which) {
   }
   if (round == 1) {
     if (r < M.r1_srl) {
-      if (M.srl_sub) r = M.srl_sub[r];
+      r = M.srl_sub ? M.srl_sub[r] : r + M.srl_first;
       int f = 1;
       while (r >= M.poff[kSRL][f + 1]) f += 2;
 #define F4_SRL(A)                                                      \
@@ -408,6 +408,94 @@ __global__ __launch_bounds__(256) void ghost_kernel(const MeshDev *__restrict__ 
       default: ghost_item<T, NDIM, NV, 32>(M, round, r, which); break;
     }
   }
+}
+
+// The x-face SRL copies of one mesh with stored ghosts, by block.  An SRL
+// record (a, b) fills b's -x ghosts from a's last g columns and a's +x
+// ghosts from b's first g columns; the records that use block b read its rows
+// at different times (they are sorted by their first block), so a row, one
+// or two cache lines, was fetched twice for 2 g of its cells.  Here one
+// workgroup reads each row of its block once, the first and last g cells in
+// adjacent lanes, and writes them to the two same-level x neighbours
+// (coarse-fine and boundary faces keep their own records).  Each face pair is
+// still written exactly once per side.  Used for 3D blocks of 16^3 and 32^3:
+// an 8^3 block is too little work for a workgroup, and its records measure
+// faster.
+template <typename T, int NV, int N>
+__device__ void srl_x_block(const MeshDev &M, T *u, int64_t b) {
+  constexpr int NF = 6;
+  // the block's same-level -x and +x neighbours (-1: none)
+  __shared__ int64_t nbr[2];
+  if (threadIdx.x < 2) {
+    const int32_t f = M.face_info[b * NF + threadIdx.x];
+    nbr[threadIdx.x] = f <= -2 ? (int64_t)(-2 - f) : -1;
+  }
+  __syncthreads();
+  if (nbr[0] < 0 && nbr[1] < 0) return;
+  const int g = M.g;
+  const Geo<3> G(N, g);
+  const int64_t bel = G.sv * NV;
+  const int per_row = 2 * g;  // the row's first g cells, then its last g
+  const int total = NV * N * N * per_row;
+  constexpr int B = 8;  // elements in flight per thread: loads first, then stores
+  for (int e0 = threadIdx.x; e0 < total; e0 += B * blockDim.x) {
+    T val[B];
+    int64_t dsto[B];
+#pragma unroll
+    for (int q = 0; q < B; q++) {
+      const int e = e0 + q * blockDim.x;
+      dsto[q] = -1;
+      if (e >= total) continue;
+      int r = e;
+      const int c = r % per_row;
+      r /= per_row;
+      const int p1 = r % N;  // y
+      r /= N;
+      const int p2 = r % N;  // z
+      const int v = r / N;
+      const bool lo = c < g;
+      const int64_t db = nbr[lo ? 0 : 1];
+      if (db < 0) continue;
+      const int l = lo ? c : c - g;
+      const int src[3] = {lo ? l : N - 1 - l, p1, p2};   // the block's column l, or N - 1 - l
+      const int dst[3] = {lo ? N + l : -1 - l, p1, p2};  // the neighbour's ghost across its face
+      val[q] = u[b * bel + v * G.sv + G.at(src)];
+      dsto[q] = db * bel + v * G.sv + G.at(dst);
+    }
+#pragma unroll
+    for (int q = 0; q < B; q++)
+      if (dsto[q] >= 0) u[dsto[q]] = val[q];
+  }
+}
+
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void srl_x_blocks_kernel(const MeshDev *__restrict__ Mp, int64_t nb, int which) {
+  const MeshDev &M = *Mp;
+  T *u = (T *)M.s[role_buffer(which, M.cur)];
+  // XCD-aware block order (workgroup w runs on XCD w mod 8; XCD x takes the
+  // contiguous blocks [x q + min(x, r), ...), nb = 8 q + r)
+  const int64_t xq = nb / 8, xr = nb % 8, xid = blockIdx.x % 8;
+  const int64_t b = xid * xq + (xid < xr ? xid : xr) + blockIdx.x / 8;
+  if (M.N == 16) srl_x_block<T, NV, 16>(M, u, b);
+  else srl_x_block<T, NV, 32>(M, u, b);
+}
+
+hipError_t launch_srl_x_blocks(const MeshDev *d_mesh, int64_t nblocks, int which, int ndim, bool f64, hipStream_t s,
+                               int nv) {
+  if (nblocks <= 0) return hipSuccess;
+  if (ndim != 3) return hipErrorInvalidValue;
+  const unsigned nblk = (unsigned)nblocks;
+#define F4_XB(T, V) srl_x_blocks_kernel<T, V><<<nblk, 256, 0, s>>>(d_mesh, nblocks, which)
+  if (nv == 1) {  // scalar advection
+    if (f64) F4_XB(double, 1);
+    else F4_XB(float, 1);
+  } else if (f64) {
+    F4_XB(double, 5);
+  } else {
+    F4_XB(float, 5);
+  }
+#undef F4_XB
+  return hipGetLastError();
 }
 
 hipError_t launch_ghost(const MeshDev *d_meshes, int n_meshes, int64_t total, int round, int which,
