@@ -413,8 +413,8 @@ __global__ __launch_bounds__(256) void ghost_kernel(const MeshDev *__restrict__ 
 // The x-face SRL copies of one mesh with stored ghosts, by block.  An SRL
 // record (a, b) fills b's -x ghosts from a's last g columns and a's +x
 // ghosts from b's first g columns; the records that use block b read its rows
-// at different times (they are sorted by their first block), so a row, one
-// or two cache lines, was fetched twice for 2 g of its cells.  Here one
+// at different times (they are sorted by their first block), so the line or
+// lines of a row were fetched twice for 2 g of its cells.  Here one
 // workgroup reads each row of its block once, the first and last g cells in
 // adjacent lanes, and writes them to the two same-level x neighbours
 // (coarse-fine and boundary faces keep their own records).  Each face pair is

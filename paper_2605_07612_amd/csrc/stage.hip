@@ -1,8 +1,9 @@
 // Fused flux/update stage kernel (Sec. 3.2 step list, eq. feuler / eq. heun).
 //
 // Work decomposition (gfx950, wave64): a workgroup of 256 threads processes
-// one work item.  An item is a TILE x TILE column of cells of one block
-// (TILE = 16 for N = 16, 32; for N = 8 four 8 x 8 blocks share the workgroup,
+// one work item.  An item is a TX x TY column of cells of one block (16 x 16
+// for N = 16 and 32; 32 x 8 for 3-D FP32 N = 32, so that no two items share
+// the cache line of a row; for N = 8 four 8 x 8 blocks share the workgroup,
 // one per wave) that marches along k over a slab of N / ks planes.  The
 // primitive variables of the tile and of its +-2 ring are staged in LDS, in a
 // ring of three planes (k, k+1, k+2) that serves both the x/y stencils of
@@ -28,12 +29,23 @@
 
 namespace f4 {
 
-template <int N>
+// Tile of a work item: TX cells along x by TY along y (TB: bytes per value).
+// A 3-D FP32 32^3 block is split along y only: an interior row of 32 FP32
+// values is one 128-byte line, so two items that split rows along x would
+// each fetch every line (their k-marches are not synchronised) and each
+// write half lines.  In FP64 a 16-cell half row is a whole line already, and
+// the 16 x 16 tile keeps its paired edge faces.
+template <int N, int NDIM, int TB = 4>
 struct TileCfg {
-  static constexpr int TILE = (N == 8) ? 8 : 16;
-  static constexpr int SUB = 256 / (TILE * TILE);       // sub-tiles per workgroup
-  static constexpr int TPB = (N / TILE) * (N / TILE);   // tiles per block plane
+  static constexpr bool WIDE = N == 32 && NDIM == 3 && TB == 4;
+  static constexpr int TX = (N == 8) ? 8 : WIDE ? 32 : 16;
+  static constexpr int TY = (N == 8) ? 8 : WIDE ? 8 : 16;
+  static constexpr int SUB = 256 / (TX * TY);        // sub-tiles per workgroup
+  static constexpr int TPB = (N / TX) * (N / TY);    // tiles per block plane
 };
+// the host counts items without the value type: both tilings give the same
+static_assert(TileCfg<32, 3, 4>::TPB == TileCfg<32, 3, 8>::TPB && TileCfg<32, 3, 4>::SUB == TileCfg<32, 3, 8>::SUB,
+              "item counts must not depend on the value type");
 
 // Primitive planes held in LDS: k, k+1, k+2 in a ring of three slots (3D).
 template <int NDIM>
@@ -41,20 +53,20 @@ constexpr int lds_planes() { return NDIM == 3 ? 3 : 1; }
 
 // LDS elements of one work item: SUB * (planes + x faces + y faces + the
 // edge fluxes of the next plane) * NV.
-template <int NDIM, int N>
+template <int NDIM, int N, int TB>
 constexpr int item_cells() {
-  using C = TileCfg<N>;
-  return C::SUB * (lds_planes<NDIM>() * (C::TILE + 4) * (C::TILE + 4) + 2 * (C::TILE + 1) * (C::TILE + 4) + 2 * C::TILE) *
+  using C = TileCfg<N, NDIM, TB>;
+  return C::SUB * (lds_planes<NDIM>() * (C::TX + 4) * (C::TY + 4) + 2 * (C::TY + 1) * (C::TX + 4) + 2 * C::TX) *
          (NDIM + 2);
 }
 
 // LDS elements per workgroup: the maximum over the block sizes in NM.
-template <int NDIM, int NM>
+template <int NDIM, int NM, int TB>
 constexpr int smem_cells() {
   int c = 0;
-  if (NM & 1) c = item_cells<NDIM, 8>() > c ? item_cells<NDIM, 8>() : c;
-  if (NM & 2) c = item_cells<NDIM, 16>() > c ? item_cells<NDIM, 16>() : c;
-  if (NM & 4) c = item_cells<NDIM, 32>() > c ? item_cells<NDIM, 32>() : c;
+  if (NM & 1) c = item_cells<NDIM, 8, TB>() > c ? item_cells<NDIM, 8, TB>() : c;
+  if (NM & 2) c = item_cells<NDIM, 16, TB>() > c ? item_cells<NDIM, 16, TB>() : c;
+  if (NM & 4) c = item_cells<NDIM, 32, TB>() > c ? item_cells<NDIM, 32, TB>() : c;
   return c;
 }
 
@@ -92,13 +104,13 @@ template <typename T, int NDIM, int N, int SCH, bool FEAT = false>
 __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t local, T *smem,
                                            double &vmax, bool &bad, double *feat_raw = nullptr,
                                            const SubStep &ss = SubStep{}) {
-  using C = TileCfg<N>;
-  constexpr int TILE = C::TILE, SUB = C::SUB, TPB = C::TPB;
+  using C = TileCfg<N, NDIM, (int)sizeof(T)>;
+  constexpr int TX = C::TX, TY = C::TY, SUB = C::SUB, TPB = C::TPB;
   constexpr int NV = NDIM + 2;
-  constexpr int LP = TILE + 4;
-  constexpr int PLANE = LP * LP;
-  constexpr int NFX = (TILE + 1) * LP;  // x (and y) face flux slots per variable (rows of LP)
-  constexpr int TT = TILE * TILE;
+  constexpr int LP = TX + 4;            // LDS row stride
+  constexpr int PLANE = LP * (TY + 4);
+  constexpr int NFX = (TY + 1) * LP;  // x (and y) face flux slots per variable (rows of LP)
+  constexpr int TT = TX * TY;
   constexpr int NF = 2 * NDIM;
 
   const int tid = threadIdx.x;
@@ -106,18 +118,23 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   // slab are wave-uniform, and so are the base addresses derived from them
   const int sub = __builtin_amdgcn_readfirstlane(tid / TT), lt = tid % TT;
   // Lanes to cells: LDS has 32 banks of 4 bytes and serves a wave in two
-  // halves of 32 lanes.  With the row stride LP = TILE + 4 (20, or 12 for
+  // halves of 32 lanes.  With the row stride LP = TX + 4 (20, or 12 for
   // 8 x 8 tiles), rows r and r + 4 (r + 2) start 16 (24) banks apart, so a
   // half wave that holds two rows of 16 (four rows of 8) spaced that way
   // reads and writes every plane and face array without bank conflicts;
   // adjacent rows would share 4 banks.  Each wave thus holds the rows
   // w, w + 4, w + 8, w + 12 of a 16 x 16 tile (w the wave), or the even rows
-  // then the odd rows of an 8 x 8 tile.
+  // then the odd rows of an 8 x 8 tile.  In a 32 x 8 tile a half wave is one
+  // whole row (the wave holds rows w and w + 4).
   int ti, tj;
-  if constexpr (TILE == 16) {
+  if constexpr (TX == 16) {
     const int w = lt >> 6, l = lt & 63;
     ti = l & 15;
     tj = w + 4 * (l >> 4);
+  } else if constexpr (TX == 32) {
+    const int w = lt >> 6, l = lt & 63;
+    ti = l & 31;
+    tj = w + 4 * (l >> 5);
   } else {
     const int q = lt >> 3;
     ti = lt & 7;
@@ -129,7 +146,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   const bool valid = (s / TPB) < M.nb;
   const int64_t b = valid ? s / TPB : M.nb - 1;
   const int tile = (int)(s % TPB);
-  const int i0 = (tile % (N / TILE)) * TILE, j0 = (tile / (N / TILE)) * TILE;
+  const int i0 = (tile % (N / TX)) * TX, j0 = (tile / (N / TX)) * TY;
   const int kd = (NDIM == 3) ? N / ks : 1;
   const int k0 = (NDIM == 3) ? kslab * kd : 0, k1 = k0 + kd;
   const int g = M.g, P = N + 2 * g;
@@ -165,10 +182,10 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   auto nbr_of = [&](int f) -> int64_t { return (M.gather && finfo[f] <= -2) ? (int64_t)(-2 - finfo[f]) : -1; };
 
   constexpr int NS = lds_planes<NDIM>();
-  T *Wring = smem + sub * (NS * PLANE + 2 * NFX + 2 * TILE) * NV;  // [slot][v][PLANE]
-  T *FX = Wring + NS * PLANE * NV;                                  // [v][TILE (+ 1)][LP]: TILE + 1 x faces a row
-  T *FY = FX + NFX * NV;                                            // [v][TILE + 1][LP]: TILE y faces a row
-  T *XE = FY + NFX * NV;  // [v][2 TILE]: edge fluxes (+x column, +y row) of plane k + 1
+  T *Wring = smem + sub * (NS * PLANE + 2 * NFX + 2 * TX) * NV;  // [slot][v][PLANE]
+  T *FX = Wring + NS * PLANE * NV;                                // [v][TY (+ 1)][LP]: TX + 1 x faces a row
+  T *FY = FX + NFX * NV;                                          // [v][TY + 1][LP]: TX y faces a row
+  T *XE = FY + NFX * NV;  // [v][2 TX]: edge fluxes (+x column, +y row) of plane k + 1 (square tiles)
   auto slot = [&](int kk) -> T * { return NS == 1 ? Wring : Wring + (kk % NS) * (PLANE * NV); };
 
   auto off = [&](int ii, int jj, int kk) -> int { return cell_off<NDIM>(ii, jj, kk, N, g); };
@@ -189,16 +206,16 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
   };
 
   // ring cell of this thread (x ghosts: 4 per row; y ghosts: 4 rows)
-  const bool ring = lt < 8 * TILE;
+  const bool ring = lt < 4 * (TX + TY);
   int ri = 0, rj = 0;
-  if (lt < 4 * TILE) {
+  if (lt < 4 * TY) {
     const int c = lt & 3;
     rj = lt >> 2;
-    ri = (c < 2) ? c - 2 : TILE + c - 2;
+    ri = (c < 2) ? c - 2 : TX + c - 2;
   } else if (ring) {
-    const int r = lt - 4 * TILE, c = r / TILE;
-    ri = r % TILE;
-    rj = (c < 2) ? c - 2 : TILE + c - 2;
+    const int r = lt - 4 * TY, c = r / TX;
+    ri = r % TX;
+    rj = (c < 2) ? c - 2 : TY + c - 2;
   }
   const int ring_lds = (rj + 2) * LP + (ri + 2);
   const int own_lds = (tj + 2) * LP + (ti + 2);
@@ -404,7 +421,7 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
     // x and y faces of the plane: every thread computes the -x and the -y
     // face of its cell (FX[v][fj][fi], FY[v][fj][fi], rows of LP, both NFX per
     // variable).
-    // The TILE extra +x faces of the last column and the TILE extra +y faces
+    // The TY extra +x faces of the last column and the TX extra +y faces
     // of the last row run together in lanes of one wave (the y ones on
     // exchanged velocities); with 4 waves per tile the wave rotates with the
     // plane (pair) so that every SIMD gets its share.
@@ -419,14 +436,17 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       for (int v = 0; v < NV; v++) FY[v * NFX + tj * LP + ti] = F[v];
       if (tj == 0 && j0 == 0) store_bflux(2, i0 + ti, k, F);
     }
-    if constexpr (NDIM == 3 && TT == 256) {
+    if constexpr (NDIM == 3 && TT == 256 && TX == TY) {
+      constexpr int TILE = TX;
       // 3D tiles of 16 x 16: the edge faces of planes k and k + 1 together,
       // every other plane, in the 64 lanes of one wave (one plane's 2 TILE
       // edge faces would leave half of it idle); the fluxes of plane k + 1
       // wait in XE and are put in place on the next plane (the planes of a
       // slab come in pairs: N / kslabs is even).  For 8^3 blocks each wave
       // keeps its own plane's 16 edge faces: pairing them there costs more
-      // registers (and occupancy) than it saves.
+      // registers (and occupancy) than it saves.  A 32 x 8 tile has 40 edge
+      // faces a plane, too many to pair in 64 lanes: one wave takes them on
+      // every plane.
       const int pair = (k - k0) >> 1;
       const int e = lt - 64 * ((pair + (int)local) & 3);
       if (((k - k0) & 1) == 0) {
@@ -456,16 +476,16 @@ __device__ __forceinline__ void stage_item(const MeshDev &M, int stage, int64_t 
       }
     } else {
       const int e = (TT == 256) ? lt - 64 * ((k + (int)local) & 3) : lt;
-      if (e >= 0 && e < 2 * TILE) {
-        const bool sw = e >= TILE;
-        const int m = sw ? e - TILE : e;
+      if (e >= 0 && e < TX + TY) {
+        const bool sw = e >= TY;
+        const int m = sw ? e - TY : e;
         T F[NV];
-        plane_face<T, NDIM, PLANE, SCH>(Wp, sw ? TILE * LP + m + 2 : (m + 2) * LP + TILE, sw ? LP : 1, sw, gamma, F);
-        T *out = sw ? FY + TILE * LP + m : FX + m * LP + TILE;
+        plane_face<T, NDIM, PLANE, SCH>(Wp, sw ? TY * LP + m + 2 : (m + 2) * LP + TX, sw ? LP : 1, sw, gamma, F);
+        T *out = sw ? FY + TY * LP + m : FX + m * LP + TX;
 #pragma unroll
         for (int v = 0; v < NV; v++) out[v * NFX] = F[v];
-        if (!sw && i0 + TILE == N) store_bflux(1, j0 + m, k, F);
-        if (sw && j0 + TILE == N) store_bflux(3, i0 + m, k, F);
+        if (!sw && i0 + TX == N) store_bflux(1, j0 + m, k, F);
+        if (sw && j0 + TY == N) store_bflux(3, i0 + m, k, F);
       }
     }
     __syncthreads();
@@ -574,7 +594,7 @@ template <typename T, int NDIM, int NM, int STG, int SCH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM, STG>())))
 void stage_kernel(const MeshDev *__restrict__ meshes, int n_meshes, int64_t total, int xcd, SubStep ss) {
   constexpr int stage = STG;
-  __shared__ T smem[smem_cells<NDIM, NM>()];
+  __shared__ T smem[smem_cells<NDIM, NM, (int)sizeof(T)>()];
   double vmax = 0.0;
   bool bad = false;
   int mprev = -1;
@@ -633,7 +653,7 @@ static void launch_t(unsigned nblk, int nmask, const MeshDev *d, int n, int64_t 
 template <typename T, int NDIM, int NM, int SCH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves<T, NM, 1>())))
 void stage1_feat_kernel(const MeshDev *__restrict__ Mp, int64_t total, double *feat_raw) {
-  __shared__ T smem[smem_cells<NDIM, NM>()];
+  __shared__ T smem[smem_cells<NDIM, NM, (int)sizeof(T)>()];
   constexpr int N = (NM == 1) ? 8 : (NM == 2) ? 16 : 32;
   double vmax = 0.0;
   bool bad = false;
@@ -691,12 +711,16 @@ template hipError_t launch_stage_sch<F4_SCHEME>(const MeshDev *, int, int64_t, i
 template hipError_t launch_feat_sch<F4_SCHEME>(const MeshDev *, int64_t, int, bool, int, double *, hipStream_t);
 
 #if F4_SCHEME == 0
+template <int N, int NDIM>
+static int64_t items_of(int64_t nb, int ks) {
+  using C = TileCfg<N, NDIM>;
+  const int64_t tiles = nb * C::TPB;
+  return ((tiles + C::SUB - 1) / C::SUB) * (NDIM == 3 ? ks : 1);
+}
+
 int64_t stage_items_for(int ndim, int N, int64_t nb, int ks) {
-  const int tile = (N == 8) ? 8 : 16;
-  const int sub = 256 / (tile * tile);
-  const int tpb = (N / tile) * (N / tile);
-  const int64_t tiles = nb * tpb;
-  return ((tiles + sub - 1) / sub) * (ndim == 3 ? ks : 1);
+  if (ndim == 3) return N == 8 ? items_of<8, 3>(nb, ks) : N == 16 ? items_of<16, 3>(nb, ks) : items_of<32, 3>(nb, ks);
+  return N == 8 ? items_of<8, 2>(nb, ks) : N == 16 ? items_of<16, 2>(nb, ks) : items_of<32, 2>(nb, ks);
 }
 
 // the other schemes' launchers live in the other compiles of this file
