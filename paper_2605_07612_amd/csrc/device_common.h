@@ -62,15 +62,22 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return fma(r, e, r);
 }
 
-// sqrt(r) and 1/sqrt(r) of a positive density: one reciprocal square root
-// (FP32), or IEEE square root and the refined reciprocal of it (FP64).
+// sqrt(r) and 1/sqrt(r) of a positive, normal density: one reciprocal
+// square root and s = r q.  FP64 refines the hardware estimate of 1/sqrt(r)
+// by two Newton-Raphson steps q <- q + (q/2)(1 - r q^2), each of which about
+// doubles the correct bits, so q and s are within a few ulp (the IEEE square
+// root and a refined reciprocal of it cost about twice the instructions).
 __device__ __forceinline__ void sqrt_and_rsq(float r, float &s, float &q) {
   q = __builtin_amdgcn_rsqf(r);
   s = r * q;
 }
 __device__ __forceinline__ void sqrt_and_rsq(double r, double &s, double &q) {
-  s = sqrt(r);
-  q = rcp_nr(s);
+  double y = __builtin_amdgcn_rsq(r);
+  double e = fma(-(r * y), y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-(r * y), y, 1.0);
+  q = fma(0.5 * y, e, y);
+  s = r * q;
 }
 
 // Reciprocal and square root: the hardware approximations (about 1 ulp) for
