@@ -333,6 +333,67 @@ __device__ void bc_record(const MeshDev &M, T *u, int side, int64_t rec, int32_t
   }
 }
 
+// y and z faces: the ghost rows (y) and planes (z) are whole row parts of N
+// interior x cells, so each thread moves 16 bytes (4 FP32 or 2 FP64 values
+// along x) with one vector load and one vector store.  Every offset is a
+// multiple of 16 bytes: N is a multiple of 4, the row part of a row starts
+// at row N, the variable stride P^d and the block stride NV P^d are
+// multiples of 4 (P = N + 2g is even), and state buffers are 16-byte aligned.
+template <typename T>
+struct Quad {
+  static constexpr int W = 16 / (int)sizeof(T);
+  typedef T type __attribute__((ext_vector_type(W)));
+};
+
+template <typename T, int NDIM, int NV, int N, int ax>
+__device__ void srl_record_rows(const MeshDev &M, T *u, int32_t a, int32_t b) {
+  static_assert(ax >= 1 && ax < NDIM, "row copies serve the y and z faces");
+  using VT = typename Quad<T>::type;
+  constexpr int W = Quad<T>::W, NW = N / W;
+  static_assert(N % W == 0, "rows hold whole 16-byte chunks");
+  constexpr int N2 = (NDIM == 3) ? N : 1;
+  const Geo<NDIM> G(N, M.g);
+  const int g = M.g;
+  constexpr int t2 = Tang<NDIM, ax>::t2;
+  const int64_t bel = G.sv * NV;
+  const int total = 2 * NV * N2 * NW * g;
+  constexpr int B = 4;  // chunks in flight per thread: loads first, then stores
+  for (int e0 = threadIdx.x; e0 < total; e0 += B * blockDim.x) {
+    VT val[B];
+    int64_t dsto[B];
+#pragma unroll
+    for (int q = 0; q < B; q++) {
+      const int e = e0 + q * blockDim.x;
+      dsto[q] = -1;
+      if (e >= total) continue;
+      int l, p2, r = e;
+      const int c = r % NW;  // 16-byte chunk of the row part
+      r /= NW;
+      if (ax == 1) {  // the g ghost rows of a plane are adjacent
+        l = r % g; r /= g;
+        p2 = r % N2; r /= N2;
+      } else {        // a z ghost plane is N^2 contiguous values
+        p2 = r % N2; r /= N2;
+        l = r % g; r /= g;
+      }
+      const int v = r % NV, side = r / NV;
+      int src[3] = {c * W, 0, 0}, dst[3] = {c * W, 0, 0};
+      if constexpr (t2 >= 0) src[t2] = dst[t2] = p2;
+      int64_t sb, db;
+      if (side == 0) {  // b's -ax ghosts from a's last layers
+        src[ax] = N - 1 - l; dst[ax] = -1 - l; sb = a; db = b;
+      } else {          // a's +ax ghosts from b's first layers
+        src[ax] = l; dst[ax] = N + l; sb = b; db = a;
+      }
+      val[q] = *(const VT *)(u + sb * bel + v * G.sv + G.at(src));
+      dsto[q] = db * bel + v * G.sv + G.at(dst);
+    }
+#pragma unroll
+    for (int q = 0; q < B; q++)
+      if (dsto[q] >= 0) *(VT *)(u + dsto[q]) = val[q];
+  }
+}
+
 template <typename T, int NDIM, int NV, int N>
 __device__ void ghost_item(const MeshDev &M, int round, int64_t r, int which) {
   T *u = (T *)M.s[role_buffer(which, M.cur)];
@@ -348,11 +409,13 @@ __device__ void ghost_item(const MeshDev &M, int round, int64_t r, int which) {
       r = M.srl_sub ? M.srl_sub[r] : r + M.srl_first;
       int f = 1;
       while (r >= M.poff[kSRL][f + 1]) f += 2;
-#define F4_SRL(A)                                                      \
-  do {                                                                 \
-    if ((A) == 0 && M.g == 2)                                          \
+#define F4_SRL(A)                                                          \
+  do {                                                                     \
+    if constexpr ((A) > 0)                                                 \
+      srl_record_rows<T, NDIM, NV, N, A>(M, u, M.srl[2 * r], M.srl[2 * r + 1]); \
+    else if (M.g == 2)                                                     \
       srl_record_x2<T, NDIM, NV, N>(M, u, M.srl[2 * r], M.srl[2 * r + 1]); \
-    else                                                               \
+    else                                                                   \
       srl_record<T, NDIM, NV, N, A>(M, u, M.srl[2 * r], M.srl[2 * r + 1]); \
   } while (0)
       F4_BY_AXIS(F4_SRL)
