@@ -85,7 +85,7 @@ def face_ghost_mask(ndim, N, g):
 
 
 # Bounds of a GPU state against the FP64 oracle: the volume-weighted relative
-# L1 error of the benchmark spec (FP64 1e-12, FP32 2e-5) and, so that an error
+# L1 error of the parity target (FP64 1e-12, FP32 2e-5) and, so that an error
 # confined to a few cells cannot hide in the global norm, a per-element bound
 # max |a - b| <= tol * max |b| over every cell and variable (FP64 1e-10,
 # FP32 1e-5: a few hundred roundings of the state's own precision).
