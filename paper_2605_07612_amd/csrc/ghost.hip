@@ -204,20 +204,36 @@ __device__ void f2c_record(const MeshDev &M, T *u, int side, int32_t cb, int32_t
 
 // limited prolongation (Sec. 2.2) of coarse cell P of block data uc for the
 // child whose position is sig (+-1 per axis); slopes and sum in FP64, axes
-// summed in order x, y, z
+// summed in order x, y, z.  The stencil (P and its two neighbours per axis)
+// is loaded first, so that a thread can keep several in flight.
 template <typename T, int NDIM>
-__device__ __forceinline__ double prolong(const T *uc, const Geo<NDIM> &G, const int P[3], const int sig[3]) {
-  // no contraction: u_P + corr / 4 rounded twice as written, which also
-  // holds when corr / 4 is subnormal (where a fused multiply-add would differ)
-#pragma clang fp contract(off)
-  const double up = uc[G.at(P)];
-  double corr = 0.0;
+struct Stencil {
+  T c, lo[NDIM], hi[NDIM];
+};
+
+template <typename T, int NDIM>
+__device__ __forceinline__ void load_stencil(const T *uc, const Geo<NDIM> &G, const int P[3], Stencil<T, NDIM> &s) {
+  s.c = uc[G.at(P)];
 #pragma unroll
   for (int d = 0; d < NDIM; d++) {
     int lo[3] = {P[0], P[1], P[2]}, hi[3] = {P[0], P[1], P[2]};
     lo[d] -= 1;
     hi[d] += 1;
-    const double delta = mm(up - (double)uc[G.at(lo)], (double)uc[G.at(hi)] - up);
+    s.lo[d] = uc[G.at(lo)];
+    s.hi[d] = uc[G.at(hi)];
+  }
+}
+
+template <typename T, int NDIM>
+__device__ __forceinline__ double prolong(const Stencil<T, NDIM> &s, const int sig[3]) {
+  // no contraction: u_P + corr / 4 rounded twice as written, which also
+  // holds when corr / 4 is subnormal (where a fused multiply-add would differ)
+#pragma clang fp contract(off)
+  const double up = s.c;
+  double corr = 0.0;
+#pragma unroll
+  for (int d = 0; d < NDIM; d++) {
+    const double delta = mm(up - (double)s.lo[d], (double)s.hi[d] - up);
     const double term = sig[d] > 0 ? delta : -delta;
     corr = (d == 0) ? term : corr + term;
   }
@@ -234,32 +250,48 @@ __device__ void c2f_record(const MeshDev &M, T *u, int side, int32_t q, int32_t 
   const int bt1 = h & 1, bt2 = (h >> 1) & 1;
   const int64_t bel = G.sv * NV;
   const int total = NV * N2 * N * g;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    int l, p1, p2, v, r = e;
-    if (ax == 0) {
-      l = r % g; r /= g;
-      p1 = r % N; r /= N;
-    } else {
-      p1 = r % N; r /= N;
-      l = r % g; r /= g;
+  // elements in flight per thread, stencils first, then values: two in FP32;
+  // in FP64 a second stencil would cost the ghost kernel a wave per SIMD
+  constexpr int B = sizeof(T) == 4 ? 2 : 1;
+  for (int e0 = threadIdx.x; e0 < total; e0 += B * blockDim.x) {
+    Stencil<T, NDIM> st[B];
+    int sg[B][3];
+    int64_t dsto[B];
+#pragma unroll
+    for (int k = 0; k < B; k++) {
+      const int e = e0 + k * blockDim.x;
+      dsto[k] = -1;
+      if (e >= total) continue;
+      int l, p1, p2, v, r = e;
+      if (ax == 0) {
+        l = r % g; r /= g;
+        p1 = r % N; r /= N;
+      } else {
+        p1 = r % N; r /= N;
+        l = r % g; r /= g;
+      }
+      p2 = r % N2; v = r / N2;
+      const int L = l + 1;
+      int fc[3] = {0, 0, 0}, P[3] = {0, 0, 0};
+      sg[k][0] = sg[k][1] = sg[k][2] = 0;
+      fc[ax] = side ? N - 1 + L : -L;
+      const int fn = side ? (L - 1) : (2 * N - L);
+      P[ax] = fn >> 1;
+      sg[k][ax] = (fn & 1) ? 1 : -1;
+      fc[t1] = p1;
+      P[t1] = bt1 * H + (p1 >> 1);
+      sg[k][t1] = (p1 & 1) ? 1 : -1;
+      if constexpr (t2 >= 0) {
+        fc[t2] = p2;
+        P[t2] = bt2 * H + (p2 >> 1);
+        sg[k][t2] = (p2 & 1) ? 1 : -1;
+      }
+      load_stencil<T, NDIM>(u + (int64_t)cb * bel + v * G.sv, G, P, st[k]);
+      dsto[k] = (int64_t)q * bel + v * G.sv + G.at(fc);
     }
-    p2 = r % N2; v = r / N2;
-    const int L = l + 1;
-    int fc[3] = {0, 0, 0}, P[3] = {0, 0, 0}, sig[3] = {0, 0, 0};
-    fc[ax] = side ? N - 1 + L : -L;
-    const int fn = side ? (L - 1) : (2 * N - L);
-    P[ax] = fn >> 1;
-    sig[ax] = (fn & 1) ? 1 : -1;
-    fc[t1] = p1;
-    P[t1] = bt1 * H + (p1 >> 1);
-    sig[t1] = (p1 & 1) ? 1 : -1;
-    if constexpr (t2 >= 0) {
-      fc[t2] = p2;
-      P[t2] = bt2 * H + (p2 >> 1);
-      sig[t2] = (p2 & 1) ? 1 : -1;
-    }
-    const double val = prolong<T, NDIM>(u + (int64_t)cb * bel + v * G.sv, G, P, sig);
-    u[(int64_t)q * bel + v * G.sv + G.at(fc)] = (T)val;
+#pragma unroll
+    for (int k = 0; k < B; k++)
+      if (dsto[k] >= 0) u[dsto[k]] = (T)prolong<T, NDIM>(st[k], sg[k]);
   }
 }
 
