@@ -109,35 +109,63 @@ __global__ __launch_bounds__(256) void fluxfix_kernel(const MeshDev *__restrict_
   const int64_t fv = (int64_t)N * N2;  // face values per variable
   const T *bf = (const T *)M.bflux_f;
   const T *bc = (const T *)M.bflux_c;
+  // the fine-side flux slots of the face's 2^(d-1) F2C records, read once
+  __shared__ int32_t kfs[PER];
+  constexpr int B = 2;  // face cells in flight per thread: loads first, then updates
   for (int f = 0; f < NF; f++) {
     const int info = M.face_info[(int64_t)cb * NF + f];
     if (info < 0 || !(info & 1)) continue;
     const int ax = f / 2, side = f % 2;
     const int t1 = (ax == 0) ? 1 : 0, t2 = (NDIM == 3) ? ((ax == 2) ? 1 : 2) : -1;
     const int64_t grp = info >> 1;
-    for (int e = threadIdx.x; e < NV * fv; e += blockDim.x) {
-      const int p1 = e % N, p2 = (e / N) % N2, v = e / (int)fv;
-      const int bt1 = p1 >= H, bt2 = (NDIM == 3) ? (p2 >= H) : 0;
-      const int h = bt1 + 2 * bt2;
-      const int32_t kf = M.f2c[4 * (grp * PER + h) + 3];
-      const double Fc = (double)bc[(grp * NV + v) * fv + (int64_t)p2 * N + p1];
-      const int q1 = 2 * (p1 - bt1 * H), q2 = (NDIM == 3) ? 2 * (p2 - bt2 * H) : 0;
-      const T *ff = bf + ((int64_t)kf * NV + v) * fv;
-      double mean;
-      if (NDIM == 3) {
-        const double s0 = (double)ff[(int64_t)q2 * N + q1] + (double)ff[(int64_t)q2 * N + q1 + 1];
-        const double s1 = (double)ff[(int64_t)(q2 + 1) * N + q1] + (double)ff[(int64_t)(q2 + 1) * N + q1 + 1];
-        mean = (s0 + s1) * 0.25;
-      } else {
-        mean = ((double)ff[q1] + (double)ff[q1 + 1]) * 0.5;
+    if (threadIdx.x < PER) kfs[threadIdx.x] = M.f2c[4 * (grp * PER + threadIdx.x) + 3];
+    __syncthreads();
+    const int total = NV * (int)fv;
+    for (int e0 = threadIdx.x; e0 < total; e0 += B * blockDim.x) {
+      double Fc[B], f0[B], f1[B], f2[B], f3[B], uv[B];
+      int64_t o[B];
+#pragma unroll
+      for (int k = 0; k < B; k++) {
+        const int e = e0 + k * blockDim.x;
+        o[k] = -1;
+        if (e >= total) continue;
+        const int p1 = e % N, p2 = (e / N) % N2, v = e / (int)fv;
+        const int bt1 = p1 >= H, bt2 = (NDIM == 3) ? (p2 >= H) : 0;
+        const int32_t kf = kfs[bt1 + 2 * bt2];
+        Fc[k] = (double)bc[(grp * NV + v) * fv + (int64_t)p2 * N + p1];
+        const int q1 = 2 * (p1 - bt1 * H), q2 = (NDIM == 3) ? 2 * (p2 - bt2 * H) : 0;
+        const T *ff = bf + ((int64_t)kf * NV + v) * fv;
+        if (NDIM == 3) {
+          f0[k] = (double)ff[(int64_t)q2 * N + q1];
+          f1[k] = (double)ff[(int64_t)q2 * N + q1 + 1];
+          f2[k] = (double)ff[(int64_t)(q2 + 1) * N + q1];
+          f3[k] = (double)ff[(int64_t)(q2 + 1) * N + q1 + 1];
+        } else {
+          f0[k] = (double)ff[q1];
+          f1[k] = (double)ff[q1 + 1];
+          f2[k] = f3[k] = 0.0;
+        }
+        int c[3] = {0, 0, 0};
+        c[ax] = side ? N - 1 : 0;
+        c[t1] = p1;
+        if (t2 >= 0) c[t2] = p2;
+        o[k] = (int64_t)v * sv + cell_off<NDIM>(c[0], c[1], c[2], N, g);
+        uv[k] = (double)uo[o[k]];
       }
-      int c[3] = {0, 0, 0};
-      c[ax] = side ? N - 1 : 0;
-      c[t1] = p1;
-      if (t2 >= 0) c[t2] = p2;
-      const int64_t o = (int64_t)v * sv + cell_off<NDIM>(c[0], c[1], c[2], N, g);
-      const double corr = side ? dts * (Fc - mean) / dx : dts * (mean - Fc) / dx;
-      uo[o] = (T)((double)uo[o] + corr);
+#pragma unroll
+      for (int k = 0; k < B; k++) {
+        if (o[k] < 0) continue;
+        double mean;
+        if (NDIM == 3) {
+          const double s0 = f0[k] + f1[k];
+          const double s1 = f2[k] + f3[k];
+          mean = (s0 + s1) * 0.25;
+        } else {
+          mean = (f0[k] + f1[k]) * 0.5;
+        }
+        const double corr = side ? dts * (Fc[k] - mean) / dx : dts * (mean - Fc[k]) / dx;
+        uo[o[k]] = (T)(uv[k] + corr);
+      }
     }
     __syncthreads();
   }
