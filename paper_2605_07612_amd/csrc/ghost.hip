@@ -372,7 +372,7 @@ __device__ void bc_record(const MeshDev &M, T *u, int side, int64_t rec, int32_t
 // at row N, the variable stride P^d and the block stride NV P^d are
 // multiples of 4 (P = N + 2g is even), and state buffers are 16-byte aligned.
 template <typename T>
-struct Quad {
+struct Quad {  // one 16-byte chunk: W values of T (four FP32, two FP64)
   static constexpr int W = 16 / (int)sizeof(T);
   typedef T type __attribute__((ext_vector_type(W)));
 };
