@@ -504,15 +504,29 @@ def main():
                   fluxfix_share=round(ph_tl["fluxfix"] / ph_tl["step"], 4))
         del bt, m
         torch.cuda.empty_cache()
-        m = make_tl(f4.F64)
-        m.step(args.warmup)
-        st64, _ = timed_steps(lambda k: m.step(k), args.steps, torch.cuda.synchronize)
-        tl["fp64_plain"] = {"value": round(cells_tl * 2 * args.steps / st64 / 1e9, 4),
-                            "ms_per_step": round(st64 / args.steps * 1e3, 4)}
-        del m
-        torch.cuda.empty_cache()
+        # the other three forms: FP32 plain (per-kernel launches, stored
+        # ghosts), FP64 plain (the paper's form) and FP64 batched (the FP32
+        # leg's launch configuration, not tuned for FP64)
+        for prec, form in ((f4.F32, "fp32_plain"), (f4.F64, "fp64_plain"), (f4.F64, "fp64_batched")):
+            m = make_tl(prec)
+            if form.endswith("batched"):
+                run = f4.Batch([m])
+                run.set_config(cfg_tl[0], cfg_tl[1], cfg_tl[3], 1, wg_stage2=cfg_tl[2])
+                step = run.step
+            else:
+                run, step = None, (lambda k, m=m: m.step(k))
+            step(args.warmup)
+            sx, _ = timed_steps(step, args.steps, torch.cuda.synchronize)
+            tl[form] = {"value": round(cells_tl * 2 * args.steps / sx / 1e9, 4),
+                        "ms_per_step": round(sx / args.steps * 1e3, 4)}
+            if run is not None:
+                tl[form]["config"] = list(cfg_tl)
+                run.close()
+            del run, step, m
+            torch.cuda.empty_cache()
         log(f"two-level blast: FP32 batched {g_tl:.2f} Gcell-updates/s (ghost rounds {100 * ghost_share:.1f} % "
-            f"of the step), FP64 plain {tl['fp64_plain']['value']:.2f}")
+            f"of the step), FP32 plain {tl['fp32_plain']['value']:.2f}, FP64 plain {tl['fp64_plain']['value']:.2f}, "
+            f"FP64 batched {tl['fp64_batched']['value']:.2f}")
         result["two_level_blast"] = tl
 
     # ---------------- scalar advection (Sec. 3.4): the paper's highest-throughput
